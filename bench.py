@@ -1,0 +1,149 @@
+"""Benchmark: forward + Poisson log-likelihood evaluations per second on the
+config-1 workload (oblate 600 Hz star, a circular cap and an annulus,
+128x128 cells per spot, 128 phases, 256 energies, 300 channels, synthetic
+atmosphere table, absorption and response), on one MI355X.
+
+A step is one full evaluation of the hot path (setup, FP64 deflection
+tables, fine-phase traces, atmosphere collapse, intensity accumulation,
+ring reduction and absorption, MFMA response fold, FP64 log-likelihood) for
+one parameter vector, inputs resident in device memory.
+
+Prints one JSON line.  `value` is the plain (one vector per call) rate; the
+batched rate (B vectors per call) is reported beside it.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "forward+logL evals/sec at config[1], plain vs batched vs +grad, <=1e-4 rel err"
+# Algorithmic FP32 work per (cell, phase, energy) unit of the intensity
+# accumulation: x index and fraction 3, cubic Lagrange weights 10, 4-term
+# dot 7, scale and accumulate 2; plus the mu contraction of the ~63 x nodes
+# an energy window touches (8 FLOP each) amortised over 256 energies (~2).
+FLOP_PER_UNIT = 24.0
+PEAK_FP32_TFLOPS = 157.3
+
+
+def cpu_baseline(sample_cells: int):
+    import numpy as np
+
+    import oracle
+    import synthetic as syn
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(os.cpu_count() or 1, 16)
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    spec, p = syn.config1(n_cells=sample_cells)
+    os_ = oracle.OracleSpec(spec)
+    t0 = time.perf_counter()
+    _, cnt, _ = oracle.forward(os_, p)
+    data = syn.poisson_data(cnt)
+    oracle.loglike_from_counts(cnt, data)
+    dt = time.perf_counter() - t0
+    scale = (128.0 / sample_cells) ** 2          # work is linear in the number of cells
+    return {"value": 1.0 / (dt * scale), "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"config-1 workload at {sample_cells}x{sample_cells} cells per spot "
+                      f"(1/{scale:.0f} of the cells, all phases/energies/channels), {dt:.2f} s, "
+                      f"scaled linearly in cells"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=64, help="vectors per call in the batched leg (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=64, help="cells per spot of the oracle sample (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the batched path shards "
+              "parameter vectors across GPUs by design but no multi-GPU run is part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2510_07764_amd as ppm
+    import synthetic as syn
+
+    dev = torch.device("cuda:0")
+    spec, p = syn.config1()
+    gold = os.path.join(ROOT, "tests", "golden", "config1_data.npy")
+    data = np.load(gold)
+    data_t = torch.tensor(data, device=dev)
+
+    # ---------------- plain: one parameter vector per call
+    plan = ppm.Plan(spec, max_batch=1)
+    pt = torch.tensor(p[None], dtype=torch.float64, device=dev)
+    ll = torch.empty(1, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        plan.loglike(pt, data_t, out=ll)
+    torch.cuda.synchronize()
+    plan.profile_begin(args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.loglike(pt, data_t, out=ll)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hot_ms, n_hot = plan.profile_end()
+    plain_s = (t1 - t0) / args.steps
+    pairs = plan.visible_pairs(1)
+    units = pairs * plan.n_energy
+    hot_avg_s = hot_ms / max(n_hot, 1) * 1e-3
+    achieved = units * FLOP_PER_UNIT / hot_avg_s / 1e12
+
+    # ---------------- batched: B config-1-shape vectors per call
+    batched = None
+    if args.batch > 0:
+        B = args.batch
+        draws = syn.config4_draws(B)
+        planb = ppm.Plan(spec, max_batch=B)
+        ptb = torch.tensor(draws, dtype=torch.float64, device=dev)
+        llb = torch.empty(B, dtype=torch.float64, device=dev)
+        planb.loglike(ptb, data_t, out=llb)
+        torch.cuda.synchronize()
+        kb = max(2, args.steps // 10)
+        t0 = time.perf_counter()
+        for _ in range(kb):
+            planb.loglike(ptb, data_t, out=llb)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / kb
+        batched = {"evals_per_s": B / tb, "batch": B, "ms_per_call": tb * 1e3,
+                   "finite": bool(torch.isfinite(llb).all().item())}
+        del planb
+
+    cpu = cpu_baseline(args.cpu_sample) if args.cpu_sample > 0 else None
+    out = {
+        "metric": METRIC,
+        "value": 1.0 / plain_s,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": plain_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "config-1: oblate 600 Hz star, cap + annulus, 128x128 cells per spot, "
+                               "128 phases, 256 energies, 300 channels, synthetic atmosphere, absorption, response",
+                   "plain": "one parameter vector per call", "logL": float(ll.item())},
+        "batched": batched,
+        "grad": None,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_accum_table", "kernel_ms": hot_avg_s * 1e3, "units": units,
+                     "flop_per_unit": FLOP_PER_UNIT},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,160 @@
+/*
+ * libppm — MI355X (gfx950) implementation of the energy-resolved X-ray
+ * pulse-profile forward model and its Poisson log-likelihood
+ * (Zhou & Huang, "GPU-accelerated X-ray pulse profile modeling",
+ * arXiv:2510.07764).
+ *
+ * C ABI.  All entry points return an int status (PPM_OK = 0, negative on
+ * error) and never throw.  Device buffers are caller-owned and must hold
+ * the sizes stated; the plan owns its tables and scratch.  Calls are
+ * asynchronous on the given HIP stream (pass the stream handle as void*,
+ * NULL = the default stream); no call synchronises the host except where
+ * stated.  One plan must not be used from two streams at the same time.
+ * Results are bitwise reproducible for fixed inputs.
+ *
+ * Parameter record: 16 doubles per instance, row-major [B][16]:
+ *   0 M [M_sun]     1 R_e [km]     2 inclination [rad]   3 Phi [cycles]
+ *   4 N_H [1e20 cm^-2]  5 nu [Hz]  6 D [pc]              7 unused
+ *   8 theta_1 [rad] 9 zeta_1 [rad] 10 logT_1             11 unused
+ *  12 theta_2 [rad] 13 zeta_2 [rad] 14 logT_2            15 dphi_2 [cycles]
+ * The twelve differentiable slots, in gradient order, are
+ *   0, 1, 2, 3, 4, 8, 9, 10, 12, 13, 14, 15.
+ */
+#ifndef PPM_H
+#define PPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PPM_NPARAM 16
+#define PPM_NGRAD 12
+
+/* return codes */
+#define PPM_OK 0
+#define PPM_ERR_ARG (-1)        /* null pointer, size or layout the plan does not support */
+#define PPM_ERR_BATCH (-2)      /* B larger than the plan's max_batch, or B < 1 */
+#define PPM_ERR_HIP (-3)        /* a HIP runtime call failed (see ppm_last_error) */
+#define PPM_ERR_UNSUPPORTED (-4)/* spec feature not implemented (e.g. non-uniform x axis) */
+#define PPM_ERR_ALLOC (-5)      /* device allocation at plan creation failed */
+
+/* per-instance status codes (written by every evaluation) */
+#define PPM_INST_OK 0
+#define PPM_INST_NONFINITE 1    /* a parameter is NaN or Inf */
+#define PPM_INST_BAD_STAR 2     /* M <= 0, R_e <= 0, D <= 0, nu < 0, or R_e <= 1.5 R_S */
+#define PPM_INST_COMPACT 3      /* GM/(R_e c^2) > 0.28: multiple images not modelled (Sect. 6) */
+#define PPM_INST_BAD_SPOT 4     /* spot colatitude outside [0, pi] or radius outside (0, pi] */
+#define PPM_INST_FAST_SPIN 5    /* surface speed beta >= 0.6 somewhere on the star */
+
+enum ppm_mode { PPM_MODE_SD = 0, PPM_MODE_OS = 1 };
+enum ppm_intensity { PPM_I_BLACKBODY = 0, PPM_I_TABLE = 1 };
+enum ppm_shape { PPM_SHAPE_CAP = 0, PPM_SHAPE_ANNULUS = 1, PPM_SHAPE_CRESCENT = 2 };
+enum ppm_precision { PPM_F32 = 0, PPM_F64 = 1 };
+
+/*
+ * Static description of the model (host memory; copied at plan creation).
+ *
+ *  mode        S+D (spherical star, Doppler) or OS (oblate Schwarzschild), Sect. 2.2
+ *  intensity   isotropic blackbody (App. C) or a 4D atmosphere table (Sect. 2.5)
+ *  n_spots     1 or 2; spot s uses params 8+4s .. 11+4s
+ *  shape[s]    cap, annulus (inner radius shape_a*zeta) or crescent (mask cap of
+ *              radius shape_a*zeta centred shape_b*zeta towards the equator)
+ *  n_rings[s], n_phi[s]   spot grid: rings of equal colatitude width, cells of
+ *              equal azimuth width per ring (annulus: n_phi even, half per arc)
+ *  n_fp        fine rotation phases of the pseudo-patch light curve (Sect. 2.8.3)
+ *  n_phase     output phase bins, centres (k + 1/2)/n_phase
+ *  n_energy    model energies energy_kev[E] (keV), any increasing grid
+ *  n_chan      response channels; rsp[E][C] in cm^2 keV (row-major)
+ *  sigma_cm2   absorption cross-section per H atom [E] (NULL: no absorption)
+ *  t_exp       exposure [s]; counts per bin = t_exp / n_phase * flux . rsp
+ *  nT, ng, nmu, nx, ax_*, log_intensity
+ *              atmosphere axes (logT, log g, mu, log(E/kT)) and table
+ *              log10(I / T^3) [nT][ng][nmu][nx]; logT, log g and x axes must be
+ *              uniformly spaced; ignored for the blackbody model
+ *  n_alpha     nodes of the per-ring FP64 deflection table (>= 64)
+ *  precision   PPM_F32: FP32 bulk intensity/accumulate, MFMA FP32 fold;
+ *              PPM_F64: FP64 throughout (blackbody model only)
+ */
+typedef struct {
+    int32_t mode, intensity, n_spots;
+    int32_t shape[2], n_rings[2], n_phi[2];
+    double shape_a[2], shape_b[2];
+    int32_t n_fp, n_phase, n_energy, n_chan;
+    const double *energy_kev;
+    const double *sigma_cm2;
+    const double *rsp;
+    double t_exp;
+    int32_t nT, ng, nmu, nx;
+    const double *ax_T, *ax_g, *ax_mu, *ax_x;
+    const double *log_intensity;
+    int32_t n_alpha;
+    int32_t precision;
+} ppm_spec;
+
+typedef struct ppm_plan ppm_plan;
+
+/* Creates a plan: validates the spec, uploads tables (atmosphere converted to
+ * linear FP32), allocates every device buffer an evaluation of up to
+ * max_batch instances needs.  All device allocation happens here.
+ * max_cells: largest per-spot grid side (rings = cells per ring) that a
+ * per-instance resolution override may ask for (0: the spec's own). */
+int ppm_plan_create(const ppm_spec *spec, int max_batch, int max_cells, ppm_plan **out);
+void ppm_plan_destroy(ppm_plan *plan);
+
+/* Forward model (Sects. 2.3-2.8): counts_dev[B][n_phase][n_chan] (double,
+ * device).  params_dev: [B][16] doubles (device).  n_cells_host: NULL, or
+ * B ints (host) giving each instance's cells per side for both spots
+ * (rings = cells per ring = n), at most the plan's max_cells. */
+int ppm_forward(ppm_plan *plan, const double *params_dev, int B, const int32_t *n_cells_host,
+                double *counts_dev, void *stream);
+
+/* Photon flux before absorption and response: flux_dev[B][n_phase][n_energy]
+ * (ph cm^-2 s^-1 keV^-1, double).  Same arguments as ppm_forward. */
+int ppm_flux(ppm_plan *plan, const double *params_dev, int B, const int32_t *n_cells_host,
+             double *flux_dev, void *stream);
+
+/* Poisson log-likelihood sum d ln m - m - ln(d!) over all phase-channel bins
+ * for each instance: logl_dev[B] (double, device).  data_dev:
+ * [n_phase][n_chan] int32 counts shared by all instances (device).
+ * counts_dev may be NULL; otherwise it receives the model counts.
+ * An instance with a nonzero status gets logL = -inf. */
+int ppm_loglike(ppm_plan *plan, const double *params_dev, int B, const int32_t *n_cells_host,
+                const int32_t *data_dev, double *logl_dev, double *counts_dev, void *stream);
+
+/* Per-instance status codes of the last evaluation: status_dev[B] (device). */
+int ppm_instance_status(ppm_plan *plan, int B, int32_t *status_dev, void *stream);
+
+/* Host-side parameter validation with the same rules the device applies;
+ * status_host[B]. */
+int ppm_validate_params(const double *params_host, int B, int n_spots, int32_t *status_host);
+
+/* Introspection for tests: copies to host (synchronising the stream) the
+ * per-ring FP64 deflection table of instance b, ring r of the last
+ * evaluation: out[n_alpha][4] = (psi, dpsi/dalpha, c dt/R, d(c dt/R)/dalpha)
+ * at alpha_j = alpha_max * j / (n_alpha - 1); info[4] = (alpha_max, psi_top,
+ * u, R [cm]).  And the fine-phase trace out_tr[n_fp+1][4] = (F, z, phi_o, mu)
+ * with trace_info[3] = (visible, inv_min, inv_max). */
+int ppm_debug_ring(ppm_plan *plan, int b, int r, double *table_out, double *info_out,
+                   double *trace_out, int32_t *trace_info, void *stream);
+
+/* Number of (cell, phase) pairs with nonzero flux in the last evaluation,
+ * summed over instances (host; synchronises the stream). */
+int ppm_visible_pairs(ppm_plan *plan, int B, long long *out, void *stream);
+
+/* Timing of the intensity-accumulation kernel (the hot loop) with HIP events
+ * recorded on the caller's stream around each launch, for the next max_calls
+ * evaluations.  ppm_profile_end synchronises on the recorded events and
+ * returns the summed kernel time [ms] and the number of calls timed. */
+int ppm_profile_begin(ppm_plan *plan, int max_calls);
+int ppm_profile_end(ppm_plan *plan, double *hot_ms_total, int *n_calls);
+
+const char *ppm_status_string(int code);
+const char *ppm_last_error(void);
+int ppm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -447,7 +447,7 @@ int orc_trace_ring(const orc_spec *s, const double *p, const orc_ring *g,
     if (!ring_visible) return 0;
     if (imin <= imax) {
         /* Eqs. (41)-(44): zero flux and mu, linear fill of z and phi_o */
-        int a = imin - 1, b = imax + 1;
+        int a = imin - 1, b = imax + 1 > nfp ? nfp : imax + 1;   /* sample n_fp repeats sample 0 */
         for (int i = imin; i <= imax; ++i) {
             double t = (double)(i - a) / (double)(b - a);
             F[i] = 0.0; mu[i] = 0.0;

@@ -1,0 +1,257 @@
+"""MI355X (gfx950) pulse-profile forward model and Poisson likelihood.
+
+Thin ctypes binding of ``libppm.so`` (C ABI in ``include/ppm.h``).  Every
+step of the model runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch supplies device memory and the current HIP
+stream.  There is no CPU fallback: importing works without a GPU, but
+creating a plan needs the built library and a HIP device, and fails loudly
+otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libppm.so")
+
+NPARAM = 16
+NGRAD = 12
+GRAD_SLOTS = (0, 1, 2, 3, 4, 8, 9, 10, 12, 13, 14, 15)
+MODE_SD, MODE_OS = 0, 1
+I_BLACKBODY, I_TABLE = 0, 1
+F32, F64 = 0, 1
+
+_lib = None
+
+
+class PPMError(RuntimeError):
+    pass
+
+
+class _Spec(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("intensity", C.c_int32), ("n_spots", C.c_int32),
+                ("shape", C.c_int32 * 2), ("n_rings", C.c_int32 * 2), ("n_phi", C.c_int32 * 2),
+                ("shape_a", C.c_double * 2), ("shape_b", C.c_double * 2),
+                ("n_fp", C.c_int32), ("n_phase", C.c_int32), ("n_energy", C.c_int32), ("n_chan", C.c_int32),
+                ("energy_kev", C.POINTER(C.c_double)), ("sigma_cm2", C.POINTER(C.c_double)),
+                ("rsp", C.POINTER(C.c_double)), ("t_exp", C.c_double),
+                ("nT", C.c_int32), ("ng", C.c_int32), ("nmu", C.c_int32), ("nx", C.c_int32),
+                ("ax_T", C.POINTER(C.c_double)), ("ax_g", C.POINTER(C.c_double)),
+                ("ax_mu", C.POINTER(C.c_double)), ("ax_x", C.POINTER(C.c_double)),
+                ("log_intensity", C.POINTER(C.c_double)),
+                ("n_alpha", C.c_int32), ("precision", C.c_int32)]
+
+
+_VP = C.c_void_p
+_I32P = C.POINTER(C.c_int32)
+_DP = C.POINTER(C.c_double)
+
+# name -> (restype, argtypes); mirrors include/ppm.h
+SIGNATURES = {
+    "ppm_plan_create": (C.c_int, [C.POINTER(_Spec), C.c_int, C.c_int, C.POINTER(_VP)]),
+    "ppm_plan_destroy": (None, [_VP]),
+    "ppm_forward": (C.c_int, [_VP, _VP, C.c_int, _I32P, _VP, _VP]),
+    "ppm_flux": (C.c_int, [_VP, _VP, C.c_int, _I32P, _VP, _VP]),
+    "ppm_loglike": (C.c_int, [_VP, _VP, C.c_int, _I32P, _VP, _VP, _VP, _VP]),
+    "ppm_instance_status": (C.c_int, [_VP, C.c_int, _VP, _VP]),
+    "ppm_validate_params": (C.c_int, [_DP, C.c_int, C.c_int, _I32P]),
+    "ppm_debug_ring": (C.c_int, [_VP, C.c_int, C.c_int, _DP, _DP, _DP, _I32P, _VP]),
+    "ppm_visible_pairs": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_longlong), _VP]),
+    "ppm_profile_begin": (C.c_int, [_VP, C.c_int]),
+    "ppm_profile_end": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    "ppm_status_string": (C.c_char_p, [C.c_int]),
+    "ppm_last_error": (C.c_char_p, []),
+    "ppm_version": (C.c_int, []),
+}
+
+
+def lib():
+    """Loads the in-tree HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PPMError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        L = lib()
+        raise PPMError(f"{what} failed ({rc}: {L.ppm_status_string(rc).decode()}): "
+                       f"{L.ppm_last_error().decode()}")
+
+
+def validate_params(params: np.ndarray, n_spots: int) -> np.ndarray:
+    """Host-side parameter validation (same rules as the device)."""
+    p = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64)
+    out = np.zeros(p.shape[0], dtype=np.int32)
+    _check(lib().ppm_validate_params(p.ctypes.data_as(_DP), p.shape[0], n_spots, out.ctypes.data_as(_I32P)),
+           "ppm_validate_params")
+    return out
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A plan for one model spec (a dict as built by ``synthetic.config*``)."""
+
+    def __init__(self, spec: dict, max_batch: int = 1, max_cells: int = 0, n_alpha: int | None = None):
+        self.keep = []
+
+        def arr(x):
+            if x is None:
+                return None
+            a = np.ascontiguousarray(x, dtype=np.float64)
+            self.keep.append(a)
+            return a.ctypes.data_as(_DP)
+
+        s = _Spec()
+        s.mode = spec["mode"]
+        s.intensity = spec["intensity"]
+        s.n_spots = spec["n_spots"]
+        for i in range(2):
+            s.shape[i] = spec["shape"][i]
+            s.n_rings[i] = spec["n_rings"][i]
+            s.n_phi[i] = spec["n_phi"][i]
+            s.shape_a[i] = spec["shape_a"][i]
+            s.shape_b[i] = spec["shape_b"][i]
+        s.n_fp = spec["n_fp"]
+        s.n_phase = spec["n_phase"]
+        e = np.asarray(spec["energy"], dtype=np.float64)
+        s.n_energy = len(e)
+        s.energy_kev = arr(e)
+        s.sigma_cm2 = arr(spec.get("sigma"))
+        rsp = np.asarray(spec["rsp"], dtype=np.float64)
+        s.n_chan = rsp.shape[1]
+        s.rsp = arr(rsp)
+        s.t_exp = spec["t_exp"]
+        if spec["intensity"] == I_TABLE:
+            logi = np.asarray(spec["atmos_logI"], dtype=np.float64)
+            s.nT, s.ng, s.nmu, s.nx = logi.shape
+            at, ag, am, ax = spec["atmos_axes"]
+            s.ax_T, s.ax_g, s.ax_mu, s.ax_x = arr(at), arr(ag), arr(am), arr(ax)
+            s.log_intensity = arr(logi)
+        s.n_alpha = n_alpha if n_alpha is not None else spec.get("n_alpha", 512)
+        s.precision = F64 if spec.get("precision", "f32") == "f64" else F32
+        self.spec = spec
+        self.n_phase = s.n_phase
+        self.n_energy = s.n_energy
+        self.n_chan = s.n_chan
+        self.n_fp = s.n_fp
+        self.n_alpha = s.n_alpha
+        self.max_batch = max_batch
+        self.r_tot = sum(max(spec["n_rings"][i], max_cells) for i in range(min(2, spec["n_spots"])))
+        h = C.c_void_p()
+        _check(lib().ppm_plan_create(C.byref(s), max_batch, max_cells, C.byref(h)), "ppm_plan_create")
+        self.handle = h
+        self.keep = []
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ppm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _ncells(n_cells, B):
+        if n_cells is None:
+            return None, None
+        a = np.ascontiguousarray(n_cells, dtype=np.int32)
+        assert a.shape == (B,)
+        return a, a.ctypes.data_as(_I32P)
+
+    def _params(self, params):
+        import torch
+        assert params.is_cuda and params.dtype == torch.float64 and params.is_contiguous()
+        assert params.dim() == 2 and params.shape[1] == NPARAM
+        return params.shape[0]
+
+    def forward(self, params, n_cells=None, out=None, stream=None):
+        """counts[B, P, C] (float64, device)."""
+        import torch
+        B = self._params(params)
+        if out is None:
+            out = torch.empty((B, self.n_phase, self.n_chan), dtype=torch.float64, device=params.device)
+        keep, nc = self._ncells(n_cells, B)
+        _check(lib().ppm_forward(self.handle, _dptr(params), B, nc, _dptr(out), _stream_handle(stream)),
+               "ppm_forward")
+        return out
+
+    def flux(self, params, n_cells=None, out=None, stream=None):
+        """Photon flux before absorption and response, [B, P, E] float64."""
+        import torch
+        B = self._params(params)
+        if out is None:
+            out = torch.empty((B, self.n_phase, self.n_energy), dtype=torch.float64, device=params.device)
+        keep, nc = self._ncells(n_cells, B)
+        _check(lib().ppm_flux(self.handle, _dptr(params), B, nc, _dptr(out), _stream_handle(stream)), "ppm_flux")
+        return out
+
+    def loglike(self, params, data, n_cells=None, counts=None, out=None, stream=None):
+        """logL[B] (float64, device); data: int32 [P, C] on the device."""
+        import torch
+        B = self._params(params)
+        assert data.is_cuda and data.dtype == torch.int32 and data.is_contiguous()
+        assert data.numel() == self.n_phase * self.n_chan
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=params.device)
+        keep, nc = self._ncells(n_cells, B)
+        cptr = _dptr(counts) if counts is not None else None
+        _check(lib().ppm_loglike(self.handle, _dptr(params), B, nc, _dptr(data), _dptr(out), cptr,
+                                 _stream_handle(stream)), "ppm_loglike")
+        return out
+
+    def status(self, B, stream=None):
+        import torch
+        out = torch.empty(B, dtype=torch.int32, device="cuda")
+        _check(lib().ppm_instance_status(self.handle, B, _dptr(out), _stream_handle(stream)), "ppm_instance_status")
+        return out
+
+    def debug_ring(self, b, r, stream=None):
+        tab = np.zeros((self.n_alpha, 4))
+        info = np.zeros(4)
+        tr = np.zeros((self.n_fp + 1, 4))
+        ti = np.zeros(3, dtype=np.int32)
+        _check(lib().ppm_debug_ring(self.handle, b, r, tab.ctypes.data_as(_DP), info.ctypes.data_as(_DP),
+                                    tr.ctypes.data_as(_DP), ti.ctypes.data_as(_I32P), _stream_handle(stream)),
+               "ppm_debug_ring")
+        return dict(table=tab, alpha_max=info[0], psi_top=info[1], u=info[2], R=info[3], trace=tr,
+                    visible=bool(ti[0]), inv=(int(ti[1]), int(ti[2])))
+
+    def profile_begin(self, max_calls):
+        _check(lib().ppm_profile_begin(self.handle, max_calls), "ppm_profile_begin")
+
+    def profile_end(self):
+        """(summed hot-kernel milliseconds, number of timed calls)."""
+        ms = C.c_double()
+        n = C.c_int()
+        _check(lib().ppm_profile_end(self.handle, C.byref(ms), C.byref(n)), "ppm_profile_end")
+        return ms.value, n.value
+
+    def visible_pairs(self, B, stream=None):
+        out = C.c_longlong()
+        _check(lib().ppm_visible_pairs(self.handle, B, C.byref(out), _stream_handle(stream)), "ppm_visible_pairs")
+        return out.value

@@ -1,0 +1,472 @@
+// C-ABI of libppm: plan management, argument validation, launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ppm.h"
+#include "ppm_internal.h"
+#include "ppm_launch.h"
+
+using namespace ppm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where)
+{
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return PPM_ERR_HIP;
+}
+
+// Gauss-Legendre nodes and weights on [0, 1] (Newton iteration on P_n).
+void gauss_legendre01(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+        }
+        x[i] = 0.5 * (1.0 - z);
+        w[i] = 1.0 / ((1.0 - z * z) * dp * dp);   // (2/((1-z^2) P'^2)) / 2
+    }
+}
+
+bool uniform_axis(const double *a, int n, double &x0, double &h)
+{
+    if (n < 2) return false;
+    x0 = a[0];
+    h = (a[n - 1] - a[0]) / (n - 1);
+    if (!(h > 0.0)) return false;
+    for (int i = 0; i < n; ++i)
+        if (std::fabs(a[i] - (x0 + h * i)) > 1e-9 * std::fabs(h) * n) return false;
+    return true;
+}
+
+}  // namespace
+
+struct ppm_plan {
+    DevSpec S;
+    Workspace W;
+    int max_batch = 0;
+    int max_cells = 0;
+    int precision = PPM_F32;
+    std::vector<void *> allocs;
+    std::vector<int32_t> last_ncells;
+    bool ncells_valid = false;
+    int last_B = 0;
+    // hot-kernel timing: one event pair per recorded call
+    std::vector<hipEvent_t> ev;
+    int prof_cap = 0, prof_n = 0;
+    bool prof_on = false;
+
+    template <typename T>
+    T *dalloc(size_t n)
+    {
+        if (n == 0) return nullptr;
+        void *p = nullptr;
+        if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) return nullptr;
+        allocs.push_back(p);
+        return static_cast<T *>(p);
+    }
+    template <typename T>
+    T *upload(const T *host, size_t n)
+    {
+        T *d = dalloc<T>(n);
+        if (d && hipMemcpy(d, host, n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+        return d;
+    }
+    void events(hipEvent_t &a, hipEvent_t &b)
+    {
+        a = b = nullptr;
+        if (!prof_on || prof_n >= prof_cap) return;
+        a = ev[2 * prof_n];
+        b = ev[2 * prof_n + 1];
+        ++prof_n;
+    }
+    ~ppm_plan()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
+extern "C" {
+
+int ppm_version(void) { return 1; }
+
+const char *ppm_last_error(void) { return g_last_error.c_str(); }
+
+const char *ppm_status_string(int code)
+{
+    switch (code) {
+    case PPM_OK: return "ok";
+    case PPM_ERR_ARG: return "invalid argument";
+    case PPM_ERR_BATCH: return "batch size outside [1, max_batch]";
+    case PPM_ERR_HIP: return "HIP runtime error";
+    case PPM_ERR_UNSUPPORTED: return "unsupported spec";
+    case PPM_ERR_ALLOC: return "device allocation failed";
+    default: return "unknown status";
+    }
+}
+
+int ppm_validate_params(const double *params_host, int B, int n_spots, int32_t *status_host)
+{
+    if (!params_host || !status_host || B < 1 || n_spots < 1 || n_spots > 2)
+        return fail(PPM_ERR_ARG, "ppm_validate_params: bad arguments");
+    for (int b = 0; b < B; ++b) status_host[b] = validate_params(params_host + (size_t)b * PPM_NPARAM, n_spots);
+    return PPM_OK;
+}
+
+int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan **out)
+{
+    if (!sp || !out) return fail(PPM_ERR_ARG, "ppm_plan_create: null pointer");
+    *out = nullptr;
+    if (max_batch < 1) return fail(PPM_ERR_ARG, "max_batch must be >= 1");
+    if (sp->n_spots < 1 || sp->n_spots > 2) return fail(PPM_ERR_ARG, "n_spots must be 1 or 2");
+    if (sp->mode != PPM_MODE_SD && sp->mode != PPM_MODE_OS) return fail(PPM_ERR_ARG, "bad mode");
+    if (sp->intensity != PPM_I_BLACKBODY && sp->intensity != PPM_I_TABLE) return fail(PPM_ERR_ARG, "bad intensity");
+    if (sp->precision != PPM_F32 && sp->precision != PPM_F64) return fail(PPM_ERR_ARG, "bad precision");
+    if (sp->precision == PPM_F64 && sp->intensity != PPM_I_BLACKBODY)
+        return fail(PPM_ERR_UNSUPPORTED, "FP64 precision is implemented for the blackbody model only");
+    for (int s = 0; s < sp->n_spots; ++s) {
+        if (sp->shape[s] < 0 || sp->shape[s] > 2) return fail(PPM_ERR_ARG, "bad spot shape");
+        if (sp->n_rings[s] < 1 || sp->n_phi[s] < 1) return fail(PPM_ERR_ARG, "spot grid must be >= 1x1");
+        if (sp->shape[s] == PPM_SHAPE_ANNULUS && (sp->n_phi[s] % 2))
+            return fail(PPM_ERR_ARG, "annulus needs an even number of cells per ring");
+        if (sp->shape[s] != PPM_SHAPE_CAP && !(sp->shape_a[s] > 0.0 && sp->shape_a[s] < 1.0))
+            return fail(PPM_ERR_ARG, "annulus / crescent ratio must lie in (0, 1)");
+        if (max_cells > 0 && sp->shape[s] == PPM_SHAPE_ANNULUS && (max_cells % 2))
+            return fail(PPM_ERR_ARG, "max_cells must be even with an annulus");
+    }
+    if (sp->n_fp < 4 || sp->n_phase < 1 || sp->n_energy < 1 || sp->n_chan < 1)
+        return fail(PPM_ERR_ARG, "n_fp >= 4, n_phase, n_energy, n_chan >= 1 required");
+    if (!sp->energy_kev || !sp->rsp) return fail(PPM_ERR_ARG, "energy and rsp are required");
+    for (int e = 0; e < sp->n_energy; ++e) {
+        if (!(sp->energy_kev[e] > 0.0)) return fail(PPM_ERR_ARG, "energies must be positive");
+        if (e && !(sp->energy_kev[e] > sp->energy_kev[e - 1])) return fail(PPM_ERR_ARG, "energies must increase");
+    }
+    if (!(sp->t_exp > 0.0)) return fail(PPM_ERR_ARG, "t_exp must be positive");
+    if (sp->n_alpha < 64 || sp->n_alpha > 8192) return fail(PPM_ERR_ARG, "n_alpha must lie in [64, 8192]");
+    if (sp->n_energy > 64 * 8) return fail(PPM_ERR_UNSUPPORTED, "at most 512 energies");
+    double tmp0, tmp1;
+    if (sp->intensity == PPM_I_TABLE) {
+        if (!sp->ax_T || !sp->ax_g || !sp->ax_mu || !sp->ax_x || !sp->log_intensity)
+            return fail(PPM_ERR_ARG, "table intensity needs axes and values");
+        if (sp->nT < 2 || sp->ng < 2 || sp->nmu < 6 || sp->nmu > kMaxMu || sp->nx < 4)
+            return fail(PPM_ERR_ARG, "atmosphere table too small (or more than 128 mu nodes)");
+        if (!uniform_axis(sp->ax_T, sp->nT, tmp0, tmp1) || !uniform_axis(sp->ax_g, sp->ng, tmp0, tmp1)
+            || !uniform_axis(sp->ax_x, sp->nx, tmp0, tmp1))
+            return fail(PPM_ERR_UNSUPPORTED, "logT, log g and x axes must be uniformly spaced");
+        for (int i = 1; i < sp->nmu; ++i)
+            if (!(sp->ax_mu[i] > sp->ax_mu[i - 1])) return fail(PPM_ERR_ARG, "mu axis must increase");
+    }
+
+    ppm_plan *pl = new (std::nothrow) ppm_plan();
+    if (!pl) return fail(PPM_ERR_ALLOC, "host allocation failed");
+    DevSpec &S = pl->S;
+    std::memset(&S, 0, sizeof(S));
+    S.mode = sp->mode;
+    S.intensity = sp->intensity;
+    S.n_spots = sp->n_spots;
+    for (int s = 0; s < 2; ++s) {
+        bool on = s < sp->n_spots;
+        S.shape[s] = on ? sp->shape[s] : 0;
+        S.shape_a[s] = on ? sp->shape_a[s] : 0.0;
+        S.shape_b[s] = on ? sp->shape_b[s] : 0.0;
+        S.n_rings_spec[s] = on ? sp->n_rings[s] : 0;
+        S.n_phi_spec[s] = on ? sp->n_phi[s] : 0;
+        int mx = on ? sp->n_rings[s] : 0;
+        if (on && max_cells > mx) mx = max_cells;
+        S.rings_max[s] = mx;
+    }
+    S.R_tot = S.rings_max[0] + S.rings_max[1];
+    S.n_fp = sp->n_fp;
+    S.P = sp->n_phase;
+    S.E = sp->n_energy;
+    S.C = sp->n_chan;
+    S.t_exp = sp->t_exp;
+    S.n_alpha = sp->n_alpha;
+    S.n_quad = 96;
+    pl->max_batch = max_batch;
+    pl->max_cells = max_cells;
+    pl->precision = sp->precision;
+
+    std::vector<double> glx, glw;
+    gauss_legendre01(S.n_quad, glx, glw);
+    S.glx = pl->upload(glx.data(), glx.size());
+    S.glw = pl->upload(glw.data(), glw.size());
+    S.energy = pl->upload(sp->energy_kev, S.E);
+    if (sp->sigma_cm2) S.sigma = pl->upload(sp->sigma_cm2, S.E);
+    {
+        size_t n = (size_t)S.E * S.C;
+        std::vector<float> r32(n);
+        for (size_t i = 0; i < n; ++i) r32[i] = (float)sp->rsp[i];
+        S.rsp32 = pl->upload(r32.data(), n);
+        if (sp->precision == PPM_F64) S.rsp64 = pl->upload(sp->rsp, n);
+    }
+    if (sp->intensity == PPM_I_TABLE) {
+        S.nT = sp->nT; S.ng = sp->ng; S.nmu = sp->nmu; S.nx = sp->nx;
+        uniform_axis(sp->ax_T, S.nT, S.T0, S.hT);
+        uniform_axis(sp->ax_g, S.ng, S.g0, S.hg);
+        uniform_axis(sp->ax_x, S.nx, S.x0, S.hx);
+        size_t n = (size_t)S.nT * S.ng * S.nmu * S.nx;
+        std::vector<float> lin(n);
+        for (size_t i = 0; i < n; ++i) lin[i] = (float)std::pow(10.0, sp->log_intensity[i]);
+        S.atm = pl->upload(lin.data(), n);
+        S.ax_mu = pl->upload(sp->ax_mu, S.nmu);
+    }
+    // workspace
+    Workspace &W = pl->W;
+    std::memset(&W, 0, sizeof(W));
+    const size_t B = max_batch, R = S.R_tot;
+    W.stars = pl->dalloc<StarRec>(B);
+    W.rings = pl->dalloc<RingRec>(B * R);
+    W.table = pl->dalloc<double4>(B * R * S.n_alpha);
+    W.trace = pl->dalloc<double4>(B * R * (S.n_fp + 1));
+    W.vis_pairs = pl->dalloc<int32_t>(B * R);
+    W.ncells = pl->dalloc<int32_t>(B);
+    W.counts = pl->dalloc<double>(B * S.P * S.C);
+    bool ok = W.stars && W.rings && W.table && W.trace && W.vis_pairs && W.ncells && W.counts
+           && S.glx && S.glw && S.energy && S.rsp32;
+    if (S.intensity == PPM_I_TABLE) {
+        W.sub = pl->dalloc<float>(B * R * S.nmu * S.nx);
+        W.partial32 = pl->dalloc<float>(B * R * S.P * S.E);
+        W.fold_in32 = pl->dalloc<float>(B * S.P * S.E);
+        ok = ok && W.sub && W.partial32 && W.fold_in32 && S.atm && S.ax_mu;
+    } else {
+        W.partial64 = pl->dalloc<double>(B * R * S.P * S.E);
+        if (sp->precision == PPM_F64) {
+            W.fold_in64 = pl->dalloc<double>(B * S.P * S.E);
+            ok = ok && W.fold_in64 && S.rsp64;
+        } else {
+            W.fold_in32 = pl->dalloc<float>(B * S.P * S.E);
+            ok = ok && W.fold_in32;
+        }
+        ok = ok && W.partial64;
+    }
+    if (!ok) {
+        delete pl;
+        return fail(PPM_ERR_ALLOC, "device allocation or upload failed");
+    }
+    if (S.intensity == PPM_I_TABLE) {
+        size_t lds = accum_table_lds(S);
+        if (lds > 160 * 1024) {
+            delete pl;
+            return fail(PPM_ERR_UNSUPPORTED, "atmosphere sub-table does not fit in LDS");
+        }
+    }
+    *out = pl;
+    return PPM_OK;
+}
+
+void ppm_plan_destroy(ppm_plan *plan) { delete plan; }
+
+static int prepare(ppm_plan *pl, const double *params, int B, const int32_t *ncells_host,
+                   const int32_t **ncells_dev)
+{
+    if (!pl || !params) return fail(PPM_ERR_ARG, "null plan or params");
+    if (B < 1 || B > pl->max_batch) return fail(PPM_ERR_BATCH, "batch outside [1, max_batch]");
+    *ncells_dev = nullptr;
+    if (ncells_host) {
+        for (int b = 0; b < B; ++b) {
+            int n = ncells_host[b];
+            int lim = pl->max_cells > 0 ? pl->max_cells : 0;
+            for (int s = 0; s < pl->S.n_spots; ++s)
+                if (lim < pl->S.rings_max[s]) lim = pl->S.rings_max[s];
+            if (n < 1 || n > lim) return fail(PPM_ERR_ARG, "per-instance grid outside [1, max_cells]");
+            for (int s = 0; s < pl->S.n_spots; ++s)
+                if (pl->S.shape[s] == PPM_SHAPE_ANNULUS && (n % 2))
+                    return fail(PPM_ERR_ARG, "annulus needs an even per-instance grid");
+            for (int s = 0; s < pl->S.n_spots; ++s)
+                if (n > pl->S.rings_max[s]) return fail(PPM_ERR_ARG, "per-instance grid exceeds the plan");
+        }
+        bool same = pl->ncells_valid && (int)pl->last_ncells.size() >= B
+                 && std::memcmp(pl->last_ncells.data(), ncells_host, sizeof(int32_t) * B) == 0;
+        if (!same) {
+            hipError_t e = hipMemcpy(pl->W.ncells, ncells_host, sizeof(int32_t) * B, hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, "upload of per-instance grids");
+            pl->last_ncells.assign(ncells_host, ncells_host + B);
+            pl->ncells_valid = true;
+        }
+        *ncells_dev = pl->W.ncells;
+    }
+    pl->last_B = B;
+    return PPM_OK;
+}
+
+int ppm_forward(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_cells_host,
+                double *counts_dev, void *stream)
+{
+    const int32_t *nc = nullptr;
+    int rc = prepare(pl, params_dev, B, n_cells_host, &nc);
+    if (rc) return rc;
+    if (!counts_dev) return fail(PPM_ERR_ARG, "null counts buffer");
+    hipEvent_t e0, e1;
+    pl->events(e0, e1);
+    hipError_t e = launch_forward(pl->S, pl->W, params_dev, nc, B, (hipStream_t)stream, nullptr, counts_dev, e0, e1);
+    return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_forward launch");
+}
+
+int ppm_flux(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_cells_host, double *flux_dev,
+             void *stream)
+{
+    const int32_t *nc = nullptr;
+    int rc = prepare(pl, params_dev, B, n_cells_host, &nc);
+    if (rc) return rc;
+    if (!flux_dev) return fail(PPM_ERR_ARG, "null flux buffer");
+    hipEvent_t e0, e1;
+    pl->events(e0, e1);
+    hipError_t e = launch_forward(pl->S, pl->W, params_dev, nc, B, (hipStream_t)stream, flux_dev, pl->W.counts, e0, e1);
+    return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_flux launch");
+}
+
+int ppm_loglike(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_cells_host,
+                const int32_t *data_dev, double *logl_dev, double *counts_dev, void *stream)
+{
+    const int32_t *nc = nullptr;
+    int rc = prepare(pl, params_dev, B, n_cells_host, &nc);
+    if (rc) return rc;
+    if (!data_dev || !logl_dev) return fail(PPM_ERR_ARG, "null data or logl buffer");
+    double *cnt = counts_dev ? counts_dev : pl->W.counts;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    pl->events(e0, e1);
+    hipError_t e = launch_forward(pl->S, pl->W, params_dev, nc, B, st, nullptr, cnt, e0, e1);
+    if (e != hipSuccess) return hip_fail(e, "ppm_loglike forward");
+    e = launch_loglike(pl->W, cnt, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
+    return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike reduction");
+}
+
+int ppm_instance_status(ppm_plan *pl, int B, int32_t *status_dev, void *stream)
+{
+    if (!pl || !status_dev) return fail(PPM_ERR_ARG, "null argument");
+    if (B < 1 || B > pl->max_batch) return fail(PPM_ERR_BATCH, "batch outside [1, max_batch]");
+    hipError_t e = launch_status(pl->W, B, status_dev, (hipStream_t)stream);
+    return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_instance_status");
+}
+
+int ppm_debug_ring(ppm_plan *pl, int b, int r, double *table_out, double *info_out, double *trace_out,
+                   int32_t *trace_info, void *stream)
+{
+    if (!pl) return fail(PPM_ERR_ARG, "null plan");
+    if (b < 0 || b >= pl->max_batch || r < 0 || r >= pl->S.R_tot) return fail(PPM_ERR_ARG, "ring out of range");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "ppm_debug_ring sync");
+    const size_t ring = (size_t)b * pl->S.R_tot + r;
+    RingRec g;
+    e = hipMemcpy(&g, pl->W.rings + ring, sizeof(g), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "ppm_debug_ring copy");
+    if (table_out) {
+        e = hipMemcpy(table_out, pl->W.table + ring * pl->S.n_alpha, sizeof(double4) * pl->S.n_alpha,
+                      hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "ppm_debug_ring table copy");
+    }
+    if (info_out) {
+        double4 last;
+        e = hipMemcpy(&last, pl->W.table + ring * pl->S.n_alpha + pl->S.n_alpha - 1, sizeof(last),
+                      hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "ppm_debug_ring info copy");
+        info_out[0] = g.alpha_max;
+        info_out[1] = last.x;
+        info_out[2] = g.u;
+        info_out[3] = g.R;
+    }
+    if (trace_out) {
+        e = hipMemcpy(trace_out, pl->W.trace + ring * (pl->S.n_fp + 1), sizeof(double4) * (pl->S.n_fp + 1),
+                      hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "ppm_debug_ring trace copy");
+    }
+    if (trace_info) {
+        trace_info[0] = g.visible;
+        trace_info[1] = g.inv_min;
+        trace_info[2] = g.inv_max;
+    }
+    return PPM_OK;
+}
+
+int ppm_profile_begin(ppm_plan *pl, int max_calls)
+{
+    if (!pl || max_calls < 1) return fail(PPM_ERR_ARG, "ppm_profile_begin: bad arguments");
+    if ((int)pl->ev.size() < 2 * max_calls) {
+        for (hipEvent_t e : pl->ev) (void)hipEventDestroy(e);
+        pl->ev.assign(2 * max_calls, nullptr);
+        for (auto &e : pl->ev) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return hip_fail(r, "ppm_profile_begin event");
+        }
+    }
+    pl->prof_cap = max_calls;
+    pl->prof_n = 0;
+    pl->prof_on = true;
+    return PPM_OK;
+}
+
+int ppm_profile_end(ppm_plan *pl, double *hot_ms_total, int *n_calls)
+{
+    if (!pl || !hot_ms_total || !n_calls) return fail(PPM_ERR_ARG, "ppm_profile_end: null argument");
+    double tot = 0.0;
+    for (int i = 0; i < pl->prof_n; ++i) {
+        hipError_t r = hipEventSynchronize(pl->ev[2 * i + 1]);
+        if (r != hipSuccess) return hip_fail(r, "ppm_profile_end sync");
+        float ms = 0.0f;
+        r = hipEventElapsedTime(&ms, pl->ev[2 * i], pl->ev[2 * i + 1]);
+        if (r != hipSuccess) return hip_fail(r, "ppm_profile_end elapsed");
+        tot += ms;
+    }
+    *hot_ms_total = tot;
+    *n_calls = pl->prof_n;
+    pl->prof_on = false;
+    pl->prof_n = 0;
+    return PPM_OK;
+}
+
+int ppm_visible_pairs(ppm_plan *pl, int B, long long *out, void *stream)
+{
+    if (!pl || !out) return fail(PPM_ERR_ARG, "null argument");
+    if (B < 1 || B > pl->max_batch) return fail(PPM_ERR_BATCH, "batch outside [1, max_batch]");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ppm_visible_pairs sync");
+    std::vector<int32_t> v((size_t)B * pl->S.R_tot);
+    e = hipMemcpy(v.data(), pl->W.vis_pairs, sizeof(int32_t) * v.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "ppm_visible_pairs copy");
+    long long s = 0;
+    for (int32_t x : v) s += x;
+    *out = s;
+    return PPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// Internal records shared by the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ppm {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 2.0 * kPi;
+constexpr double kHalfPi = 0.5 * kPi;
+
+// physical constants, CGS + keV
+constexpr double kC = 2.99792458e10;
+constexpr double kGMsun = 1.3271244e26;
+constexpr double kKB = 8.617333262e-8;
+constexpr double kH = 4.135667696e-18;
+constexpr double kPc = 3.0856775814913673e18;
+
+constexpr int kMaxQuad = 128;     // Gauss-Legendre nodes of the deflection quadrature
+constexpr int kMaxMu = 128;       // mu nodes held in constant memory
+
+// Static model description as seen by the kernels (device pointers).
+struct DevSpec {
+    int mode, intensity, n_spots;
+    int shape[2];
+    double shape_a[2], shape_b[2];
+    int n_fp, P, E, C;
+    int nT, ng, nmu, nx;
+    int n_alpha, n_quad;
+    int R_tot;            // ring slots per instance (spot 0 then spot 1)
+    int rings_max[2];     // ring slots of each spot
+    int n_rings_spec[2], n_phi_spec[2];   // default grid of each spot
+    double t_exp;
+    double T0, hT, g0, hg, x0, hx;   // uniform logT, log g, x axes
+    const double *energy;   // [E] keV
+    const double *sigma;    // [E] cm^2 (nullptr: no absorption)
+    const float *rsp32;     // [E][C]
+    const double *rsp64;    // [E][C]
+    const float *atm;       // [nT][ng][nmu][nx] linear I/T^3
+    const double *ax_mu;    // [nmu]
+    const double *glx, *glw;  // Gauss-Legendre on [0, 1], n_quad nodes
+};
+
+struct StarRec {
+    double GM, Rs, Re, x, Obar, o2, g0, D, nu, si, ci, NH;
+    int status;
+    int pad;
+};
+
+struct RingRec {
+    double theta, dcos, R, u, sq1u, f, coseta, sineta, logg, beta, gamma;
+    double dphi_out, dphi_in, dphi_cell, w_cell;
+    double alpha_max, cdt_obl;   // c dt(R)/R of Eq. (16)
+    double phi_spot;             // -2 pi (Phi + dphi_s)
+    double logT, T, kT;
+    double tm, cos_zm;           // crescent mask centre colatitude, cos(mask radius)
+    int spot, shape, n_cells, active;
+    int visible, inv_min, inv_max, pad;
+};
+
+}  // namespace ppm

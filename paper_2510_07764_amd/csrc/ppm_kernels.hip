@@ -1,0 +1,898 @@
+// gfx950 kernels of the pulse-profile forward model and Poisson likelihood.
+//
+// Pipeline of one evaluation (all instances of a batch at once):
+//   k_setup      FP64 star and ring records, parameter validation
+//   k_table      FP64 per-ring deflection / delay table on alpha nodes
+//   k_trace      FP64 pseudo-patch fine-phase trace with invisible fill
+//   k_subtable   per-ring (logT, log g) collapse of the atmosphere table
+//   k_accum_*    shift-and-add intensity accumulation (the hot loop)
+//   k_reduce     deterministic sum over rings, absorption
+//   k_fold_*     response fold on the matrix cores (MFMA)
+//   k_loglike    Poisson log-likelihood, FP64
+// Section and equation numbers refer to arXiv:2510.07764.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ppm_internal.h"
+#include "ppm_launch.h"
+#include "../../include/ppm.h"
+
+namespace ppm {
+
+// ---------------------------------------------------------------------------
+// parameter validation (host and device share these rules)
+// ---------------------------------------------------------------------------
+__host__ __device__ int validate_params(const double *p, int n_spots)
+{
+    const int used[14] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 13, 14, 15};
+    int nused = n_spots > 1 ? 14 : 10;
+    for (int i = 0; i < nused; ++i)
+        if (!isfinite(p[used[i]])) return PPM_INST_NONFINITE;
+    if (p[0] <= 0.0 || p[1] <= 0.0 || p[6] <= 0.0 || p[5] < 0.0 || p[4] < 0.0) return PPM_INST_BAD_STAR;
+    double GM = p[0] * kGMsun, Re = p[1] * 1e5;
+    double Rs = 2.0 * GM / (kC * kC);
+    if (Re <= 1.5 * Rs) return PPM_INST_BAD_STAR;
+    if (GM / (kC * kC * Re) > 0.28 * (1.0 + 1e-12)) return PPM_INST_COMPACT;   // inclusive limit
+    for (int s = 0; s < n_spots; ++s) {
+        double th = p[8 + 4 * s], z = p[9 + 4 * s];
+        if (th < 0.0 || th > kPi || z <= 0.0 || z > kPi) return PPM_INST_BAD_SPOT;
+    }
+    double beta_eq = kTwoPi * p[5] * Re / (kC * sqrt(1.0 - Rs / Re));
+    if (beta_eq >= 0.6) return PPM_INST_FAST_SPIN;
+    return PPM_INST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// k_setup: star (Eqs. 7, 8, 11) and spot rings (Eqs. 2, 3, 9, 10, 18)
+// ---------------------------------------------------------------------------
+__device__ static double gravity_ratio(const StarRec &st, int mode, double th)
+{
+    if (mode != PPM_MODE_OS) return 1.0;
+    double x = st.x, O2 = st.Obar * st.Obar, O4 = O2 * O2, O6 = O4 * O2;
+    double sn = sin(th), c = cos(th);
+    double s2 = sn * sn, c2 = c * c;
+    double e4 = O4 * (13.47 * x - 27.13 * x * x);
+    return 1.0 + s2 * (O2 * (-0.791 + 0.776 * x) + O4 * (-1.315 * x + 2.431 * x * x) + O6 * (-1.172 * x))
+         + c2 * (O2 * (1.138 - 1.431 * x) + O4 * (0.653 * x - 2.864 * x * x) + O6 * (0.975 * x) - e4)
+         + fabs(c) * e4;
+}
+
+// azimuthal half-width of a ring at colatitude th inside a cap (tc, z)
+__device__ static double arc_halfwidth(double th, double tc, double z)
+{
+    double den = sin(th) * sin(tc);
+    double num = cos(z) - cos(th) * cos(tc);
+    if (den <= 0.0) return num <= 0.0 ? kPi : 0.0;
+    double a = num / den;
+    if (a <= -1.0) return kPi;
+    if (a >= 1.0) return 0.0;
+    return acos(a);
+}
+
+__device__ static double cdt_oblate(double Re, double Rs, double R)
+{
+    return Re - R + Rs * log((Re - Rs) / (R - Rs));   // Eq. (16)
+}
+
+__global__ void k_setup(DevSpec S, const double *params, const int32_t *n_cells, StarRec *stars,
+                        RingRec *rings)
+{
+    const int b = blockIdx.x;
+    const double *p = params + (size_t)b * PPM_NPARAM;
+    __shared__ StarRec st;
+    if (threadIdx.x == 0) {
+        StarRec s;
+        s.status = validate_params(p, S.n_spots);
+        s.GM = p[0] * kGMsun;
+        s.Re = p[1] * 1e5;
+        s.Rs = 2.0 * s.GM / (kC * kC);
+        s.x = s.GM / (kC * kC * s.Re);
+        s.Obar = kTwoPi * p[5] * sqrt(s.Re * s.Re * s.Re / s.GM);
+        s.o2 = (S.mode == PPM_MODE_OS) ? s.Obar * s.Obar * (-0.788 + 1.030 * s.x) : 0.0;
+        s.g0 = s.GM / (s.Re * s.Re) / sqrt(1.0 - s.Rs / s.Re);
+        s.D = p[6] * kPc;
+        s.nu = p[5];
+        s.si = sin(p[2]);
+        s.ci = cos(p[2]);
+        s.NH = p[4] * 1e20;
+        s.pad = 0;
+        st = s;
+        stars[b] = s;
+    }
+    __syncthreads();
+    const int ncell_override = n_cells ? n_cells[b] : 0;
+    for (int r = threadIdx.x; r < S.R_tot; r += blockDim.x) {
+        RingRec g;
+        int spot = (r < S.rings_max[0]) ? 0 : 1;
+        int lr = spot == 0 ? r : r - S.rings_max[0];
+        int nr = ncell_override > 0 ? ncell_override : S.n_rings_spec[spot];
+        int np = ncell_override > 0 ? ncell_override : S.n_phi_spec[spot];
+        g.spot = spot;
+        g.shape = S.shape[spot];
+        g.active = 0;
+        g.visible = 0;
+        g.inv_min = 0;
+        g.inv_max = -1;
+        g.pad = 0;
+        g.n_cells = 0;
+        bool live = st.status == PPM_INST_OK && spot < S.n_spots && lr < nr;
+        double tc = p[8 + 4 * spot], z = p[9 + 4 * spot];
+        if (!live) { tc = 0.5; z = 0.1; }
+        double lo = fmax(0.0, tc - z), hi = fmin(kPi, tc + z);
+        double e0 = lo + (hi - lo) * lr / nr, e1 = lo + (hi - lo) * (lr + 1) / nr;
+        double th = 0.5 * (e0 + e1);
+        g.theta = th;
+        g.dcos = cos(e0) - cos(e1);
+        double ct = cos(th), sn = sin(th);
+        g.R = st.Re * (1.0 + st.o2 * ct * ct);                    // Eq. (7)
+        double dR = -2.0 * st.Re * st.o2 * ct * sn;
+        g.u = st.Rs / g.R;
+        g.sq1u = sqrt(1.0 - g.u);
+        g.f = dR / (g.R * g.sq1u);                                 // Eq. (2)
+        g.coseta = 1.0 / sqrt(1.0 + g.f * g.f);                    // Eq. (3)
+        g.sineta = g.f / sqrt(1.0 + g.f * g.f);
+        g.logg = log10(st.g0 * gravity_ratio(st, S.mode, th));     // Eqs. (10), (11)
+        g.beta = kTwoPi * st.nu * g.R * sn / (kC * g.sq1u);        // Eq. (18)
+        g.gamma = 1.0 / sqrt(1.0 - g.beta * g.beta);
+        g.dphi_out = arc_halfwidth(th, tc, z);
+        if (g.shape == PPM_SHAPE_ANNULUS) {
+            g.dphi_in = arc_halfwidth(th, tc, S.shape_a[spot] * z);
+            g.dphi_cell = (g.dphi_out - g.dphi_in) / (0.5 * np);
+        } else {
+            g.dphi_in = 0.0;
+            g.dphi_cell = 2.0 * g.dphi_out / np;
+        }
+        g.w_cell = g.R * g.R * sqrt(1.0 + g.f * g.f) * g.dcos * g.dphi_cell / (st.D * st.D);  // Eq. (9)
+        double acap;
+        {
+            double v = 1.5 * g.u * sqrt(3.0 * (1.0 - g.u));
+            acap = v >= 1.0 ? kHalfPi : kPi - asin(v);
+        }
+        double amax = kHalfPi + fabs(atan(g.f));
+        if (amax > acap - 1e-6) amax = acap - 1e-6;
+        g.alpha_max = amax;
+        g.cdt_obl = cdt_oblate(st.Re, st.Rs, g.R) / g.R;
+        g.phi_spot = -kTwoPi * (p[3] + (spot == 1 ? p[15] : 0.0));
+        g.logT = p[10 + 4 * spot];
+        g.T = pow(10.0, g.logT);
+        g.kT = kKB * g.T;
+        double sgn = (tc >= kHalfPi) ? 1.0 : -1.0;
+        g.tm = tc - sgn * S.shape_b[spot] * z;
+        g.cos_zm = cos(S.shape_a[spot] * z);
+        if (live) g.n_cells = np;
+        rings[(size_t)b * S.R_tot + r] = g;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_table: FP64 deflection and delay table per ring (Sect. 2.3, 2.8.2).
+// Nodes are uniform in alpha on [0, alpha_max]; each stores psi (Eq. 32),
+// dpsi/dalpha, the total delay c dt / R (Eqs. 35, 16, 17) and its alpha
+// derivative, so that lookups can use C1 cubic Hermite interpolation.
+// Quadrature: Gauss-Legendre after x = A sinh(tau), A = cos(a)/(sin(a)
+// sqrt(q0)), which resolves the boundary layer of width ~cos(alpha) at
+// x -> 0 for near-grazing rays.
+// ---------------------------------------------------------------------------
+__device__ static inline double q_s2(double x, double v)
+{
+    double t = 1.0 - x * x;
+    return 2.0 - x * x - v * t * t / (1.0 - v);
+}
+
+// psi, dpsi/dalpha and c dt_p/R for an outgoing ray, 0 <= alpha <= pi/2
+__device__ static void bend_out(const DevSpec &S, double u, double alpha, double &psi, double &dpsi,
+                                double &tp)
+{
+    const double sq = sqrt(1.0 - u);
+    if (alpha <= 0.0) { psi = 0.0; dpsi = 1.0 / sq; tp = 0.0; return; }
+    double c = cos(alpha), s = sin(alpha);
+    const double q0 = 2.0 - u / (1.0 - u);
+    if (c < 1e-9) {
+        // tangent ray: x/sqrt(x^2 s^2 q) = 1/(s sqrt q), regular on [0, 1]
+        double I1 = 0.0, IT = 0.0;
+        for (int q = 0; q < S.n_quad; ++q) {
+            double x = S.glx[q], w = S.glw[q];
+            double rq = sqrt(q_s2(x, u));
+            I1 += w / rq;
+            IT += w / (rq * (1.0 + x * s * rq));
+        }
+        psi = 2.0 / sq * I1;
+        dpsi = 2.0 / (sq * q0);
+        tp = 2.0 * s / (1.0 - u) * IT;
+        return;
+    }
+    double A = c / (s * sqrt(q0));
+    double L = asinh(1.0 / A);
+    double I1 = 0.0, I3 = 0.0, IT = 0.0;
+    for (int q = 0; q < S.n_quad; ++q) {
+        double tau = L * S.glx[q];
+        double x = A * sinh(tau);
+        double dx = A * cosh(tau) * L * S.glw[q];
+        double D = c * c + x * x * s * s * q_s2(x, u);
+        double r = sqrt(D);
+        double ir = 1.0 / r;
+        I1 += x * ir * dx;
+        I3 += x * ir / D * dx;
+        IT += x * ir / (1.0 + r) * dx;
+    }
+    psi = 2.0 * s / sq * I1;
+    dpsi = 2.0 * c / sq * I3;
+    tp = 2.0 * s * s / (1.0 - u) * IT;
+}
+
+// psi(v, pi/2), c dt_p/R (v, pi/2) and their v-derivatives (periastron leg)
+__device__ static void grazing(const DevSpec &S, double v, double &ph, double &dph, double &th,
+                               double &dth)
+{
+    double J = 0.0, J3 = 0.0, K = 0.0, K1 = 0.0;
+    for (int q = 0; q < S.n_quad; ++q) {
+        double x = S.glx[q], w = S.glw[q];
+        double t = 1.0 - x * x;
+        double Q = 2.0 - x * x - v * t * t / (1.0 - v);
+        double rq = sqrt(Q);
+        J += w / rq;
+        J3 += w * t * t / (Q * rq);
+        double gq = rq + x * Q;
+        K += w / gq;
+        K1 += w * (0.5 / rq + x) * t * t / (gq * gq);
+    }
+    double om = 1.0 - v;
+    ph = 2.0 / sqrt(om) * J;
+    dph = (J + J3 / om) / (om * sqrt(om));
+    th = 2.0 / om * K;
+    dth = 2.0 / (om * om) * K + 2.0 / om * K1 / (om * om);
+}
+
+__global__ void k_table(DevSpec S, const StarRec *stars, const RingRec *rings, double4 *table)
+{
+    const int r = blockIdx.x, b = blockIdx.y;
+    const RingRec g = rings[(size_t)b * S.R_tot + r];
+    if (g.n_cells == 0) return;
+    const StarRec st = stars[b];
+    const double u = g.u;
+    const double dal = g.alpha_max / (S.n_alpha - 1);
+    double4 *tab = table + ((size_t)b * S.R_tot + r) * S.n_alpha;
+    for (int j = threadIdx.x; j < S.n_alpha; j += blockDim.x) {
+        double a = dal * j;
+        if (j == S.n_alpha - 1) a = g.alpha_max;
+        double psi, dpsi, T, dT;
+        if (a <= kHalfPi) {
+            double tp;
+            bend_out(S, u, a, psi, dpsi, tp);
+            T = tp + g.cdt_obl;
+            dT = dpsi * sin(a) / g.sq1u;          // d(c dt)/d psi = b (impact parameter)
+        } else {
+            // inward ray through a periastron at rho R (Eqs. 13, 14, 17)
+            double be = kPi - a;
+            double psb, dpsb, tpb;
+            bend_out(S, u, be, psb, dpsb, tpb);
+            double sa = sin(a), ca = cos(a);
+            double kk = sqrt(3.0 * (1.0 - u));
+            double arg = 3.0 * u * kk / (2.0 * sa);
+            if (arg > 1.0) arg = 1.0;
+            double rho = -2.0 * sa / kk * cos((acos(arg) + kTwoPi) / 3.0);
+            double k = sa * sa / (1.0 - u), kp = 2.0 * sa * ca / (1.0 - u);
+            double rhop = kp * (rho - u) / (3.0 * rho * rho - k);
+            double v = u / rho, vp = -u * rhop / (rho * rho);
+            double ph, dph, th, dth;
+            grazing(S, v, ph, dph, th, dth);
+            psi = 2.0 * ph - psb;
+            dpsi = 2.0 * dph * vp + dpsb;
+            double Rp = rho * g.R;
+            double cdtp = cdt_oblate(st.Re, st.Rs, Rp) / g.R;
+            T = 2.0 * rho * th - tpb + 2.0 * cdtp - g.cdt_obl;
+            double dtpb = dpsb * sin(be) / g.sq1u;
+            dT = 2.0 * rhop * th + 2.0 * rho * dth * vp + dtpb - 2.0 * rhop * rho / (rho - u);
+        }
+        tab[j] = make_double4(psi, dpsi, T, dT);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_trace: pseudo-patch light curve of one ring (Sect. 2.8.3, Eqs. 38-44)
+// ---------------------------------------------------------------------------
+__device__ static inline void hermite(double t, double &h00, double &h10, double &h01, double &h11)
+{
+    double t2 = t * t, t3 = t2 * t;
+    h00 = 2.0 * t3 - 3.0 * t2 + 1.0;
+    h10 = t3 - 2.0 * t2 + t;
+    h01 = -2.0 * t3 + 3.0 * t2;
+    h11 = t3 - t2;
+}
+
+__device__ static inline void dhermite(double t, double &d00, double &d10, double &d01, double &d11)
+{
+    double t2 = t * t;
+    d00 = 6.0 * t2 - 6.0 * t;
+    d10 = 3.0 * t2 - 4.0 * t + 1.0;
+    d01 = -6.0 * t2 + 6.0 * t;
+    d11 = 3.0 * t2 - 2.0 * t;
+}
+
+__global__ void k_trace(DevSpec S, const StarRec *stars, RingRec *rings, const double4 *table,
+                        double4 *trace)
+{
+    extern __shared__ double4 lds_tab[];
+    const int r = blockIdx.x, b = blockIdx.y;
+    RingRec *gp = rings + (size_t)b * S.R_tot + r;
+    const RingRec g = *gp;
+    if (g.n_cells == 0) return;
+    const StarRec st = stars[b];
+    const int na = S.n_alpha, nfp = S.n_fp;
+    double4 *tr_lds = lds_tab + na;            // n_fp + 1 entries
+    const double4 *tab = table + ((size_t)b * S.R_tot + r) * na;
+    for (int j = threadIdx.x; j < na; j += blockDim.x) lds_tab[j] = tab[j];
+    __shared__ int imin, imax;
+    if (threadIdx.x == 0) { imin = nfp; imax = 0; }   // invisible-range initialisation of Sect. 2.8.3
+    __syncthreads();
+    const double psi_top = lds_tab[na - 1].x;
+    const double dal = g.alpha_max / (na - 1);
+    const double sth = sin(g.theta), cth = cos(g.theta);
+    for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
+        double phi = kTwoPi * i / nfp;
+        double sphi, cphi;
+        sincos(phi, &sphi, &cphi);
+        double cpsi = st.si * sth * cphi + st.ci * cth;           // Table 2
+        cpsi = fmin(1.0, fmax(-1.0, cpsi));
+        double psi = acos(cpsi);
+        bool vis = psi <= psi_top;
+        double F = 0.0, z = 0.0, po = 0.0, mu = 0.0;
+        if (vis) {
+            double a, sr, lf;
+            if (psi < 1e-7) {
+                a = psi * g.sq1u;            // sub-observer limit, alpha = psi sqrt(1-u)
+                sr = g.sq1u;
+                lf = 1.0 - g.u;
+            } else {
+                int lo = 0, hi = na - 1;
+                while (hi - lo > 1) {
+                    int mid = (lo + hi) >> 1;
+                    if (lds_tab[mid].x <= psi) lo = mid; else hi = mid;
+                }
+                double p0 = lds_tab[lo].x, p1 = lds_tab[lo + 1].x;
+                double h = p1 - p0;
+                double t = (psi - p0) / h;
+                double a0 = dal * lo, a1 = dal * (lo + 1);
+                if (lo + 1 == na - 1) a1 = g.alpha_max;
+                double m0 = 1.0 / lds_tab[lo].y, m1 = 1.0 / lds_tab[lo + 1].y;
+                double h00, h10, h01, h11, d00, d10, d01, d11;
+                hermite(t, h00, h10, h01, h11);
+                dhermite(t, d00, d10, d01, d11);
+                a = h00 * a0 + h10 * h * m0 + h01 * a1 + h11 * h * m1;
+                double dadpsi = (d00 * a0 + d10 * h * m0 + d01 * a1 + d11 * h * m1) / h;
+                sr = sin(a) / sin(psi);
+                lf = sr * dadpsi;                  // d cos(alpha) / d cos(psi)
+            }
+            double ca = cos(a);
+            // Eq. (4)
+            double cs = ca * g.coseta + sr * g.sineta * (st.ci * sth - st.si * cth * cphi);
+            if (cs > 0.0) {
+                double cxi = -sr * st.si * sphi;                      // Table 2
+                double delta = 1.0 / (g.gamma * (1.0 - g.beta * cxi));  // Eq. (19)
+                mu = delta * cs;                                        // Eq. (20)
+                F = g.sq1u * delta * delta * delta * mu * lf * g.gamma; // Eq. (40)
+                z = 1.0 / (delta * g.sq1u);
+                int jj = (int)floor(a / dal);
+                jj = jj < 0 ? 0 : (jj > na - 2 ? na - 2 : jj);
+                double ta = (a - dal * jj) / dal;
+                double h00, h10, h01, h11;
+                hermite(ta, h00, h10, h01, h11);
+                double T = h00 * lds_tab[jj].z + h10 * dal * lds_tab[jj].w + h01 * lds_tab[jj + 1].z
+                         + h11 * dal * lds_tab[jj + 1].w;
+                po = phi / kTwoPi + st.nu * g.R * T / kC;
+            } else {
+                vis = false;
+            }
+        }
+        if (!vis) {
+            atomicMin(&imin, i);
+            atomicMax(&imax, i);
+            F = 0.0; z = 0.0; po = 0.0; mu = 0.0;
+        }
+        tr_lds[i] = make_double4(F, z, po, mu);
+    }
+    __syncthreads();
+    const int a0 = imin, a1 = imax;
+    const bool ring_visible = a0 != 0;    // invisible at phi = 0: the ring is skipped
+    if (ring_visible && a0 <= a1) {
+        // Eqs. (41)-(44): zero flux and mu, linear fill of z and phi_o
+        // sample n_fp repeats sample 0, so a visible ring has a1 < n_fp
+        const int ia = a0 - 1, ib = a1 + 1 > nfp ? nfp : a1 + 1;
+        const double4 va = tr_lds[ia], vb = tr_lds[ib];
+        for (int i = a0 + threadIdx.x; i <= a1; i += blockDim.x) {
+            double t = (double)(i - ia) / (double)(ib - ia);
+            tr_lds[i] = make_double4(0.0, va.y + (vb.y - va.y) * t, va.z + (vb.z - va.z) * t, 0.0);
+        }
+    }
+    __syncthreads();
+    double4 *out = trace + ((size_t)b * S.R_tot + r) * (nfp + 1);
+    for (int i = threadIdx.x; i <= nfp; i += blockDim.x) out[i] = tr_lds[i];
+    if (threadIdx.x == 0) {
+        gp->visible = ring_visible ? 1 : 0;
+        gp->inv_min = a0;
+        gp->inv_max = a1;
+        gp->active = (ring_visible && g.w_cell > 0.0) ? 1 : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_subtable: linear (logT, log g) collapse of the atmosphere table for one
+// ring (mixed-order scheme of Sect. 4: linear on these two axes, clamped at
+// the edges), giving sub[mu][x] = I/T^3 at the ring's (logT, log g).
+// ---------------------------------------------------------------------------
+__device__ static inline int lin_bracket(double v, double v0, double h, int n, double &w1)
+{
+    double t = (v - v0) / h;
+    if (t <= 0.0) { w1 = 0.0; return 0; }
+    if (t >= n - 1) { w1 = 1.0; return n - 2; }
+    int i = (int)floor(t);
+    if (i > n - 2) i = n - 2;
+    w1 = t - i;
+    return i;
+}
+
+__global__ void k_subtable(DevSpec S, const RingRec *rings, float *sub)
+{
+    const int r = blockIdx.x, b = blockIdx.y;
+    const RingRec g = rings[(size_t)b * S.R_tot + r];
+    if (!g.active) return;
+    double wt1, wg1;
+    int it = lin_bracket(g.logT, S.T0, S.hT, S.nT, wt1);
+    int ig = lin_bracket(g.logg, S.g0, S.hg, S.ng, wg1);
+    const float w00 = (float)((1.0 - wt1) * (1.0 - wg1)), w01 = (float)((1.0 - wt1) * wg1);
+    const float w10 = (float)(wt1 * (1.0 - wg1)), w11 = (float)(wt1 * wg1);
+    const size_t slab = (size_t)S.nmu * S.nx;
+    const float *s00 = S.atm + ((size_t)it * S.ng + ig) * slab;
+    const float *s01 = s00 + slab;
+    const float *s10 = S.atm + ((size_t)(it + 1) * S.ng + ig) * slab;
+    const float *s11 = s10 + slab;
+    float *out = sub + ((size_t)b * S.R_tot + r) * slab;
+    for (size_t i = threadIdx.x; i < slab; i += blockDim.x)
+        out[i] = w00 * s00[i] + w01 * s01[i] + w10 * s10[i] + w11 * s11[i];
+}
+
+// ---------------------------------------------------------------------------
+// shared per-(cell, phase) work: cell azimuth, crescent mask, observed-phase
+// lookup (Eqs. 45-46) in FP64 on the ring's fine-phase arrays in LDS.
+// ---------------------------------------------------------------------------
+__device__ static inline double cell_offset(const RingRec &g, int j)
+{
+    if (g.shape == PPM_SHAPE_ANNULUS) {
+        int h = g.n_cells / 2;
+        if (j < h) return -(g.dphi_in + (h - 1 - j + 0.5) * g.dphi_cell);
+        return g.dphi_in + (j - h + 0.5) * g.dphi_cell;
+    }
+    return -g.dphi_out + (j + 0.5) * g.dphi_cell;
+}
+
+__device__ static inline bool cell_masked(const RingRec &g, double off)
+{
+    if (g.shape != PPM_SHAPE_CRESCENT) return false;
+    double cd = cos(g.theta) * cos(g.tm) + sin(g.theta) * sin(g.tm) * cos(off);
+    return cd > g.cos_zm;
+}
+
+struct PhaseSample { double F, z, mu; };
+
+__device__ static inline PhaseSample phase_lookup(const double4 *tr, int nfp, double php)
+{
+    int lo = 0, hi = nfp;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (tr[mid].z <= php) lo = mid; else hi = mid;
+    }
+    const double4 a = tr[lo], c = tr[lo + 1];
+    double w = (php - a.z) / (c.z - a.z);
+    w = fmin(1.0, fmax(0.0, w));
+    PhaseSample s;
+    s.F = a.x + w * (c.x - a.x);
+    s.z = a.y + w * (c.y - a.y);
+    s.mu = a.w + w * (c.w - a.w);
+    return s;
+}
+
+__device__ static inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// k_accum_table: shift-and-add with the mixed-order atmosphere table
+// (Eq. 47).  Block = (ring, tile of phases); wave = one phase at a time;
+// lane = EPL consecutive energies (FP32 accumulators in registers).
+// Per (cell, phase): FP64 phase lookup, mu weights (cubic Lagrange, linear
+// in the protected small-mu zone and the last interval), contraction of the
+// ring's sub-table over mu into S[x] in LDS; per energy: x = log10(z E / kT),
+// cubic Lagrange in x (linear in the first and last interval, zero outside).
+// ---------------------------------------------------------------------------
+template <int EPL>
+__global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const RingRec *rings,
+                                                     const double4 *trace, const float *sub,
+                                                     float *partial, int32_t *vis_pairs, int PT)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int r = blockIdx.y, b = blockIdx.z;
+    const RingRec g = rings[(size_t)b * S.R_tot + r];
+    if (!g.active) return;
+    const int nfp = S.n_fp, nmu = S.nmu, nx = S.nx, E = S.E, P = S.P;
+    double4 *tr = (double4 *)lds_raw;                          // nfp + 1
+    double *axmu = (double *)(tr + nfp + 1);                   // nmu
+    float *tab = (float *)(axmu + nmu);                        // nmu * nx
+    float *Sb = tab + nmu * nx;                                // 4 waves * nx
+    const double4 *gtr = trace + ((size_t)b * S.R_tot + r) * (nfp + 1);
+    for (int i = threadIdx.x; i <= nfp; i += blockDim.x) tr[i] = gtr[i];
+    for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
+    const float *gsub = sub + ((size_t)b * S.R_tot + r) * nmu * nx;
+    for (int i = threadIdx.x; i < nmu * nx; i += blockDim.x) tab[i] = gsub[i];
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float *Sw = Sb + wave * nx;
+    const double phio0 = tr[0].z;
+    const double inv2pi = 1.0 / kTwoPi;
+    const double lkT = log10(g.kT);
+    double tb[EPL];
+#pragma unroll
+    for (int m = 0; m < EPL; ++m) {
+        int e = lane * EPL + m;
+        tb[m] = e < E ? (log10(S.energy[e]) - lkT - S.x0) / S.hx : 0.0;
+    }
+    const double mu_lo = axmu[0], mu_hi = axmu[nmu - 1];
+    int npairs = 0;
+    const int k_begin = blockIdx.x * PT;
+    for (int kk = wave; kk < PT; kk += 4) {
+        const int k = k_begin + kk;
+        if (k >= P) break;
+        float acc[EPL];
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) acc[m] = 0.0f;
+        const double Phik = (k + 0.5) / P;
+        for (int j = 0; j < g.n_cells; ++j) {
+            const double off = cell_offset(g, j);
+            if (cell_masked(g, off)) continue;
+            double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
+            double php = (a - floor(a)) + phio0;                       // Eq. (45)
+            PhaseSample ps = phase_lookup(tr, nfp, php);               // Eq. (46)
+            if (ps.F == 0.0) continue;
+            ++npairs;
+            // mu weights
+            double mu = fmin(mu_hi, fmax(mu_lo, ps.mu));
+            int lo = 0, hi = nmu - 1;
+            while (hi - lo > 1) {
+                int mid = (lo + hi) >> 1;
+                if (axmu[mid] <= mu) lo = mid; else hi = mid;
+            }
+            float wm[4];
+            int m0;
+            if (lo < 3 || lo == nmu - 2) {
+                double t = (mu - axmu[lo]) / (axmu[lo + 1] - axmu[lo]);
+                m0 = lo;
+                wm[0] = (float)(1.0 - t); wm[1] = (float)t; wm[2] = 0.0f; wm[3] = 0.0f;
+            } else {
+                m0 = lo - 1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    double num = 1.0, den = 1.0;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        if (s == q) continue;
+                        num *= mu - axmu[m0 + s];
+                        den *= axmu[m0 + q] - axmu[m0 + s];
+                    }
+                    wm[q] = (float)(num / den);
+                }
+            }
+            const int nrow = (lo < 3 || lo == nmu - 2) ? 2 : 4;
+            const float *t0 = tab + m0 * nx;
+            for (int n = lane; n < nx; n += 64) {
+                float s = wm[0] * t0[n] + wm[1] * t0[nx + n];
+                if (nrow == 4) s += wm[2] * t0[2 * nx + n] + wm[3] * t0[3 * nx + n];
+                Sw[n] = s;
+            }
+            wave_sync();
+            const double tz = log10(ps.z) / S.hx;
+            const float Fp = (float)ps.F;
+#pragma unroll
+            for (int m = 0; m < EPL; ++m) {
+                double t = tz + tb[m];
+                if (lane * EPL + m >= E || t < 0.0 || t > nx - 1) continue;
+                int i = (int)floor(t);
+                if (i > nx - 2) i = nx - 2;
+                float f = (float)(t - i);
+                float I;
+                if (i == 0 || i == nx - 2) {
+                    I = Sw[i] + f * (Sw[i + 1] - Sw[i]);
+                } else {
+                    float fm1 = f - 1.0f, fm2 = f - 2.0f, fp1 = f + 1.0f;
+                    float w0 = -f * fm1 * fm2 * (1.0f / 6.0f);
+                    float w1 = fp1 * fm1 * fm2 * 0.5f;
+                    float w2 = -fp1 * f * fm2 * 0.5f;
+                    float w3 = fp1 * f * fm1 * (1.0f / 6.0f);
+                    I = w0 * Sw[i - 1] + w1 * Sw[i] + w2 * Sw[i + 1] + w3 * Sw[i + 2];
+                }
+                acc[m] += Fp * I;
+            }
+            wave_sync();
+        }
+        const double scale = g.w_cell * g.T * g.T * g.T;
+        float *out = partial + (((size_t)b * S.R_tot + r) * P + k) * E;
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) {
+            int e = lane * EPL + m;
+            if (e < E) out[e] = (float)(acc[m] * (scale / S.energy[e]));
+        }
+    }
+    if (lane == 0 && npairs) atomicAdd(&vis_pairs[(size_t)b * S.R_tot + r], npairs);
+}
+
+// ---------------------------------------------------------------------------
+// k_accum_bb: FP64 shift-and-add with the isotropic blackbody of App. C
+// ---------------------------------------------------------------------------
+template <int EPL>
+__global__ __launch_bounds__(256) void k_accum_bb(DevSpec S, const RingRec *rings, const double4 *trace,
+                                                  double *partial, int32_t *vis_pairs, int PT)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int r = blockIdx.y, b = blockIdx.z;
+    const RingRec g = rings[(size_t)b * S.R_tot + r];
+    if (!g.active) return;
+    const int nfp = S.n_fp, E = S.E, P = S.P;
+    double4 *tr = (double4 *)lds_raw;
+    const double4 *gtr = trace + ((size_t)b * S.R_tot + r) * (nfp + 1);
+    for (int i = threadIdx.x; i <= nfp; i += blockDim.x) tr[i] = gtr[i];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double phio0 = tr[0].z;
+    const double inv2pi = 1.0 / kTwoPi;
+    const double ikT = 1.0 / g.kT;
+    const double pref = 2.0 / (kH * kH * kH * kC * kC);
+    double Ee[EPL];
+#pragma unroll
+    for (int m = 0; m < EPL; ++m) {
+        int e = lane * EPL + m;
+        Ee[m] = e < E ? S.energy[e] : 1.0;
+    }
+    int npairs = 0;
+    const int k_begin = blockIdx.x * PT;
+    for (int kk = wave; kk < PT; kk += 4) {
+        const int k = k_begin + kk;
+        if (k >= P) break;
+        double acc[EPL];
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) acc[m] = 0.0;
+        const double Phik = (k + 0.5) / P;
+        for (int j = 0; j < g.n_cells; ++j) {
+            const double off = cell_offset(g, j);
+            if (cell_masked(g, off)) continue;
+            double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
+            double php = (a - floor(a)) + phio0;
+            PhaseSample ps = phase_lookup(tr, nfp, php);
+            if (ps.F == 0.0) continue;
+            ++npairs;
+#pragma unroll
+            for (int m = 0; m < EPL; ++m) {
+                double Ep = ps.z * Ee[m];
+                double I = pref * Ep * Ep * Ep / expm1(Ep * ikT);
+                acc[m] += ps.F * I;
+            }
+        }
+        double *out = partial + (((size_t)b * S.R_tot + r) * P + k) * E;
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) {
+            int e = lane * EPL + m;
+            if (e < E) out[e] = acc[m] * g.w_cell / Ee[m];
+        }
+    }
+    if (lane == 0 && npairs) atomicAdd(&vis_pairs[(size_t)b * S.R_tot + r], npairs);
+}
+
+// ---------------------------------------------------------------------------
+// k_reduce: fixed-order FP64 sum of the ring partials, then absorption
+// (Eq. 22) and the exposure per phase bin, ready for the fold.
+// ---------------------------------------------------------------------------
+template <typename TP, typename TA>
+__global__ void k_reduce(DevSpec S, const StarRec *stars, const RingRec *rings, const TP *partial,
+                         double *flux, TA *fold_in)
+{
+    const int k = blockIdx.x, b = blockIdx.y;
+    const int E = S.E, P = S.P;
+    const StarRec st = stars[b];
+    const double texp = S.t_exp / P;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+        double s = 0.0;
+        for (int r = 0; r < S.R_tot; ++r) {
+            if (!rings[(size_t)b * S.R_tot + r].active) continue;
+            s += (double)partial[(((size_t)b * S.R_tot + r) * P + k) * E + e];
+        }
+        if (st.status != PPM_INST_OK) s = 0.0;
+        if (flux) flux[((size_t)b * P + k) * E + e] = s;
+        double att = S.sigma ? exp(-st.NH * S.sigma[e]) : 1.0;
+        fold_in[((size_t)b * P + k) * E + e] = (TA)(s * att * texp);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_fold: counts[M][C] = A[M][E] . RSP[E][C] on the matrix cores.  One wave
+// per 16x16 output tile, K in steps of 4 (v_mfma_*_16x16x4): lane l supplies
+// A[l%16][k0 + l/16] and RSP[k0 + l/16][l%16]; the tile comes back as
+// D[4 (l/16) + v][l%16] in accumulator v.
+// ---------------------------------------------------------------------------
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(64) void k_fold_f32(const float *A, const float *B, double *out, int M,
+                                                 int N, int K)
+{
+    const int n0 = blockIdx.x * 16, m0 = blockIdx.y * 16;
+    const int l = threadIdx.x, li = l & 15, lk = l >> 4;
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    const bool mrow = (m0 + li) < M, ncol = (n0 + li) < N;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int k = k0 + lk;
+        float a = (mrow && k < K) ? A[(size_t)(m0 + li) * K + k] : 0.0f;
+        float bv = (ncol && k < K) ? B[(size_t)k * N + n0 + li] : 0.0f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        int row = m0 + 4 * lk + v, col = n0 + li;
+        if (row < M && col < N) out[(size_t)row * N + col] = (double)acc[v];
+    }
+}
+
+// FP64 path (small workloads): one thread per output element, plain FMA loop.
+__global__ __launch_bounds__(256) void k_fold_f64(const double *A, const double *B, double *out, int M,
+                                                  int N, int K)
+{
+    const int col = blockIdx.x * blockDim.x + threadIdx.x, row = blockIdx.y;
+    if (col >= N || row >= M) return;
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) acc = fma(A[(size_t)row * K + k], B[(size_t)k * N + col], acc);
+    out[(size_t)row * N + col] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// k_loglike: Poisson log-likelihood per instance, FP64, fixed-order block
+// reduction.  d = 0 contributes -m; m <= 0 with d > 0 gives -inf.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_loglike(const StarRec *stars, const double *counts,
+                                                 const int32_t *data, int PC, double *logl)
+{
+    const int b = blockIdx.x;
+    __shared__ double red[256];
+    __shared__ int bad[256];
+    double s = 0.0;
+    int nbad = 0;
+    const double *m = counts + (size_t)b * PC;
+    for (int i = threadIdx.x; i < PC; i += 256) {
+        int d = data[i];
+        double mi = m[i];
+        if (d == 0) { s -= mi; continue; }
+        if (!(mi > 0.0)) { ++nbad; continue; }
+        s += d * log(mi) - mi - lgamma(d + 1.0);
+    }
+    red[threadIdx.x] = s;
+    bad[threadIdx.x] = nbad;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[threadIdx.x] += red[threadIdx.x + w];
+            bad[threadIdx.x] += bad[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double v = red[0];
+        if (bad[0] || stars[b].status != PPM_INST_OK) v = -INFINITY;
+        logl[b] = v;
+    }
+}
+
+__global__ void k_zero_i32(int32_t *p, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void k_status(const StarRec *stars, int B, int32_t *out)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) out[b] = stars[b].status;
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers (host)
+// ---------------------------------------------------------------------------
+size_t accum_table_lds(const DevSpec &S)
+{
+    return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * S.nmu + sizeof(float) * S.nmu * S.nx
+         + sizeof(float) * 4 * S.nx;
+}
+
+hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *params,
+                          const int32_t *ncells_dev, int B, hipStream_t st, double *flux_out,
+                          double *counts_out, hipEvent_t ev_hot0, hipEvent_t ev_hot1)
+{
+    const bool want_flux_f64 = flux_out != nullptr;
+    hipLaunchKernelGGL(k_setup, dim3(B), dim3(256), 0, st, S, params, ncells_dev, W.stars, W.rings);
+    hipLaunchKernelGGL(k_table, dim3(S.R_tot, B), dim3(256), 0, st, S, W.stars, W.rings, W.table);
+    size_t lds_tr = sizeof(double4) * (S.n_alpha + S.n_fp + 1);
+    hipLaunchKernelGGL(k_trace, dim3(S.R_tot, B), dim3(256), lds_tr, st, S, W.stars, W.rings, W.table,
+                       W.trace);
+    {
+        size_t n = (size_t)B * S.R_tot;
+        hipLaunchKernelGGL(k_zero_i32, dim3((n + 255) / 256), dim3(256), 0, st, W.vis_pairs, n);
+    }
+    const int PT = 16;
+    dim3 grid((S.P + PT - 1) / PT, S.R_tot, B);
+    if (S.intensity == PPM_I_TABLE) {
+        hipLaunchKernelGGL(k_subtable, dim3(S.R_tot, B), dim3(256), 0, st, S, W.rings, W.sub);
+        size_t lds = accum_table_lds(S);
+        if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
+        int epl = (S.E + 63) / 64;
+        if (epl <= 1)
+            hipLaunchKernelGGL(k_accum_table<1>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+                               W.partial32, W.vis_pairs, PT);
+        else if (epl <= 2)
+            hipLaunchKernelGGL(k_accum_table<2>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+                               W.partial32, W.vis_pairs, PT);
+        else if (epl <= 4)
+            hipLaunchKernelGGL(k_accum_table<4>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+                               W.partial32, W.vis_pairs, PT);
+        else
+            hipLaunchKernelGGL(k_accum_table<8>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+                               W.partial32, W.vis_pairs, PT);
+        if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
+        hipLaunchKernelGGL((k_reduce<float, float>), dim3(S.P, B), dim3(256), 0, st, S, W.stars, W.rings,
+                           W.partial32, want_flux_f64 ? flux_out : nullptr, W.fold_in32);
+        hipLaunchKernelGGL(k_fold_f32, dim3((S.C + 15) / 16, (B * S.P + 15) / 16), dim3(64), 0, st,
+                           W.fold_in32, S.rsp32, counts_out, B * S.P, S.C, S.E);
+    } else {
+        size_t lds = sizeof(double4) * (S.n_fp + 1);
+        int epl = (S.E + 63) / 64;
+        if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
+        if (epl <= 1)
+            hipLaunchKernelGGL(k_accum_bb<1>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.partial64,
+                               W.vis_pairs, PT);
+        else if (epl <= 2)
+            hipLaunchKernelGGL(k_accum_bb<2>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.partial64,
+                               W.vis_pairs, PT);
+        else if (epl <= 4)
+            hipLaunchKernelGGL(k_accum_bb<4>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.partial64,
+                               W.vis_pairs, PT);
+        else
+            hipLaunchKernelGGL(k_accum_bb<8>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.partial64,
+                               W.vis_pairs, PT);
+        if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
+        if (S.rsp64) {
+            hipLaunchKernelGGL((k_reduce<double, double>), dim3(S.P, B), dim3(256), 0, st, S, W.stars,
+                               W.rings, W.partial64, want_flux_f64 ? flux_out : nullptr, W.fold_in64);
+            hipLaunchKernelGGL(k_fold_f64, dim3((S.C + 255) / 256, B * S.P), dim3(256), 0, st,
+                               W.fold_in64, S.rsp64, counts_out, B * S.P, S.C, S.E);
+        } else {
+            hipLaunchKernelGGL((k_reduce<double, float>), dim3(S.P, B), dim3(256), 0, st, S, W.stars,
+                               W.rings, W.partial64, want_flux_f64 ? flux_out : nullptr, W.fold_in32);
+            hipLaunchKernelGGL(k_fold_f32, dim3((S.C + 15) / 16, (B * S.P + 15) / 16), dim3(64), 0, st,
+                               W.fold_in32, S.rsp32, counts_out, B * S.P, S.C, S.E);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_loglike(const Workspace &W, const double *counts, int B, int PC, const int32_t *data,
+                          double *logl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_loglike, dim3(B), dim3(256), 0, st, W.stars, counts, data, PC, logl);
+    return hipGetLastError();
+}
+
+hipError_t launch_status(const Workspace &W, int B, int32_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_status, dim3((B + 255) / 256), dim3(256), 0, st, W.stars, B, out);
+    return hipGetLastError();
+}
+
+}  // namespace ppm

@@ -1,0 +1,36 @@
+// Device workspace of a plan and the host-side launch wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ppm_internal.h"
+
+namespace ppm {
+
+struct Workspace {
+    StarRec *stars;        // [B]
+    RingRec *rings;        // [B][R_tot]
+    double4 *table;        // [B][R_tot][n_alpha]
+    double4 *trace;        // [B][R_tot][n_fp + 1]
+    float *sub;            // [B][R_tot][nmu][nx]      (table intensity)
+    float *partial32;      // [B][R_tot][P][E]         (FP32 path)
+    double *partial64;     // [B][R_tot][P][E]         (FP64 path)
+    float *fold_in32;      // [B][P][E]
+    double *fold_in64;     // [B][P][E]
+    double *counts;        // [B][P][C]
+    int32_t *vis_pairs;    // [B][R_tot]
+    int32_t *ncells;       // [B] per-instance grid override
+};
+
+__host__ __device__ int validate_params(const double *p, int n_spots);
+
+hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *params,
+                          const int32_t *ncells_dev, int B, hipStream_t st, double *flux_out,
+                          double *counts_out, hipEvent_t ev_hot0 = nullptr, hipEvent_t ev_hot1 = nullptr);
+hipError_t launch_loglike(const Workspace &W, const double *counts, int B, int PC, const int32_t *data,
+                          double *logl, hipStream_t st);
+hipError_t launch_status(const Workspace &W, int B, int32_t *out, hipStream_t st);
+size_t accum_table_lds(const DevSpec &S);
+
+}  // namespace ppm

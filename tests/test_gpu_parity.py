@@ -1,0 +1,217 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bar: per phase-channel (or phase-energy) bin, |gpu - oracle| / oracle <= 1e-4
+for bins at or above 1e-6 of the peak (FP32 bulk path); the FP64 path and
+the FP64 intermediate stages (deflection table, fine-phase trace) are held to
+much tighter bounds derived from their arithmetic.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch, torch.device("cuda:0")
+
+
+def rel_err(got, ref, floor=1e-6):
+    ref = np.asarray(ref)
+    got = np.asarray(got)
+    sel = ref >= floor * ref.max()
+    return float(np.max(np.abs(got[sel] - ref[sel]) / ref[sel])), int(sel.sum())
+
+
+def gpu_run(torch_dev, spec, params, what="counts", **kw):
+    import paper_2510_07764_amd as ppm
+    torch, dev = torch_dev
+    p = np.atleast_2d(params)
+    plan = ppm.Plan(spec, max_batch=p.shape[0], **kw)
+    pt = torch.tensor(p, dtype=torch.float64, device=dev)
+    out = plan.forward(pt) if what == "counts" else plan.flux(pt)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), plan, pt
+
+
+def test_config0_fp64(torch_dev):
+    spec, p = syn.config0()
+    ref, cnt_ref, _ = oracle.forward(spec, p)
+    got, plan, pt = gpu_run(torch_dev, spec, p, what="flux")
+    err, n = rel_err(got[0], ref)
+    print(f"config0 FP64 flux: max rel err {err:.3e} over {n} bins")
+    assert err < 1e-9
+    cnt = plan.forward(pt)
+    err2, _ = rel_err(cnt.cpu().numpy()[0], cnt_ref)
+    assert err2 < 1e-9
+
+
+@pytest.mark.parametrize("mode", [syn.MODE_SD, syn.MODE_OS])
+def test_deflection_table_and_trace(torch_dev, mode):
+    spec, p = syn.config1(n_cells=8, n_phase=16, n_energy=32)
+    spec["mode"] = mode
+    got, plan, pt = gpu_run(torch_dev, spec, p)
+    rings = oracle.rings(spec, p, 0) + oracle.rings(spec, p, 1)
+    checked_inward = False
+    for r in (0, 3, 7, 8, 12, 15):
+        d = plan.debug_ring(0, r)
+        rg = rings[r]
+        assert d["u"] == pytest.approx(rg.u, rel=1e-14)
+        assert d["alpha_max"] == pytest.approx(rg.alpha_max, rel=1e-14)
+        na = plan.n_alpha
+        st = oracle.star(spec, p)
+        for j in list(range(0, na, 37)) + [na - 1]:
+            a = d["alpha_max"] * j / (na - 1) if j < na - 1 else d["alpha_max"]
+            psi, dpsi, T, dT = d["table"][j]
+            assert psi == pytest.approx(oracle.psi(rg.u, a), rel=1e-11, abs=1e-14)
+            assert dpsi == pytest.approx(oracle.dpsi_dalpha(rg.u, a), rel=1e-8)
+            tot = oracle.total_delay(spec, p, rg.R, rg.u, a)
+            assert T == pytest.approx(tot, rel=1e-11, abs=1e-13)
+            checked_inward |= a > math.pi / 2
+        tr = oracle.trace_ring(spec, p, rg)
+        assert d["visible"] == tr["visible"]
+        if not tr["visible"]:
+            continue
+        assert d["inv"] == tr["inv"]
+        g = d["trace"]
+        np.testing.assert_allclose(g[:, 0], tr["F"], rtol=1e-9, atol=1e-12 * tr["F"].max())
+        np.testing.assert_allclose(g[:, 1], tr["z"], rtol=1e-11)
+        np.testing.assert_allclose(g[:, 2], tr["phio"], rtol=1e-11, atol=1e-13)
+        np.testing.assert_allclose(g[:, 3], tr["mu"], rtol=1e-9, atol=1e-12)
+    if mode == syn.MODE_OS:
+        assert checked_inward
+
+
+@pytest.mark.parametrize("cells,phases,energies", [(16, 32, 64), (40, 48, 256), (24, 17, 100)])
+def test_config1_parity(torch_dev, cells, phases, energies):
+    spec, p = syn.config1(n_cells=cells, n_phase=phases, n_energy=energies)
+    ft, cnt, _ = oracle.forward(spec, p)
+    got, plan, pt = gpu_run(torch_dev, spec, p)
+    err, n = rel_err(got[0], cnt)
+    print(f"config1 {cells}x{cells} P={phases} E={energies}: counts max rel err {err:.3e} over {n} bins")
+    assert err < TOL
+    fl = plan.flux(pt).cpu().numpy()[0]
+    err2, _ = rel_err(fl, ft)
+    assert err2 < TOL
+
+
+def test_config1_full_size_golden(torch_dev):
+    """Full-size workload (128x128 cells per spot, 128 phases, 256 energies,
+    300 channels) in the benchmark's launch configuration, against the
+    stored oracle counts; likelihood against the stored oracle value."""
+    import paper_2510_07764_amd as ppm
+    torch, dev = torch_dev
+    ref = np.load(os.path.join(HERE, "golden", "config1_counts.npy"))
+    data = np.load(os.path.join(HERE, "golden", "config1_data.npy"))
+    meta = json.load(open(os.path.join(HERE, "golden", "config1_meta.json")))
+    spec, p = syn.config1()
+    assert syn.digest(spec["atmos_logI"]) == meta["digest_atmos"]
+    plan = ppm.Plan(spec, max_batch=1)
+    pt = torch.tensor(p[None], dtype=torch.float64, device=dev)
+    counts = torch.empty((1, 128, 300), dtype=torch.float64, device=dev)
+    ll = plan.loglike(pt, torch.tensor(data, device=dev), counts=counts)
+    torch.cuda.synchronize()
+    got = counts.cpu().numpy()[0]
+    err, n = rel_err(got, ref)
+    print(f"config1 full: counts max rel err {err:.3e} over {n} bins; logL {ll.item():.6f} vs {meta['loglike']:.6f}")
+    assert err < TOL
+    assert abs(ll.item() - meta["loglike"]) <= TOL * np.abs(data - ref).sum()
+    assert plan.visible_pairs(1) == meta["diag"]["n_visible_pairs"]
+
+
+def test_config2_reduced(torch_dev):
+    """Compactness 0.28, pole-straddling cap and a near-grazing crescent."""
+    spec, p = syn.config2(n_cells=48, n_phase=32, n_fp=512)
+    spec["energy"] = syn.logspace(0.2, 3.0, 64)
+    syn.attach_instrument(spec)
+    ft, cnt, diag = oracle.forward(spec, p)
+    assert diag["n_multi_image"] == 0
+    got, plan, pt = gpu_run(torch_dev, spec, p)
+    assert plan.status(1).cpu().numpy().tolist() == [0]
+    err, n = rel_err(got[0], cnt)
+    print(f"config2 reduced: counts max rel err {err:.3e} over {n} bins")
+    assert err < TOL
+
+
+def test_batch_matches_singles_and_is_deterministic(torch_dev):
+    import paper_2510_07764_amd as ppm
+    torch, dev = torch_dev
+    spec, _ = syn.config1(n_cells=16, n_phase=32, n_energy=64)
+    draws = syn.config4_draws(4)
+    plan = ppm.Plan(spec, max_batch=4)
+    pt = torch.tensor(draws, dtype=torch.float64, device=dev)
+    a = plan.forward(pt).cpu().numpy()
+    b = plan.forward(pt).cpu().numpy()
+    assert np.array_equal(a, b)
+    for i in range(4):
+        one = plan.forward(pt[i:i + 1].contiguous()).cpu().numpy()
+        assert np.array_equal(one[0], a[i])
+    # one instance against the oracle
+    _, cnt, _ = oracle.forward(spec, draws[2])
+    err, _ = rel_err(a[2], cnt)
+    assert err < TOL
+
+
+def test_invalid_instance_status(torch_dev):
+    import paper_2510_07764_amd as ppm
+    torch, dev = torch_dev
+    spec, p = syn.config1(n_cells=8, n_phase=16, n_energy=32)
+    _, cnt, _ = oracle.forward(spec, p)
+    data = syn.poisson_data(cnt)
+    rows = np.stack([p, p, p])
+    rows[1, 0] = float("nan")
+    rows[2, 9] = -0.1
+    plan = ppm.Plan(spec, max_batch=3)
+    pt = torch.tensor(rows, dtype=torch.float64, device=dev)
+    ll = plan.loglike(pt, torch.tensor(data, device=dev)).cpu().numpy()
+    st = plan.status(3).cpu().numpy()
+    assert st.tolist() == [0, 1, 4]
+    assert np.isfinite(ll[0]) and ll[1] == -np.inf and ll[2] == -np.inf
+    assert ll[0] == pytest.approx(oracle.loglike_from_counts(cnt, data), abs=TOL * np.abs(data - cnt).sum())
+
+
+def test_per_instance_grid_override(torch_dev):
+    import paper_2510_07764_amd as ppm
+    torch, dev = torch_dev
+    spec16, p = syn.config1(n_cells=16, n_phase=32, n_energy=64)
+    spec8, _ = syn.config1(n_cells=8, n_phase=32, n_energy=64)
+    plan = ppm.Plan(spec16, max_batch=2, max_cells=24)
+    pt = torch.tensor(np.stack([p, p]), dtype=torch.float64, device=dev)
+    got = plan.forward(pt, n_cells=[8, 24]).cpu().numpy()
+    _, c8, _ = oracle.forward(spec8, p)
+    spec24, _ = syn.config1(n_cells=24, n_phase=32, n_energy=64)
+    _, c24, _ = oracle.forward(spec24, p)
+    assert rel_err(got[0], c8)[0] < TOL
+    assert rel_err(got[1], c24)[0] < TOL
+
+
+def test_hidden_spot_and_partial_visibility(torch_dev):
+    spec, p = syn.config1(n_cells=12, n_phase=24, n_energy=48)
+    q = p.copy()
+    q[2] = 0.2                 # observer near the north pole
+    q[12] = 3.0                # spot 2 near the south pole: never visible
+    q[13] = 0.1
+    ft, cnt, _ = oracle.forward(spec, q)
+    got, plan, pt = gpu_run(torch_dev, spec, q, what="flux")
+    assert rel_err(got[0], ft)[0] < TOL
+    s1 = dict(spec, n_spots=1)
+    ft1, _, _ = oracle.forward(s1, q)
+    np.testing.assert_allclose(ft, ft1, rtol=1e-13)     # spot 2 contributes nothing
+    # a single spot that rises and sets every rotation
+    q = p.copy()
+    q[8] = 2.3
+    ft, cnt, _ = oracle.forward(s1, q)
+    assert (ft[:, 10] < 1e-3 * ft[:, 10].max()).any()
+    got, _, _ = gpu_run(torch_dev, s1, q)
+    assert rel_err(got[0], cnt)[0] < TOL

@@ -1,0 +1,78 @@
+"""Host-side checks of libppm that need no GPU: the library loads, exports
+every entry point declared in include/ppm.h, the binding mirrors them, the
+host parameter validation follows the documented rules, and spec errors are
+reported before any device call."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "ppm.h")).read()
+    return sorted(set(re.findall(r"\b(ppm_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2510_07764_amd as ppm
+    return ppm.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    import paper_2510_07764_amd as ppm
+    syms = declared_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(L, s), s
+        assert s in ppm.SIGNATURES, s
+    assert L.ppm_version() >= 1
+
+
+def test_host_validation_rules():
+    import paper_2510_07764_amd as ppm
+    _, p = syn.config1()
+    rows = [p.copy() for _ in range(7)]
+    rows[1][2] = math.nan
+    rows[2][0] = -1.0
+    rows[3][0] = 0.3 * 12.5e5 * syn.C_CGS ** 2 / syn.GM_SUN         # compactness 0.3
+    rows[4][9] = 0.0
+    rows[5][5] = 3000.0                                           # beta_eq > 0.6
+    rows[6][12] = 4.0
+    st = ppm.validate_params(np.array(rows), 2)
+    assert st.tolist() == [0, 1, 2, 3, 4, 5, 4]
+    # one-spot specs ignore the second spot's slots
+    q = p.copy()
+    q[12:16] = math.nan
+    assert ppm.validate_params(q, 1).tolist() == [0]
+    assert ppm.validate_params(q, 2).tolist() == [1]
+    # the seeded batch draws are all valid
+    draws, _ = syn.config3_draws(64)
+    assert np.all(ppm.validate_params(draws, 2) == 0)
+
+
+def test_spec_errors_before_device_use():
+    import paper_2510_07764_amd as ppm
+    spec, _ = syn.config1(n_cells=8, n_phase=8, n_energy=16)
+    bad = dict(spec, n_phi=[8, 7])                     # odd annulus
+    with pytest.raises(ppm.PPMError, match="even"):
+        ppm.Plan(bad)
+    at, ag, am, ax = spec["atmos_axes"]
+    ax2 = ax.copy()
+    ax2[5] += 1e-3
+    with pytest.raises(ppm.PPMError, match="uniformly"):
+        ppm.Plan(dict(spec, atmos_axes=(at, ag, am, ax2)))
+    with pytest.raises(ppm.PPMError, match="FP64"):
+        ppm.Plan(dict(spec, precision="f64"))
+    with pytest.raises(ppm.PPMError, match="n_spots"):
+        ppm.Plan(dict(spec, n_spots=3))
+    e = spec["energy"].copy()
+    e[3] = e[2]
+    with pytest.raises(ppm.PPMError, match="increase"):
+        ppm.Plan(dict(spec, energy=e))
