@@ -242,6 +242,15 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         uniform_axis(sp->ax_T, S.nT, S.T0, S.hT);
         uniform_axis(sp->ax_g, S.ng, S.g0, S.hg);
         uniform_axis(sp->ax_x, S.nx, S.x0, S.hx);
+        // windowed accumulation: the energy grid spans r_span x intervals; the
+        // per-ring window adds the redshift spread (z ratio <= (1+b)/(1-b) = 4
+        // for surface speeds below 0.6 c) and the cubic stencil.
+        S.tb0 = (std::log10(sp->energy_kev[0]) - S.x0) / S.hx;
+        S.r_span = (std::log10(sp->energy_kev[S.E - 1]) - std::log10(sp->energy_kev[0])) / S.hx;
+        S.W_max = (int)std::ceil(S.r_span + std::log10(4.0) / S.hx) + 8;
+        if (S.W_max > S.nx) S.W_max = S.nx;
+        S.fast = (S.r_span <= 59.0) ? 1 : 0;
+        S.sub_stride = S.fast ? ((S.nmu * S.W_max + 3) & ~3) : S.nmu * S.nx;
         size_t n = (size_t)S.nT * S.ng * S.nmu * S.nx;
         std::vector<float> lin(n);
         for (size_t i = 0; i < n; ++i) lin[i] = (float)std::pow(10.0, sp->log_intensity[i]);
@@ -262,7 +271,7 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     bool ok = W.stars && W.rings && W.table && W.trace && W.vis_pairs && W.ncells && W.counts
            && S.glx && S.glw && S.energy && S.rsp32;
     if (S.intensity == PPM_I_TABLE) {
-        W.sub = pl->dalloc<float>(B * R * S.nmu * S.nx);
+        W.sub = pl->dalloc<float>(B * R * (size_t)S.sub_stride);
         W.partial32 = pl->dalloc<float>(B * R * S.P * S.E);
         W.fold_in32 = pl->dalloc<float>(B * S.P * S.E);
         ok = ok && W.sub && W.partial32 && W.fold_in32 && S.atm && S.ax_mu;

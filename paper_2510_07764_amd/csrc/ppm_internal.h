@@ -28,6 +28,10 @@ struct DevSpec {
     int n_fp, P, E, C;
     int nT, ng, nmu, nx;
     int n_alpha, n_quad;
+    int fast;             // 1: windowed accumulation kernel applies (energy span <= 59 x-intervals)
+    int W_max;            // x-node window of the per-ring sub-table
+    int sub_stride;       // floats per ring in the sub-table buffer (multiple of 4)
+    double tb0, r_span;   // (log10 E_0 - x0)/hx and (log10 E_last - log10 E_0)/hx
     int R_tot;            // ring slots per instance (spot 0 then spot 1)
     int rings_max[2];     // ring slots of each spot
     int n_rings_spec[2], n_phi_spec[2];   // default grid of each spot
@@ -57,6 +61,8 @@ struct RingRec {
     double tm, cos_zm;           // crescent mask centre colatitude, cos(mask radius)
     int spot, shape, n_cells, active;
     int visible, inv_min, inv_max, pad;
+    double zmin, zmax;           // range of the fine-phase redshift factor z
+    int xw0, xw;                 // x-node window [xw0, xw0 + xw) of the ring's sub-table
 };
 
 }  // namespace ppm

@@ -408,12 +408,43 @@ __global__ void k_trace(DevSpec S, const StarRec *stars, RingRec *rings, const d
     }
     __syncthreads();
     double4 *out = trace + ((size_t)b * S.R_tot + r) * (nfp + 1);
-    for (int i = threadIdx.x; i <= nfp; i += blockDim.x) out[i] = tr_lds[i];
+    double zlo = 1e300, zhi = 0.0;
+    for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
+        double4 v = tr_lds[i];
+        out[i] = v;
+        if (v.y > 0.0) { zlo = fmin(zlo, v.y); zhi = fmax(zhi, v.y); }
+    }
+    __shared__ double red_lo[256], red_hi[256];
+    red_lo[threadIdx.x] = zlo;
+    red_hi[threadIdx.x] = zhi;
+    __syncthreads();
     if (threadIdx.x == 0) {
+        for (int t = 1; t < blockDim.x; ++t) { zlo = fmin(zlo, red_lo[t]); zhi = fmax(zhi, red_hi[t]); }
         gp->visible = ring_visible ? 1 : 0;
         gp->inv_min = a0;
         gp->inv_max = a1;
-        gp->active = (ring_visible && g.w_cell > 0.0) ? 1 : 0;
+        int active = (ring_visible && g.w_cell > 0.0) ? 1 : 0;
+        gp->zmin = zlo;
+        gp->zmax = zhi;
+        if (active && S.intensity == PPM_I_TABLE) {
+            // x nodes any (cell, phase, energy) of this ring can touch, plus the
+            // cubic stencil: t = (log10(z E / kT) - x0) / hx
+            double lkt = log10(g.kT) / S.hx;
+            double tlo = log10(zlo) / S.hx + S.tb0 - lkt;
+            double thi = log10(zhi) / S.hx + S.tb0 + S.r_span - lkt;
+            int w0 = (int)floor(tlo) - 2, w1 = (int)floor(thi) + 3;
+            w0 = w0 < 0 ? 0 : w0;
+            w1 = w1 > S.nx - 1 ? S.nx - 1 : w1;
+            int w = w1 - w0 + 1;
+            if (w < 1) { w0 = 0; w = 1; }
+            if (w > S.W_max) w = S.W_max;   // cannot happen for surface speeds below 0.6 c
+            gp->xw0 = w0;
+            gp->xw = w;
+        } else {
+            gp->xw0 = 0;
+            gp->xw = 0;
+        }
+        gp->active = active;
     }
 }
 
@@ -448,6 +479,21 @@ __global__ void k_subtable(DevSpec S, const RingRec *rings, float *sub)
     const float *s01 = s00 + slab;
     const float *s10 = S.atm + ((size_t)(it + 1) * S.ng + ig) * slab;
     const float *s11 = s10 + slab;
+    if (S.fast) {
+        // window [xw0, xw0 + W_max) of every mu row, row stride W_max
+        const int W = S.W_max, xw0 = g.xw0, xw = g.xw;
+        float *out = sub + ((size_t)b * S.R_tot + r) * (size_t)S.sub_stride;
+        for (int i = threadIdx.x; i < S.nmu * W; i += blockDim.x) {
+            int m = i / W, c = i - m * W;
+            float v = 0.0f;
+            if (c < xw) {
+                size_t o = (size_t)m * S.nx + xw0 + c;
+                v = w00 * s00[o] + w01 * s01[o] + w10 * s10[o] + w11 * s11[o];
+            }
+            out[i] = v;
+        }
+        return;
+    }
     float *out = sub + ((size_t)b * S.R_tot + r) * slab;
     for (size_t i = threadIdx.x; i < slab; i += blockDim.x)
         out[i] = w00 * s00[i] + w01 * s01[i] + w10 * s10[i] + w11 * s11[i];
@@ -491,6 +537,11 @@ __device__ static inline PhaseSample phase_lookup(const double4 *tr, int nfp, do
     s.z = a.y + w * (c.y - a.y);
     s.mu = a.w + w * (c.w - a.w);
     return s;
+}
+
+__device__ static inline float readlane_f(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
 __device__ static inline void wave_sync()
@@ -617,6 +668,181 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const RingRec *r
                 acc[m] += Fp * I;
             }
             wave_sync();
+        }
+        const double scale = g.w_cell * g.T * g.T * g.T;
+        float *out = partial + (((size_t)b * S.R_tot + r) * P + k) * E;
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) {
+            int e = lane * EPL + m;
+            if (e < E) out[e] = (float)(acc[m] * (scale / S.energy[e]));
+        }
+    }
+    if (lane == 0 && npairs) atomicAdd(&vis_pairs[(size_t)b * S.R_tot + r], npairs);
+}
+
+
+// ---------------------------------------------------------------------------
+// k_accum_fast: shift-and-add with the mixed-order atmosphere table (Eq. 47),
+// windowed formulation.  Block = (ring, tile of PT phases), 4 waves; a wave
+// owns one phase at a time and EPL consecutive energies per lane (FP32
+// accumulators in registers, fixed summation order over cells).
+//  stage A  lane = cell: FP64 observed-phase lookup (Eqs. 45-46), mu
+//           weights (cubic Lagrange; linear in the protected small-mu zone
+//           and the last interval) pre-scaled by F_p, and the x position
+//           T0 = (log10(z_p E_0 / kT) - x0)/hx split into I0 = floor(T0) and
+//           frac0; visible pairs are compacted with a wave ballot;
+//  stage B  per visible pair: lane = x node I0 - 1 + lane, mu contraction of
+//           the ring's LDS sub-table; lane = x interval I0 + lane, cubic
+//           coefficients of the interpolant on that interval (linear in the
+//           first and last interval of the table, zero outside) into an LDS
+//           quad; per energy, t = frac0 + (tb_e - tb_0), one quad read and a
+//           three-FMA Horner step.
+// The polynomial form equals the cubic Lagrange interpolant of the oracle
+// on each interval; the energy window of one pair spans at most 61
+// intervals (checked at plan creation).
+// ---------------------------------------------------------------------------
+template <int EPL>
+__global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const RingRec *rings, const double4 *trace,
+                                                    const float *sub, float *partial, int32_t *vis_pairs, int PT)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int r = blockIdx.y, b = blockIdx.z;
+    const RingRec g = rings[(size_t)b * S.R_tot + r];
+    if (!g.active) return;
+    const int nfp = S.n_fp, nmu = S.nmu, nx = S.nx, E = S.E, P = S.P, W = S.W_max;
+    double4 *tr = (double4 *)lds_raw;                          // nfp + 1
+    double *axmu = (double *)(tr + nfp + 1);                   // nmu (padded to 16 bytes)
+    float *tab = (float *)(axmu + ((nmu + 1) & ~1));           // sub_stride, 16-byte aligned
+    float4 *Qb = (float4 *)(tab + S.sub_stride);               // 4 waves * 64 quads
+    float *Sb = (float *)(Qb + 4 * 64);                        // 4 waves * 68
+    const double4 *gtr = trace + ((size_t)b * S.R_tot + r) * (nfp + 1);
+    for (int i = threadIdx.x; i <= nfp; i += blockDim.x) tr[i] = gtr[i];
+    for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
+    // per-ring stride is a multiple of 4 floats: 16-byte aligned rows of float4
+    const float4 *gsub = (const float4 *)(sub + ((size_t)b * S.R_tot + r) * (size_t)S.sub_stride);
+    float4 *tab4 = (float4 *)tab;
+    for (int i = threadIdx.x; i < S.sub_stride / 4; i += blockDim.x) tab4[i] = gsub[i];
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float4 *Qw = Qb + wave * 64;
+    float *Sw = Sb + wave * 68;
+    if (lane < 4) Sw[64 + lane] = 0.0f;
+    const double phio0 = tr[0].z;
+    const double inv2pi = 1.0 / kTwoPi;
+    const double tbk = S.tb0 - log10(g.kT) / S.hx;   // (log10(E_0/kT) - x0)/hx
+    const double ihx = 1.0 / S.hx;
+    float tbr[EPL];
+#pragma unroll
+    for (int m = 0; m < EPL; ++m) {
+        int e = lane * EPL + m;
+        tbr[m] = e < E ? (float)((log10(S.energy[e]) - log10(S.energy[0])) * ihx) : 0.0f;
+    }
+    const double mu_lo = axmu[0], mu_hi = axmu[nmu - 1];
+    const int xw0 = g.xw0, xw = g.xw;
+    int npairs = 0;
+    const int k_begin = blockIdx.x * PT;
+    for (int kk = wave; kk < PT; kk += 4) {
+        const int k = k_begin + kk;
+        if (k >= P) break;
+        float acc[EPL];
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) acc[m] = 0.0f;
+        const double Phik = (k + 0.5) / P;
+        for (int c0 = 0; c0 < g.n_cells; c0 += 64) {
+            // ---------------- stage A: one (cell, phase) pair per lane
+            const int j = c0 + lane;
+            bool vis = false;
+            float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, fr = 0.f;
+            int I0 = 0, m0 = 0;
+            if (j < g.n_cells) {
+                const double off = cell_offset(g, j);
+                if (!cell_masked(g, off)) {
+                    double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
+                    double php = (a - floor(a)) + phio0;                    // Eq. (45)
+                    PhaseSample ps = phase_lookup(tr, nfp, php);            // Eq. (46)
+                    if (ps.F != 0.0) {
+                        vis = true;
+                        double mu = fmin(mu_hi, fmax(mu_lo, ps.mu));
+                        int lo = 0, hi = nmu - 1;
+                        while (hi - lo > 1) {
+                            int mid = (lo + hi) >> 1;
+                            if (axmu[mid] <= mu) lo = mid; else hi = mid;
+                        }
+                        double w[4] = {0.0, 0.0, 0.0, 0.0};
+                        if (lo < 3 || lo == nmu - 2) {
+                            double t = (mu - axmu[lo]) / (axmu[lo + 1] - axmu[lo]);
+                            m0 = lo < nmu - 4 ? lo : nmu - 4;
+                            w[lo - m0] = 1.0 - t;
+                            w[lo + 1 - m0] = t;
+                        } else {
+                            m0 = lo - 1;
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                double num = 1.0, den = 1.0;
+#pragma unroll
+                                for (int s2 = 0; s2 < 4; ++s2) {
+                                    if (s2 == q) continue;
+                                    num *= mu - axmu[m0 + s2];
+                                    den *= axmu[m0 + q] - axmu[m0 + s2];
+                                }
+                                w[q] = num / den;
+                            }
+                        }
+                        w0 = (float)(w[0] * ps.F);
+                        w1 = (float)(w[1] * ps.F);
+                        w2 = (float)(w[2] * ps.F);
+                        w3 = (float)(w[3] * ps.F);
+                        double T0 = log10(ps.z) * ihx + tbk;
+                        double fl = floor(T0);
+                        I0 = (int)fl;
+                        fr = (float)(T0 - fl);
+                    }
+                }
+            }
+            uint64_t mask = __ballot(vis);
+            npairs += __popcll(mask);
+            // ---------------- stage B: the visible pairs one after another
+            while (mask) {
+                const int p = __ffsll((unsigned long long)mask) - 1;
+                mask &= mask - 1;
+                const float pw0 = readlane_f(w0, p), pw1 = readlane_f(w1, p), pw2 = readlane_f(w2, p),
+                            pw3 = readlane_f(w3, p), pfr = readlane_f(fr, p);
+                const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
+                // mu contraction at x node I0 - 1 + lane
+                const int col = pI0 - 1 + lane - xw0;
+                float Sv = 0.0f;
+                if (col >= 0 && col < xw) {
+                    const float *t0 = tab + pm0 * W + col;
+                    Sv = pw0 * t0[0] + pw1 * t0[W] + pw2 * t0[2 * W] + pw3 * t0[3 * W];
+                }
+                Sw[lane] = Sv;
+                wave_sync();
+                const float s1 = Sw[lane + 1], s2 = Sw[lane + 2], s3 = Sw[lane + 3];
+                // interpolant on x interval gi = I0 + lane (nodes gi-1 .. gi+2)
+                const int gi = pI0 + lane;
+                float4 qd = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (gi >= 0 && gi <= nx - 2) {
+                    if (gi == 0 || gi == nx - 2) {
+                        qd = make_float4(s1, s2 - s1, 0.f, 0.f);
+                    } else {
+                        float c2 = 0.5f * (Sv + s2) - s1;
+                        float c3 = (s3 - Sv) * (1.0f / 6.0f) + 0.5f * (s1 - s2);
+                        qd = make_float4(s1, s2 - s1 - c2 - c3, c2, c3);
+                    }
+                }
+                Qw[lane] = qd;
+                wave_sync();
+#pragma unroll
+                for (int m = 0; m < EPL; ++m) {
+                    const float t = pfr + tbr[m];
+                    const int il = (int)t;
+                    const float f = t - (float)il;
+                    const float4 q = Qw[il];
+                    acc[m] += q.x + f * (q.y + f * (q.z + f * q.w));
+                }
+                wave_sync();
+            }
         }
         const double scale = g.w_cell * g.T * g.T * g.T;
         float *out = partial + (((size_t)b * S.R_tot + r) * P + k) * E;
@@ -808,6 +1034,9 @@ __global__ void k_status(const StarRec *stars, int B, int32_t *out)
 // ---------------------------------------------------------------------------
 size_t accum_table_lds(const DevSpec &S)
 {
+    if (S.fast)
+        return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
+             + sizeof(float) * S.sub_stride + sizeof(float4) * 4 * 64 + sizeof(float) * 4 * 68;
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * S.nmu + sizeof(float) * S.nmu * S.nx
          + sizeof(float) * 4 * S.nx;
 }
@@ -833,7 +1062,20 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
         size_t lds = accum_table_lds(S);
         if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
         int epl = (S.E + 63) / 64;
-        if (epl <= 1)
+        if (S.fast) {
+            if (epl <= 1)
+                hipLaunchKernelGGL(k_accum_fast<1>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+                                   W.partial32, W.vis_pairs, PT);
+            else if (epl <= 2)
+                hipLaunchKernelGGL(k_accum_fast<2>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+                                   W.partial32, W.vis_pairs, PT);
+            else if (epl <= 4)
+                hipLaunchKernelGGL(k_accum_fast<4>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+                                   W.partial32, W.vis_pairs, PT);
+            else
+                hipLaunchKernelGGL(k_accum_fast<8>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+                                   W.partial32, W.vis_pairs, PT);
+        } else if (epl <= 1)
             hipLaunchKernelGGL(k_accum_table<1>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
                                W.partial32, W.vis_pairs, PT);
         else if (epl <= 2)
