@@ -219,13 +219,19 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     S.C = sp->n_chan;
     S.t_exp = sp->t_exp;
     S.n_alpha = sp->n_alpha;
-    S.n_quad = 96;
     pl->max_batch = max_batch;
     pl->max_cells = max_cells;
     pl->precision = sp->precision;
 
+    // Gauss-Legendre rules of 32, 48 and 64 nodes, back to back
     std::vector<double> glx, glw;
-    gauss_legendre01(S.n_quad, glx, glw);
+    for (int n : {32, 48, 64}) {
+        std::vector<double> x, w;
+        gauss_legendre01(n, x, w);
+        glx.insert(glx.end(), x.begin(), x.end());
+        glw.insert(glw.end(), w.begin(), w.end());
+    }
+    S.n_quad = (int)glx.size();
     S.glx = pl->upload(glx.data(), glx.size());
     S.glw = pl->upload(glw.data(), glw.size());
     S.energy = pl->upload(sp->energy_kev, S.E);
@@ -268,7 +274,9 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     W.vis_pairs = pl->dalloc<int32_t>(B * R);
     W.ncells = pl->dalloc<int32_t>(B);
     W.counts = pl->dalloc<double>(B * S.P * S.C);
-    bool ok = W.stars && W.rings && W.table && W.trace && W.vis_pairs && W.ncells && W.counts
+    W.ll_part = pl->dalloc<double>(B * loglike_blocks(S.P * S.C));
+    W.ll_bad = pl->dalloc<int32_t>(B * loglike_blocks(S.P * S.C));
+    bool ok = W.stars && W.rings && W.table && W.trace && W.vis_pairs && W.ncells && W.counts && W.ll_part && W.ll_bad
            && S.glx && S.glw && S.energy && S.rsp32;
     if (S.intensity == PPM_I_TABLE) {
         W.sub = pl->dalloc<float>(B * R * (size_t)S.sub_stride);

@@ -21,6 +21,8 @@ struct Workspace {
     double *counts;        // [B][P][C]
     int32_t *vis_pairs;    // [B][R_tot]
     int32_t *ncells;       // [B] per-instance grid override
+    double *ll_part;       // [B][loglike_blocks] first-stage likelihood sums
+    int32_t *ll_bad;       // [B][loglike_blocks] bins with m <= 0 and d > 0
 };
 
 __host__ __device__ int validate_params(const double *p, int n_spots);
@@ -32,5 +34,6 @@ hipError_t launch_loglike(const Workspace &W, const double *counts, int B, int P
                           double *logl, hipStream_t st);
 hipError_t launch_status(const Workspace &W, int B, int32_t *out, hipStream_t st);
 size_t accum_table_lds(const DevSpec &S);
+int loglike_blocks(int PC);
 
 }  // namespace ppm
