@@ -56,7 +56,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--batch", type=int, default=64, help="vectors per call in the batched leg (0: skip)")
+    ap.add_argument("--batch", type=int, default=256, help="vectors per call in the batched leg (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=64, help="cells per spot of the oracle sample (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -97,25 +97,40 @@ def main():
     hot_avg_s = hot_ms / max(n_hot, 1) * 1e-3
     achieved = units * FLOP_PER_UNIT / hot_avg_s / 1e12
 
-    # ---------------- batched: B config-1-shape vectors per call
+    # ---------------- plain, graph-replayed: the same single-vector call
+    # submitted as one captured HIP graph per evaluation
+    gl1 = ppm.GraphedLogLike(plan, data_t, 1)
+    for _ in range(args.warmup):
+        gl1(pt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gl1(pt)
+    torch.cuda.synchronize()
+    plain_graph_s = (time.perf_counter() - t0) / args.steps
+    graph_ok = bool(torch.equal(gl1(pt), ll))
+    del gl1
+
+    # ---------------- batched: B config-1-shape vectors per graph replay
     batched = None
     if args.batch > 0:
         B = args.batch
         draws = syn.config4_draws(B)
         planb = ppm.Plan(spec, max_batch=B)
         ptb = torch.tensor(draws, dtype=torch.float64, device=dev)
-        llb = torch.empty(B, dtype=torch.float64, device=dev)
-        planb.loglike(ptb, data_t, out=llb)
+        glb = ppm.GraphedLogLike(planb, data_t, B)
+        glb(ptb)
         torch.cuda.synchronize()
         kb = max(2, args.steps // 10)
         t0 = time.perf_counter()
         for _ in range(kb):
-            planb.loglike(ptb, data_t, out=llb)
+            out_b = glb(ptb)
         torch.cuda.synchronize()
         tb = (time.perf_counter() - t0) / kb
-        batched = {"evals_per_s": B / tb, "batch": B, "ms_per_call": tb * 1e3,
-                   "finite": bool(torch.isfinite(llb).all().item())}
-        del planb
+        batched = {"evals_per_s": B / tb, "batch": B, "ms_per_call": tb * 1e3, "calls": kb,
+                   "finite": bool(torch.isfinite(out_b).all().item()),
+                   "vs_plain": (B / tb) * plain_s}
+        del glb, planb
 
     cpu = cpu_baseline(args.cpu_sample) if args.cpu_sample > 0 else None
     out = {
@@ -134,6 +149,8 @@ def main():
         "config": {"workload": "config-1: oblate 600 Hz star, cap + annulus, 128x128 cells per spot, "
                                "128 phases, 256 energies, 300 channels, synthetic atmosphere, absorption, response",
                    "plain": "one parameter vector per call", "logL": float(ll.item())},
+        "plain_graph": {"evals_per_s": 1.0 / plain_graph_s, "ms_per_call": plain_graph_s * 1e3,
+                        "matches_direct": graph_ok},
         "batched": batched,
         "grad": None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

@@ -255,3 +255,39 @@ class Plan:
         out = C.c_longlong()
         _check(lib().ppm_visible_pairs(self.handle, B, C.byref(out), _stream_handle(stream)), "ppm_visible_pairs")
         return out.value
+
+
+class GraphedLogLike:
+    """One likelihood evaluation of B parameter vectors captured as a HIP
+    graph (through torch.cuda.CUDAGraph) and replayed per call: the whole
+    launch sequence of the evaluation is submitted at once.  ``__call__``
+    copies the parameters into the captured input buffer, replays, and
+    returns the captured output tensor (overwritten by the next call)."""
+
+    def __init__(self, plan: Plan, data, B: int, n_cells=None):
+        import torch
+        self.plan = plan
+        dev = data.device
+        self.params = torch.zeros((B, NPARAM), dtype=torch.float64, device=dev)
+        self.out = torch.empty(B, dtype=torch.float64, device=dev)
+        self.data = data
+        self.n_cells = None if n_cells is None else np.ascontiguousarray(n_cells, dtype=np.int32)
+        # a valid parameter set for the warm-up (the graph records launches only)
+        from_spec = np.zeros(NPARAM)
+        from_spec[[0, 1, 2, 5, 6, 8, 9, 10, 12, 13, 14]] = [1.4, 12.0, 1.0, 100.0, 100.0, 1.0, 0.1, 6.0, 2.0,
+                                                           0.1, 6.0]
+        self.params.copy_(torch.tensor(np.tile(from_spec, (B, 1)), device=dev))
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            plan.loglike(self.params, data, n_cells=self.n_cells, out=self.out)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            plan.loglike(self.params, data, n_cells=self.n_cells, out=self.out)
+
+    def __call__(self, params):
+        self.params.copy_(params)
+        self.graph.replay()
+        return self.out

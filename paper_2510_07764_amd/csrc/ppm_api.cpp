@@ -3,8 +3,11 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -82,6 +85,11 @@ struct ppm_plan {
     Workspace W;
     int max_batch = 0;
     int max_cells = 0;
+    int chunk = 0;                 // instances per workspace pass
+    int32_t *d_list = nullptr;     // live (instance, ring) slots, chunk by chunk
+    std::vector<int> list_off, list_n;
+    int list_B = -1;               // batch size the list was built for (-1: none)
+    bool list_override = false;    // list built for per-instance grids
     int precision = PPM_F32;
     std::vector<void *> allocs;
     std::vector<int32_t> last_ncells;
@@ -263,20 +271,41 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         S.atm = pl->upload(lin.data(), n);
         S.ax_mu = pl->upload(sp->ax_mu, S.nmu);
     }
-    // workspace
+    // workspace: per-instance outputs for max_batch instances, ring-level
+    // scratch for `chunk` instances (a 16 GiB budget bounds the chunk)
     Workspace &W = pl->W;
     std::memset(&W, 0, sizeof(W));
-    const size_t B = max_batch, R = S.R_tot;
-    W.stars = pl->dalloc<StarRec>(B);
+    const size_t R = S.R_tot;
+    {
+        size_t per_ring = sizeof(RingRec) + sizeof(double4) * (S.n_alpha + S.n_fp + 1)
+                        + (S.intensity == PPM_I_TABLE ? sizeof(float) * (size_t)S.sub_stride
+                                                      + sizeof(float) * (size_t)S.P * S.E
+                                                      : sizeof(double) * (size_t)S.P * S.E);
+        size_t per_inst = per_ring * R + sizeof(double) * (size_t)S.P * S.E;
+        size_t budget = (size_t)16 << 30;
+        size_t c = budget / per_inst;
+        if (c < 1) c = 1;
+        // PPM_MAX_CHUNK caps the instances per workspace pass (tests use it to
+        // exercise multi-pass batches on small workloads)
+        if (const char *env = std::getenv("PPM_MAX_CHUNK")) {
+            long v = std::strtol(env, nullptr, 10);
+            if (v >= 1 && (size_t)v < c) c = (size_t)v;
+        }
+        pl->chunk = (int)(c < (size_t)max_batch ? c : (size_t)max_batch);
+    }
+    const size_t B = pl->chunk, BM = max_batch;
+    W.stars = pl->dalloc<StarRec>(BM);
     W.rings = pl->dalloc<RingRec>(B * R);
     W.table = pl->dalloc<double4>(B * R * S.n_alpha);
     W.trace = pl->dalloc<double4>(B * R * (S.n_fp + 1));
-    W.vis_pairs = pl->dalloc<int32_t>(B * R);
-    W.ncells = pl->dalloc<int32_t>(B);
-    W.counts = pl->dalloc<double>(B * S.P * S.C);
-    W.ll_part = pl->dalloc<double>(B * loglike_blocks(S.P * S.C));
-    W.ll_bad = pl->dalloc<int32_t>(B * loglike_blocks(S.P * S.C));
+    W.vis_pairs = pl->dalloc<int32_t>(BM * R);
+    W.ncells = pl->dalloc<int32_t>(BM);
+    W.counts = pl->dalloc<double>(BM * S.P * S.C);
+    W.ll_part = pl->dalloc<double>(BM * loglike_blocks(S.P * S.C));
+    W.ll_bad = pl->dalloc<int32_t>(BM * loglike_blocks(S.P * S.C));
+    pl->d_list = pl->dalloc<int32_t>(BM * R);
     bool ok = W.stars && W.rings && W.table && W.trace && W.vis_pairs && W.ncells && W.counts && W.ll_part && W.ll_bad
+           && pl->d_list
            && S.glx && S.glw && S.energy && S.rsp32;
     if (S.intensity == PPM_I_TABLE) {
         W.sub = pl->dalloc<float>(B * R * (size_t)S.sub_stride);
@@ -311,37 +340,90 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
 
 void ppm_plan_destroy(ppm_plan *plan) { delete plan; }
 
+// Validates the batch, uploads per-instance grids and (re)builds the work
+// list of live (instance, ring) slots when they change: chunk by chunk,
+// instances with larger grids first so the longest blocks start early.
 static int prepare(ppm_plan *pl, const double *params, int B, const int32_t *ncells_host,
                    const int32_t **ncells_dev)
 {
     if (!pl || !params) return fail(PPM_ERR_ARG, "null plan or params");
     if (B < 1 || B > pl->max_batch) return fail(PPM_ERR_BATCH, "batch outside [1, max_batch]");
+    const DevSpec &S = pl->S;
     *ncells_dev = nullptr;
+    bool rebuild = false;
     if (ncells_host) {
         for (int b = 0; b < B; ++b) {
             int n = ncells_host[b];
-            int lim = pl->max_cells > 0 ? pl->max_cells : 0;
-            for (int s = 0; s < pl->S.n_spots; ++s)
-                if (lim < pl->S.rings_max[s]) lim = pl->S.rings_max[s];
-            if (n < 1 || n > lim) return fail(PPM_ERR_ARG, "per-instance grid outside [1, max_cells]");
-            for (int s = 0; s < pl->S.n_spots; ++s)
-                if (pl->S.shape[s] == PPM_SHAPE_ANNULUS && (n % 2))
+            if (n < 1) return fail(PPM_ERR_ARG, "per-instance grid must be >= 1");
+            for (int s = 0; s < S.n_spots; ++s) {
+                if (n > S.rings_max[s]) return fail(PPM_ERR_ARG, "per-instance grid exceeds the plan's max_cells");
+                if (S.shape[s] == PPM_SHAPE_ANNULUS && (n % 2))
                     return fail(PPM_ERR_ARG, "annulus needs an even per-instance grid");
-            for (int s = 0; s < pl->S.n_spots; ++s)
-                if (n > pl->S.rings_max[s]) return fail(PPM_ERR_ARG, "per-instance grid exceeds the plan");
+            }
         }
-        bool same = pl->ncells_valid && (int)pl->last_ncells.size() >= B
+        bool same = pl->ncells_valid && pl->list_override && pl->list_B == B
                  && std::memcmp(pl->last_ncells.data(), ncells_host, sizeof(int32_t) * B) == 0;
         if (!same) {
             hipError_t e = hipMemcpy(pl->W.ncells, ncells_host, sizeof(int32_t) * B, hipMemcpyHostToDevice);
             if (e != hipSuccess) return hip_fail(e, "upload of per-instance grids");
             pl->last_ncells.assign(ncells_host, ncells_host + B);
             pl->ncells_valid = true;
+            rebuild = true;
         }
         *ncells_dev = pl->W.ncells;
+    } else if (pl->list_override || pl->list_B != B) {
+        rebuild = true;
+    }
+    if (rebuild) {
+        std::vector<int32_t> list;
+        list.reserve((size_t)B * S.R_tot);
+        pl->list_off.clear();
+        pl->list_n.clear();
+        for (int c0 = 0; c0 < B; c0 += pl->chunk) {
+            int nb = B - c0 < pl->chunk ? B - c0 : pl->chunk;
+            std::vector<std::pair<int, int>> order;   // (-cells, local instance)
+            for (int b = 0; b < nb; ++b) order.push_back({ncells_host ? -ncells_host[c0 + b] : 0, b});
+            std::stable_sort(order.begin(), order.end());
+            pl->list_off.push_back((int)list.size());
+            for (auto &o : order) {
+                int b = o.second;
+                for (int s = 0; s < S.n_spots; ++s) {
+                    int nr = ncells_host ? ncells_host[c0 + b] : S.n_rings_spec[s];
+                    int base = s == 0 ? 0 : S.rings_max[0];
+                    for (int r = 0; r < nr; ++r) list.push_back(b * S.R_tot + base + r);
+                }
+            }
+            pl->list_n.push_back((int)list.size() - pl->list_off.back());
+        }
+        hipError_t e = hipMemcpy(pl->d_list, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "upload of the work list");
+        pl->list_B = B;
+        pl->list_override = ncells_host != nullptr;
     }
     pl->last_B = B;
     return PPM_OK;
+}
+
+// One forward pass over the batch, chunk by chunk.
+static hipError_t run_forward(ppm_plan *pl, const double *params, int B, const int32_t *nc, hipStream_t st,
+                              double *flux, double *counts)
+{
+    const DevSpec &S = pl->S;
+    for (size_t ci = 0; ci < pl->list_off.size(); ++ci) {
+        int c0 = (int)ci * pl->chunk;
+        int nb = B - c0 < pl->chunk ? B - c0 : pl->chunk;
+        Workspace W = pl->W;
+        W.stars += c0;
+        W.vis_pairs += (size_t)c0 * S.R_tot;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        pl->events(e0, e1);
+        hipError_t e = launch_forward(S, W, params + (size_t)c0 * PPM_NPARAM, nc ? nc + c0 : nullptr, nb,
+                                      pl->d_list + pl->list_off[ci], pl->list_n[ci], st,
+                                      flux ? flux + (size_t)c0 * S.P * S.E : nullptr,
+                                      counts + (size_t)c0 * S.P * S.C, e0, e1);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 int ppm_forward(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_cells_host,
@@ -351,9 +433,7 @@ int ppm_forward(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_
     int rc = prepare(pl, params_dev, B, n_cells_host, &nc);
     if (rc) return rc;
     if (!counts_dev) return fail(PPM_ERR_ARG, "null counts buffer");
-    hipEvent_t e0, e1;
-    pl->events(e0, e1);
-    hipError_t e = launch_forward(pl->S, pl->W, params_dev, nc, B, (hipStream_t)stream, nullptr, counts_dev, e0, e1);
+    hipError_t e = run_forward(pl, params_dev, B, nc, (hipStream_t)stream, nullptr, counts_dev);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_forward launch");
 }
 
@@ -364,9 +444,7 @@ int ppm_flux(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_cel
     int rc = prepare(pl, params_dev, B, n_cells_host, &nc);
     if (rc) return rc;
     if (!flux_dev) return fail(PPM_ERR_ARG, "null flux buffer");
-    hipEvent_t e0, e1;
-    pl->events(e0, e1);
-    hipError_t e = launch_forward(pl->S, pl->W, params_dev, nc, B, (hipStream_t)stream, flux_dev, pl->W.counts, e0, e1);
+    hipError_t e = run_forward(pl, params_dev, B, nc, (hipStream_t)stream, flux_dev, pl->W.counts);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_flux launch");
 }
 
@@ -379,9 +457,7 @@ int ppm_loglike(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_
     if (!data_dev || !logl_dev) return fail(PPM_ERR_ARG, "null data or logl buffer");
     double *cnt = counts_dev ? counts_dev : pl->W.counts;
     hipStream_t st = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    pl->events(e0, e1);
-    hipError_t e = launch_forward(pl->S, pl->W, params_dev, nc, B, st, nullptr, cnt, e0, e1);
+    hipError_t e = run_forward(pl, params_dev, B, nc, st, nullptr, cnt);
     if (e != hipSuccess) return hip_fail(e, "ppm_loglike forward");
     e = launch_loglike(pl->W, cnt, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike reduction");
@@ -399,7 +475,8 @@ int ppm_debug_ring(ppm_plan *pl, int b, int r, double *table_out, double *info_o
                    int32_t *trace_info, void *stream)
 {
     if (!pl) return fail(PPM_ERR_ARG, "null plan");
-    if (b < 0 || b >= pl->max_batch || r < 0 || r >= pl->S.R_tot) return fail(PPM_ERR_ARG, "ring out of range");
+    if (b < 0 || b >= pl->chunk || r < 0 || r >= pl->S.R_tot)
+        return fail(PPM_ERR_ARG, "ring out of range (instances of the first workspace chunk only)");
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "ppm_debug_ring sync");

@@ -60,7 +60,7 @@ struct RingRec {
     double logT, T, kT;
     double tm, cos_zm;           // crescent mask centre colatitude, cos(mask radius)
     int spot, shape, n_cells, active;
-    int visible, inv_min, inv_max, pad;
+    int visible, inv_min, inv_max, interior;   // interior: the ring never reaches the x-axis edge intervals
     double zmin, zmax;           // range of the fine-phase redshift factor z
     int xw0, xw;                 // x-node window [xw0, xw0 + xw) of the ring's sub-table
 };

@@ -115,7 +115,7 @@ __global__ void k_setup(DevSpec S, const double *params, const int32_t *n_cells,
         g.visible = 0;
         g.inv_min = 0;
         g.inv_max = -1;
-        g.pad = 0;
+        g.interior = 0;
         g.n_cells = 0;
         bool live = st.status == PPM_INST_OK && spot < S.n_spots && lr < nr;
         double tc = p[8 + 4 * spot], z = p[9 + 4 * spot];
@@ -264,9 +264,9 @@ __device__ static void grazing(const DevSpec &S, double v, double &ph, double &d
     dth = 2.0 / (om * om) * K + 2.0 / om * K1 / (om * om);
 }
 
-__global__ void k_table(DevSpec S, const StarRec *stars, const RingRec *rings, double4 *table)
+__global__ void k_table(DevSpec S, const int32_t *list, const StarRec *stars, const RingRec *rings, double4 *table)
 {
-    const int r = blockIdx.x, b = blockIdx.y;
+    const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
     const RingRec g = rings[(size_t)b * S.R_tot + r];
     if (g.n_cells == 0) return;
     const StarRec st = stars[b];
@@ -330,11 +330,11 @@ __device__ static inline void dhermite(double t, double &d00, double &d10, doubl
     d11 = 3.0 * t2 - 2.0 * t;
 }
 
-__global__ void k_trace(DevSpec S, const StarRec *stars, RingRec *rings, const double4 *table,
+__global__ void k_trace(DevSpec S, const int32_t *list, const StarRec *stars, RingRec *rings, const double4 *table,
                         double4 *trace)
 {
     extern __shared__ double4 lds_tab[];
-    const int r = blockIdx.x, b = blockIdx.y;
+    const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
     RingRec *gp = rings + (size_t)b * S.R_tot + r;
     const RingRec g = *gp;
     if (g.n_cells == 0) return;
@@ -459,9 +459,12 @@ __global__ void k_trace(DevSpec S, const StarRec *stars, RingRec *rings, const d
             if (w > S.W_max) w = S.W_max;   // cannot happen for surface speeds below 0.6 c
             gp->xw0 = w0;
             gp->xw = w;
+            // every interval used lies in [floor(tlo), floor(thi)]
+            gp->interior = (floor(tlo) >= 1.0 && floor(thi) <= S.nx - 3) ? 1 : 0;
         } else {
             gp->xw0 = 0;
             gp->xw = 0;
+            gp->interior = 0;
         }
         gp->active = active;
     }
@@ -483,9 +486,9 @@ __device__ static inline int lin_bracket(double v, double v0, double h, int n, d
     return i;
 }
 
-__global__ void k_subtable(DevSpec S, const RingRec *rings, float *sub)
+__global__ void k_subtable(DevSpec S, const int32_t *list, const RingRec *rings, float *sub)
 {
-    const int r = blockIdx.x, b = blockIdx.y;
+    const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
     const RingRec g = rings[(size_t)b * S.R_tot + r];
     if (!g.active) return;
     double wt1, wg1;
@@ -580,12 +583,12 @@ __device__ static inline void wave_sync()
 // cubic Lagrange in x (linear in the first and last interval, zero outside).
 // ---------------------------------------------------------------------------
 template <int EPL>
-__global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const RingRec *rings,
+__global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *list, const RingRec *rings,
                                                      const double4 *trace, const float *sub,
                                                      float *partial, int32_t *vis_pairs, int PT)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int r = blockIdx.y, b = blockIdx.z;
+    const int ent = list[blockIdx.y], b = ent / S.R_tot, r = ent - b * S.R_tot;
     const RingRec g = rings[(size_t)b * S.R_tot + r];
     if (!g.active) return;
     const int nfp = S.n_fp, nmu = S.nmu, nx = S.nx, E = S.E, P = S.P;
@@ -720,12 +723,98 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const RingRec *r
 // on each interval; the energy window of one pair spans at most 61
 // intervals (checked at plan creation).
 // ---------------------------------------------------------------------------
+
+// Stage B of k_accum_fast for rings whose x window stays clear of the first
+// and last table interval: every interval is cubic, no selects.
 template <int EPL>
-__global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const RingRec *rings, const double4 *trace,
+__device__ __forceinline__ void pairs_interior(uint64_t mask, float w0, float w1, float w2, float w3, float fr,
+                                               int pk, int lane, const float *tab, int W, int xw0, float *Sw,
+                                               float4 *Qw, const float (&tbr)[EPL], float (&acc)[EPL])
+{
+    while (mask) {
+        const int p = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const float pw0 = readlane_f(w0, p), pw1 = readlane_f(w1, p), pw2 = readlane_f(w2, p),
+                    pw3 = readlane_f(w3, p), pfr = readlane_f(fr, p);
+        const int ppk = __builtin_amdgcn_readlane(pk, p);
+        const int pI0 = ppk >> 8, pm0 = ppk & 255;
+        // mu contraction at x node I0 - 1 + lane (columns past the window hold zeros)
+        int col = pI0 - 1 + lane - xw0;
+        col = col < W - 1 ? col : W - 1;
+        const float *t0 = tab + pm0 * W + col;
+        const float Sv = pw0 * t0[0] + pw1 * t0[W] + pw2 * t0[2 * W] + pw3 * t0[3 * W];
+        Sw[lane] = Sv;
+        wave_sync();
+        const float s1 = Sw[lane + 1], s2 = Sw[lane + 2], s3 = Sw[lane + 3];
+        const float c2 = 0.5f * (Sv + s2) - s1;
+        const float c3 = (s3 - Sv) * (1.0f / 6.0f) + 0.5f * (s1 - s2);
+        Qw[lane] = make_float4(s1, s2 - s1 - c2 - c3, c2, c3);
+        wave_sync();
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) {
+            const float t = pfr + tbr[m];
+            const float f = __builtin_amdgcn_fractf(t);
+            const float4 q = Qw[(int)t];
+            acc[m] += q.x + f * (q.y + f * (q.z + f * q.w));
+        }
+        wave_sync();
+    }
+}
+
+// Stage B for rings that may reach the edge intervals (linear there) or
+// leave the table (zero contribution).
+template <int EPL>
+__device__ __forceinline__ void pairs_general(uint64_t mask, float w0, float w1, float w2, float w3, float fr,
+                                              int I0, int m0, int lane, const float *tab, int W, int xw0, int xw,
+                                              int nx, float *Sw, float4 *Qw, const float (&tbr)[EPL],
+                                              float (&acc)[EPL])
+{
+    while (mask) {
+        const int p = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const float pw0 = readlane_f(w0, p), pw1 = readlane_f(w1, p), pw2 = readlane_f(w2, p),
+                    pw3 = readlane_f(w3, p), pfr = readlane_f(fr, p);
+        const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
+        const int col = pI0 - 1 + lane - xw0;
+        float Sv = 0.0f;
+        if (col >= 0 && col < xw) {
+            const float *t0 = tab + pm0 * W + col;
+            Sv = pw0 * t0[0] + pw1 * t0[W] + pw2 * t0[2 * W] + pw3 * t0[3 * W];
+        }
+        Sw[lane] = Sv;
+        wave_sync();
+        const float s1 = Sw[lane + 1], s2 = Sw[lane + 2], s3 = Sw[lane + 3];
+        // interpolant on x interval gi = I0 + lane (nodes gi-1 .. gi+2)
+        const int gi = pI0 + lane;
+        float4 qd = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gi >= 0 && gi <= nx - 2) {
+            if (gi == 0 || gi == nx - 2) {
+                qd = make_float4(s1, s2 - s1, 0.f, 0.f);
+            } else {
+                float c2 = 0.5f * (Sv + s2) - s1;
+                float c3 = (s3 - Sv) * (1.0f / 6.0f) + 0.5f * (s1 - s2);
+                qd = make_float4(s1, s2 - s1 - c2 - c3, c2, c3);
+            }
+        }
+        Qw[lane] = qd;
+        wave_sync();
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) {
+            const float t = pfr + tbr[m];
+            const float f = __builtin_amdgcn_fractf(t);
+            const float4 q = Qw[(int)t];
+            acc[m] += q.x + f * (q.y + f * (q.z + f * q.w));
+        }
+        wave_sync();
+    }
+}
+
+template <int EPL>
+__global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const int32_t *list, const RingRec *rings, const double4 *trace,
                                                     const float *sub, float *partial, int32_t *vis_pairs, int PT)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int r = blockIdx.y, b = blockIdx.z;
+    const int ent = list[blockIdx.y], b = ent / S.R_tot, r = ent - b * S.R_tot;
     const RingRec g = rings[(size_t)b * S.R_tot + r];
     if (!g.active) return;
     const int nfp = S.n_fp, nmu = S.nmu, nx = S.nx, E = S.E, P = S.P, W = S.W_max;
@@ -822,46 +911,10 @@ __global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const RingRec *ri
             uint64_t mask = __ballot(vis);
             npairs += __popcll(mask);
             // ---------------- stage B: the visible pairs one after another
-            while (mask) {
-                const int p = __ffsll((unsigned long long)mask) - 1;
-                mask &= mask - 1;
-                const float pw0 = readlane_f(w0, p), pw1 = readlane_f(w1, p), pw2 = readlane_f(w2, p),
-                            pw3 = readlane_f(w3, p), pfr = readlane_f(fr, p);
-                const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
-                // mu contraction at x node I0 - 1 + lane
-                const int col = pI0 - 1 + lane - xw0;
-                float Sv = 0.0f;
-                if (col >= 0 && col < xw) {
-                    const float *t0 = tab + pm0 * W + col;
-                    Sv = pw0 * t0[0] + pw1 * t0[W] + pw2 * t0[2 * W] + pw3 * t0[3 * W];
-                }
-                Sw[lane] = Sv;
-                wave_sync();
-                const float s1 = Sw[lane + 1], s2 = Sw[lane + 2], s3 = Sw[lane + 3];
-                // interpolant on x interval gi = I0 + lane (nodes gi-1 .. gi+2)
-                const int gi = pI0 + lane;
-                float4 qd = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (gi >= 0 && gi <= nx - 2) {
-                    if (gi == 0 || gi == nx - 2) {
-                        qd = make_float4(s1, s2 - s1, 0.f, 0.f);
-                    } else {
-                        float c2 = 0.5f * (Sv + s2) - s1;
-                        float c3 = (s3 - Sv) * (1.0f / 6.0f) + 0.5f * (s1 - s2);
-                        qd = make_float4(s1, s2 - s1 - c2 - c3, c2, c3);
-                    }
-                }
-                Qw[lane] = qd;
-                wave_sync();
-#pragma unroll
-                for (int m = 0; m < EPL; ++m) {
-                    const float t = pfr + tbr[m];
-                    const int il = (int)t;
-                    const float f = t - (float)il;
-                    const float4 q = Qw[il];
-                    acc[m] += q.x + f * (q.y + f * (q.z + f * q.w));
-                }
-                wave_sync();
-            }
+            if (g.interior)
+                pairs_interior<EPL>(mask, w0, w1, w2, w3, fr, (I0 << 8) | m0, lane, tab, W, xw0, Sw, Qw, tbr, acc);
+            else
+                pairs_general<EPL>(mask, w0, w1, w2, w3, fr, I0, m0, lane, tab, W, xw0, xw, nx, Sw, Qw, tbr, acc);
         }
         const double scale = g.w_cell * g.T * g.T * g.T;
         float *out = partial + (((size_t)b * S.R_tot + r) * P + k) * E;
@@ -878,11 +931,11 @@ __global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const RingRec *ri
 // k_accum_bb: FP64 shift-and-add with the isotropic blackbody of App. C
 // ---------------------------------------------------------------------------
 template <int EPL>
-__global__ __launch_bounds__(256) void k_accum_bb(DevSpec S, const RingRec *rings, const double4 *trace,
+__global__ __launch_bounds__(256) void k_accum_bb(DevSpec S, const int32_t *list, const RingRec *rings, const double4 *trace,
                                                   double *partial, int32_t *vis_pairs, int PT)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int r = blockIdx.y, b = blockIdx.z;
+    const int ent = list[blockIdx.y], b = ent / S.R_tot, r = ent - b * S.R_tot;
     const RingRec g = rings[(size_t)b * S.R_tot + r];
     if (!g.active) return;
     const int nfp = S.n_fp, E = S.E, P = S.P;
@@ -1096,51 +1149,51 @@ size_t accum_table_lds(const DevSpec &S)
 }
 
 hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *params,
-                          const int32_t *ncells_dev, int B, hipStream_t st, double *flux_out,
-                          double *counts_out, hipEvent_t ev_hot0, hipEvent_t ev_hot1)
+                          const int32_t *ncells_dev, int B, const int32_t *list, int n_list, hipStream_t st,
+                          double *flux_out, double *counts_out, hipEvent_t ev_hot0, hipEvent_t ev_hot1)
 {
     const bool want_flux_f64 = flux_out != nullptr;
     hipLaunchKernelGGL(k_setup, dim3((S.R_tot + 63) / 64, B), dim3(64), 0, st, S, params, ncells_dev, W.stars,
                        W.rings);
-    hipLaunchKernelGGL(k_table, dim3(S.R_tot, B), dim3(256), 0, st, S, W.stars, W.rings, W.table);
+    hipLaunchKernelGGL(k_table, dim3(n_list), dim3(256), 0, st, S, list, W.stars, W.rings, W.table);
     size_t lds_tr = sizeof(double4) * (S.n_alpha + S.n_fp + 1);
-    hipLaunchKernelGGL(k_trace, dim3(S.R_tot, B), dim3(256), lds_tr, st, S, W.stars, W.rings, W.table,
+    hipLaunchKernelGGL(k_trace, dim3(n_list), dim3(256), lds_tr, st, S, list, W.stars, W.rings, W.table,
                        W.trace);
     {
         size_t n = (size_t)B * S.R_tot;
         hipLaunchKernelGGL(k_zero_i32, dim3((n + 255) / 256), dim3(256), 0, st, W.vis_pairs, n);
     }
     const int PT = 16;
-    dim3 grid((S.P + PT - 1) / PT, S.R_tot, B);
+    dim3 grid((S.P + PT - 1) / PT, n_list);
     if (S.intensity == PPM_I_TABLE) {
-        hipLaunchKernelGGL(k_subtable, dim3(S.R_tot, B), dim3(256), 0, st, S, W.rings, W.sub);
+        hipLaunchKernelGGL(k_subtable, dim3(n_list), dim3(256), 0, st, S, list, W.rings, W.sub);
         size_t lds = accum_table_lds(S);
         if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
         int epl = (S.E + 63) / 64;
         if (S.fast) {
             if (epl <= 1)
-                hipLaunchKernelGGL(k_accum_fast<1>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+                hipLaunchKernelGGL(k_accum_fast<1>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
                                    W.partial32, W.vis_pairs, PT);
             else if (epl <= 2)
-                hipLaunchKernelGGL(k_accum_fast<2>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+                hipLaunchKernelGGL(k_accum_fast<2>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
                                    W.partial32, W.vis_pairs, PT);
             else if (epl <= 4)
-                hipLaunchKernelGGL(k_accum_fast<4>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+                hipLaunchKernelGGL(k_accum_fast<4>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
                                    W.partial32, W.vis_pairs, PT);
             else
-                hipLaunchKernelGGL(k_accum_fast<8>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+                hipLaunchKernelGGL(k_accum_fast<8>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
                                    W.partial32, W.vis_pairs, PT);
         } else if (epl <= 1)
-            hipLaunchKernelGGL(k_accum_table<1>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+            hipLaunchKernelGGL(k_accum_table<1>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
                                W.partial32, W.vis_pairs, PT);
         else if (epl <= 2)
-            hipLaunchKernelGGL(k_accum_table<2>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+            hipLaunchKernelGGL(k_accum_table<2>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
                                W.partial32, W.vis_pairs, PT);
         else if (epl <= 4)
-            hipLaunchKernelGGL(k_accum_table<4>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+            hipLaunchKernelGGL(k_accum_table<4>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
                                W.partial32, W.vis_pairs, PT);
         else
-            hipLaunchKernelGGL(k_accum_table<8>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.sub,
+            hipLaunchKernelGGL(k_accum_table<8>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
                                W.partial32, W.vis_pairs, PT);
         if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
         hipLaunchKernelGGL((k_reduce<float, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S, W.stars, W.rings,
@@ -1152,16 +1205,16 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
         int epl = (S.E + 63) / 64;
         if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
         if (epl <= 1)
-            hipLaunchKernelGGL(k_accum_bb<1>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.partial64,
+            hipLaunchKernelGGL(k_accum_bb<1>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.partial64,
                                W.vis_pairs, PT);
         else if (epl <= 2)
-            hipLaunchKernelGGL(k_accum_bb<2>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.partial64,
+            hipLaunchKernelGGL(k_accum_bb<2>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.partial64,
                                W.vis_pairs, PT);
         else if (epl <= 4)
-            hipLaunchKernelGGL(k_accum_bb<4>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.partial64,
+            hipLaunchKernelGGL(k_accum_bb<4>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.partial64,
                                W.vis_pairs, PT);
         else
-            hipLaunchKernelGGL(k_accum_bb<8>, grid, dim3(256), lds, st, S, W.rings, W.trace, W.partial64,
+            hipLaunchKernelGGL(k_accum_bb<8>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.partial64,
                                W.vis_pairs, PT);
         if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
         if (S.rsp64) {

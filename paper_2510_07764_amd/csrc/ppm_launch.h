@@ -28,8 +28,9 @@ struct Workspace {
 __host__ __device__ int validate_params(const double *p, int n_spots);
 
 hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *params,
-                          const int32_t *ncells_dev, int B, hipStream_t st, double *flux_out,
-                          double *counts_out, hipEvent_t ev_hot0 = nullptr, hipEvent_t ev_hot1 = nullptr);
+                          const int32_t *ncells_dev, int B, const int32_t *list, int n_list, hipStream_t st,
+                          double *flux_out, double *counts_out, hipEvent_t ev_hot0 = nullptr,
+                          hipEvent_t ev_hot1 = nullptr);
 hipError_t launch_loglike(const Workspace &W, const double *counts, int B, int PC, const int32_t *data,
                           double *logl, hipStream_t st);
 hipError_t launch_status(const Workspace &W, int B, int32_t *out, hipStream_t st);

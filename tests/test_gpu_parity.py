@@ -215,3 +215,60 @@ def test_hidden_spot_and_partial_visibility(torch_dev):
     assert (ft[:, 10] < 1e-3 * ft[:, 10].max()).any()
     got, _, _ = gpu_run(torch_dev, s1, q)
     assert rel_err(got[0], cnt)[0] < TOL
+
+
+def test_uneven_batch_multi_pass(torch_dev):
+    """Sampler-like draws with per-instance spot grids of different sizes in
+    one call, split over several workspace passes; each instance against the
+    oracle at its own resolution, and the batch against single calls."""
+    import subprocess
+    import sys
+    code = r'''
+import os, sys, json
+sys.path.insert(0, os.getcwd())
+import numpy as np, torch
+import oracle, synthetic as syn, paper_2510_07764_amd as ppm
+draws, _ = syn.config3_draws(5)
+res = [8, 24, 16, 32, 8]
+spec, _ = syn.config1(n_cells=8, n_phase=32, n_energy=64)
+plan = ppm.Plan(spec, max_batch=5, max_cells=32)
+pt = torch.tensor(draws, dtype=torch.float64, device="cuda")
+got = plan.forward(pt, n_cells=res).cpu().numpy()
+again = plan.forward(pt, n_cells=res).cpu().numpy()
+errs = []
+for i in range(5):
+    s, _ = syn.config1(n_cells=res[i], n_phase=32, n_energy=64)
+    _, cnt, _ = oracle.forward(s, draws[i])
+    sel = cnt >= 1e-6 * cnt.max()
+    errs.append(float(np.max(np.abs(got[i][sel] - cnt[sel]) / cnt[sel])) if sel.any() else 0.0)
+one = plan.forward(pt[3:4].contiguous(), n_cells=[res[3]]).cpu().numpy()
+print(json.dumps({"errs": errs, "same": bool(np.array_equal(got, again)), "single": bool(np.array_equal(one[0], got[3]))}))
+'''
+    env = dict(os.environ, PPM_MAX_CHUNK="2")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         cwd=os.path.dirname(HERE), timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    res = json.loads(out.stdout.strip().splitlines()[-1])
+    print("uneven batch, 3 passes:", res)
+    assert max(res["errs"]) < TOL
+    assert res["same"] and res["single"]
+
+
+def test_graph_replays_match_eager(torch_dev):
+    """Captured evaluation replayed several times with eager work and host
+    synchronisation in between; every replay equals the eager result."""
+    import paper_2510_07764_amd as ppm
+    torch, dev = torch_dev
+    spec, p = syn.config1(n_cells=16, n_phase=32, n_energy=64)
+    _, cnt, _ = oracle.forward(spec, p)
+    data = torch.tensor(syn.poisson_data(cnt), device=dev)
+    draws = syn.config4_draws(6)
+    plan = ppm.Plan(spec, max_batch=3)
+    gl = ppm.GraphedLogLike(plan, data, 3)
+    for rep in range(4):
+        rows = torch.tensor(draws[rep % 2 * 3:rep % 2 * 3 + 3], dtype=torch.float64, device=dev)
+        g = gl(rows).clone()
+        torch.cuda.synchronize()
+        eager = plan.loglike(rows, data)
+        torch.cuda.synchronize()
+        assert torch.equal(g, eager), (rep, g, eager)
