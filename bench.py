@@ -155,7 +155,7 @@ def main():
         "grad": None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "k_accum_table", "kernel_ms": hot_avg_s * 1e3, "units": units,
+                     "kernel": "k_accum_fast<4>", "kernel_ms": hot_avg_s * 1e3, "units": units,
                      "flop_per_unit": FLOP_PER_UNIT},
         "cpu_baseline": cpu,
     }
