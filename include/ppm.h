@@ -76,6 +76,8 @@ enum ppm_precision { PPM_F32 = 0, PPM_F64 = 1 };
  *  n_alpha     nodes of the per-ring FP64 deflection table (>= 64)
  *  precision   PPM_F32: FP32 bulk intensity/accumulate, MFMA FP32 fold;
  *              PPM_F64: FP64 throughout (blackbody model only)
+ *  grad        1: also allocate what ppm_loglike_grad needs (atmosphere-table
+ *              model with the windowed accumulation only); 0: forward only
  */
 typedef struct {
     int32_t mode, intensity, n_spots;
@@ -91,6 +93,7 @@ typedef struct {
     const double *log_intensity;
     int32_t n_alpha;
     int32_t precision;
+    int32_t grad;
 } ppm_spec;
 
 typedef struct ppm_plan ppm_plan;
@@ -122,6 +125,22 @@ int ppm_flux(ppm_plan *plan, const double *params_dev, int B, const int32_t *n_c
  * An instance with a nonzero status gets logL = -inf. */
 int ppm_loglike(ppm_plan *plan, const double *params_dev, int B, const int32_t *n_cells_host,
                 const int32_t *data_dev, double *logl_dev, double *counts_dev, void *stream);
+
+/* Poisson log-likelihood and its gradient with respect to the twelve
+ * differentiable parameters, in the order M, R_e, i, Phi, N_H, theta_1,
+ * zeta_1, logT_1, theta_2, zeta_2, logT_2, dphi_2 (units of the parameter
+ * record): logl_dev[B], grad_dev[B][12] (double, device).  The gradient is
+ * the derivative of the discrete model of Sects. 2.3-2.8 as evaluated by
+ * ppm_loglike (held fixed: interpolation stencils, visibility ranges, clamps,
+ * table node positions in alpha; crescent masks are not differentiated).
+ * Reverse mode through Eqs. (22), (55) and the likelihood, reverse mode over
+ * energies of Eq. (47), forward-mode tangents of the ring geometry, the
+ * deflection table and the fine-phase trace.  An instance with a nonzero
+ * status gets logL = -inf and a NaN gradient.  Needs a plan created with
+ * spec->grad = 1 (PPM_ERR_UNSUPPORTED otherwise).  Other arguments as
+ * ppm_loglike. */
+int ppm_loglike_grad(ppm_plan *plan, const double *params_dev, int B, const int32_t *n_cells_host,
+                     const int32_t *data_dev, double *logl_dev, double *grad_dev, void *stream);
 
 /* Per-instance status codes of the last evaluation: status_dev[B] (device). */
 int ppm_instance_status(ppm_plan *plan, int B, int32_t *status_dev, void *stream);

@@ -42,7 +42,7 @@ class _Spec(C.Structure):
                 ("ax_T", C.POINTER(C.c_double)), ("ax_g", C.POINTER(C.c_double)),
                 ("ax_mu", C.POINTER(C.c_double)), ("ax_x", C.POINTER(C.c_double)),
                 ("log_intensity", C.POINTER(C.c_double)),
-                ("n_alpha", C.c_int32), ("precision", C.c_int32)]
+                ("n_alpha", C.c_int32), ("precision", C.c_int32), ("grad", C.c_int32)]
 
 
 _VP = C.c_void_p
@@ -56,6 +56,7 @@ SIGNATURES = {
     "ppm_forward": (C.c_int, [_VP, _VP, C.c_int, _I32P, _VP, _VP]),
     "ppm_flux": (C.c_int, [_VP, _VP, C.c_int, _I32P, _VP, _VP]),
     "ppm_loglike": (C.c_int, [_VP, _VP, C.c_int, _I32P, _VP, _VP, _VP, _VP]),
+    "ppm_loglike_grad": (C.c_int, [_VP, _VP, C.c_int, _I32P, _VP, _VP, _VP, _VP]),
     "ppm_instance_status": (C.c_int, [_VP, C.c_int, _VP, _VP]),
     "ppm_validate_params": (C.c_int, [_DP, C.c_int, C.c_int, _I32P]),
     "ppm_debug_ring": (C.c_int, [_VP, C.c_int, C.c_int, _DP, _DP, _DP, _I32P, _VP]),
@@ -113,7 +114,8 @@ def _dptr(t):
 class Plan:
     """A plan for one model spec (a dict as built by ``synthetic.config*``)."""
 
-    def __init__(self, spec: dict, max_batch: int = 1, max_cells: int = 0, n_alpha: int | None = None):
+    def __init__(self, spec: dict, max_batch: int = 1, max_cells: int = 0, n_alpha: int | None = None,
+                 grad: bool = False):
         self.keep = []
 
         def arr(x):
@@ -151,6 +153,7 @@ class Plan:
             s.log_intensity = arr(logi)
         s.n_alpha = n_alpha if n_alpha is not None else spec.get("n_alpha", 512)
         s.precision = F64 if spec.get("precision", "f32") == "f64" else F32
+        s.grad = 1 if grad else 0
         self.spec = spec
         self.n_phase = s.n_phase
         self.n_energy = s.n_energy
@@ -224,6 +227,23 @@ class Plan:
                                  _stream_handle(stream)), "ppm_loglike")
         return out
 
+    def loglike_grad(self, params, data, n_cells=None, out=None, grad=None, stream=None):
+        """(logL[B], grad[B, 12]) float64 on the device; gradient order M, R_e,
+        i, Phi, N_H, theta_1, zeta_1, logT_1, theta_2, zeta_2, logT_2, dphi_2.
+        Needs a plan created with grad=True."""
+        import torch
+        B = self._params(params)
+        assert data.is_cuda and data.dtype == torch.int32 and data.is_contiguous()
+        assert data.numel() == self.n_phase * self.n_chan
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=params.device)
+        if grad is None:
+            grad = torch.empty((B, NGRAD), dtype=torch.float64, device=params.device)
+        keep, nc = self._ncells(n_cells, B)
+        _check(lib().ppm_loglike_grad(self.handle, _dptr(params), B, nc, _dptr(data), _dptr(out), _dptr(grad),
+                                      _stream_handle(stream)), "ppm_loglike_grad")
+        return out, grad
+
     def status(self, B, stream=None):
         import torch
         out = torch.empty(B, dtype=torch.int32, device="cuda")
@@ -258,18 +278,22 @@ class Plan:
 
 
 class GraphedLogLike:
-    """One likelihood evaluation of B parameter vectors captured as a HIP
-    graph (through torch.cuda.CUDAGraph) and replayed per call: the whole
-    launch sequence of the evaluation is submitted at once.  ``__call__``
-    copies the parameters into the captured input buffer, replays, and
-    returns the captured output tensor (overwritten by the next call)."""
+    """One likelihood evaluation of B parameter vectors (with the gradient
+    when ``grad=True``; the plan must then have been created with
+    ``grad=True``) captured as a HIP graph (through torch.cuda.CUDAGraph) and
+    replayed per call: the whole launch sequence of the evaluation is
+    submitted at once.  ``__call__`` copies the parameters into the captured
+    input buffer, replays, and returns the captured output tensor(s)
+    (overwritten by the next call): logL[B], or (logL[B], grad[B, 12])."""
 
-    def __init__(self, plan: Plan, data, B: int, n_cells=None):
+    def __init__(self, plan: Plan, data, B: int, n_cells=None, grad: bool = False):
         import torch
         self.plan = plan
+        self.with_grad = grad
         dev = data.device
         self.params = torch.zeros((B, NPARAM), dtype=torch.float64, device=dev)
         self.out = torch.empty(B, dtype=torch.float64, device=dev)
+        self.grad = torch.empty((B, NGRAD), dtype=torch.float64, device=dev) if grad else None
         self.data = data
         self.n_cells = None if n_cells is None else np.ascontiguousarray(n_cells, dtype=np.int32)
         # a valid parameter set for the warm-up (the graph records launches only)
@@ -280,14 +304,60 @@ class GraphedLogLike:
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
-            plan.loglike(self.params, data, n_cells=self.n_cells, out=self.out)
+            self._launch()
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            plan.loglike(self.params, data, n_cells=self.n_cells, out=self.out)
+            self._launch()
+
+    def _launch(self):
+        if self.with_grad:
+            self.plan.loglike_grad(self.params, self.data, n_cells=self.n_cells, out=self.out, grad=self.grad)
+        else:
+            self.plan.loglike(self.params, self.data, n_cells=self.n_cells, out=self.out)
 
     def __call__(self, params):
         self.params.copy_(params)
         self.graph.replay()
-        return self.out
+        return (self.out, self.grad) if self.with_grad else self.out
+
+
+def _autograd_function():
+    import torch
+
+    class PPMLogLike(torch.autograd.Function):
+        """logL[B] of parameter vectors [B, 16] with the library's hand-written
+        adjoint as backward: d logL / d params is zero in the slots that are
+        not differentiable (nu, D, unused)."""
+
+        @staticmethod
+        def forward(ctx, params, plan, data, n_cells=None):
+            p = params.detach().contiguous()
+            if not ctx.needs_input_grad[0]:
+                return plan.loglike(p, data, n_cells=n_cells)
+            ll, g = plan.loglike_grad(p, data, n_cells=n_cells)
+            full = torch.zeros_like(p)
+            full[:, list(GRAD_SLOTS)] = g
+            ctx.save_for_backward(full)
+            return ll
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (full,) = ctx.saved_tensors
+            return grad_out[:, None] * full, None, None, None
+
+    return PPMLogLike
+
+
+def loglike_autograd(params, plan: Plan, data, n_cells=None):
+    """Differentiable logL[B]: ``loglike_autograd(p, plan, data).sum().backward()``
+    fills ``p.grad`` through the adjoint kernels (one forward+adjoint launch
+    sequence per call)."""
+    global PPMLogLike
+    if PPMLogLike is None:
+        PPMLogLike = _autograd_function()
+    return PPMLogLike.apply(params, plan, data, n_cells)
+
+
+PPMLogLike = None

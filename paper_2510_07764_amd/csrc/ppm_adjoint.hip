@@ -1,0 +1,769 @@
+// gfx950 kernels of the gradient of the Poisson log-likelihood with respect
+// to the twelve model parameters (M, R_e, i, Phi, N_H and per spot theta,
+// zeta, logT, plus spot 2's longitude offset).
+//
+// The gradient is the exact derivative of the discrete model the forward
+// kernels evaluate (almost everywhere: interpolation stencils, visibility
+// ranges and clamps are held fixed; node positions of the per-ring
+// deflection table are held fixed in alpha).  It is assembled in three
+// modes:
+//   reverse  likelihood, response fold and absorption (Eqs. 22, 55):
+//            g_m = d/m - 1, G[k][e] = (T_exp/P) sum_c g_m[k][c] RSP[e][c],
+//            the flux adjoint G exp(-N_H sigma_e), and the N_H derivative;
+//   reverse  over energies inside the accumulation (Eq. 47): per (cell,
+//            phase) pair the five sums over e of G/E times I, dI/dx, dI/dmu,
+//            dI/dlogT, dI/dlog g of the mixed-order interpolant (Sect. 4);
+//   forward  dual-number tangents of the ring geometry (Eqs. 2-11, 18),
+//            the deflection table (d/du at fixed alpha of Eqs. 14, 16, 17,
+//            32, 35) and the fine-phase trace (Eqs. 38-44) along the five
+//            geometric directions of a ring, contracted with the per-pair
+//            sums in FP64.
+// Section and equation numbers refer to arXiv:2510.07764.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ppm_internal.h"
+#include "ppm_device.h"
+#include "ppm_launch.h"
+#include "../../include/ppm.h"
+
+namespace ppm {
+
+using D1 = Dual<1>;
+using D5 = Dual<5>;
+
+constexpr double kLn10 = 2.302585092994045684;
+
+// ---------------------------------------------------------------------------
+// k_fold_bwd: reverse mode through the likelihood, fold and absorption.
+// Block = (phase k, instance b); thread = energy.  FP64 throughout; the flux
+// adjoint divided by E is stored in FP32 for the accumulation kernel.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fold_bwd(DevSpec S, const StarRec *stars, const double *counts,
+                                                  const int32_t *data, const double *flux, float *gtil,
+                                                  double *nh_part)
+{
+    extern __shared__ double gm[];   // [C]
+    __shared__ double red[256];
+    const int k = blockIdx.x, b = blockIdx.y, P = S.P, C = S.C, E = S.E;
+    const double *m = counts + ((size_t)b * P + k) * C;
+    const int32_t *d = data + (size_t)k * C;
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        const int dc = d[c];
+        gm[c] = dc == 0 ? -1.0 : dc / m[c] - 1.0;     // d/dm of d ln m - m
+    }
+    __syncthreads();
+    const StarRec st = stars[b];
+    const double scale = S.t_exp / P;
+    double nh = 0.0;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+        double acc = 0.0;
+        for (int c = 0; c < C; ++c) acc = fma(gm[c], S.rspT64[(size_t)c * E + e], acc);
+        const double Gp = acc * scale;                 // adjoint of the absorbed flux
+        const double att = S.sigma ? exp(-st.NH * S.sigma[e]) : 1.0;
+        const size_t o = ((size_t)b * P + k) * E + e;
+        gtil[o] = (float)(Gp * att / S.energy[e]);
+        if (S.sigma) nh -= Gp * flux[o] * att * S.sigma[e] * 1e20;   // N_H in units of 1e20 cm^-2
+    }
+    red[threadIdx.x] = nh;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) nh_part[(size_t)b * P + k] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// k_table_u: d/du at fixed alpha of the per-ring table entries (psi, psi',
+// c dt/R, its alpha derivative), by a dual number in u carried through the
+// same quadrature as the forward table.  The oblate radial delay terms are
+// written with kappa = R_e/R(theta) held fixed: their kappa derivative,
+// 1 + u/(kappa - u), is the same on both branches and independent of alpha.
+// ---------------------------------------------------------------------------
+__device__ inline D1 acos_capped(const D1 &a)
+{
+    return a.v >= 1.0 ? D1(0.0) : acos(a);
+}
+
+__global__ void k_table_u(DevSpec S, const int32_t *list, const StarRec *stars, const RingRec *rings,
+                          double4 *table_u)
+{
+    const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
+    const RingRec g = rings[(size_t)b * S.R_tot + r];
+    if (!g.active) return;
+    const StarRec st = stars[b];
+    const D1 u = D1::seed(g.u, 0);
+    const double kap = st.Re / g.R;
+    const D1 sq = sqrt(1.0 - u);
+    const D1 cdt_obl = kap - 1.0 + u * log((kap - u) / (1.0 - u));   // Eq. (16) over R
+    const double dal = g.alpha_max / (S.n_alpha - 1);
+    double4 *tab = table_u + ((size_t)b * S.R_tot + r) * S.n_alpha;
+    for (int j = threadIdx.x; j < S.n_alpha; j += blockDim.x) {
+        double a = dal * j;
+        if (j == S.n_alpha - 1) a = g.alpha_max;
+        D1 psi, dpsi, T, dT;
+        if (a <= kHalfPi) {
+            D1 tp;
+            bend_out(S, u, a, psi, dpsi, tp);
+            T = tp + cdt_obl;
+            dT = dpsi * sin(a) / sq;
+        } else {
+            const double be = kPi - a;
+            D1 psb, dpsb, tpb;
+            bend_out(S, u, be, psb, dpsb, tpb);
+            const double sa = sin(a), ca = cos(a);
+            D1 kk = sqrt(3.0 * (1.0 - u));
+            D1 arg = 3.0 * u * kk / (2.0 * sa);
+            if (arg.v > 1.0) arg = D1(1.0);
+            D1 rho = -2.0 * sa / kk * cos((acos_capped(arg) + kTwoPi) / 3.0);   // Eq. (14)
+            D1 k = sa * sa / (1.0 - u), kp = 2.0 * sa * ca / (1.0 - u);
+            D1 rhop = kp * (rho - u) / (3.0 * rho * rho - k);
+            D1 v = u / rho, vp = -u * rhop / (rho * rho);
+            D1 ph, dph, th, dth;
+            grazing(S, v, ph, dph, th, dth);
+            psi = 2.0 * ph - psb;
+            dpsi = 2.0 * dph * vp + dpsb;
+            D1 cdtp = kap - rho + u * log((kap - u) / (rho - u));
+            T = 2.0 * rho * th - tpb + 2.0 * cdtp - cdt_obl;             // Eq. (17)
+            D1 dtpb = dpsb * sin(be) / sq;
+            dT = 2.0 * rhop * th + 2.0 * rho * dth * vp + dtpb - 2.0 * rhop * rho / (rho - u);
+        }
+        tab[j] = make_double4(psi.d[0], dpsi.d[0], T.d[0], dT.d[0]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_trace_tan: tangents of the fine-phase trace (F, z, phi_o, mu) of one ring
+// along its five geometric directions, and the ring-level tangents.  Thread
+// 0 redoes the ring setup of Eqs. (2)-(11), (18) and the spot grid in dual
+// numbers; every thread then redoes the visible samples of Eqs. (38)-(40)
+// with the table lookup differentiated through its node values (psi_j,
+// psi'_j, T_j, T'_j move with u and kappa).  Visibility and the invisible
+// range come from the forward trace; the fill of Eqs. (41)-(44) is linear
+// in its end samples and so are its tangents.
+// ---------------------------------------------------------------------------
+struct RingDualRaw {   // plain storage of dual numbers in shared memory
+    double sth[6], cth[6], u[6], sq1u[6], kap[6], R[6], coseta[6], sineta[6], beta[6], gamma[6], si[6], ci[6];
+};
+
+__device__ inline void put(double *dst, const D5 &x)
+{
+    dst[0] = x.v;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) dst[1 + i] = x.d[i];
+}
+
+__device__ inline D5 get(const double *src)
+{
+    D5 x(src[0]);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) x.d[i] = src[1 + i];
+    return x;
+}
+
+// node value with its tangent: v + du * u' + dk * kappa'
+__device__ inline D5 node(double v, double du, const D5 &u, double dk, const D5 &kap)
+{
+    D5 x(v);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) x.d[i] = du * u.d[i] + dk * kap.d[i];
+    return x;
+}
+
+__global__ void k_trace_tan(DevSpec S, const int32_t *list, const double *params, const int32_t *n_cells,
+                            const StarRec *stars, const RingRec *rings, const double4 *table,
+                            const double4 *table_u, const double4 *trace, double4 *tangent, RingTan *ringtan)
+{
+    extern __shared__ double4 lds4[];
+    const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
+    const size_t slot = (size_t)b * S.R_tot + r;
+    const RingRec g = rings[slot];
+    if (!g.active) return;
+    const int na = S.n_alpha, nfp = S.n_fp;
+    double4 *tab = lds4;               // na
+    double4 *tabu = tab + na;          // na
+    double4 *tg = tabu + na;           // (nfp + 1) * 5
+    __shared__ RingDualRaw rd;
+    for (int j = threadIdx.x; j < na; j += blockDim.x) {
+        tab[j] = table[slot * na + j];
+        tabu[j] = table_u[slot * na + j];
+    }
+    if (threadIdx.x == 0) {
+        const double *p = params + (size_t)b * PPM_NPARAM;
+        const int spot = g.spot;
+        const int lr = spot == 0 ? r : r - S.rings_max[0];
+        const int ov = n_cells ? n_cells[b] : 0;
+        const int nr = ov > 0 ? ov : S.n_rings_spec[spot];
+        const int np = ov > 0 ? ov : S.n_phi_spec[spot];
+        const D5 M = D5::seed(p[0], 0), Re = D5::seed(p[1] * 1e5, 1, 1e5), inc = D5::seed(p[2], 2);
+        const D5 tc = D5::seed(p[8 + 4 * spot], 3), z = D5::seed(p[9 + 4 * spot], 4);
+        const double nu = p[5], Dd = p[6] * kPc;
+        D5 GM = M * kGMsun;
+        D5 Rs = 2.0 * GM / (kC * kC);
+        D5 x = GM / (kC * kC * Re);
+        D5 Obar = kTwoPi * nu * sqrt(Re * Re * Re / GM);
+        D5 o2 = (S.mode == PPM_MODE_OS) ? Obar * Obar * (-0.788 + 1.030 * x) : D5(0.0);   // Eq. (7)
+        D5 g0 = GM / (Re * Re) / sqrt(1.0 - Rs / Re);
+        D5 lo = fmax(D5(0.0), tc - z), hi = fmin(D5(kPi), tc + z);
+        D5 e0 = lo + (hi - lo) * (double)lr / (double)nr, e1 = lo + (hi - lo) * (double)(lr + 1) / (double)nr;
+        D5 th = 0.5 * (e0 + e1);
+        D5 dcos = cos(e0) - cos(e1);
+        D5 ct = cos(th), sn = sin(th);
+        D5 R = Re * (1.0 + o2 * ct * ct);
+        D5 dR = -2.0 * Re * o2 * ct * sn;
+        D5 u = Rs / R;
+        D5 sq1u = sqrt(1.0 - u);
+        D5 f = dR / (R * sq1u);                                       // Eq. (2)
+        D5 coseta = 1.0 / sqrt(1.0 + f * f), sineta = f / sqrt(1.0 + f * f);
+        D5 logg = log10(g0 * gravity_ratio_t(S.mode, x, Obar, th));   // Eqs. (10), (11)
+        D5 beta = kTwoPi * nu * R * sn / (kC * sq1u);                  // Eq. (18)
+        D5 gamma = 1.0 / sqrt(1.0 - beta * beta);
+        D5 dout = arc_halfwidth(th, tc, z), din(0.0), dcell;
+        if (g.shape == PPM_SHAPE_ANNULUS) {
+            din = arc_halfwidth(th, tc, S.shape_a[spot] * z);
+            dcell = (dout - din) / (0.5 * np);
+        } else {
+            dcell = 2.0 * dout / (double)np;
+        }
+        D5 w = R * R * sqrt(1.0 + f * f) * dcos * dcell / (Dd * Dd);  // Eq. (9)
+        RingTan rt;
+        for (int i = 0; i < 5; ++i) {
+            rt.dlogg[i] = logg.d[i];
+            rt.dw[i] = w.d[i];
+            rt.ddout[i] = dout.d[i];
+            rt.ddin[i] = din.d[i];
+        }
+        ringtan[slot] = rt;
+        put(rd.sth, sn); put(rd.cth, ct); put(rd.u, u); put(rd.sq1u, sq1u); put(rd.kap, Re / R); put(rd.R, R);
+        put(rd.coseta, coseta); put(rd.sineta, sineta); put(rd.beta, beta); put(rd.gamma, gamma);
+        put(rd.si, sin(inc)); put(rd.ci, cos(inc));
+    }
+    __syncthreads();
+    const D5 sth = get(rd.sth), cth = get(rd.cth), u = get(rd.u), sq1u = get(rd.sq1u), kap = get(rd.kap);
+    const D5 Rr = get(rd.R), coseta = get(rd.coseta), sineta = get(rd.sineta), beta = get(rd.beta);
+    const D5 gamma = get(rd.gamma), si = get(rd.si), ci = get(rd.ci);
+    const double nu = params[(size_t)b * PPM_NPARAM + 5];
+    const double Xk = 1.0 + g.u / (kap.v - g.u);     // d(c dt/R)/d kappa, both branches
+    const double dal = g.alpha_max / (na - 1);
+    const double psi_top = tab[na - 1].x;
+    const int a0 = g.inv_min, a1 = g.inv_max;
+    for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
+        double4 out[5];
+        for (int d = 0; d < 5; ++d) out[d] = make_double4(0.0, 0.0, 0.0, 0.0);
+        const bool vis = i < a0 || i > a1;
+        if (vis) {
+            const double phi = kTwoPi * i / nfp;
+            double sphi, cphi;
+            sincos(phi, &sphi, &cphi);
+            D5 cpsi = si * sth * cphi + ci * cth;                      // Table 2
+            if (cpsi.v > 1.0) cpsi = D5(1.0);
+            if (cpsi.v < -1.0) cpsi = D5(-1.0);
+            const double spsi = ::sqrt(fmax(0.0, 1.0 - cpsi.v * cpsi.v));
+            D5 psi = spsi > 1e-7 ? acos(cpsi) : D5(::acos(cpsi.v));
+            D5 a, sr, lf;
+            if (psi.v < 1e-7) {
+                a = psi * sq1u;
+                sr = sq1u;
+                lf = 1.0 - u;
+            } else {
+                int lo = 0, hi = na - 1;
+                while (hi - lo > 1) {
+                    int mid = (lo + hi) >> 1;
+                    if (tab[mid].x <= psi.v) lo = mid; else hi = mid;
+                }
+                (void)psi_top;
+                const D5 p0 = node(tab[lo].x, tabu[lo].x, u, 0.0, kap);
+                const D5 p1 = node(tab[lo + 1].x, tabu[lo + 1].x, u, 0.0, kap);
+                const D5 m0 = 1.0 / node(tab[lo].y, tabu[lo].y, u, 0.0, kap);
+                const D5 m1 = 1.0 / node(tab[lo + 1].y, tabu[lo + 1].y, u, 0.0, kap);
+                const D5 h = p1 - p0;
+                const D5 t = (psi - p0) / h;
+                const double al0 = dal * lo;
+                const double al1 = (lo + 1 == na - 1) ? g.alpha_max : dal * (lo + 1);
+                D5 h00, h10, h01, h11, d00, d10, d01, d11;
+                hermite(t, h00, h10, h01, h11);
+                dhermite(t, d00, d10, d01, d11);
+                a = h00 * al0 + h10 * h * m0 + h01 * al1 + h11 * h * m1;
+                D5 dadpsi = (d00 * al0 + d10 * h * m0 + d01 * al1 + d11 * h * m1) / h;
+                sr = sin(a) / sin(psi);
+                lf = sr * dadpsi;
+            }
+            D5 ca = cos(a);
+            D5 cs = ca * coseta + sr * sineta * (ci * sth - si * cth * cphi);   // Eq. (4)
+            D5 cxi = -sr * si * sphi;
+            D5 delta = 1.0 / (gamma * (1.0 - beta * cxi));                     // Eq. (19)
+            D5 mu = delta * cs;                                                // Eq. (20)
+            D5 F = sq1u * delta * delta * delta * mu * lf * gamma;             // Eq. (40)
+            D5 zz = 1.0 / (delta * sq1u);
+            int jj = (int)floor(a.v / dal);
+            jj = jj < 0 ? 0 : (jj > na - 2 ? na - 2 : jj);
+            D5 ta = (a - dal * jj) / dal;
+            D5 h00, h10, h01, h11;
+            hermite(ta, h00, h10, h01, h11);
+            const D5 T0 = node(tab[jj].z, tabu[jj].z, u, Xk, kap), T1 = node(tab[jj + 1].z, tabu[jj + 1].z, u, Xk, kap);
+            const D5 dT0 = node(tab[jj].w, tabu[jj].w, u, 0.0, kap), dT1 = node(tab[jj + 1].w, tabu[jj + 1].w, u, 0.0, kap);
+            D5 T = h00 * T0 + h10 * dal * dT0 + h01 * T1 + h11 * dal * dT1;
+            D5 po = nu * Rr * T / kC;                                          // phi/2pi has no tangent
+            for (int d = 0; d < 5; ++d) out[d] = make_double4(F.d[d], zz.d[d], po.d[d], mu.d[d]);
+        }
+        for (int d = 0; d < 5; ++d) tg[i * 5 + d] = out[d];
+    }
+    __syncthreads();
+    if (a0 <= a1) {
+        const int ia = a0 - 1, ib = a1 + 1 > nfp ? nfp : a1 + 1;
+        for (int i = a0 + threadIdx.x; i <= a1; i += blockDim.x) {
+            const double t = (double)(i - ia) / (double)(ib - ia);
+            for (int d = 0; d < 5; ++d) {
+                const double4 va = tg[ia * 5 + d], vb = tg[ib * 5 + d];
+                tg[i * 5 + d] = make_double4(0.0, va.y + (vb.y - va.y) * t, va.z + (vb.z - va.z) * t, 0.0);
+            }
+        }
+    }
+    __syncthreads();
+    double4 *dst = tangent + slot * (size_t)(nfp + 1) * 5;
+    for (int i = threadIdx.x; i < (nfp + 1) * 5; i += blockDim.x) dst[i] = tg[i];
+}
+
+// ---------------------------------------------------------------------------
+// k_subtable_tg: logT and log g derivatives of the per-ring (logT, log g)
+// collapse (linear on both axes; zero where the ring is clamped to an edge),
+// over the same x window as the forward sub-table.
+// ---------------------------------------------------------------------------
+__global__ void k_subtable_tg(DevSpec S, const int32_t *list, const RingRec *rings, float2 *subtg)
+{
+    const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
+    const RingRec g = rings[(size_t)b * S.R_tot + r];
+    if (!g.active) return;
+    double wt1, wg1;
+    const int it = lin_bracket(g.logT, S.T0, S.hT, S.nT, wt1);
+    const int ig = lin_bracket(g.logg, S.g0, S.hg, S.ng, wg1);
+    const double tT = (g.logT - S.T0) / S.hT, tG = (g.logg - S.g0) / S.hg;
+    const float dT = (tT <= 0.0 || tT >= S.nT - 1) ? 0.0f : (float)(1.0 / S.hT);
+    const float dG = (tG <= 0.0 || tG >= S.ng - 1) ? 0.0f : (float)(1.0 / S.hg);
+    const float vt1 = (float)wt1, vg1 = (float)wg1;
+    const size_t slab = (size_t)S.nmu * S.nx;
+    const float *s00 = S.atm + ((size_t)it * S.ng + ig) * slab;
+    const float *s01 = s00 + slab;
+    const float *s10 = S.atm + ((size_t)(it + 1) * S.ng + ig) * slab;
+    const float *s11 = s10 + slab;
+    const int W = S.W_max, xw0 = g.xw0, xw = g.xw;
+    float2 *out = subtg + ((size_t)b * S.R_tot + r) * (size_t)S.sub_stride;
+    for (int i = threadIdx.x; i < S.nmu * W; i += blockDim.x) {
+        int m = i / W, c = i - m * W;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (c < xw) {
+            size_t o = (size_t)m * S.nx + xw0 + c;
+            const float a00 = s00[o], a01 = s01[o], a10 = s10[o], a11 = s11[o];
+            v.x = ((1.0f - vg1) * (a10 - a00) + vg1 * (a11 - a01)) * dT;
+            v.y = ((1.0f - vt1) * (a01 - a00) + vt1 * (a11 - a10)) * dG;
+        }
+        out[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_accum_adj: reverse mode of the windowed accumulation (Eq. 47) over
+// energies, per (cell, phase) pair, contracted with the geometry tangents.
+// Block = (ring, tile of kPhaseTile phases), 4 waves; a wave owns one phase
+// at a time.
+//  stage A  lane = cell: observed-phase lookup (Eqs. 45-46), mu weights and
+//           their mu derivatives (cubic Lagrange; linear in the protected
+//           zone and the last interval; zero derivative where mu is clamped),
+//           x position of the first energy; wave ballot of visible pairs;
+//  stage B  per visible pair: lane = x node, mu contraction of the sub-table
+//           and of its logT / log g derivatives; lane = x interval, cubic
+//           coefficients of V, dV/dmu, dV/dlogT, dV/dlog g into LDS quads;
+//           lane = EPL energies: Horner steps and the five sums
+//             S0 = sum G~ V, Sx = sum G~ dV/dt, Smu, ST, Sg
+//           with G~ = G[k][e]/E_e; wave sums, kept by the pair's lane;
+//  stage C  lane = pair, FP64: chain rule through the phase interpolation
+//           into the five geometric directions and the phase direction,
+//           plus the ring-level sums for the cell weight, log g and logT.
+// The nine per-lane FP64 sums are reduced over the block in a fixed order.
+// ---------------------------------------------------------------------------
+__device__ inline float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline float4 cubic_quad(float s0, float s1, float s2, float s3)
+{
+    const float c2 = 0.5f * (s0 + s2) - s1;
+    const float c3 = (s3 - s0) * (1.0f / 6.0f) + 0.5f * (s1 - s2);
+    return make_float4(s1, s2 - s1 - c2 - c3, c2, c3);
+}
+
+__device__ inline float horner(const float4 q, float f) { return q.x + f * (q.y + f * (q.z + f * q.w)); }
+
+// d(cell azimuth)/d(outer half-width) and d/d(inner half-width) of cell j
+__device__ inline void offset_coeffs(const RingRec &g, int j, double &ca, double &cb)
+{
+    if (g.shape == PPM_SHAPE_ANNULUS) {
+        const int h = g.n_cells / 2;
+        if (j < h) {
+            const double q = (h - 1 - j + 0.5) / h;
+            ca = -q;
+            cb = -1.0 + q;
+        } else {
+            const double q = (j - h + 0.5) / h;
+            ca = q;
+            cb = 1.0 - q;
+        }
+    } else {
+        ca = -1.0 + (2.0 * j + 1.0) / g.n_cells;
+        cb = 0.0;
+    }
+}
+
+template <int EPL>
+__global__ __launch_bounds__(256) void k_accum_adj(DevSpec S, const int32_t *list, const RingRec *rings,
+                                                   const RingTan *ringtan, const double4 *trace,
+                                                   const double4 *tangent, const float *sub, const float2 *subtg,
+                                                   const float *gtil, double *gpart)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int ent = list[blockIdx.y], b = ent / S.R_tot, r = ent - b * S.R_tot;
+    const size_t slot = (size_t)b * S.R_tot + r;
+    const RingRec g = rings[slot];
+    if (!g.active) return;
+    const int nfp = S.n_fp, nmu = S.nmu, nx = S.nx, E = S.E, P = S.P, W = S.W_max;
+    double4 *tr = (double4 *)lds_raw;                          // nfp + 1
+    double4 *tg = tr + nfp + 1;                                // (nfp + 1) * 5
+    double *axmu = (double *)(tg + (nfp + 1) * 5);             // nmu (padded to 16 bytes)
+    float *tab = (float *)(axmu + ((nmu + 1) & ~1));           // sub_stride
+    float2 *tab2 = (float2 *)(tab + S.sub_stride);             // sub_stride
+    float4 *Nb = (float4 *)(tab2 + S.sub_stride);              // 4 waves * 68 node values
+    float4 *Qb = Nb + 4 * 68;                                  // 4 waves * 4 * 64 quads
+    {
+        const double4 *gtr = trace + slot * (nfp + 1);
+        for (int i = threadIdx.x; i <= nfp; i += blockDim.x) tr[i] = gtr[i];
+        const double4 *gtg = tangent + slot * (size_t)(nfp + 1) * 5;
+        for (int i = threadIdx.x; i < (nfp + 1) * 5; i += blockDim.x) tg[i] = gtg[i];
+        for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
+        const float4 *gs = (const float4 *)(sub + slot * (size_t)S.sub_stride);
+        float4 *ts = (float4 *)tab;
+        for (int i = threadIdx.x; i < S.sub_stride / 4; i += blockDim.x) ts[i] = gs[i];
+        const float4 *gs2 = (const float4 *)(subtg + slot * (size_t)S.sub_stride);
+        float4 *ts2 = (float4 *)tab2;
+        for (int i = threadIdx.x; i < S.sub_stride / 2; i += blockDim.x) ts2[i] = gs2[i];
+    }
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float4 *Nw = Nb + wave * 68;
+    float4 *Qw = Qb + wave * 4 * 64;
+    if (lane < 4) Nw[64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const RingTan rt = ringtan[slot];
+    const double phio0 = tr[0].z;
+    const double inv2pi = 1.0 / kTwoPi;
+    const double tbk = S.tb0 - log10(g.kT) / S.hx;
+    const double ihx = 1.0 / S.hx;
+    float tbr[EPL];
+#pragma unroll
+    for (int m = 0; m < EPL; ++m) {
+        int e = lane * EPL + m;
+        tbr[m] = e < E ? (float)((log10(S.energy[e]) - log10(S.energy[0])) * ihx) : 0.0f;
+    }
+    const double mu_lo = axmu[0], mu_hi = axmu[nmu - 1];
+    const int xw0 = g.xw0, xw = g.xw;
+    double U[kGradAcc];
+#pragma unroll
+    for (int q = 0; q < kGradAcc; ++q) U[q] = 0.0;
+    const int k_begin = blockIdx.x * kPhaseTile;
+    for (int kk = wave; kk < kPhaseTile; kk += 4) {
+        const int k = k_begin + kk;
+        if (k >= P) break;
+        float Gr[EPL];
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) {
+            int e = lane * EPL + m;
+            Gr[m] = e < E ? gtil[((size_t)b * P + k) * E + e] : 0.0f;
+        }
+        const double Phik = (k + 0.5) / P;
+        for (int c0 = 0; c0 < g.n_cells; c0 += 64) {
+            // ---------------- stage A: one (cell, phase) pair per lane
+            const int j = c0 + lane;
+            bool vis = false, mu_clamped = false;
+            float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, fr = 0.f;
+            int I0 = 0, m0 = 0, lo = 0;
+            double wph = 0.0;
+            if (j < g.n_cells) {
+                const double off = cell_offset(g, j);
+                if (!cell_masked(g, off)) {
+                    double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
+                    double php = (a - floor(a)) + phio0;                    // Eq. (45)
+                    int l0 = 0, h0 = nfp;
+                    while (h0 - l0 > 1) {
+                        int mid = (l0 + h0) >> 1;
+                        if (tr[mid].z <= php) l0 = mid; else h0 = mid;
+                    }
+                    const double4 A = tr[l0], Cn = tr[l0 + 1];
+                    double w = (php - A.z) / (Cn.z - A.z);
+                    w = fmin(1.0, fmax(0.0, w));
+                    const double Fp = A.x + w * (Cn.x - A.x);                // Eq. (46)
+                    if (Fp != 0.0) {
+                        vis = true;
+                        lo = l0;
+                        wph = w;
+                        const double zp = A.y + w * (Cn.y - A.y);
+                        const double mup = A.w + w * (Cn.w - A.w);
+                        mu_clamped = !(mup > mu_lo && mup < mu_hi);
+                        const double mu = fmin(mu_hi, fmax(mu_lo, mup));
+                        int ml = 0, mh = nmu - 1;
+                        while (mh - ml > 1) {
+                            int mid = (ml + mh) >> 1;
+                            if (axmu[mid] <= mu) ml = mid; else mh = mid;
+                        }
+                        double wv[4] = {0.0, 0.0, 0.0, 0.0}, dv[4] = {0.0, 0.0, 0.0, 0.0};
+                        if (ml < 3 || ml == nmu - 2) {
+                            const double hmu = axmu[ml + 1] - axmu[ml];
+                            const double t = (mu - axmu[ml]) / hmu;
+                            m0 = ml < nmu - 4 ? ml : nmu - 4;
+                            wv[ml - m0] = 1.0 - t;
+                            wv[ml + 1 - m0] = t;
+                            dv[ml - m0] = -1.0 / hmu;
+                            dv[ml + 1 - m0] = 1.0 / hmu;
+                        } else {
+                            m0 = ml - 1;
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                double num = 1.0, den = 1.0, dnum = 0.0;
+#pragma unroll
+                                for (int s2 = 0; s2 < 4; ++s2) {
+                                    if (s2 == q) continue;
+                                    const double fac = mu - axmu[m0 + s2];
+                                    dnum = dnum * fac + num;       // product rule, running
+                                    num *= fac;
+                                    den *= axmu[m0 + q] - axmu[m0 + s2];
+                                }
+                                wv[q] = num / den;
+                                dv[q] = dnum / den;
+                            }
+                        }
+                        if (mu_clamped) dv[0] = dv[1] = dv[2] = dv[3] = 0.0;
+                        w0 = (float)wv[0]; w1 = (float)wv[1]; w2 = (float)wv[2]; w3 = (float)wv[3];
+                        v0 = (float)dv[0]; v1 = (float)dv[1]; v2 = (float)dv[2]; v3 = (float)dv[3];
+                        const double T0 = log10(zp) * ihx + tbk;
+                        const double fl = floor(T0);
+                        I0 = (int)fl;
+                        fr = (float)(T0 - fl);
+                    }
+                }
+            }
+            const uint64_t vmask = __ballot(vis);
+            // ---------------- stage B: the visible pairs one after another
+            float R0 = 0.f, R1 = 0.f, R2 = 0.f, R3 = 0.f, R4 = 0.f;
+            uint64_t mask = vmask;
+            while (mask) {
+                const int p = __ffsll((unsigned long long)mask) - 1;
+                mask &= mask - 1;
+                const float pw0 = readlane_f(w0, p), pw1 = readlane_f(w1, p), pw2 = readlane_f(w2, p),
+                            pw3 = readlane_f(w3, p);
+                const float pv0 = readlane_f(v0, p), pv1 = readlane_f(v1, p), pv2 = readlane_f(v2, p),
+                            pv3 = readlane_f(v3, p);
+                const float pfr = readlane_f(fr, p);
+                const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
+                const int col = pI0 - 1 + lane - xw0;
+                float4 nv = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (col >= 0 && col < xw) {
+                    const float *t0 = tab + pm0 * W + col;
+                    const float2 *u0 = tab2 + pm0 * W + col;
+                    const float a0 = t0[0], a1 = t0[W], a2 = t0[2 * W], a3 = t0[3 * W];
+                    const float2 b0 = u0[0], b1 = u0[W], b2 = u0[2 * W], b3 = u0[3 * W];
+                    nv.x = pw0 * a0 + pw1 * a1 + pw2 * a2 + pw3 * a3;
+                    nv.y = pv0 * a0 + pv1 * a1 + pv2 * a2 + pv3 * a3;
+                    nv.z = pw0 * b0.x + pw1 * b1.x + pw2 * b2.x + pw3 * b3.x;
+                    nv.w = pw0 * b0.y + pw1 * b1.y + pw2 * b2.y + pw3 * b3.y;
+                }
+                Nw[lane] = nv;
+                wave_sync();
+                {
+                    const float4 n1 = Nw[lane + 1], n2 = Nw[lane + 2], n3 = Nw[lane + 3];
+                    const int gi = pI0 + lane;
+                    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0, q3 = q0;
+                    if (gi >= 0 && gi <= nx - 2) {
+                        if (gi == 0 || gi == nx - 2) {
+                            q0 = make_float4(n1.x, n2.x - n1.x, 0.f, 0.f);
+                            q1 = make_float4(n1.y, n2.y - n1.y, 0.f, 0.f);
+                            q2 = make_float4(n1.z, n2.z - n1.z, 0.f, 0.f);
+                            q3 = make_float4(n1.w, n2.w - n1.w, 0.f, 0.f);
+                        } else {
+                            q0 = cubic_quad(nv.x, n1.x, n2.x, n3.x);
+                            q1 = cubic_quad(nv.y, n1.y, n2.y, n3.y);
+                            q2 = cubic_quad(nv.z, n1.z, n2.z, n3.z);
+                            q3 = cubic_quad(nv.w, n1.w, n2.w, n3.w);
+                        }
+                    }
+                    Qw[lane] = q0;
+                    Qw[64 + lane] = q1;
+                    Qw[128 + lane] = q2;
+                    Qw[192 + lane] = q3;
+                }
+                wave_sync();
+                float s0 = 0.f, sx = 0.f, sm = 0.f, sT = 0.f, sg = 0.f;
+#pragma unroll
+                for (int m = 0; m < EPL; ++m) {
+                    const float t = pfr + tbr[m];
+                    const float f = __builtin_amdgcn_fractf(t);
+                    const int ix = (int)t;
+                    const float4 qa = Qw[ix], qm = Qw[64 + ix], qt = Qw[128 + ix], qg = Qw[192 + ix];
+                    const float G = Gr[m];
+                    s0 += G * horner(qa, f);
+                    sx += G * (qa.y + f * (2.0f * qa.z + 3.0f * f * qa.w));
+                    sm += G * horner(qm, f);
+                    sT += G * horner(qt, f);
+                    sg += G * horner(qg, f);
+                }
+                wave_sync();
+                s0 = wave_sum(s0);
+                sx = wave_sum(sx);
+                sm = wave_sum(sm);
+                sT = wave_sum(sT);
+                sg = wave_sum(sg);
+                if (lane == p) { R0 = s0; R1 = sx; R2 = sm; R3 = sT; R4 = sg; }
+            }
+            // ---------------- stage C: chain rule per pair, FP64
+            if (vis) {
+                const double4 A = tr[lo], Cn = tr[lo + 1];
+                const double dph = Cn.z - A.z;
+                const double w = wph;
+                const double Fp = A.x + w * (Cn.x - A.x), zp = A.y + w * (Cn.y - A.y);
+                const double S0 = R0, Sx = (double)R1 * ihx, Sm = R2, ST = R3, Sg = R4;
+                const double cF = S0, cz = Fp * Sx / (zp * kLn10), cm = mu_clamped ? 0.0 : Fp * Sm;
+                const double dFd = Cn.x - A.x, dzd = Cn.y - A.y, dmd = Cn.w - A.w;
+                double ca, cb;
+                offset_coeffs(g, j, ca, cb);
+#pragma unroll
+                for (int d = 0; d < 5; ++d) {
+                    const double4 t0 = tg[lo * 5 + d], t1 = tg[(lo + 1) * 5 + d];
+                    const double dphp = (ca * rt.ddout[d] + cb * rt.ddin[d]) * inv2pi;
+                    const double ww = (dphp - t0.z - w * (t1.z - t0.z)) / dph;
+                    const double dF = t0.x + w * (t1.x - t0.x) + dFd * ww;
+                    const double dz = t0.y + w * (t1.y - t0.y) + dzd * ww;
+                    const double dm = t0.w + w * (t1.w - t0.w) + dmd * ww;
+                    U[d] += cF * dF + cz * dz + cm * dm;
+                }
+                U[5] -= (cF * dFd + cz * dzd + cm * dmd) / dph;     // d php / d Phi = -1
+                U[6] += Fp * S0;
+                U[7] += Fp * Sg;
+                U[8] += Fp * (3.0 * kLn10 * S0 + ST - Sx);
+            }
+        }
+    }
+    // fixed-order block reduction of the nine sums
+    __shared__ double red[4][kGradAcc];
+#pragma unroll
+    for (int q = 0; q < kGradAcc; ++q) {
+        const double v = wave_sum_d(U[q]);
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kGradAcc) {
+        const int q = threadIdx.x;
+        const double v = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+        gpart[(slot * gridDim.x + blockIdx.x) * kGradAcc + q] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_grad_final: per instance, the ring sums times the ring constants and
+// ring-level tangents, in a fixed ring order, plus the N_H term.
+// Gradient order: M, R_e, i, Phi, N_H, theta_1, zeta_1, logT_1, theta_2,
+// zeta_2, logT_2, dphi_2.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_grad_final(DevSpec S, const StarRec *stars, const RingRec *rings,
+                                                   const RingTan *ringtan, const double *gpart, int n_tile,
+                                                   const double *nh_part, double *grad)
+{
+    const int b = blockIdx.x;
+    __shared__ double red[64][PPM_NGRAD];
+    double acc[PPM_NGRAD];
+#pragma unroll
+    for (int q = 0; q < PPM_NGRAD; ++q) acc[q] = 0.0;
+    for (int r = threadIdx.x; r < S.R_tot; r += blockDim.x) {
+        const size_t slot = (size_t)b * S.R_tot + r;
+        const RingRec g = rings[slot];
+        if (!g.active) continue;
+        const RingTan rt = ringtan[slot];
+        double U[kGradAcc];
+        for (int q = 0; q < kGradAcc; ++q) U[q] = 0.0;
+        for (int t = 0; t < n_tile; ++t)
+            for (int q = 0; q < kGradAcc; ++q) U[q] += gpart[(slot * n_tile + t) * kGradAcc + q];
+        const double T3 = g.T * g.T * g.T, c = g.w_cell * T3;
+        const int s = g.spot;
+        for (int d = 0; d < 5; ++d) {
+            const double v = c * (U[d] + U[7] * rt.dlogg[d]) + T3 * U[6] * rt.dw[d];
+            const int idx = d < 3 ? d : (d == 3 ? 5 + 3 * s : 6 + 3 * s);
+            acc[idx] += v;
+        }
+        acc[3] += c * U[5];
+        if (s == 1) acc[11] += c * U[5];
+        acc[7 + 3 * s] += c * U[8];
+    }
+    for (int q = 0; q < PPM_NGRAD; ++q) red[threadIdx.x][q] = acc[q];
+    __syncthreads();
+    if (threadIdx.x < PPM_NGRAD) {
+        const int q = threadIdx.x;
+        double v = 0.0;
+        for (int t = 0; t < 64; ++t) v += red[t][q];
+        if (q == 4)
+            for (int k = 0; k < S.P; ++k) v += nh_part[(size_t)b * S.P + k];
+        if (stars[b].status != PPM_INST_OK) v = NAN;
+        grad[(size_t)b * PPM_NGRAD + q] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers (host)
+// ---------------------------------------------------------------------------
+size_t accum_adj_lds(const DevSpec &S)
+{
+    return sizeof(double4) * (S.n_fp + 1) * 6 + sizeof(double) * ((S.nmu + 1) & ~1)
+         + sizeof(float) * S.sub_stride * 3 + sizeof(float4) * 4 * 68 + sizeof(float4) * 4 * 4 * 64;
+}
+
+hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev,
+                       int B, const int32_t *list, int n_list, const double *counts, const int32_t *data,
+                       double *grad, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fold_bwd, dim3(S.P, B), dim3(256), sizeof(double) * S.C, st, S, W.stars, counts, data,
+                       W.flux, W.gtil, W.nh_part);
+    hipLaunchKernelGGL(k_table_u, dim3(n_list), dim3(256), 0, st, S, list, W.stars, W.rings, W.table_u);
+    size_t lds_tt = sizeof(double4) * (2 * S.n_alpha + (S.n_fp + 1) * 5);
+    hipLaunchKernelGGL(k_trace_tan, dim3(n_list), dim3(256), lds_tt, st, S, list, params, ncells_dev, W.stars,
+                       W.rings, W.table, W.table_u, W.trace, W.tangent, W.ringtan);
+    hipLaunchKernelGGL(k_subtable_tg, dim3(n_list), dim3(256), 0, st, S, list, W.rings, W.subtg);
+    const int n_tile = (S.P + kPhaseTile - 1) / kPhaseTile;
+    dim3 grid(n_tile, n_list);
+    size_t lds = accum_adj_lds(S);
+    int epl = (S.E + 63) / 64;
+    if (epl <= 1)
+        hipLaunchKernelGGL(k_accum_adj<1>, grid, dim3(256), lds, st, S, list, W.rings, W.ringtan, W.trace,
+                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart);
+    else if (epl <= 2)
+        hipLaunchKernelGGL(k_accum_adj<2>, grid, dim3(256), lds, st, S, list, W.rings, W.ringtan, W.trace,
+                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart);
+    else if (epl <= 4)
+        hipLaunchKernelGGL(k_accum_adj<4>, grid, dim3(256), lds, st, S, list, W.rings, W.ringtan, W.trace,
+                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart);
+    else
+        hipLaunchKernelGGL(k_accum_adj<8>, grid, dim3(256), lds, st, S, list, W.rings, W.ringtan, W.trace,
+                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart);
+    hipLaunchKernelGGL(k_grad_final, dim3(B), dim3(64), 0, st, S, W.stars, W.rings, W.ringtan, W.gpart, n_tile,
+                       W.nh_part, grad);
+    return hipGetLastError();
+}
+
+}  // namespace ppm

@@ -91,6 +91,7 @@ struct ppm_plan {
     int list_B = -1;               // batch size the list was built for (-1: none)
     bool list_override = false;    // list built for per-instance grids
     int precision = PPM_F32;
+    bool grad = false;             // gradient buffers allocated
     std::vector<void *> allocs;
     std::vector<int32_t> last_ncells;
     bool ncells_valid = false;
@@ -189,6 +190,9 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     if (!(sp->t_exp > 0.0)) return fail(PPM_ERR_ARG, "t_exp must be positive");
     if (sp->n_alpha < 64 || sp->n_alpha > 8192) return fail(PPM_ERR_ARG, "n_alpha must lie in [64, 8192]");
     if (sp->n_energy > 64 * 8) return fail(PPM_ERR_UNSUPPORTED, "at most 512 energies");
+    if (sp->grad != 0 && sp->grad != 1) return fail(PPM_ERR_ARG, "grad must be 0 or 1");
+    if (sp->grad && sp->intensity != PPM_I_TABLE)
+        return fail(PPM_ERR_UNSUPPORTED, "gradients are implemented for the atmosphere-table model only");
     double tmp0, tmp1;
     if (sp->intensity == PPM_I_TABLE) {
         if (!sp->ax_T || !sp->ax_g || !sp->ax_mu || !sp->ax_x || !sp->log_intensity)
@@ -230,6 +234,7 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     pl->max_batch = max_batch;
     pl->max_cells = max_cells;
     pl->precision = sp->precision;
+    pl->grad = sp->grad != 0;
 
     // Gauss-Legendre rules of 32, 48 and 64 nodes, back to back
     std::vector<double> glx, glw;
@@ -250,6 +255,12 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         for (size_t i = 0; i < n; ++i) r32[i] = (float)sp->rsp[i];
         S.rsp32 = pl->upload(r32.data(), n);
         if (sp->precision == PPM_F64) S.rsp64 = pl->upload(sp->rsp, n);
+        if (sp->grad) {
+            std::vector<double> rt(n);
+            for (int e = 0; e < S.E; ++e)
+                for (int c = 0; c < S.C; ++c) rt[(size_t)c * S.E + e] = sp->rsp[(size_t)e * S.C + c];
+            S.rspT64 = pl->upload(rt.data(), n);
+        }
     }
     if (sp->intensity == PPM_I_TABLE) {
         S.nT = sp->nT; S.ng = sp->ng; S.nmu = sp->nmu; S.nx = sp->nx;
@@ -264,6 +275,10 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         S.W_max = (int)std::ceil(S.r_span + std::log10(4.0) / S.hx) + 8;
         if (S.W_max > S.nx) S.W_max = S.nx;
         S.fast = (S.r_span <= 59.0) ? 1 : 0;
+        if (sp->grad && !S.fast) {
+            delete pl;
+            return fail(PPM_ERR_UNSUPPORTED, "gradients need an energy grid spanning at most 59 x intervals");
+        }
         S.sub_stride = S.fast ? ((S.nmu * S.W_max + 3) & ~3) : S.nmu * S.nx;
         size_t n = (size_t)S.nT * S.ng * S.nmu * S.nx;
         std::vector<float> lin(n);
@@ -281,7 +296,12 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
                         + (S.intensity == PPM_I_TABLE ? sizeof(float) * (size_t)S.sub_stride
                                                       + sizeof(float) * (size_t)S.P * S.E
                                                       : sizeof(double) * (size_t)S.P * S.E);
-        size_t per_inst = per_ring * R + sizeof(double) * (size_t)S.P * S.E;
+        if (sp->grad)
+            per_ring += sizeof(double4) * ((size_t)S.n_alpha + (size_t)(S.n_fp + 1) * 5) + sizeof(RingTan)
+                      + sizeof(float2) * (size_t)S.sub_stride
+                      + sizeof(double) * kGradAcc * (size_t)((S.P + kPhaseTile - 1) / kPhaseTile);
+        size_t per_inst = per_ring * R + sizeof(double) * (size_t)S.P * S.E
+                        + (sp->grad ? (sizeof(double) + sizeof(float)) * (size_t)S.P * S.E : 0);
         size_t budget = (size_t)16 << 30;
         size_t c = budget / per_inst;
         if (c < 1) c = 1;
@@ -323,6 +343,19 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         }
         ok = ok && W.partial64;
     }
+    if (sp->grad) {
+        const size_t n_tile = (S.P + kPhaseTile - 1) / kPhaseTile;
+        W.table_u = pl->dalloc<double4>(B * R * S.n_alpha);
+        W.tangent = pl->dalloc<double4>(B * R * (S.n_fp + 1) * 5);
+        W.ringtan = pl->dalloc<RingTan>(B * R);
+        W.subtg = pl->dalloc<float2>(B * R * (size_t)S.sub_stride);
+        W.flux = pl->dalloc<double>(B * S.P * S.E);
+        W.gtil = pl->dalloc<float>(B * S.P * S.E);
+        W.nh_part = pl->dalloc<double>(B * S.P);
+        W.gpart = pl->dalloc<double>(B * R * n_tile * kGradAcc);
+        ok = ok && W.table_u && W.tangent && W.ringtan && W.subtg && W.flux && W.gtil && W.nh_part && W.gpart
+           && S.rspT64;
+    }
     if (!ok) {
         delete pl;
         return fail(PPM_ERR_ALLOC, "device allocation or upload failed");
@@ -332,6 +365,10 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         if (lds > 160 * 1024) {
             delete pl;
             return fail(PPM_ERR_UNSUPPORTED, "atmosphere sub-table does not fit in LDS");
+        }
+        if (sp->grad && accum_adj_lds(S) > 160 * 1024) {
+            delete pl;
+            return fail(PPM_ERR_UNSUPPORTED, "adjoint working set does not fit in LDS");
         }
     }
     *out = pl;
@@ -461,6 +498,42 @@ int ppm_loglike(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_
     if (e != hipSuccess) return hip_fail(e, "ppm_loglike forward");
     e = launch_loglike(pl->W, cnt, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike reduction");
+}
+
+int ppm_loglike_grad(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_cells_host,
+                     const int32_t *data_dev, double *logl_dev, double *grad_dev, void *stream)
+{
+    if (!pl) return fail(PPM_ERR_ARG, "null plan");
+    if (!pl->grad) return fail(PPM_ERR_UNSUPPORTED, "plan created without gradient buffers (spec->grad = 0)");
+    const int32_t *nc = nullptr;
+    int rc = prepare(pl, params_dev, B, n_cells_host, &nc);
+    if (rc) return rc;
+    if (!data_dev || !logl_dev || !grad_dev) return fail(PPM_ERR_ARG, "null data, logl or grad buffer");
+    const DevSpec &S = pl->S;
+    hipStream_t st = (hipStream_t)stream;
+    double *cnt = pl->W.counts;
+    // each workspace pass: forward (keeping the pre-absorption flux), then the
+    // adjoint of the same instances while their ring scratch is live
+    for (size_t ci = 0; ci < pl->list_off.size(); ++ci) {
+        int c0 = (int)ci * pl->chunk;
+        int nb = B - c0 < pl->chunk ? B - c0 : pl->chunk;
+        Workspace W = pl->W;
+        W.stars += c0;
+        W.vis_pairs += (size_t)c0 * S.R_tot;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        pl->events(e0, e1);
+        const double *pc = params_dev + (size_t)c0 * PPM_NPARAM;
+        const int32_t *ncc = nc ? nc + c0 : nullptr;
+        double *cc = cnt + (size_t)c0 * S.P * S.C;
+        hipError_t e = launch_forward(S, W, pc, ncc, nb, pl->d_list + pl->list_off[ci], pl->list_n[ci], st, W.flux,
+                                      cc, e0, e1);
+        if (e != hipSuccess) return hip_fail(e, "ppm_loglike_grad forward");
+        e = launch_grad(S, W, pc, ncc, nb, pl->d_list + pl->list_off[ci], pl->list_n[ci], cc, data_dev,
+                        grad_dev + (size_t)c0 * PPM_NGRAD, st);
+        if (e != hipSuccess) return hip_fail(e, "ppm_loglike_grad adjoint");
+    }
+    hipError_t e = launch_loglike(pl->W, cnt, B, S.P * S.C, data_dev, logl_dev, st);
+    return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike_grad reduction");
 }
 
 int ppm_instance_status(ppm_plan *pl, int B, int32_t *status_dev, void *stream)

@@ -1,0 +1,232 @@
+// Device helpers shared by the forward and the adjoint kernels: star
+// geometry, the deflection quadrature, Hermite bases, table brackets, cell
+// azimuths and the observed-phase lookup.  Templated helpers take double or
+// a dual number (forward-mode tangents).
+// Section and equation numbers refer to arXiv:2510.07764.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ppm_internal.h"
+#include "ppm_dual.h"
+#include "../../include/ppm.h"
+
+namespace ppm {
+
+// g(theta)/g0 of Eqs. (10), (11)
+template <class T>
+__device__ inline T gravity_ratio_t(int mode, const T &x, const T &Obar, const T &th)
+{
+    if (mode != PPM_MODE_OS) return T(1.0);
+    T O2 = Obar * Obar, O4 = O2 * O2, O6 = O4 * O2;
+    T sn = sin(th), c = cos(th);
+    T s2 = sn * sn, c2 = c * c;
+    T e4 = O4 * (13.47 * x - 27.13 * x * x);
+    return 1.0 + s2 * (O2 * (-0.791 + 0.776 * x) + O4 * (-1.315 * x + 2.431 * x * x) + O6 * (-1.172 * x))
+         + c2 * (O2 * (1.138 - 1.431 * x) + O4 * (0.653 * x - 2.864 * x * x) + O6 * (0.975 * x) - e4)
+         + fabs(c) * e4;
+}
+
+__device__ inline double gravity_ratio(const StarRec &st, int mode, double th)
+{
+    return gravity_ratio_t<double>(mode, st.x, st.Obar, th);
+}
+
+// azimuthal half-width of a ring at colatitude th inside a cap (tc, z)
+template <class T>
+__device__ inline T arc_halfwidth(const T &th, const T &tc, const T &z)
+{
+    T den = sin(th) * sin(tc);
+    T num = cos(z) - cos(th) * cos(tc);
+    if (value(den) <= 0.0) return T(value(num) <= 0.0 ? kPi : 0.0);
+    T a = num / den;
+    if (value(a) <= -1.0) return T(kPi);
+    if (value(a) >= 1.0) return T(0.0);
+    return acos(a);
+}
+
+__device__ inline double cdt_oblate(double Re, double Rs, double R)
+{
+    return Re - R + Rs * log((Re - Rs) / (R - Rs));   // Eq. (16)
+}
+
+
+template <class X, class V>
+__device__ inline auto q_s2(const X &x, const V &v) -> decltype(x * v)
+{
+    auto t = 1.0 - x * x;
+    return 2.0 - x * x - v * t * t / (1.0 - v);
+}
+
+// Gauss-Legendre rules on [0, 1] held back to back: 32, 48 and 64 nodes.
+__device__ inline void gl_rule(const DevSpec &S, int n, const double *&x, const double *&w)
+{
+    int off = n == 32 ? 0 : (n == 48 ? 32 : 80);
+    x = S.glx + off;
+    w = S.glw + off;
+}
+
+// psi, dpsi/dalpha and c dt_p/R for an outgoing ray, 0 <= alpha <= pi/2.
+// The rule order follows cos(alpha): the sinh map leaves an integrand
+// analytic in a strip whose width shrinks only logarithmically as
+// cos(alpha) -> 0, and 32/48/64 nodes keep the relative error below 1e-12.
+// U = double, or a dual number carrying d/du.
+template <class U>
+__device__ void bend_out(const DevSpec &S, const U &u, double alpha, U &psi, U &dpsi, U &tp)
+{
+    const U sq = sqrt(1.0 - u);
+    if (alpha <= 0.0) { psi = U(0.0); dpsi = 1.0 / sq; tp = U(0.0); return; }
+    double c = cos(alpha), s = sin(alpha);
+    const U q0 = 2.0 - u / (1.0 - u);
+    const double *gx, *gw;
+    if (c < 1e-9) {
+        // tangent ray: x/sqrt(x^2 s^2 q) = 1/(s sqrt q), regular on [0, 1]
+        gl_rule(S, 32, gx, gw);
+        U I1 = U(0.0), IT = U(0.0);
+        for (int q = 0; q < 32; ++q) {
+            double x = gx[q], w = gw[q];
+            U rq = sqrt(q_s2(x, u));
+            I1 += w / rq;
+            IT += w / (rq * (1.0 + x * s * rq));
+        }
+        psi = 2.0 / sq * I1;
+        dpsi = 2.0 / (sq * q0);
+        tp = 2.0 * s / (1.0 - u) * IT;
+        return;
+    }
+    const int n = c >= 1e-2 ? 32 : (c >= 1e-4 ? 48 : 64);
+    gl_rule(S, n, gx, gw);
+    U A = c / (s * sqrt(q0));
+    U L = asinh(1.0 / A);
+    U I1 = U(0.0), I3 = U(0.0), IT = U(0.0);
+    for (int q = 0; q < n; ++q) {
+        U ex = exp(L * gx[q]);
+        U iex = 1.0 / ex;
+        U x = 0.5 * A * (ex - iex);
+        U dx = 0.5 * A * (ex + iex) * L * gw[q];
+        U D = c * c + x * x * s * s * q_s2(x, u);
+        U r = sqrt(D);
+        U ir = 1.0 / r;
+        U xr = x * ir * dx;
+        I1 += xr;
+        I3 += xr / D;
+        IT += xr / (1.0 + r);
+    }
+    psi = 2.0 * s / sq * I1;
+    dpsi = 2.0 * c / sq * I3;
+    tp = 2.0 * s * s / (1.0 - u) * IT;
+}
+
+// psi(v, pi/2), c dt_p/R (v, pi/2) and their v-derivatives (periastron leg)
+template <class U>
+__device__ void grazing(const DevSpec &S, const U &v, U &ph, U &dph, U &th, U &dth)
+{
+    U J = U(0.0), J3 = U(0.0), K = U(0.0), K1 = U(0.0);
+    const double *gx, *gw;
+    gl_rule(S, 48, gx, gw);   // smooth integrands (q(0) > 0 below the photon sphere)
+    for (int q = 0; q < 48; ++q) {
+        double x = gx[q], w = gw[q];
+        double t = 1.0 - x * x;
+        U Q = 2.0 - x * x - v * t * t / (1.0 - v);
+        U rq = sqrt(Q);
+        J += w / rq;
+        J3 += w * t * t / (Q * rq);
+        U gq = rq + x * Q;
+        K += w / gq;
+        K1 += w * (0.5 / rq + x) * t * t / (gq * gq);
+    }
+    U om = 1.0 - v;
+    ph = 2.0 / sqrt(om) * J;
+    dph = (J + J3 / om) / (om * sqrt(om));
+    th = 2.0 / om * K;
+    dth = 2.0 / (om * om) * K + 2.0 / om * K1 / (om * om);
+}
+
+
+template <class T>
+__device__ inline void hermite(const T &t, T &h00, T &h10, T &h01, T &h11)
+{
+    T t2 = t * t, t3 = t2 * t;
+    h00 = 2.0 * t3 - 3.0 * t2 + 1.0;
+    h10 = t3 - 2.0 * t2 + t;
+    h01 = -2.0 * t3 + 3.0 * t2;
+    h11 = t3 - t2;
+}
+
+template <class T>
+__device__ inline void dhermite(const T &t, T &d00, T &d10, T &d01, T &d11)
+{
+    T t2 = t * t;
+    d00 = 6.0 * t2 - 6.0 * t;
+    d10 = 3.0 * t2 - 4.0 * t + 1.0;
+    d01 = -6.0 * t2 + 6.0 * t;
+    d11 = 3.0 * t2 - 2.0 * t;
+}
+
+
+__device__ inline int lin_bracket(double v, double v0, double h, int n, double &w1)
+{
+    double t = (v - v0) / h;
+    if (t <= 0.0) { w1 = 0.0; return 0; }
+    if (t >= n - 1) { w1 = 1.0; return n - 2; }
+    int i = (int)floor(t);
+    if (i > n - 2) i = n - 2;
+    w1 = t - i;
+    return i;
+}
+
+
+// cell azimuth, crescent mask, observed-phase lookup (Eqs. 45-46) on the
+// ring's fine-phase arrays
+__device__ inline double cell_offset(const RingRec &g, int j)
+{
+    if (g.shape == PPM_SHAPE_ANNULUS) {
+        int h = g.n_cells / 2;
+        if (j < h) return -(g.dphi_in + (h - 1 - j + 0.5) * g.dphi_cell);
+        return g.dphi_in + (j - h + 0.5) * g.dphi_cell;
+    }
+    return -g.dphi_out + (j + 0.5) * g.dphi_cell;
+}
+
+__device__ inline bool cell_masked(const RingRec &g, double off)
+{
+    if (g.shape != PPM_SHAPE_CRESCENT) return false;
+    double cd = cos(g.theta) * cos(g.tm) + sin(g.theta) * sin(g.tm) * cos(off);
+    return cd > g.cos_zm;
+}
+
+struct PhaseSample { double F, z, mu; };
+
+__device__ inline PhaseSample phase_lookup(const double4 *tr, int nfp, double php)
+{
+    int lo = 0, hi = nfp;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (tr[mid].z <= php) lo = mid; else hi = mid;
+    }
+    const double4 a = tr[lo], c = tr[lo + 1];
+    double w = (php - a.z) / (c.z - a.z);
+    w = fmin(1.0, fmax(0.0, w));
+    PhaseSample s;
+    s.F = a.x + w * (c.x - a.x);
+    s.z = a.y + w * (c.y - a.y);
+    s.mu = a.w + w * (c.w - a.w);
+    return s;
+}
+
+__device__ inline float readlane_f(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+
+}  // namespace ppm

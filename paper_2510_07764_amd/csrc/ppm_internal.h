@@ -41,6 +41,7 @@ struct DevSpec {
     const double *sigma;    // [E] cm^2 (nullptr: no absorption)
     const float *rsp32;     // [E][C]
     const double *rsp64;    // [E][C]
+    const double *rspT64;   // [C][E] (gradient plans: backward fold)
     const float *atm;       // [nT][ng][nmu][nx] linear I/T^3
     const double *ax_mu;    // [nmu]
     const double *glx, *glw;  // Gauss-Legendre on [0, 1], n_quad nodes
@@ -63,6 +64,13 @@ struct RingRec {
     int visible, inv_min, inv_max, interior;   // interior: the ring never reaches the x-axis edge intervals
     double zmin, zmax;           // range of the fine-phase redshift factor z
     int xw0, xw;                 // x-node window [xw0, xw0 + xw) of the ring's sub-table
+};
+
+// Ring-level tangents along the five local directions of a ring's geometry
+// (M, R_e, inclination, the ring's spot colatitude and angular radius).
+struct RingTan {
+    double dlogg[5], dw[5];      // log g of the ring, cell weight
+    double ddout[5], ddin[5];    // arc half-widths (outer, inner)
 };
 
 }  // namespace ppm

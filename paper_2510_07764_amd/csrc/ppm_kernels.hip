@@ -16,6 +16,7 @@
 #include <stdint.h>
 
 #include "ppm_internal.h"
+#include "ppm_device.h"
 #include "ppm_launch.h"
 #include "../../include/ppm.h"
 
@@ -47,35 +48,6 @@ __host__ __device__ int validate_params(const double *p, int n_spots)
 // ---------------------------------------------------------------------------
 // k_setup: star (Eqs. 7, 8, 11) and spot rings (Eqs. 2, 3, 9, 10, 18)
 // ---------------------------------------------------------------------------
-__device__ static double gravity_ratio(const StarRec &st, int mode, double th)
-{
-    if (mode != PPM_MODE_OS) return 1.0;
-    double x = st.x, O2 = st.Obar * st.Obar, O4 = O2 * O2, O6 = O4 * O2;
-    double sn = sin(th), c = cos(th);
-    double s2 = sn * sn, c2 = c * c;
-    double e4 = O4 * (13.47 * x - 27.13 * x * x);
-    return 1.0 + s2 * (O2 * (-0.791 + 0.776 * x) + O4 * (-1.315 * x + 2.431 * x * x) + O6 * (-1.172 * x))
-         + c2 * (O2 * (1.138 - 1.431 * x) + O4 * (0.653 * x - 2.864 * x * x) + O6 * (0.975 * x) - e4)
-         + fabs(c) * e4;
-}
-
-// azimuthal half-width of a ring at colatitude th inside a cap (tc, z)
-__device__ static double arc_halfwidth(double th, double tc, double z)
-{
-    double den = sin(th) * sin(tc);
-    double num = cos(z) - cos(th) * cos(tc);
-    if (den <= 0.0) return num <= 0.0 ? kPi : 0.0;
-    double a = num / den;
-    if (a <= -1.0) return kPi;
-    if (a >= 1.0) return 0.0;
-    return acos(a);
-}
-
-__device__ static double cdt_oblate(double Re, double Rs, double R)
-{
-    return Re - R + Rs * log((Re - Rs) / (R - Rs));   // Eq. (16)
-}
-
 __global__ void k_setup(DevSpec S, const double *params, const int32_t *n_cells, StarRec *stars,
                         RingRec *rings)
 {
@@ -175,95 +147,6 @@ __global__ void k_setup(DevSpec S, const double *params, const int32_t *n_cells,
 // sqrt(q0)), which resolves the boundary layer of width ~cos(alpha) at
 // x -> 0 for near-grazing rays.
 // ---------------------------------------------------------------------------
-__device__ static inline double q_s2(double x, double v)
-{
-    double t = 1.0 - x * x;
-    return 2.0 - x * x - v * t * t / (1.0 - v);
-}
-
-// Gauss-Legendre rules on [0, 1] held back to back: 32, 48 and 64 nodes.
-__device__ static inline void gl_rule(const DevSpec &S, int n, const double *&x, const double *&w)
-{
-    int off = n == 32 ? 0 : (n == 48 ? 32 : 80);
-    x = S.glx + off;
-    w = S.glw + off;
-}
-
-// psi, dpsi/dalpha and c dt_p/R for an outgoing ray, 0 <= alpha <= pi/2.
-// The rule order follows cos(alpha): the sinh map leaves an integrand
-// analytic in a strip whose width shrinks only logarithmically as
-// cos(alpha) -> 0, and 32/48/64 nodes keep the relative error below 1e-12.
-__device__ static void bend_out(const DevSpec &S, double u, double alpha, double &psi, double &dpsi,
-                                double &tp)
-{
-    const double sq = sqrt(1.0 - u);
-    if (alpha <= 0.0) { psi = 0.0; dpsi = 1.0 / sq; tp = 0.0; return; }
-    double c = cos(alpha), s = sin(alpha);
-    const double q0 = 2.0 - u / (1.0 - u);
-    const double *gx, *gw;
-    if (c < 1e-9) {
-        // tangent ray: x/sqrt(x^2 s^2 q) = 1/(s sqrt q), regular on [0, 1]
-        gl_rule(S, 32, gx, gw);
-        double I1 = 0.0, IT = 0.0;
-        for (int q = 0; q < 32; ++q) {
-            double x = gx[q], w = gw[q];
-            double rq = sqrt(q_s2(x, u));
-            I1 += w / rq;
-            IT += w / (rq * (1.0 + x * s * rq));
-        }
-        psi = 2.0 / sq * I1;
-        dpsi = 2.0 / (sq * q0);
-        tp = 2.0 * s / (1.0 - u) * IT;
-        return;
-    }
-    const int n = c >= 1e-2 ? 32 : (c >= 1e-4 ? 48 : 64);
-    gl_rule(S, n, gx, gw);
-    double A = c / (s * sqrt(q0));
-    double L = asinh(1.0 / A);
-    double I1 = 0.0, I3 = 0.0, IT = 0.0;
-    for (int q = 0; q < n; ++q) {
-        double ex = exp(L * gx[q]);
-        double iex = 1.0 / ex;
-        double x = 0.5 * A * (ex - iex);
-        double dx = 0.5 * A * (ex + iex) * L * gw[q];
-        double D = c * c + x * x * s * s * q_s2(x, u);
-        double r = sqrt(D);
-        double ir = 1.0 / r;
-        double xr = x * ir * dx;
-        I1 += xr;
-        I3 += xr / D;
-        IT += xr / (1.0 + r);
-    }
-    psi = 2.0 * s / sq * I1;
-    dpsi = 2.0 * c / sq * I3;
-    tp = 2.0 * s * s / (1.0 - u) * IT;
-}
-
-// psi(v, pi/2), c dt_p/R (v, pi/2) and their v-derivatives (periastron leg)
-__device__ static void grazing(const DevSpec &S, double v, double &ph, double &dph, double &th,
-                               double &dth)
-{
-    double J = 0.0, J3 = 0.0, K = 0.0, K1 = 0.0;
-    const double *gx, *gw;
-    gl_rule(S, 48, gx, gw);   // smooth integrands (q(0) > 0 below the photon sphere)
-    for (int q = 0; q < 48; ++q) {
-        double x = gx[q], w = gw[q];
-        double t = 1.0 - x * x;
-        double Q = 2.0 - x * x - v * t * t / (1.0 - v);
-        double rq = sqrt(Q);
-        J += w / rq;
-        J3 += w * t * t / (Q * rq);
-        double gq = rq + x * Q;
-        K += w / gq;
-        K1 += w * (0.5 / rq + x) * t * t / (gq * gq);
-    }
-    double om = 1.0 - v;
-    ph = 2.0 / sqrt(om) * J;
-    dph = (J + J3 / om) / (om * sqrt(om));
-    th = 2.0 / om * K;
-    dth = 2.0 / (om * om) * K + 2.0 / om * K1 / (om * om);
-}
-
 __global__ void k_table(DevSpec S, const int32_t *list, const StarRec *stars, const RingRec *rings, double4 *table)
 {
     const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
@@ -312,24 +195,6 @@ __global__ void k_table(DevSpec S, const int32_t *list, const StarRec *stars, co
 // ---------------------------------------------------------------------------
 // k_trace: pseudo-patch light curve of one ring (Sect. 2.8.3, Eqs. 38-44)
 // ---------------------------------------------------------------------------
-__device__ static inline void hermite(double t, double &h00, double &h10, double &h01, double &h11)
-{
-    double t2 = t * t, t3 = t2 * t;
-    h00 = 2.0 * t3 - 3.0 * t2 + 1.0;
-    h10 = t3 - 2.0 * t2 + t;
-    h01 = -2.0 * t3 + 3.0 * t2;
-    h11 = t3 - t2;
-}
-
-__device__ static inline void dhermite(double t, double &d00, double &d10, double &d01, double &d11)
-{
-    double t2 = t * t;
-    d00 = 6.0 * t2 - 6.0 * t;
-    d10 = 3.0 * t2 - 4.0 * t + 1.0;
-    d01 = -6.0 * t2 + 6.0 * t;
-    d11 = 3.0 * t2 - 2.0 * t;
-}
-
 __global__ void k_trace(DevSpec S, const int32_t *list, const StarRec *stars, RingRec *rings, const double4 *table,
                         double4 *trace)
 {
@@ -475,17 +340,6 @@ __global__ void k_trace(DevSpec S, const int32_t *list, const StarRec *stars, Ri
 // ring (mixed-order scheme of Sect. 4: linear on these two axes, clamped at
 // the edges), giving sub[mu][x] = I/T^3 at the ring's (logT, log g).
 // ---------------------------------------------------------------------------
-__device__ static inline int lin_bracket(double v, double v0, double h, int n, double &w1)
-{
-    double t = (v - v0) / h;
-    if (t <= 0.0) { w1 = 0.0; return 0; }
-    if (t >= n - 1) { w1 = 1.0; return n - 2; }
-    int i = (int)floor(t);
-    if (i > n - 2) i = n - 2;
-    w1 = t - i;
-    return i;
-}
-
 __global__ void k_subtable(DevSpec S, const int32_t *list, const RingRec *rings, float *sub)
 {
     const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
@@ -519,58 +373,6 @@ __global__ void k_subtable(DevSpec S, const int32_t *list, const RingRec *rings,
     float *out = sub + ((size_t)b * S.R_tot + r) * slab;
     for (size_t i = threadIdx.x; i < slab; i += blockDim.x)
         out[i] = w00 * s00[i] + w01 * s01[i] + w10 * s10[i] + w11 * s11[i];
-}
-
-// ---------------------------------------------------------------------------
-// shared per-(cell, phase) work: cell azimuth, crescent mask, observed-phase
-// lookup (Eqs. 45-46) in FP64 on the ring's fine-phase arrays in LDS.
-// ---------------------------------------------------------------------------
-__device__ static inline double cell_offset(const RingRec &g, int j)
-{
-    if (g.shape == PPM_SHAPE_ANNULUS) {
-        int h = g.n_cells / 2;
-        if (j < h) return -(g.dphi_in + (h - 1 - j + 0.5) * g.dphi_cell);
-        return g.dphi_in + (j - h + 0.5) * g.dphi_cell;
-    }
-    return -g.dphi_out + (j + 0.5) * g.dphi_cell;
-}
-
-__device__ static inline bool cell_masked(const RingRec &g, double off)
-{
-    if (g.shape != PPM_SHAPE_CRESCENT) return false;
-    double cd = cos(g.theta) * cos(g.tm) + sin(g.theta) * sin(g.tm) * cos(off);
-    return cd > g.cos_zm;
-}
-
-struct PhaseSample { double F, z, mu; };
-
-__device__ static inline PhaseSample phase_lookup(const double4 *tr, int nfp, double php)
-{
-    int lo = 0, hi = nfp;
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (tr[mid].z <= php) lo = mid; else hi = mid;
-    }
-    const double4 a = tr[lo], c = tr[lo + 1];
-    double w = (php - a.z) / (c.z - a.z);
-    w = fmin(1.0, fmax(0.0, w));
-    PhaseSample s;
-    s.F = a.x + w * (c.x - a.x);
-    s.z = a.y + w * (c.y - a.y);
-    s.mu = a.w + w * (c.w - a.w);
-    return s;
-}
-
-__device__ static inline float readlane_f(float v, int lane)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-
-__device__ static inline void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ---------------------------------------------------------------------------
@@ -1163,7 +965,7 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
         size_t n = (size_t)B * S.R_tot;
         hipLaunchKernelGGL(k_zero_i32, dim3((n + 255) / 256), dim3(256), 0, st, W.vis_pairs, n);
     }
-    const int PT = 16;
+    const int PT = kPhaseTile;
     dim3 grid((S.P + PT - 1) / PT, n_list);
     if (S.intensity == PPM_I_TABLE) {
         hipLaunchKernelGGL(k_subtable, dim3(n_list), dim3(256), 0, st, S, list, W.rings, W.sub);

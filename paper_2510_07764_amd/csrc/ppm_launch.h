@@ -23,7 +23,19 @@ struct Workspace {
     int32_t *ncells;       // [B] per-instance grid override
     double *ll_part;       // [B][loglike_blocks] first-stage likelihood sums
     int32_t *ll_bad;       // [B][loglike_blocks] bins with m <= 0 and d > 0
+    // gradient plans only
+    double4 *table_u;      // [B][R_tot][n_alpha] d/du (psi, psi', T, T') at fixed alpha
+    double4 *tangent;      // [B][R_tot][n_fp + 1][5] tangents of (F, z, phi_o, mu)
+    RingTan *ringtan;      // [B][R_tot]
+    float2 *subtg;         // [B][R_tot][sub_stride] d sub / d logT, d sub / d log g
+    double *flux;          // [B][P][E] flux before absorption
+    float *gtil;           // [B][P][E] adjoint of the flux divided by E
+    double *nh_part;       // [B][P] N_H gradient per phase
+    double *gpart;         // [B][R_tot][n_tile][kGradAcc] per-block adjoint sums
 };
+
+constexpr int kPhaseTile = 16;   // phases per block of the accumulation kernels
+constexpr int kGradAcc = 9;      // per-ring adjoint sums of the accumulation kernel
 
 __host__ __device__ int validate_params(const double *p, int n_spots);
 
@@ -34,7 +46,11 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
 hipError_t launch_loglike(const Workspace &W, const double *counts, int B, int PC, const int32_t *data,
                           double *logl, hipStream_t st);
 hipError_t launch_status(const Workspace &W, int B, int32_t *out, hipStream_t st);
+hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev,
+                       int B, const int32_t *list, int n_list, const double *counts, const int32_t *data,
+                       double *grad, hipStream_t st);
 size_t accum_table_lds(const DevSpec &S);
+size_t accum_adj_lds(const DevSpec &S);
 int loglike_blocks(int PC);
 
 }  // namespace ppm
