@@ -9,7 +9,9 @@ ring reduction and absorption, MFMA response fold, FP64 log-likelihood) for
 one parameter vector, inputs resident in device memory.
 
 Prints one JSON line.  `value` is the plain (one vector per call) rate; the
-batched rate (B vectors per call) is reported beside it.
+graph-replayed plain rate, the batched rate (B vectors per call) and the
++grad rate (logL and its twelve-parameter gradient, B vectors per call) are
+reported beside it.
 """
 import argparse
 import json
@@ -57,6 +59,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=256, help="vectors per call in the batched leg (0: skip)")
+    ap.add_argument("--grad-batch", type=int, default=256, help="vectors per call in the +grad leg (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=64, help="cells per spot of the oracle sample (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -132,6 +135,27 @@ def main():
                    "vs_plain": (B / tb) * plain_s}
         del glb, planb
 
+    # ---------------- +grad: logL and the twelve-parameter gradient, B vectors per graph replay
+    grad = None
+    if args.grad_batch > 0:
+        B = args.grad_batch
+        draws = syn.config4_draws(B)
+        plang = ppm.Plan(spec, max_batch=B, grad=True)
+        ptg = torch.tensor(draws, dtype=torch.float64, device=dev)
+        glg = ppm.GraphedLogLike(plang, data_t, B, grad=True)
+        glg(ptg)
+        torch.cuda.synchronize()
+        kg = max(2, args.steps // 10)
+        t0 = time.perf_counter()
+        for _ in range(kg):
+            out_l, out_g = glg(ptg)
+        torch.cuda.synchronize()
+        tg = (time.perf_counter() - t0) / kg
+        grad = {"evals_per_s": B / tg, "batch": B, "ms_per_call": tg * 1e3, "calls": kg,
+                "finite": bool(torch.isfinite(out_g).all().item()),
+                "vs_plain": (B / tg) * plain_s}
+        del glg, plang
+
     cpu = cpu_baseline(args.cpu_sample) if args.cpu_sample > 0 else None
     out = {
         "metric": METRIC,
@@ -152,7 +176,7 @@ def main():
         "plain_graph": {"evals_per_s": 1.0 / plain_graph_s, "ms_per_call": plain_graph_s * 1e3,
                         "matches_direct": graph_ok},
         "batched": batched,
-        "grad": None,
+        "grad": grad,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "kernel": "k_accum_fast<4>", "kernel_ms": hot_avg_s * 1e3, "units": units,

@@ -367,8 +367,8 @@ __global__ void k_subtable_tg(DevSpec S, const int32_t *list, const RingRec *rin
 // ---------------------------------------------------------------------------
 // k_accum_adj: reverse mode of the windowed accumulation (Eq. 47) over
 // energies, per (cell, phase) pair, contracted with the geometry tangents.
-// Block = (ring, tile of kPhaseTile phases), 4 waves; a wave owns one phase
-// at a time.
+// Block = (ring, tile of kPhaseTile phases), kAdjWaves waves; a wave owns one
+// phase at a time.
 //  stage A  lane = cell: observed-phase lookup (Eqs. 45-46), mu weights and
 //           their mu derivatives (cubic Lagrange; linear in the protected
 //           zone and the last interval; zero derivative where mu is clamped),
@@ -376,19 +376,33 @@ __global__ void k_subtable_tg(DevSpec S, const int32_t *list, const RingRec *rin
 //  stage B  per visible pair: lane = x node, mu contraction of the sub-table
 //           and of its logT / log g derivatives; lane = x interval, cubic
 //           coefficients of V, dV/dmu, dV/dlogT, dV/dlog g into LDS quads;
-//           lane = EPL energies: Horner steps and the five sums
-//             S0 = sum G~ V, Sx = sum G~ dV/dt, Smu, ST, Sg
-//           with G~ = G[k][e]/E_e; wave sums, kept by the pair's lane;
+//           lane = EPL energies: Horner steps and the sums over e of G~ V,
+//           G~ dV/dt, G~ dV/dmu (wave totals kept by the pair's lane) and
+//           F_p G~ dV/dlogT, F_p G~ dV/dlog g (lane-local FP64 sums), with
+//           G~ = G[k][e]/E_e;
 //  stage C  lane = pair, FP64: chain rule through the phase interpolation
 //           into the five geometric directions and the phase direction,
 //           plus the ring-level sums for the cell weight, log g and logT.
 // The nine per-lane FP64 sums are reduced over the block in a fixed order.
 // ---------------------------------------------------------------------------
-__device__ inline float wave_sum(float v)
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline float dpp_mov(float v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+// sum over the 64 lanes, returned uniform: DPP within rows of 16 lanes
+// (quad swaps, half-row and row mirrors), row broadcasts 15 and 31 across
+// rows, the total read from lane 63
+__device__ inline float wave_total(float v)
+{
+    v += dpp_mov<0xB1>(v);
+    v += dpp_mov<0x4E>(v);
+    v += dpp_mov<0x141>(v);
+    v += dpp_mov<0x140>(v);
+    v += dpp_mov<0x142, 0xa>(v);
+    v += dpp_mov<0x143, 0xc>(v);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 __device__ inline double wave_sum_d(double v)
@@ -427,8 +441,10 @@ __device__ inline void offset_coeffs(const RingRec &g, int j, double &ca, double
     }
 }
 
+constexpr int kAdjWaves = 8;   // waves per block of k_accum_adj
+
 template <int EPL>
-__global__ __launch_bounds__(256) void k_accum_adj(DevSpec S, const int32_t *list, const RingRec *rings,
+__global__ __launch_bounds__(64 * kAdjWaves) void k_accum_adj(DevSpec S, const int32_t *list, const RingRec *rings,
                                                    const RingTan *ringtan, const double4 *trace,
                                                    const double4 *tangent, const float *sub, const float2 *subtg,
                                                    const float *gtil, double *gpart)
@@ -440,17 +456,15 @@ __global__ __launch_bounds__(256) void k_accum_adj(DevSpec S, const int32_t *lis
     if (!g.active) return;
     const int nfp = S.n_fp, nmu = S.nmu, nx = S.nx, E = S.E, P = S.P, W = S.W_max;
     double4 *tr = (double4 *)lds_raw;                          // nfp + 1
-    double4 *tg = tr + nfp + 1;                                // (nfp + 1) * 5
-    double *axmu = (double *)(tg + (nfp + 1) * 5);             // nmu (padded to 16 bytes)
+    double *axmu = (double *)(tr + nfp + 1);                   // nmu (padded to 16 bytes)
     float *tab = (float *)(axmu + ((nmu + 1) & ~1));           // sub_stride
     float2 *tab2 = (float2 *)(tab + S.sub_stride);             // sub_stride
-    float4 *Nb = (float4 *)(tab2 + S.sub_stride);              // 4 waves * 68 node values
-    float4 *Qb = Nb + 4 * 68;                                  // 4 waves * 4 * 64 quads
+    float4 *Nb = (float4 *)(tab2 + S.sub_stride);              // kAdjWaves * 68 node values
+    float4 *Qb = Nb + kAdjWaves * 68;                          // kAdjWaves * 4 * 64 quads
+    const double4 *tg = tangent + slot * (size_t)(nfp + 1) * 5;   // read through the caches in stage C
     {
         const double4 *gtr = trace + slot * (nfp + 1);
         for (int i = threadIdx.x; i <= nfp; i += blockDim.x) tr[i] = gtr[i];
-        const double4 *gtg = tangent + slot * (size_t)(nfp + 1) * 5;
-        for (int i = threadIdx.x; i < (nfp + 1) * 5; i += blockDim.x) tg[i] = gtg[i];
         for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
         const float4 *gs = (const float4 *)(sub + slot * (size_t)S.sub_stride);
         float4 *ts = (float4 *)tab;
@@ -481,8 +495,9 @@ __global__ __launch_bounds__(256) void k_accum_adj(DevSpec S, const int32_t *lis
     double U[kGradAcc];
 #pragma unroll
     for (int q = 0; q < kGradAcc; ++q) U[q] = 0.0;
+    double accT = 0.0, accG = 0.0;   // lane-local F_p-weighted logT / log g sums
     const int k_begin = blockIdx.x * kPhaseTile;
-    for (int kk = wave; kk < kPhaseTile; kk += 4) {
+    for (int kk = wave; kk < kPhaseTile; kk += kAdjWaves) {
         const int k = k_begin + kk;
         if (k >= P) break;
         float Gr[EPL];
@@ -499,6 +514,7 @@ __global__ __launch_bounds__(256) void k_accum_adj(DevSpec S, const int32_t *lis
             float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, fr = 0.f;
             int I0 = 0, m0 = 0, lo = 0;
             double wph = 0.0;
+            float Fpf = 0.f;
             if (j < g.n_cells) {
                 const double off = cell_offset(g, j);
                 if (!cell_masked(g, off)) {
@@ -517,6 +533,7 @@ __global__ __launch_bounds__(256) void k_accum_adj(DevSpec S, const int32_t *lis
                         vis = true;
                         lo = l0;
                         wph = w;
+                        Fpf = (float)Fp;
                         const double zp = A.y + w * (Cn.y - A.y);
                         const double mup = A.w + w * (Cn.w - A.w);
                         mu_clamped = !(mup > mu_lo && mup < mu_hi);
@@ -564,7 +581,7 @@ __global__ __launch_bounds__(256) void k_accum_adj(DevSpec S, const int32_t *lis
             }
             const uint64_t vmask = __ballot(vis);
             // ---------------- stage B: the visible pairs one after another
-            float R0 = 0.f, R1 = 0.f, R2 = 0.f, R3 = 0.f, R4 = 0.f;
+            float R0 = 0.f, R1 = 0.f, R2 = 0.f;
             uint64_t mask = vmask;
             while (mask) {
                 const int p = __ffsll((unsigned long long)mask) - 1;
@@ -573,7 +590,7 @@ __global__ __launch_bounds__(256) void k_accum_adj(DevSpec S, const int32_t *lis
                             pw3 = readlane_f(w3, p);
                 const float pv0 = readlane_f(v0, p), pv1 = readlane_f(v1, p), pv2 = readlane_f(v2, p),
                             pv3 = readlane_f(v3, p);
-                const float pfr = readlane_f(fr, p);
+                const float pfr = readlane_f(fr, p), pF = readlane_f(Fpf, p);
                 const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
                 const int col = pI0 - 1 + lane - xw0;
                 float4 nv = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -627,12 +644,12 @@ __global__ __launch_bounds__(256) void k_accum_adj(DevSpec S, const int32_t *lis
                     sg += G * horner(qg, f);
                 }
                 wave_sync();
-                s0 = wave_sum(s0);
-                sx = wave_sum(sx);
-                sm = wave_sum(sm);
-                sT = wave_sum(sT);
-                sg = wave_sum(sg);
-                if (lane == p) { R0 = s0; R1 = sx; R2 = sm; R3 = sT; R4 = sg; }
+                accT += (double)(pF * sT);
+                accG += (double)(pF * sg);
+                s0 = wave_total(s0);
+                sx = wave_total(sx);
+                sm = wave_total(sm);
+                if (lane == p) { R0 = s0; R1 = sx; R2 = sm; }
             }
             // ---------------- stage C: chain rule per pair, FP64
             if (vis) {
@@ -640,7 +657,7 @@ __global__ __launch_bounds__(256) void k_accum_adj(DevSpec S, const int32_t *lis
                 const double dph = Cn.z - A.z;
                 const double w = wph;
                 const double Fp = A.x + w * (Cn.x - A.x), zp = A.y + w * (Cn.y - A.y);
-                const double S0 = R0, Sx = (double)R1 * ihx, Sm = R2, ST = R3, Sg = R4;
+                const double S0 = R0, Sx = (double)R1 * ihx, Sm = R2;
                 const double cF = S0, cz = Fp * Sx / (zp * kLn10), cm = mu_clamped ? 0.0 : Fp * Sm;
                 const double dFd = Cn.x - A.x, dzd = Cn.y - A.y, dmd = Cn.w - A.w;
                 double ca, cb;
@@ -657,13 +674,14 @@ __global__ __launch_bounds__(256) void k_accum_adj(DevSpec S, const int32_t *lis
                 }
                 U[5] -= (cF * dFd + cz * dzd + cm * dmd) / dph;     // d php / d Phi = -1
                 U[6] += Fp * S0;
-                U[7] += Fp * Sg;
-                U[8] += Fp * (3.0 * kLn10 * S0 + ST - Sx);
+                U[8] += Fp * (3.0 * kLn10 * S0 - Sx);
             }
         }
     }
+    U[7] += accG;
+    U[8] += accT;
     // fixed-order block reduction of the nine sums
-    __shared__ double red[4][kGradAcc];
+    __shared__ double red[kAdjWaves][kGradAcc];
 #pragma unroll
     for (int q = 0; q < kGradAcc; ++q) {
         const double v = wave_sum_d(U[q]);
@@ -672,7 +690,8 @@ __global__ __launch_bounds__(256) void k_accum_adj(DevSpec S, const int32_t *lis
     __syncthreads();
     if (threadIdx.x < kGradAcc) {
         const int q = threadIdx.x;
-        const double v = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+        double v = 0.0;
+        for (int w8 = 0; w8 < kAdjWaves; ++w8) v += red[w8][q];
         gpart[(slot * gridDim.x + blockIdx.x) * kGradAcc + q] = v;
     }
 }
@@ -730,8 +749,9 @@ __global__ __launch_bounds__(64) void k_grad_final(DevSpec S, const StarRec *sta
 // ---------------------------------------------------------------------------
 size_t accum_adj_lds(const DevSpec &S)
 {
-    return sizeof(double4) * (S.n_fp + 1) * 6 + sizeof(double) * ((S.nmu + 1) & ~1)
-         + sizeof(float) * S.sub_stride * 3 + sizeof(float4) * 4 * 68 + sizeof(float4) * 4 * 4 * 64;
+    return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
+         + sizeof(float) * S.sub_stride * 3 + sizeof(float4) * kAdjWaves * 68
+         + sizeof(float4) * kAdjWaves * 4 * 64;
 }
 
 hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev,
@@ -750,16 +770,16 @@ hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *param
     size_t lds = accum_adj_lds(S);
     int epl = (S.E + 63) / 64;
     if (epl <= 1)
-        hipLaunchKernelGGL(k_accum_adj<1>, grid, dim3(256), lds, st, S, list, W.rings, W.ringtan, W.trace,
+        hipLaunchKernelGGL(k_accum_adj<1>, grid, dim3(64 * kAdjWaves), lds, st, S, list, W.rings, W.ringtan, W.trace,
                            W.tangent, W.sub, W.subtg, W.gtil, W.gpart);
     else if (epl <= 2)
-        hipLaunchKernelGGL(k_accum_adj<2>, grid, dim3(256), lds, st, S, list, W.rings, W.ringtan, W.trace,
+        hipLaunchKernelGGL(k_accum_adj<2>, grid, dim3(64 * kAdjWaves), lds, st, S, list, W.rings, W.ringtan, W.trace,
                            W.tangent, W.sub, W.subtg, W.gtil, W.gpart);
     else if (epl <= 4)
-        hipLaunchKernelGGL(k_accum_adj<4>, grid, dim3(256), lds, st, S, list, W.rings, W.ringtan, W.trace,
+        hipLaunchKernelGGL(k_accum_adj<4>, grid, dim3(64 * kAdjWaves), lds, st, S, list, W.rings, W.ringtan, W.trace,
                            W.tangent, W.sub, W.subtg, W.gtil, W.gpart);
     else
-        hipLaunchKernelGGL(k_accum_adj<8>, grid, dim3(256), lds, st, S, list, W.rings, W.ringtan, W.trace,
+        hipLaunchKernelGGL(k_accum_adj<8>, grid, dim3(64 * kAdjWaves), lds, st, S, list, W.rings, W.ringtan, W.trace,
                            W.tangent, W.sub, W.subtg, W.gtil, W.gpart);
     hipLaunchKernelGGL(k_grad_final, dim3(B), dim3(64), 0, st, S, W.stars, W.rings, W.ringtan, W.gpart, n_tile,
                        W.nh_part, grad);
