@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=256, help="vectors per call in the batched leg (0: skip)")
     ap.add_argument("--grad-batch", type=int, default=256, help="vectors per call in the +grad leg (0: skip)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run device-to-device copies of this many MiB (HBM counter calibration; 0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=64, help="cells per spot of the oracle sample (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -155,6 +157,15 @@ def main():
                 "finite": bool(torch.isfinite(out_g).all().item()),
                 "vs_plain": (B / tg) * plain_s}
         del glg, plang
+
+    if args.copy_mib > 0:
+        # plain copy kernel of known size: reads and writes copy_mib MiB each
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = cpu_baseline(args.cpu_sample) if args.cpu_sample > 0 else None
     out = {

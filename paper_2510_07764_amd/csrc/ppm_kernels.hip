@@ -720,10 +720,23 @@ __global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const int32_t *li
         }
         const double scale = g.w_cell * g.T * g.T * g.T;
         float *out = partial + (((size_t)b * S.R_tot + r) * P + k) * E;
+        if (EPL == 4 && (E & 3) == 0) {
+            // one 16-byte store per lane: whole cache lines, no read for ownership
+            const int e = lane * 4;
+            if (e < E) {
+                float4 v;
+                v.x = (float)(acc[0] * (scale / S.energy[e]));
+                v.y = (float)(acc[1 % EPL] * (scale / S.energy[e + 1]));
+                v.z = (float)(acc[2 % EPL] * (scale / S.energy[e + 2]));
+                v.w = (float)(acc[3 % EPL] * (scale / S.energy[e + 3]));
+                *(float4 *)(out + e) = v;
+            }
+        } else {
 #pragma unroll
-        for (int m = 0; m < EPL; ++m) {
-            int e = lane * EPL + m;
-            if (e < E) out[e] = (float)(acc[m] * (scale / S.energy[e]));
+            for (int m = 0; m < EPL; ++m) {
+                int e = lane * EPL + m;
+                if (e < E) out[e] = (float)(acc[m] * (scale / S.energy[e]));
+            }
         }
     }
     if (lane == 0 && npairs) atomicAdd(&vis_pairs[(size_t)b * S.R_tot + r], npairs);
