@@ -447,10 +447,13 @@ template <int EPL>
 __global__ __launch_bounds__(64 * kAdjWaves) void k_accum_adj(DevSpec S, const int32_t *list, const RingRec *rings,
                                                    const RingTan *ringtan, const double4 *trace,
                                                    const double4 *tangent, const float *sub, const float2 *subtg,
-                                                   const float *gtil, double *gpart)
+                                                   const float *gtil, double *gpart, int n_list)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int ent = list[blockIdx.y], b = ent / S.R_tot, r = ent - b * S.R_tot;
+    const int n_tile = (S.P + kPhaseTile - 1) / kPhaseTile;
+    int li, tile;
+    if (!xcd_block(n_list, n_tile, li, tile)) return;
+    const int ent = list[li], b = ent / S.R_tot, r = ent - b * S.R_tot;
     const size_t slot = (size_t)b * S.R_tot + r;
     const RingRec g = rings[slot];
     if (!g.active) return;
@@ -496,7 +499,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_accum_adj(DevSpec S, const i
 #pragma unroll
     for (int q = 0; q < kGradAcc; ++q) U[q] = 0.0;
     double accT = 0.0, accG = 0.0;   // lane-local F_p-weighted logT / log g sums
-    const int k_begin = blockIdx.x * kPhaseTile;
+    const int k_begin = tile * kPhaseTile;
     for (int kk = wave; kk < kPhaseTile; kk += kAdjWaves) {
         const int k = k_begin + kk;
         if (k >= P) break;
@@ -692,7 +695,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_accum_adj(DevSpec S, const i
         const int q = threadIdx.x;
         double v = 0.0;
         for (int w8 = 0; w8 < kAdjWaves; ++w8) v += red[w8][q];
-        gpart[(slot * gridDim.x + blockIdx.x) * kGradAcc + q] = v;
+        gpart[(slot * n_tile + tile) * kGradAcc + q] = v;
     }
 }
 
@@ -766,21 +769,21 @@ hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *param
                        W.rings, W.table, W.table_u, W.trace, W.tangent, W.ringtan);
     hipLaunchKernelGGL(k_subtable_tg, dim3(n_list), dim3(256), 0, st, S, list, W.rings, W.subtg);
     const int n_tile = (S.P + kPhaseTile - 1) / kPhaseTile;
-    dim3 grid(n_tile, n_list);
+    dim3 grid(xcd_grid(n_list, n_tile));
     size_t lds = accum_adj_lds(S);
     int epl = (S.E + 63) / 64;
     if (epl <= 1)
         hipLaunchKernelGGL(k_accum_adj<1>, grid, dim3(64 * kAdjWaves), lds, st, S, list, W.rings, W.ringtan, W.trace,
-                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart);
+                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n_list);
     else if (epl <= 2)
         hipLaunchKernelGGL(k_accum_adj<2>, grid, dim3(64 * kAdjWaves), lds, st, S, list, W.rings, W.ringtan, W.trace,
-                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart);
+                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n_list);
     else if (epl <= 4)
         hipLaunchKernelGGL(k_accum_adj<4>, grid, dim3(64 * kAdjWaves), lds, st, S, list, W.rings, W.ringtan, W.trace,
-                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart);
+                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n_list);
     else
         hipLaunchKernelGGL(k_accum_adj<8>, grid, dim3(64 * kAdjWaves), lds, st, S, list, W.rings, W.ringtan, W.trace,
-                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart);
+                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n_list);
     hipLaunchKernelGGL(k_grad_final, dim3(B), dim3(64), 0, st, S, W.stars, W.rings, W.ringtan, W.gpart, n_tile,
                        W.nh_part, grad);
     return hipGetLastError();

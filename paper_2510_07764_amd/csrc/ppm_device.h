@@ -216,6 +216,26 @@ __device__ inline PhaseSample phase_lookup(const double4 *tr, int nfp, double ph
     return s;
 }
 
+// The accumulation kernels run on 1D grids: block L is dispatched to XCD
+// L % kXcds (round-robin), so the n_tile phase tiles of one ring are given
+// block numbers on the same XCD and share its L2 copy of the ring's
+// sub-table and trace.  Blocks past the work list return at once.
+constexpr int kXcds = 8;
+
+__host__ __device__ inline int xcd_grid(int n_list, int n_tile)
+{
+    return kXcds * n_tile * ((n_list + kXcds - 1) / kXcds);
+}
+
+__device__ inline bool xcd_block(int n_list, int n_tile, int &li, int &tile)
+{
+    const int L = blockIdx.x, x = L % kXcds, j = L / kXcds;
+    const int g = j / n_tile;
+    tile = j - g * n_tile;
+    li = g * kXcds + x;
+    return li < n_list;
+}
+
 __device__ inline float readlane_f(float v, int lane)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));

@@ -387,10 +387,12 @@ __global__ void k_subtable(DevSpec S, const int32_t *list, const RingRec *rings,
 template <int EPL>
 __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *list, const RingRec *rings,
                                                      const double4 *trace, const float *sub,
-                                                     float *partial, int32_t *vis_pairs, int PT)
+                                                     float *partial, int32_t *vis_pairs, int PT, int n_list)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int ent = list[blockIdx.y], b = ent / S.R_tot, r = ent - b * S.R_tot;
+    int li, tile;
+    if (!xcd_block(n_list, (S.P + PT - 1) / PT, li, tile)) return;
+    const int ent = list[li], b = ent / S.R_tot, r = ent - b * S.R_tot;
     const RingRec g = rings[(size_t)b * S.R_tot + r];
     if (!g.active) return;
     const int nfp = S.n_fp, nmu = S.nmu, nx = S.nx, E = S.E, P = S.P;
@@ -418,7 +420,7 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
     }
     const double mu_lo = axmu[0], mu_hi = axmu[nmu - 1];
     int npairs = 0;
-    const int k_begin = blockIdx.x * PT;
+    const int k_begin = tile * PT;
     for (int kk = wave; kk < PT; kk += 4) {
         const int k = k_begin + kk;
         if (k >= P) break;
@@ -613,10 +615,12 @@ __device__ __forceinline__ void pairs_general(uint64_t mask, float w0, float w1,
 
 template <int EPL>
 __global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const int32_t *list, const RingRec *rings, const double4 *trace,
-                                                    const float *sub, float *partial, int32_t *vis_pairs, int PT)
+                                                    const float *sub, float *partial, int32_t *vis_pairs, int PT, int n_list)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int ent = list[blockIdx.y], b = ent / S.R_tot, r = ent - b * S.R_tot;
+    int li, tile;
+    if (!xcd_block(n_list, (S.P + PT - 1) / PT, li, tile)) return;
+    const int ent = list[li], b = ent / S.R_tot, r = ent - b * S.R_tot;
     const RingRec g = rings[(size_t)b * S.R_tot + r];
     if (!g.active) return;
     const int nfp = S.n_fp, nmu = S.nmu, nx = S.nx, E = S.E, P = S.P, W = S.W_max;
@@ -651,7 +655,7 @@ __global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const int32_t *li
     const double mu_lo = axmu[0], mu_hi = axmu[nmu - 1];
     const int xw0 = g.xw0, xw = g.xw;
     int npairs = 0;
-    const int k_begin = blockIdx.x * PT;
+    const int k_begin = tile * PT;
     for (int kk = wave; kk < PT; kk += 4) {
         const int k = k_begin + kk;
         if (k >= P) break;
@@ -747,10 +751,12 @@ __global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const int32_t *li
 // ---------------------------------------------------------------------------
 template <int EPL>
 __global__ __launch_bounds__(256) void k_accum_bb(DevSpec S, const int32_t *list, const RingRec *rings, const double4 *trace,
-                                                  double *partial, int32_t *vis_pairs, int PT)
+                                                  double *partial, int32_t *vis_pairs, int PT, int n_list)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int ent = list[blockIdx.y], b = ent / S.R_tot, r = ent - b * S.R_tot;
+    int li, tile;
+    if (!xcd_block(n_list, (S.P + PT - 1) / PT, li, tile)) return;
+    const int ent = list[li], b = ent / S.R_tot, r = ent - b * S.R_tot;
     const RingRec g = rings[(size_t)b * S.R_tot + r];
     if (!g.active) return;
     const int nfp = S.n_fp, E = S.E, P = S.P;
@@ -770,7 +776,7 @@ __global__ __launch_bounds__(256) void k_accum_bb(DevSpec S, const int32_t *list
         Ee[m] = e < E ? S.energy[e] : 1.0;
     }
     int npairs = 0;
-    const int k_begin = blockIdx.x * PT;
+    const int k_begin = tile * PT;
     for (int kk = wave; kk < PT; kk += 4) {
         const int k = k_begin + kk;
         if (k >= P) break;
@@ -979,7 +985,7 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
         hipLaunchKernelGGL(k_zero_i32, dim3((n + 255) / 256), dim3(256), 0, st, W.vis_pairs, n);
     }
     const int PT = kPhaseTile;
-    dim3 grid((S.P + PT - 1) / PT, n_list);
+    dim3 grid(xcd_grid(n_list, (S.P + PT - 1) / PT));
     if (S.intensity == PPM_I_TABLE) {
         hipLaunchKernelGGL(k_subtable, dim3(n_list), dim3(256), 0, st, S, list, W.rings, W.sub);
         size_t lds = accum_table_lds(S);
@@ -988,28 +994,28 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
         if (S.fast) {
             if (epl <= 1)
                 hipLaunchKernelGGL(k_accum_fast<1>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
-                                   W.partial32, W.vis_pairs, PT);
+                                   W.partial32, W.vis_pairs, PT, n_list);
             else if (epl <= 2)
                 hipLaunchKernelGGL(k_accum_fast<2>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
-                                   W.partial32, W.vis_pairs, PT);
+                                   W.partial32, W.vis_pairs, PT, n_list);
             else if (epl <= 4)
                 hipLaunchKernelGGL(k_accum_fast<4>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
-                                   W.partial32, W.vis_pairs, PT);
+                                   W.partial32, W.vis_pairs, PT, n_list);
             else
                 hipLaunchKernelGGL(k_accum_fast<8>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
-                                   W.partial32, W.vis_pairs, PT);
+                                   W.partial32, W.vis_pairs, PT, n_list);
         } else if (epl <= 1)
             hipLaunchKernelGGL(k_accum_table<1>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
-                               W.partial32, W.vis_pairs, PT);
+                               W.partial32, W.vis_pairs, PT, n_list);
         else if (epl <= 2)
             hipLaunchKernelGGL(k_accum_table<2>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
-                               W.partial32, W.vis_pairs, PT);
+                               W.partial32, W.vis_pairs, PT, n_list);
         else if (epl <= 4)
             hipLaunchKernelGGL(k_accum_table<4>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
-                               W.partial32, W.vis_pairs, PT);
+                               W.partial32, W.vis_pairs, PT, n_list);
         else
             hipLaunchKernelGGL(k_accum_table<8>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
-                               W.partial32, W.vis_pairs, PT);
+                               W.partial32, W.vis_pairs, PT, n_list);
         if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
         hipLaunchKernelGGL((k_reduce<float, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S, W.stars, W.rings,
                            W.partial32, want_flux_f64 ? flux_out : nullptr, W.fold_in32);
@@ -1021,16 +1027,16 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
         if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
         if (epl <= 1)
             hipLaunchKernelGGL(k_accum_bb<1>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.partial64,
-                               W.vis_pairs, PT);
+                               W.vis_pairs, PT, n_list);
         else if (epl <= 2)
             hipLaunchKernelGGL(k_accum_bb<2>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.partial64,
-                               W.vis_pairs, PT);
+                               W.vis_pairs, PT, n_list);
         else if (epl <= 4)
             hipLaunchKernelGGL(k_accum_bb<4>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.partial64,
-                               W.vis_pairs, PT);
+                               W.vis_pairs, PT, n_list);
         else
             hipLaunchKernelGGL(k_accum_bb<8>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.partial64,
-                               W.vis_pairs, PT);
+                               W.vis_pairs, PT, n_list);
         if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
         if (S.rsp64) {
             hipLaunchKernelGGL((k_reduce<double, double>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S, W.stars,
