@@ -88,7 +88,7 @@ __device__ inline D1 acos_capped(const D1 &a)
     return a.v >= 1.0 ? D1(0.0) : acos(a);
 }
 
-__global__ void k_table_u(DevSpec S, const int32_t *list, const StarRec *stars, const RingRec *rings,
+__global__ __launch_bounds__(64) void k_table_u(DevSpec S, const int32_t *list, const StarRec *stars, const RingRec *rings,
                           double4 *table_u)
 {
     const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
@@ -101,7 +101,7 @@ __global__ void k_table_u(DevSpec S, const int32_t *list, const StarRec *stars, 
     const D1 cdt_obl = kap - 1.0 + u * log((kap - u) / (1.0 - u));   // Eq. (16) over R
     const double dal = g.alpha_max / (S.n_alpha - 1);
     double4 *tab = table_u + ((size_t)b * S.R_tot + r) * S.n_alpha;
-    for (int j = threadIdx.x; j < S.n_alpha; j += blockDim.x) {
+    for (int j = blockIdx.y * blockDim.x + threadIdx.x; j < S.n_alpha; j += gridDim.y * blockDim.x) {
         double a = dal * j;
         if (j == S.n_alpha - 1) a = g.alpha_max;
         D1 psi, dpsi, T, dT;
@@ -173,7 +173,7 @@ __device__ inline D5 node(double v, double du, const D5 &u, double dk, const D5 
     return x;
 }
 
-__global__ void k_trace_tan(DevSpec S, const int32_t *list, const double *params, const int32_t *n_cells,
+__global__ __launch_bounds__(256) void k_trace_tan(DevSpec S, const int32_t *list, const double *params, const int32_t *n_cells,
                             const StarRec *stars, const RingRec *rings, const double4 *table,
                             const double4 *table_u, const double4 *trace, double4 *tangent, RingTan *ringtan)
 {
@@ -332,7 +332,7 @@ __global__ void k_trace_tan(DevSpec S, const int32_t *list, const double *params
 // collapse (linear on both axes; zero where the ring is clamped to an edge),
 // over the same x window as the forward sub-table.
 // ---------------------------------------------------------------------------
-__global__ void k_subtable_tg(DevSpec S, const int32_t *list, const RingRec *rings, float2 *subtg)
+__global__ __launch_bounds__(256) void k_subtable_tg(DevSpec S, const int32_t *list, const RingRec *rings, float2 *subtg)
 {
     const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
     const RingRec g = rings[(size_t)b * S.R_tot + r];
@@ -763,7 +763,8 @@ hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *param
 {
     hipLaunchKernelGGL(k_fold_bwd, dim3(S.P, B), dim3(256), sizeof(double) * S.C, st, S, W.stars, counts, data,
                        W.flux, W.gtil, W.nh_part);
-    hipLaunchKernelGGL(k_table_u, dim3(n_list), dim3(256), 0, st, S, list, W.stars, W.rings, W.table_u);
+    hipLaunchKernelGGL(k_table_u, dim3(n_list, (S.n_alpha + 63) / 64), dim3(64), 0, st, S, list, W.stars, W.rings,
+                       W.table_u);
     size_t lds_tt = sizeof(double4) * (2 * S.n_alpha + (S.n_fp + 1) * 5);
     hipLaunchKernelGGL(k_trace_tan, dim3(n_list), dim3(256), lds_tt, st, S, list, params, ncells_dev, W.stars,
                        W.rings, W.table, W.table_u, W.trace, W.tangent, W.ringtan);

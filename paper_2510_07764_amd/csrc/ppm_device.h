@@ -100,18 +100,22 @@ __device__ void bend_out(const DevSpec &S, const U &u, double alpha, U &psi, U &
     gl_rule(S, n, gx, gw);
     U A = c / (s * sqrt(q0));
     U L = asinh(1.0 / A);
+    const U w = u / (1.0 - u);        // q(x) = 2 - x^2 - w (1 - x^2)^2
+    const U hA = 0.5 * A, hAL = 0.5 * A * L;
+    const double s2 = s * s, c2 = c * c;
     U I1 = U(0.0), I3 = U(0.0), IT = U(0.0);
     for (int q = 0; q < n; ++q) {
         U ex = exp(L * gx[q]);
         U iex = 1.0 / ex;
-        U x = 0.5 * A * (ex - iex);
-        U dx = 0.5 * A * (ex + iex) * L * gw[q];
-        U D = c * c + x * x * s * s * q_s2(x, u);
+        U x = hA * (ex - iex);
+        U dx = hAL * (ex + iex) * gw[q];
+        U x2 = x * x, t = 1.0 - x2;
+        U D = c2 + x2 * s2 * (2.0 - x2 - w * t * t);
         U r = sqrt(D);
         U ir = 1.0 / r;
         U xr = x * ir * dx;
         I1 += xr;
-        I3 += xr / D;
+        I3 += xr * ir * ir;
         IT += xr / (1.0 + r);
     }
     psi = 2.0 * s / sq * I1;
@@ -126,16 +130,19 @@ __device__ void grazing(const DevSpec &S, const U &v, U &ph, U &dph, U &th, U &d
     U J = U(0.0), J3 = U(0.0), K = U(0.0), K1 = U(0.0);
     const double *gx, *gw;
     gl_rule(S, 48, gx, gw);   // smooth integrands (q(0) > 0 below the photon sphere)
+    const U vw = v / (1.0 - v);
     for (int q = 0; q < 48; ++q) {
         double x = gx[q], w = gw[q];
-        double t = 1.0 - x * x;
-        U Q = 2.0 - x * x - v * t * t / (1.0 - v);
+        double t = 1.0 - x * x, tt = t * t;
+        U Q = 2.0 - x * x - vw * tt;
         U rq = sqrt(Q);
-        J += w / rq;
-        J3 += w * t * t / (Q * rq);
+        U irq = 1.0 / rq;
+        J += w * irq;
+        J3 += w * tt * (irq * irq * irq);
         U gq = rq + x * Q;
-        K += w / gq;
-        K1 += w * (0.5 / rq + x) * t * t / (gq * gq);
+        U igq = 1.0 / gq;
+        K += w * igq;
+        K1 += w * (0.5 * irq + x) * tt * (igq * igq);
     }
     U om = 1.0 - v;
     ph = 2.0 / sqrt(om) * J;

@@ -3,8 +3,8 @@
 // Pipeline of one evaluation (all instances of a batch at once):
 //   k_setup      FP64 star and ring records, parameter validation
 //   k_table      FP64 per-ring deflection / delay table on alpha nodes
-//   k_trace      FP64 pseudo-patch fine-phase trace with invisible fill
-//   k_subtable   per-ring (logT, log g) collapse of the atmosphere table
+//   k_trace      FP64 pseudo-patch fine-phase trace with invisible fill, then
+//                the per-ring (logT, log g) collapse of the atmosphere table
 //   k_accum_*    shift-and-add intensity accumulation (the hot loop)
 //   k_reduce     deterministic sum over rings, absorption
 //   k_fold_*     response fold on the matrix cores (MFMA)
@@ -48,8 +48,8 @@ __host__ __device__ int validate_params(const double *p, int n_spots)
 // ---------------------------------------------------------------------------
 // k_setup: star (Eqs. 7, 8, 11) and spot rings (Eqs. 2, 3, 9, 10, 18)
 // ---------------------------------------------------------------------------
-__global__ void k_setup(DevSpec S, const double *params, const int32_t *n_cells, StarRec *stars,
-                        RingRec *rings)
+__global__ __launch_bounds__(64) void k_setup(DevSpec S, const double *params, const int32_t *n_cells, StarRec *stars,
+                        RingRec *rings, int32_t *vis_pairs)
 {
     const int b = blockIdx.y;
     const double *p = params + (size_t)b * PPM_NPARAM;
@@ -135,6 +135,7 @@ __global__ void k_setup(DevSpec S, const double *params, const int32_t *n_cells,
         g.cos_zm = cos(S.shape_a[spot] * z);
         if (live) g.n_cells = np;
         rings[(size_t)b * S.R_tot + r] = g;
+        vis_pairs[(size_t)b * S.R_tot + r] = 0;
     }
 }
 
@@ -147,7 +148,7 @@ __global__ void k_setup(DevSpec S, const double *params, const int32_t *n_cells,
 // sqrt(q0)), which resolves the boundary layer of width ~cos(alpha) at
 // x -> 0 for near-grazing rays.
 // ---------------------------------------------------------------------------
-__global__ void k_table(DevSpec S, const int32_t *list, const StarRec *stars, const RingRec *rings, double4 *table)
+__global__ __launch_bounds__(64) void k_table(DevSpec S, const int32_t *list, const StarRec *stars, const RingRec *rings, double4 *table)
 {
     const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
     const RingRec g = rings[(size_t)b * S.R_tot + r];
@@ -156,7 +157,7 @@ __global__ void k_table(DevSpec S, const int32_t *list, const StarRec *stars, co
     const double u = g.u;
     const double dal = g.alpha_max / (S.n_alpha - 1);
     double4 *tab = table + ((size_t)b * S.R_tot + r) * S.n_alpha;
-    for (int j = threadIdx.x; j < S.n_alpha; j += blockDim.x) {
+    for (int j = blockIdx.y * blockDim.x + threadIdx.x; j < S.n_alpha; j += gridDim.y * blockDim.x) {
         double a = dal * j;
         if (j == S.n_alpha - 1) a = g.alpha_max;
         double psi, dpsi, T, dT;
@@ -193,10 +194,47 @@ __global__ void k_table(DevSpec S, const int32_t *list, const StarRec *stars, co
 }
 
 // ---------------------------------------------------------------------------
+// subtable_ring: linear (logT, log g) collapse of the atmosphere table for one
+// ring (run by k_trace once the ring's x window is known) (mixed-order scheme of Sect. 4: linear on these two axes, clamped at
+// the edges), giving sub[mu][x] = I/T^3 at the ring's (logT, log g).
+// ---------------------------------------------------------------------------
+__device__ static void subtable_ring(const DevSpec &S, const RingRec &g, int xw0, int xw, size_t slot, float *sub)
+{
+    double wt1, wg1;
+    int it = lin_bracket(g.logT, S.T0, S.hT, S.nT, wt1);
+    int ig = lin_bracket(g.logg, S.g0, S.hg, S.ng, wg1);
+    const float w00 = (float)((1.0 - wt1) * (1.0 - wg1)), w01 = (float)((1.0 - wt1) * wg1);
+    const float w10 = (float)(wt1 * (1.0 - wg1)), w11 = (float)(wt1 * wg1);
+    const size_t slab = (size_t)S.nmu * S.nx;
+    const float *s00 = S.atm + ((size_t)it * S.ng + ig) * slab;
+    const float *s01 = s00 + slab;
+    const float *s10 = S.atm + ((size_t)(it + 1) * S.ng + ig) * slab;
+    const float *s11 = s10 + slab;
+    if (S.fast) {
+        // window [xw0, xw0 + W_max) of every mu row, row stride W_max
+        const int W = S.W_max;
+        float *out = sub + slot * (size_t)S.sub_stride;
+        for (int i = threadIdx.x; i < S.nmu * W; i += blockDim.x) {
+            int m = i / W, c = i - m * W;
+            float v = 0.0f;
+            if (c < xw) {
+                size_t o = (size_t)m * S.nx + xw0 + c;
+                v = w00 * s00[o] + w01 * s01[o] + w10 * s10[o] + w11 * s11[o];
+            }
+            out[i] = v;
+        }
+        return;
+    }
+    float *out = sub + slot * slab;
+    for (size_t i = threadIdx.x; i < slab; i += blockDim.x)
+        out[i] = w00 * s00[i] + w01 * s01[i] + w10 * s10[i] + w11 * s11[i];
+}
+
+// ---------------------------------------------------------------------------
 // k_trace: pseudo-patch light curve of one ring (Sect. 2.8.3, Eqs. 38-44)
 // ---------------------------------------------------------------------------
-__global__ void k_trace(DevSpec S, const int32_t *list, const StarRec *stars, RingRec *rings, const double4 *table,
-                        double4 *trace)
+__global__ __launch_bounds__(256) void k_trace(DevSpec S, const int32_t *list, const StarRec *stars, RingRec *rings, const double4 *table,
+                        double4 *trace, float *sub)
 {
     extern __shared__ double4 lds_tab[];
     const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
@@ -299,6 +337,7 @@ __global__ void k_trace(DevSpec S, const int32_t *list, const StarRec *stars, Ri
         if (v.y > 0.0) { zlo = fmin(zlo, v.y); zhi = fmax(zhi, v.y); }
     }
     __shared__ double red_lo[256], red_hi[256];
+    __shared__ int sh_active, sh_w0, sh_w;
     red_lo[threadIdx.x] = zlo;
     red_hi[threadIdx.x] = zhi;
     __syncthreads();
@@ -332,48 +371,15 @@ __global__ void k_trace(DevSpec S, const int32_t *list, const StarRec *stars, Ri
             gp->interior = 0;
         }
         gp->active = active;
+        sh_active = active;
+        sh_w0 = gp->xw0;
+        sh_w = gp->xw;
     }
+    __syncthreads();
+    // the ring's (logT, log g) collapse of the atmosphere table
+    if (sh_active && S.intensity == PPM_I_TABLE) subtable_ring(S, g, sh_w0, sh_w, (size_t)b * S.R_tot + r, sub);
 }
 
-// ---------------------------------------------------------------------------
-// k_subtable: linear (logT, log g) collapse of the atmosphere table for one
-// ring (mixed-order scheme of Sect. 4: linear on these two axes, clamped at
-// the edges), giving sub[mu][x] = I/T^3 at the ring's (logT, log g).
-// ---------------------------------------------------------------------------
-__global__ void k_subtable(DevSpec S, const int32_t *list, const RingRec *rings, float *sub)
-{
-    const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
-    const RingRec g = rings[(size_t)b * S.R_tot + r];
-    if (!g.active) return;
-    double wt1, wg1;
-    int it = lin_bracket(g.logT, S.T0, S.hT, S.nT, wt1);
-    int ig = lin_bracket(g.logg, S.g0, S.hg, S.ng, wg1);
-    const float w00 = (float)((1.0 - wt1) * (1.0 - wg1)), w01 = (float)((1.0 - wt1) * wg1);
-    const float w10 = (float)(wt1 * (1.0 - wg1)), w11 = (float)(wt1 * wg1);
-    const size_t slab = (size_t)S.nmu * S.nx;
-    const float *s00 = S.atm + ((size_t)it * S.ng + ig) * slab;
-    const float *s01 = s00 + slab;
-    const float *s10 = S.atm + ((size_t)(it + 1) * S.ng + ig) * slab;
-    const float *s11 = s10 + slab;
-    if (S.fast) {
-        // window [xw0, xw0 + W_max) of every mu row, row stride W_max
-        const int W = S.W_max, xw0 = g.xw0, xw = g.xw;
-        float *out = sub + ((size_t)b * S.R_tot + r) * (size_t)S.sub_stride;
-        for (int i = threadIdx.x; i < S.nmu * W; i += blockDim.x) {
-            int m = i / W, c = i - m * W;
-            float v = 0.0f;
-            if (c < xw) {
-                size_t o = (size_t)m * S.nx + xw0 + c;
-                v = w00 * s00[o] + w01 * s01[o] + w10 * s10[o] + w11 * s11[o];
-            }
-            out[i] = v;
-        }
-        return;
-    }
-    float *out = sub + ((size_t)b * S.R_tot + r) * slab;
-    for (size_t i = threadIdx.x; i < slab; i += blockDim.x)
-        out[i] = w00 * s00[i] + w01 * s01[i] + w10 * s10[i] + w11 * s11[i];
-}
 
 // ---------------------------------------------------------------------------
 // k_accum_table: shift-and-add with the mixed-order atmosphere table
@@ -850,31 +856,88 @@ __global__ __launch_bounds__(256) void k_reduce(DevSpec S, const StarRec *stars,
     }
 }
 
+// FP32 partials with E % 4 == 0: a thread owns four consecutive energies and
+// reads them with 16-byte loads; eight ring groups per block.
+__global__ __launch_bounds__(512) void k_reduce4(DevSpec S, const StarRec *stars, const RingRec *rings,
+                                                 const float *partial, double *flux, float *fold_in)
+{
+    extern __shared__ unsigned char act[];
+    __shared__ double4 red[8][64];
+    const int k = blockIdx.x, b = blockIdx.z;
+    const int E = S.E, P = S.P, R = S.R_tot;
+    const int el = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int e = (blockIdx.y * 64 + el) * 4;
+    for (int r = threadIdx.x; r < R; r += blockDim.x) act[r] = (unsigned char)rings[(size_t)b * R + r].active;
+    __syncthreads();
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (e < E) {
+        const float *base = partial + ((size_t)b * R * P + k) * E + e;
+        const size_t rs = (size_t)P * E;
+        for (int r = grp; r < R; r += 8) {
+            if (!act[r]) continue;
+            const float4 v = *(const float4 *)(base + r * rs);
+            s0 += (double)v.x;
+            s1 += (double)v.y;
+            s2 += (double)v.z;
+            s3 += (double)v.w;
+        }
+    }
+    red[grp][el] = make_double4(s0, s1, s2, s3);
+    __syncthreads();
+    if (grp == 0 && e < E) {
+        double t[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int g2 = 0; g2 < 8; ++g2) {
+            const double4 v = red[g2][el];
+            t[0] += v.x; t[1] += v.y; t[2] += v.z; t[3] += v.w;
+        }
+        const StarRec st = stars[b];
+        const size_t o = ((size_t)b * P + k) * E + e;
+        for (int q = 0; q < 4; ++q) {
+            double sv = st.status != PPM_INST_OK ? 0.0 : t[q];
+            if (flux) flux[o + q] = sv;
+            double att = S.sigma ? exp(-st.NH * S.sigma[e + q]) : 1.0;
+            fold_in[o + q] = (float)(sv * att * (S.t_exp / P));
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
-// k_fold: counts[M][C] = A[M][E] . RSP[E][C] on the matrix cores.  One wave
-// per 16x16 output tile, K in steps of 4 (v_mfma_*_16x16x4): lane l supplies
-// A[l%16][k0 + l/16] and RSP[k0 + l/16][l%16]; the tile comes back as
-// D[4 (l/16) + v][l%16] in accumulator v.
+// k_fold: counts[M][C] = A[M][E] . RSP[E][C] on the matrix cores.  Block =
+// one 16x16 output tile, four waves splitting K into quarters; per wave K in
+// steps of 4 (v_mfma_f32_16x16x4f32): lane l supplies A[l%16][k0 + l/16] and
+// RSP[k0 + l/16][l%16]; the tile comes back as D[4 (l/16) + v][l%16] in
+// accumulator v.  The four partial tiles are summed in LDS in wave order.
 // ---------------------------------------------------------------------------
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(64) void k_fold_f32(const float *A, const float *B, double *out, int M,
-                                                 int N, int K)
+__global__ __launch_bounds__(256) void k_fold_f32(const float *A, const float *B, double *out, int M,
+                                                  int N, int K)
 {
+    __shared__ floatx4 part[4][64];
     const int n0 = blockIdx.x * 16, m0 = blockIdx.y * 16;
-    const int l = threadIdx.x, li = l & 15, lk = l >> 4;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+    const int kq = ((K + 15) / 16) * 4;
+    const int kb = wave * kq, ke = min(K, kb + kq);
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     const bool mrow = (m0 + li) < M, ncol = (n0 + li) < N;
-    for (int k0 = 0; k0 < K; k0 += 4) {
+    for (int k0 = kb; k0 < ke; k0 += 4) {
         const int k = k0 + lk;
-        float a = (mrow && k < K) ? A[(size_t)(m0 + li) * K + k] : 0.0f;
-        float bv = (ncol && k < K) ? B[(size_t)k * N + n0 + li] : 0.0f;
+        float a = (mrow && k < ke) ? A[(size_t)(m0 + li) * K + k] : 0.0f;
+        float bv = (ncol && k < ke) ? B[(size_t)k * N + n0 + li] : 0.0f;
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
     }
+    part[wave][l] = acc;
+    __syncthreads();
+    if (wave == 0) {
+        floatx4 t = part[0][l];
+        t += part[1][l];
+        t += part[2][l];
+        t += part[3][l];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        int row = m0 + 4 * lk + v, col = n0 + li;
-        if (row < M && col < N) out[(size_t)row * N + col] = (double)acc[v];
+        for (int v = 0; v < 4; ++v) {
+            int row = m0 + 4 * lk + v, col = n0 + li;
+            if (row < M && col < N) out[(size_t)row * N + col] = (double)t[v];
+        }
     }
 }
 
@@ -893,7 +956,7 @@ __global__ __launch_bounds__(256) void k_fold_f64(const double *A, const double 
 // k_loglike: Poisson log-likelihood per instance, FP64, fixed-order block
 // reduction.  d = 0 contributes -m; m <= 0 with d > 0 gives -inf.
 // ---------------------------------------------------------------------------
-constexpr int kLLChunk = 2048;   // bins per block of the first likelihood stage
+constexpr int kLLChunk = 512;    // bins per block of the first likelihood stage
 
 __global__ __launch_bounds__(256) void k_loglike_part(const double *counts, const int32_t *data, int PC,
                                                       double *part, int32_t *bad)
@@ -943,12 +1006,6 @@ __global__ void k_loglike_final(const StarRec *stars, const double *part, const 
     logl[b] = s;
 }
 
-__global__ void k_zero_i32(int32_t *p, size_t n)
-{
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
 __global__ void k_status(const StarRec *stars, int B, int32_t *out)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -975,19 +1032,15 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
 {
     const bool want_flux_f64 = flux_out != nullptr;
     hipLaunchKernelGGL(k_setup, dim3((S.R_tot + 63) / 64, B), dim3(64), 0, st, S, params, ncells_dev, W.stars,
-                       W.rings);
-    hipLaunchKernelGGL(k_table, dim3(n_list), dim3(256), 0, st, S, list, W.stars, W.rings, W.table);
+                       W.rings, W.vis_pairs);
+    hipLaunchKernelGGL(k_table, dim3(n_list, (S.n_alpha + 63) / 64), dim3(64), 0, st, S, list, W.stars, W.rings,
+                       W.table);
     size_t lds_tr = sizeof(double4) * (S.n_alpha + S.n_fp + 1);
     hipLaunchKernelGGL(k_trace, dim3(n_list), dim3(256), lds_tr, st, S, list, W.stars, W.rings, W.table,
-                       W.trace);
-    {
-        size_t n = (size_t)B * S.R_tot;
-        hipLaunchKernelGGL(k_zero_i32, dim3((n + 255) / 256), dim3(256), 0, st, W.vis_pairs, n);
-    }
+                       W.trace, W.sub);
     const int PT = kPhaseTile;
     dim3 grid(xcd_grid(n_list, (S.P + PT - 1) / PT));
     if (S.intensity == PPM_I_TABLE) {
-        hipLaunchKernelGGL(k_subtable, dim3(n_list), dim3(256), 0, st, S, list, W.rings, W.sub);
         size_t lds = accum_table_lds(S);
         if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
         int epl = (S.E + 63) / 64;
@@ -1017,9 +1070,13 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
             hipLaunchKernelGGL(k_accum_table<8>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
                                W.partial32, W.vis_pairs, PT, n_list);
         if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
-        hipLaunchKernelGGL((k_reduce<float, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S, W.stars, W.rings,
-                           W.partial32, want_flux_f64 ? flux_out : nullptr, W.fold_in32);
-        hipLaunchKernelGGL(k_fold_f32, dim3((S.C + 15) / 16, (B * S.P + 15) / 16), dim3(64), 0, st,
+        if ((S.E & 3) == 0)
+            hipLaunchKernelGGL(k_reduce4, dim3(S.P, (S.E + 255) / 256, B), dim3(512), S.R_tot, st, S, W.stars,
+                               W.rings, W.partial32, want_flux_f64 ? flux_out : nullptr, W.fold_in32);
+        else
+            hipLaunchKernelGGL((k_reduce<float, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S,
+                               W.stars, W.rings, W.partial32, want_flux_f64 ? flux_out : nullptr, W.fold_in32);
+        hipLaunchKernelGGL(k_fold_f32, dim3((S.C + 15) / 16, (B * S.P + 15) / 16), dim3(256), 0, st,
                            W.fold_in32, S.rsp32, counts_out, B * S.P, S.C, S.E);
     } else {
         size_t lds = sizeof(double4) * (S.n_fp + 1);
@@ -1046,7 +1103,7 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
         } else {
             hipLaunchKernelGGL((k_reduce<double, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S, W.stars,
                                W.rings, W.partial64, want_flux_f64 ? flux_out : nullptr, W.fold_in32);
-            hipLaunchKernelGGL(k_fold_f32, dim3((S.C + 15) / 16, (B * S.P + 15) / 16), dim3(64), 0, st,
+            hipLaunchKernelGGL(k_fold_f32, dim3((S.C + 15) / 16, (B * S.P + 15) / 16), dim3(256), 0, st,
                                W.fold_in32, S.rsp32, counts_out, B * S.P, S.C, S.E);
         }
     }
