@@ -34,7 +34,7 @@ struct Workspace {
     double *gpart;         // [B][R_tot][n_tile][kGradAcc] per-block adjoint sums
 };
 
-constexpr int kPhaseTile = 16;   // phases per block of the accumulation kernels
+constexpr int kPhaseTile = 8;    // phases per block of the accumulation kernels
 constexpr int kGradAcc = 9;      // per-ring adjoint sums of the accumulation kernel
 
 __host__ __device__ int validate_params(const double *p, int n_spots);
