@@ -14,6 +14,7 @@ graph-replayed plain rate, the batched rate (B vectors per call) and the
 reported beside it.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -30,6 +31,31 @@ METRIC = "forward+logL evals/sec at config[1], plain vs batched vs +grad, <=1e-4
 # an energy window touches (8 FLOP each) amortised over 256 energies (~2).
 FLOP_PER_UNIT = 24.0
 PEAK_FP32_TFLOPS = 157.3
+
+# HBM traffic of the hot kernel per launch (config-1 workload, one vector):
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two rocprofv3 --pmc runs,
+# each scaled by what the same counter reads for a 256 MiB device-to-device
+# copy (FETCH_SIZE reads half the copied bytes on this part, WRITE_SIZE all
+# of them).  Valid only for the kernel sources the counters were taken on;
+# any change to them reports null until the counters are taken again.
+KERNEL_SOURCES = ("ppm_kernels.hip", "ppm_device.h", "ppm_dual.h", "ppm_internal.h", "ppm_launch.h")
+TRAFFIC = {"sources_sha256": None, "fetch_kib": None, "write_kib": None, "fetch_scale": None,
+           "write_scale": None, "profile": "profiles/k_accum_fast_config1_traffic.md"}
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_07764_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def hot_kernel_traffic():
+    t = TRAFFIC
+    if t["sources_sha256"] is None or t["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 
 
 def cpu_baseline(sample_cells: int):
@@ -59,6 +85,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=256, help="vectors per call in the batched leg (0: skip)")
+    ap.add_argument("--batch-large", type=int, default=1024,
+                    help="vectors per call in the second batched leg (0: skip)")
     ap.add_argument("--grad-batch", type=int, default=256, help="vectors per call in the +grad leg (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run device-to-device copies of this many MiB (HBM counter calibration; 0: skip)")
@@ -117,12 +145,16 @@ def main():
     del gl1
 
     # ---------------- batched: B config-1-shape vectors per graph replay
-    batched = None
-    if args.batch > 0:
-        B = args.batch
+    def batched_leg(B):
         draws = syn.config4_draws(B)
         planb = ppm.Plan(spec, max_batch=B)
         ptb = torch.tensor(draws, dtype=torch.float64, device=dev)
+        # one direct call with the hot kernel timed (events on the launch stream)
+        planb.profile_begin(64)
+        planb.loglike(ptb, data_t)
+        torch.cuda.synchronize()
+        hms, nh = planb.profile_end()
+        bunits = planb.visible_pairs(B) * planb.n_energy
         glb = ppm.GraphedLogLike(planb, data_t, B)
         glb(ptb)
         torch.cuda.synchronize()
@@ -132,10 +164,16 @@ def main():
             out_b = glb(ptb)
         torch.cuda.synchronize()
         tb = (time.perf_counter() - t0) / kb
-        batched = {"evals_per_s": B / tb, "batch": B, "ms_per_call": tb * 1e3, "calls": kb,
-                   "finite": bool(torch.isfinite(out_b).all().item()),
-                   "vs_plain": (B / tb) * plain_s}
+        bach = bunits * FLOP_PER_UNIT / (hms * 1e-3) / 1e12
+        res = {"evals_per_s": B / tb, "batch": B, "ms_per_call": tb * 1e3, "calls": kb,
+               "finite": bool(torch.isfinite(out_b).all().item()), "vs_plain": (B / tb) * plain_s,
+               "hot_kernel_ms": hms, "hot_kernel_launches": nh, "units": bunits,
+               "roofline_frac": bach / PEAK_FP32_TFLOPS}
         del glb, planb
+        return res
+
+    batched = batched_leg(args.batch) if args.batch > 0 else None
+    batched_large = batched_leg(args.batch_large) if args.batch_large > 0 else None
 
     # ---------------- +grad: logL and the twelve-parameter gradient, B vectors per graph replay
     grad = None
@@ -187,9 +225,10 @@ def main():
         "plain_graph": {"evals_per_s": 1.0 / plain_graph_s, "ms_per_call": plain_graph_s * 1e3,
                         "matches_direct": graph_ok},
         "batched": batched,
+        "batched_large": batched_large,
         "grad": grad,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": hot_kernel_traffic(),
                      "kernel": "k_accum_fast<4>", "kernel_ms": hot_avg_s * 1e3, "units": units,
                      "flop_per_unit": FLOP_PER_UNIT},
         "cpu_baseline": cpu,

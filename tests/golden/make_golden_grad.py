@@ -7,9 +7,11 @@ Calls only the FP64 CPU oracle (and the seeded input generators):
                      (128x128 cells per spot, 128 phases, 256 energies) and
                      the stored config-1 data: the oracle's logL and its
                      central finite differences over the twelve
-                     differentiable slots with steps h_i = s |theta_i|,
-                     s = 1e-4 and s = 1e-6.
-Run: python tests/golden/make_golden_grad.py   (about an hour on 8 cores)
+                     differentiable slots with steps h_i = s |theta_i| for
+                     s in 1e-4, 1e-5, 1e-6, 1e-7.
+Steps already present in an existing file are kept (each step set takes
+about 20 minutes on 8 cores).
+Run: python tests/golden/make_golden_grad.py
 """
 import json
 import os
@@ -24,20 +26,32 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 import synthetic as syn  # noqa: E402
 
+STEPS = (1e-4, 1e-5, 1e-6, 1e-7)
+
 
 def main():
+    path = os.path.join(HERE, "config4_grad.json")
     spec, _ = syn.config1()
     os_ = oracle.OracleSpec(spec)
     data = np.load(os.path.join(HERE, "config1_data.npy"))
     q = syn.config4_draws(1)[0]
+    out = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            out = json.load(f)
+        assert np.array_equal(np.array(out["params"]), q)
     t0 = time.time()
-    out = dict(params=q.tolist(), slots=list(syn.GRAD_SLOTS), loglike=oracle.loglike(os_, q, data))
-    for s in (1e-4, 1e-6):
+    if "loglike" not in out:
+        out.update(params=q.tolist(), slots=list(syn.GRAD_SLOTS), loglike=oracle.loglike(os_, q, data))
+    for s in STEPS:
+        key = "fd_%g" % s
+        if key in out:
+            continue
         g = oracle.fd_gradient(os_, q, data, syn.GRAD_SLOTS, rel_step=s)
-        out["fd_%g" % s] = g.tolist()
+        out[key] = g.tolist()
         print(s, g.tolist(), "%.0f s" % (time.time() - t0), flush=True)
-    with open(os.path.join(HERE, "config4_grad.json"), "w") as f:
-        json.dump(out, f, indent=1)
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
 
 
 if __name__ == "__main__":
