@@ -39,8 +39,9 @@ PEAK_FP32_TFLOPS = 157.3
 # of them).  Valid only for the kernel sources the counters were taken on;
 # any change to them reports null until the counters are taken again.
 KERNEL_SOURCES = ("ppm_kernels.hip", "ppm_device.h", "ppm_dual.h", "ppm_internal.h", "ppm_launch.h")
-TRAFFIC = {"sources_sha256": None, "fetch_kib": None, "write_kib": None, "fetch_scale": None,
-           "write_scale": None, "profile": "profiles/k_accum_fast_config1_traffic.md"}
+TRAFFIC = {"sources_sha256": "221e61ff896ddbe90930f0abaac6f778a07c0666ca62f7272a5c4a2f315fe759",
+           "fetch_kib": 4287.48, "write_kib": 33198.96, "fetch_scale": 1.99980, "write_scale": 1.0,
+           "profile": "profiles/k_accum_fast_config1_traffic.md"}
 
 
 def kernel_sources_sha256():
@@ -90,7 +91,8 @@ def main():
     ap.add_argument("--grad-batch", type=int, default=256, help="vectors per call in the +grad leg (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run device-to-device copies of this many MiB (HBM counter calibration; 0: skip)")
-    ap.add_argument("--cpu-sample", type=int, default=64, help="cells per spot of the oracle sample (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=128,
+                    help="cells per spot of the oracle sample (128: the whole workload; 0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the batched path shards "
