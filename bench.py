@@ -59,25 +59,38 @@ def hot_kernel_traffic():
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 
 
-def cpu_baseline(sample_cells: int):
-    import numpy as np
-
+def cpu_baseline(sample_cells: int, one_core_cells: int):
+    """The FP64 oracle timed on the host: all cores (at most 16, the box's
+    share) on sample_cells per spot, and one core on one_core_cells per spot;
+    work is linear in the number of cells, so each is scaled to the whole
+    workload."""
     import oracle
     import synthetic as syn
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(os.cpu_count() or 1, 16)
-    os.environ["OMP_NUM_THREADS"] = str(threads)
-    spec, p = syn.config1(n_cells=sample_cells)
-    os_ = oracle.OracleSpec(spec)
-    t0 = time.perf_counter()
-    _, cnt, _ = oracle.forward(os_, p)
-    data = syn.poisson_data(cnt)
-    oracle.loglike_from_counts(cnt, data)
-    dt = time.perf_counter() - t0
-    scale = (128.0 / sample_cells) ** 2          # work is linear in the number of cells
-    return {"value": 1.0 / (dt * scale), "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"config-1 workload at {sample_cells}x{sample_cells} cells per spot "
-                      f"(1/{scale:.0f} of the cells, all phases/energies/channels), {dt:.2f} s, "
-                      f"scaled linearly in cells"}
+
+    def run(cells, threads):
+        oracle.set_threads(threads)
+        spec, p = syn.config1(n_cells=cells)
+        os_ = oracle.OracleSpec(spec)
+        t0 = time.perf_counter()
+        _, cnt, _ = oracle.forward(os_, p)
+        data = syn.poisson_data(cnt)
+        oracle.loglike_from_counts(cnt, data)
+        dt = time.perf_counter() - t0
+        scale = (128.0 / cells) ** 2
+        return dt, scale
+
+    threads = min(os.cpu_count() or 1, 16)
+    dt, scale = run(sample_cells, threads)
+    out = {"value": 1.0 / (dt * scale), "unit": "evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"config-1 workload at {sample_cells}x{sample_cells} cells per spot "
+                     f"({'the whole workload' if scale == 1 else f'1/{scale:.0f} of the cells, scaled linearly'}; "
+                     f"all phases/energies/channels), {dt:.2f} s on {threads} threads"}
+    if one_core_cells > 0:
+        dt1, scale1 = run(one_core_cells, 1)
+        out["one_core"] = {"value": 1.0 / (dt1 * scale1), "unit": "evals/s", "cores": 1,
+                           "sample": f"{one_core_cells}x{one_core_cells} cells per spot (1/{scale1:.0f} of the "
+                                     f"cells), {dt1:.2f} s, scaled linearly"}
+    return out
 
 
 def main():
@@ -89,6 +102,8 @@ def main():
     ap.add_argument("--batch-large", type=int, default=1024,
                     help="vectors per call in the second batched leg (0: skip)")
     ap.add_argument("--grad-batch", type=int, default=256, help="vectors per call in the +grad leg (0: skip)")
+    ap.add_argument("--cpu-one-core", type=int, default=32,
+                    help="cells per spot of the single-core oracle sample (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run device-to-device copies of this many MiB (HBM counter calibration; 0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=128,
@@ -207,7 +222,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    cpu = cpu_baseline(args.cpu_sample) if args.cpu_sample > 0 else None
+    cpu = cpu_baseline(args.cpu_sample, args.cpu_one_core) if args.cpu_sample > 0 else None
     out = {
         "metric": METRIC,
         "value": 1.0 / plain_s,

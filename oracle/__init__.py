@@ -107,6 +107,8 @@ def lib():
         L.orc_forward.argtypes = [C.POINTER(Spec), _D, _D, _D, C.POINTER(Diag)]
         L.orc_loglike_counts.restype = C.c_double
         L.orc_loglike_counts.argtypes = [_D, C.POINTER(C.c_int), C.c_longlong]
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -181,6 +183,11 @@ def loglike_from_counts(counts, data) -> float:
 def loglike(spec, params, data) -> float:
     _, cnt, _ = forward(spec, params)
     return loglike_from_counts(cnt, data)
+
+
+def set_threads(n: int):
+    """OpenMP threads of the oracle's ring loop (timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 def fd_gradient(spec, params, data, slots, rel_step=1e-4):

@@ -698,6 +698,17 @@ int orc_forward(const orc_spec *s, const double *p, double *Ft, double *counts, 
     return 0;
 }
 
+/* Threads of the ring loop of orc_forward (timing only; results do not
+ * depend on it). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Poisson log-likelihood  sum d ln m - m - ln Gamma(d + 1). */
 double orc_loglike_counts(const double *m, const int *d, long long n)
 {

@@ -90,6 +90,7 @@ double orc_blackbody(double E_kev, double T_kelvin);
    counts[P][C] (NULL to skip). */
 int orc_forward(const orc_spec *s, const double *p, double *Ft, double *counts, orc_diag *diag);
 double orc_loglike_counts(const double *counts, const int *data, long long n);
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }
