@@ -50,7 +50,7 @@ class Spec(C.Structure):
                 ("nT", C.c_int), ("ng", C.c_int), ("nmu", C.c_int), ("nx", C.c_int),
                 ("ax_T", C.POINTER(C.c_double)), ("ax_g", C.POINTER(C.c_double)),
                 ("ax_mu", C.POINTER(C.c_double)), ("ax_x", C.POINTER(C.c_double)),
-                ("logI", C.POINTER(C.c_double))]
+                ("logI", C.POINTER(C.c_double)), ("interp", C.c_int)]
 
 
 class Diag(C.Structure):
@@ -157,6 +157,7 @@ class OracleSpec:
             s.nT, s.ng, s.nmu, s.nx = logi.shape
             s.ax_T, s.ax_g, s.ax_mu, s.ax_x = [_ptr(a) for a in axes]
             s.logI = _ptr(logi)
+        s.interp = int(spec.get("interp", 0))
         self.s = s
         self.n_phase = s.n_phase
         self.n_energy = s.n_energy

@@ -502,23 +502,67 @@ static int find_interval(const double *ax, int n, double v)
     return i;
 }
 
-/* Mixed-order interpolation (Sect. 4; strategy (d)):
+/* Four-node Lagrange weights on nodes ax[s0 .. s0+3] at v. */
+static void lagrange_at(const double *ax, int s0, double v, double w[4])
+{
+    for (int a = 0; a < 4; ++a) {
+        double num = 1.0, den = 1.0;
+        for (int b = 0; b < 4; ++b) {
+            if (b == a) continue;
+            num *= v - ax[s0 + b];
+            den *= ax[s0 + a] - ax[s0 + b];
+        }
+        w[a] = num / den;
+    }
+}
+
+/* Cubic stencil of one axis for v inside it: the four nodes around the
+ * bracketing interval, shifted inward at the two ends of the axis.
+ * Returns the first node. */
+static int cubic_w(const double *ax, int n, double v, double w[4])
+{
+    int i = find_interval(ax, n, v);
+    int s0 = i - 1;
+    if (s0 < 0) s0 = 0;
+    if (s0 > n - 4) s0 = n - 4;
+    lagrange_at(ax, s0, v, w);
+    return s0;
+}
+
+/* Clamp v to the axis, counting values outside it. */
+static double clamp_axis(const double *ax, int n, double v, long long *clamp)
+{
+    if (v < ax[0]) { if (clamp) (*clamp)++; return ax[0]; }
+    if (v > ax[n - 1]) { if (clamp) (*clamp)++; return ax[n - 1]; }
+    return v;
+}
+
+/* Atmosphere interpolation (Sect. 4), in linear space (I/T^3); returns I/T^3.
+ * mode 0, strategy (d), mixed order (the default):
  *   logT, log g : linear, clamped at the table edges;
  *   mu          : cubic Lagrange, linear in the protected zone spanned by the
  *                 four smallest-mu nodes and in the last interval; mu clamped
  *                 to [mu_0, mu_last];
  *   x=log(E/kT) : cubic Lagrange, linear in the first and last interval;
  *                 outside the axis the intensity is zero.
- * mode 1 selects strategy (a) cubic everywhere (x and mu; still linear in
- * the two outermost intervals where a four-node stencil does not exist).
- * The table is interpolated in linear space (I/T^3); returns I/T^3. */
+ * mode 1, strategy (a): cubic Lagrange on all four axes (logT, log g and mu
+ *   clamped), the four-node stencil shifted inward at every axis end;
+ * mode 2, strategy (b): mode 1 with negative results set to zero;
+ * mode 3, strategy (c): mode 1 but linear in the protected small-mu zone.
+ * In every mode x outside its axis gives zero. */
 double orc_atmo_interp_mode(const orc_spec *s, const double *linI, double logT, double logg,
                             double mu, double x, int mode, orc_diag *diag)
 {
     int nT = s->nT, ng = s->ng, nmu = s->nmu, nx = s->nx;
-    double wT[2], wg[2], wm[4] = {0, 0, 0, 0}, wx[4] = {0, 0, 0, 0};
-    int iT = lin_w(s->ax_T, nT, logT, wT, diag ? &diag->n_clamp_T : NULL);
-    int ig = lin_w(s->ax_g, ng, logg, wg, diag ? &diag->n_clamp_g : NULL);
+    double wT[4] = {0, 0, 0, 0}, wg[4] = {0, 0, 0, 0}, wm[4] = {0, 0, 0, 0}, wx[4] = {0, 0, 0, 0};
+    int iT, ig;
+    if (mode == 0) {
+        iT = lin_w(s->ax_T, nT, logT, wT, diag ? &diag->n_clamp_T : NULL);
+        ig = lin_w(s->ax_g, ng, logg, wg, diag ? &diag->n_clamp_g : NULL);
+    } else {
+        iT = cubic_w(s->ax_T, nT, clamp_axis(s->ax_T, nT, logT, diag ? &diag->n_clamp_T : NULL), wT);
+        ig = cubic_w(s->ax_g, ng, clamp_axis(s->ax_g, ng, logg, diag ? &diag->n_clamp_g : NULL), wg);
+    }
     if (x < s->ax_x[0] || x > s->ax_x[nx - 1]) {
         if (diag) diag->n_x_outside++;
         return 0.0;
@@ -528,24 +572,30 @@ double orc_atmo_interp_mode(const orc_spec *s, const double *linI, double logT, 
     if (m > s->ax_mu[nmu - 1]) m = s->ax_mu[nmu - 1];
     int im = find_interval(s->ax_mu, nmu, m);
     int m0;
-    int lin_mu = (mode == 0) ? (im < 3 || im == nmu - 2) : (im == 0 || im == nmu - 2);
+    int lin_mu = (mode == 0) ? (im < 3 || im == nmu - 2) : (mode == 3 ? im < 3 : 0);
     if (lin_mu) {
         double t = (m - s->ax_mu[im]) / (s->ax_mu[im + 1] - s->ax_mu[im]);
         m0 = im; wm[0] = 1.0 - t; wm[1] = t;
-    } else {
+    } else if (mode == 0) {
         m0 = im - 1; lagrange4(s->ax_mu, im, m, wm);
+    } else {
+        m0 = cubic_w(s->ax_mu, nmu, m, wm);
     }
     int ix = find_interval(s->ax_x, nx, x);
     int x0;
-    if (ix == 0 || ix == nx - 2) {
+    if (mode == 0 && (ix == 0 || ix == nx - 2)) {
         double t = (x - s->ax_x[ix]) / (s->ax_x[ix + 1] - s->ax_x[ix]);
         x0 = ix; wx[0] = 1.0 - t; wx[1] = t;
-    } else {
+    } else if (mode == 0) {
         x0 = ix - 1; lagrange4(s->ax_x, ix, x, wx);
+    } else {
+        x0 = cubic_w(s->ax_x, nx, x, wx);
     }
     double acc = 0.0;
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
+    for (int a = 0; a < 4; ++a) {
+        if (wT[a] == 0.0) continue;
+        for (int b = 0; b < 4; ++b) {
+            if (wg[b] == 0.0) continue;
             for (int c = 0; c < 4; ++c) {
                 if (wm[c] == 0.0) continue;
                 for (int d = 0; d < 4; ++d) {
@@ -554,13 +604,16 @@ double orc_atmo_interp_mode(const orc_spec *s, const double *linI, double logT, 
                     acc += wT[a] * wg[b] * wm[c] * wx[d] * linI[idx];
                 }
             }
+        }
+    }
+    if (mode == 2 && acc < 0.0) acc = 0.0;
     return acc;
 }
 
 double orc_atmo(const orc_spec *s, const double *linI, double logT, double logg,
                 double mu, double x, orc_diag *diag)
 {
-    return orc_atmo_interp_mode(s, linI, logT, logg, mu, x, 0, diag);
+    return orc_atmo_interp_mode(s, linI, logT, logg, mu, x, s->interp, diag);
 }
 
 /* ------------------------------------------------------------------------ */

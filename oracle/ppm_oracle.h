@@ -42,6 +42,9 @@ typedef struct {
     int nT, ng, nmu, nx;
     const double *ax_T, *ax_g, *ax_mu, *ax_x;
     const double *logI;    /* [nT][ng][nmu][nx] log10(I/T^3) */
+    int interp;            /* atmosphere interpolation strategy of Sect. 4: 0 (d) mixed,
+                              1 (a) cubic, 2 (b) cubic clipped at zero, 3 (c) cubic with
+                              linear protected small-mu zone */
 } orc_spec;
 
 typedef struct {

@@ -8,8 +8,11 @@ strategy (d)) and of the synthetic table it is fed.
   result is the linear interpolant of the two bracketing nodes; in the
   first and last x interval it is linear as well;
 * outside the x axis the intensity is zero; logT and log g are clamped;
-* strategy (a) (cubic everywhere) differs from (d) exactly in the
-  protected zone;
+* strategy (a) (cubic on all four axes, stencils shifted inward at the
+  axis ends) reproduces a table cubic in every axis exactly, edge intervals
+  included, where (d) does not; strategy (c) is (a) but linear in the
+  protected zone; strategy (b) is max(0, (a)), and on a steep limb (a)
+  undershoots below zero in the small-mu intervals while (c) and (d) do not;
 * the synthetic table is blackbody x cubic limb polynomial: the interpolant
   is exact in mu, logT and log g away from the linear zones and within the
   cubic Lagrange remainder bound in x.
@@ -148,3 +151,83 @@ def test_synthetic_table_closed_form():
         bound = 1.1 * d4 / 24.0 * abs(np.prod(xj - nodes)) * pm
         err = abs(oracle.atmo(spec, lin, lt, lg, m, xj) - V(lt, lg, m, xj))
         assert err <= bound + 1e-12 * V(lt, lg, m, xj)
+
+
+# ---------------------------------------------------------------- strategies (a)-(c)
+def cubic4_fn(T, G, M, X):
+    """Cubic in each of the four axes (logT and log g included)."""
+    t, g = T - 6.0, G - 14.2
+    return (3.0 + 0.5 * t - 0.8 * t ** 2 + 0.6 * t ** 3) * (2.0 + 0.3 * g + 0.9 * g ** 2 - 0.7 * g ** 3) * \
+        (2 + M - 0.7 * M ** 2 + 0.4 * M ** 3) * (5 + X + 0.3 * X ** 2 - 0.2 * X ** 3)
+
+
+def test_strategy_a_cubic_everywhere_is_exact_for_cubics():
+    """Strategy (a): four-node Lagrange on every axis, stencils shifted inward
+    at the axis ends, so a table cubic in each axis is reproduced exactly
+    everywhere inside the axes, edge intervals included; the mixed default
+    (d) is not (linear in logT and log g)."""
+    spec, lin = make(cubic4_fn)
+    at, ag, am, ax = AX
+    rng = np.random.default_rng(7)
+    worst_d = 0.0
+    for _ in range(300):
+        lt = rng.uniform(at[0], at[-1])
+        lg = rng.uniform(ag[0], ag[-1])
+        m = rng.uniform(am[0], am[-1])
+        x = rng.uniform(ax[0], ax[-1])
+        exact = cubic4_fn(lt, lg, m, x)
+        assert oracle.atmo(spec, lin, lt, lg, m, x, mode=1) == pytest.approx(exact, rel=1e-11)
+        worst_d = max(worst_d, abs(oracle.atmo(spec, lin, lt, lg, m, x, mode=0) / exact - 1))
+    assert worst_d > 1e-6
+    # edge intervals of every axis
+    for lt, lg, m, x in ((at[0] + 0.3 * (at[1] - at[0]), ag[-1] - 0.2 * (ag[-1] - ag[-2]),
+                          am[0] + 0.5 * (am[1] - am[0]), ax[0] + 0.4 * (ax[1] - ax[0])),
+                         (at[-1] - 0.1 * (at[-1] - at[-2]), ag[0] + 0.7 * (ag[1] - ag[0]),
+                          am[-1] - 0.3 * (am[-1] - am[-2]), ax[-1] - 0.6 * (ax[-1] - ax[-2]))):
+        assert oracle.atmo(spec, lin, lt, lg, m, x, mode=1) == pytest.approx(cubic4_fn(lt, lg, m, x), rel=1e-11)
+
+
+def test_strategy_c_linear_only_in_protected_zone():
+    """Strategy (c): as (a) except linear in mu between the bracketing nodes
+    in the three smallest-mu intervals."""
+    spec, lin = make(cubic4_fn)
+    at, ag, am, ax = AX
+    lt, lg, x = 6.37, 14.03, 0.77
+    for k in range(3):
+        m = am[k] + 0.41 * (am[k + 1] - am[k])
+        f0 = oracle.atmo(spec, lin, lt, lg, am[k], x, mode=1)
+        f1 = oracle.atmo(spec, lin, lt, lg, am[k + 1], x, mode=1)
+        assert oracle.atmo(spec, lin, lt, lg, m, x, mode=3) == pytest.approx(f0 + 0.41 * (f1 - f0), rel=1e-12)
+        assert f0 == pytest.approx(cubic4_fn(lt, lg, am[k], x), rel=1e-11)
+    for k in (3, 20, len(am) - 2):
+        m = am[k] + 0.41 * (am[k + 1] - am[k])
+        assert oracle.atmo(spec, lin, lt, lg, m, x, mode=3) == oracle.atmo(spec, lin, lt, lg, m, x, mode=1)
+
+
+def steep_limb_fn(T, G, M, X):
+    """Positive table with a steep rise off mu = 0 (nearly zero at the first
+    two mu nodes, a plateau from the fourth): the cubic stencil over the
+    first four nodes dips below zero between the second and third."""
+    mu3 = AX[2][3]
+    return (1.0 + 0.1 * (T - 6.0)) * (1e-6 + np.minimum(M / mu3, 1.0) ** 8) * (1.0 + 0.1 * X) + 0.0 * G
+
+
+def test_strategy_b_clips_the_cubic_undershoot():
+    """Strategy (b) equals max(0, (a)); on a steep limb the cubic of (a)
+    undershoots below zero in the first mu intervals while the mixed (d)
+    and (c) stay non-negative there (linear in the protected zone)."""
+    spec, lin = make(steep_limb_fn)
+    at, ag, am, ax = AX
+    assert np.all(lin > 0)
+    lt, lg, x = 6.0, 14.2, 0.5
+    found = 0
+    for k in range(4):
+        for t in np.linspace(0.05, 0.95, 19):
+            m = am[k] + t * (am[k + 1] - am[k])
+            a = oracle.atmo(spec, lin, lt, lg, m, x, mode=1)
+            b = oracle.atmo(spec, lin, lt, lg, m, x, mode=2)
+            assert b == max(0.0, a)
+            assert oracle.atmo(spec, lin, lt, lg, m, x, mode=0) >= 0.0
+            assert oracle.atmo(spec, lin, lt, lg, m, x, mode=3) >= 0.0
+            found += a < 0.0
+    assert found > 0
