@@ -52,6 +52,7 @@ enum ppm_mode { PPM_MODE_SD = 0, PPM_MODE_OS = 1 };
 enum ppm_intensity { PPM_I_BLACKBODY = 0, PPM_I_TABLE = 1 };
 enum ppm_shape { PPM_SHAPE_CAP = 0, PPM_SHAPE_ANNULUS = 1, PPM_SHAPE_CRESCENT = 2 };
 enum ppm_precision { PPM_F32 = 0, PPM_F64 = 1 };
+enum ppm_interp { PPM_INTERP_MIXED = 0, PPM_INTERP_CUBIC = 1, PPM_INTERP_CUBIC_CLIP = 2, PPM_INTERP_CUBIC_LINMU = 3 };
 
 /*
  * Static description of the model (host memory; copied at plan creation).
@@ -78,6 +79,15 @@ enum ppm_precision { PPM_F32 = 0, PPM_F64 = 1 };
  *              PPM_F64: FP64 throughout (blackbody model only)
  *  grad        1: also allocate what ppm_loglike_grad needs (atmosphere-table
  *              model with the windowed accumulation only); 0: forward only
+ *  interp      atmosphere interpolation strategy of Sect. 4: PPM_INTERP_MIXED
+ *              (d, the default: linear in logT and log g, cubic in mu and x,
+ *              linear in the protected small-mu zone and at the table edges),
+ *              PPM_INTERP_CUBIC (a: cubic Lagrange on all four axes, stencils
+ *              shifted inward at the axis ends), PPM_INTERP_CUBIC_CLIP (b: (a)
+ *              with negative intensities set to zero), PPM_INTERP_CUBIC_LINMU
+ *              (c: (a) but linear in the protected zone).  (a)-(c) need at
+ *              least four nodes on every axis, run on the generic kernel and
+ *              have no gradient.
  */
 typedef struct {
     int32_t mode, intensity, n_spots;
@@ -94,6 +104,7 @@ typedef struct {
     int32_t n_alpha;
     int32_t precision;
     int32_t grad;
+    int32_t interp;
 } ppm_spec;
 
 typedef struct ppm_plan ppm_plan;

@@ -56,7 +56,7 @@ class Spec(C.Structure):
 class Diag(C.Structure):
     _fields_ = [("n_clamp_T", C.c_longlong), ("n_clamp_g", C.c_longlong),
                 ("n_x_outside", C.c_longlong), ("n_multi_image", C.c_longlong),
-                ("n_visible_pairs", C.c_longlong), ("status", C.c_int)]
+                ("n_visible_pairs", C.c_longlong), ("status", C.c_int), ("n_negative", C.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -606,6 +606,7 @@ double orc_atmo_interp_mode(const orc_spec *s, const double *linI, double logT, 
             }
         }
     }
+    if (acc < 0.0 && diag) diag->n_negative++;
     if (mode == 2 && acc < 0.0) acc = 0.0;
     return acc;
 }
@@ -635,7 +636,7 @@ static void ring_accumulate(const orc_spec *s, const double *p, int spot, const 
     double *F = malloc(sizeof(double) * 4 * (nfp + 1));
     double *z = F + (nfp + 1), *phio = z + (nfp + 1), *mu = phio + (nfp + 1);
     int inv[2];
-    orc_diag local = {0, 0, 0, 0, 0, 0};
+    orc_diag local = {0, 0, 0, 0, 0, 0, 0};
     if (!orc_trace_ring(s, p, g, F, z, phio, mu, inv, &local) || g->w_cell <= 0.0) {
         free(F);
         if (diag) {
@@ -690,6 +691,7 @@ static void ring_accumulate(const orc_spec *s, const double *p, int spot, const 
             diag->n_x_outside += local.n_x_outside;
             diag->n_multi_image += local.n_multi_image;
             diag->n_visible_pairs += local.n_visible_pairs;
+            diag->n_negative += local.n_negative;
         }
     }
 }

@@ -50,6 +50,7 @@ typedef struct {
 typedef struct {
     long long n_clamp_T, n_clamp_g, n_x_outside, n_multi_image, n_visible_pairs;
     int status;
+    long long n_negative;  /* interpolated intensities below zero (before any clipping) */
 } orc_diag;
 
 typedef struct {

@@ -23,6 +23,7 @@ GRAD_SLOTS = (0, 1, 2, 3, 4, 8, 9, 10, 12, 13, 14, 15)
 MODE_SD, MODE_OS = 0, 1
 I_BLACKBODY, I_TABLE = 0, 1
 F32, F64 = 0, 1
+INTERP_MIXED, INTERP_CUBIC, INTERP_CUBIC_CLIP, INTERP_CUBIC_LINMU = 0, 1, 2, 3
 
 _lib = None
 
@@ -42,7 +43,8 @@ class _Spec(C.Structure):
                 ("ax_T", C.POINTER(C.c_double)), ("ax_g", C.POINTER(C.c_double)),
                 ("ax_mu", C.POINTER(C.c_double)), ("ax_x", C.POINTER(C.c_double)),
                 ("log_intensity", C.POINTER(C.c_double)),
-                ("n_alpha", C.c_int32), ("precision", C.c_int32), ("grad", C.c_int32)]
+                ("n_alpha", C.c_int32), ("precision", C.c_int32), ("grad", C.c_int32),
+                ("interp", C.c_int32)]
 
 
 _VP = C.c_void_p
@@ -154,6 +156,7 @@ class Plan:
         s.n_alpha = n_alpha if n_alpha is not None else spec.get("n_alpha", 512)
         s.precision = F64 if spec.get("precision", "f32") == "f64" else F32
         s.grad = 1 if grad else 0
+        s.interp = int(spec.get("interp", 0))
         self.spec = spec
         self.n_phase = s.n_phase
         self.n_energy = s.n_energy

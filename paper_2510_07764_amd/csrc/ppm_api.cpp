@@ -191,6 +191,14 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     if (sp->n_alpha < 64 || sp->n_alpha > 8192) return fail(PPM_ERR_ARG, "n_alpha must lie in [64, 8192]");
     if (sp->n_energy > 64 * 8) return fail(PPM_ERR_UNSUPPORTED, "at most 512 energies");
     if (sp->grad != 0 && sp->grad != 1) return fail(PPM_ERR_ARG, "grad must be 0 or 1");
+    if (sp->interp < PPM_INTERP_MIXED || sp->interp > PPM_INTERP_CUBIC_LINMU)
+        return fail(PPM_ERR_ARG, "interp must be one of the four strategies");
+    if (sp->interp != PPM_INTERP_MIXED) {
+        if (sp->intensity != PPM_I_TABLE) return fail(PPM_ERR_ARG, "interp applies to the atmosphere table only");
+        if (sp->grad) return fail(PPM_ERR_UNSUPPORTED, "gradients are implemented for the mixed strategy (d) only");
+        if (sp->nT < 4 || sp->ng < 4 || sp->nmu < 4 || sp->nx < 4)
+            return fail(PPM_ERR_ARG, "cubic strategies need at least four nodes on every table axis");
+    }
     if (sp->grad && sp->intensity != PPM_I_TABLE)
         return fail(PPM_ERR_UNSUPPORTED, "gradients are implemented for the atmosphere-table model only");
     double tmp0, tmp1;
@@ -212,6 +220,7 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     std::memset(&S, 0, sizeof(S));
     S.mode = sp->mode;
     S.intensity = sp->intensity;
+    S.interp = sp->interp;
     S.n_spots = sp->n_spots;
     for (int s = 0; s < 2; ++s) {
         bool on = s < sp->n_spots;
@@ -274,7 +283,7 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         S.r_span = (std::log10(sp->energy_kev[S.E - 1]) - std::log10(sp->energy_kev[0])) / S.hx;
         S.W_max = (int)std::ceil(S.r_span + std::log10(4.0) / S.hx) + 8;
         if (S.W_max > S.nx) S.W_max = S.nx;
-        S.fast = (S.r_span <= 59.0) ? 1 : 0;
+        S.fast = (S.r_span <= 59.0 && S.interp == PPM_INTERP_MIXED) ? 1 : 0;
         if (sp->grad && !S.fast) {
             delete pl;
             return fail(PPM_ERR_UNSUPPORTED, "gradients need an energy grid spanning at most 59 x intervals");

@@ -23,6 +23,7 @@ constexpr int kMaxMu = 128;       // mu nodes held in constant memory
 // Static model description as seen by the kernels (device pointers).
 struct DevSpec {
     int mode, intensity, n_spots;
+    int interp;           // atmosphere interpolation strategy (ppm_interp)
     int shape[2];
     double shape_a[2], shape_b[2];
     int n_fp, P, E, C;

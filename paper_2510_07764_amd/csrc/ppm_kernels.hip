@@ -198,8 +198,45 @@ __global__ __launch_bounds__(64) void k_table(DevSpec S, const int32_t *list, co
 // ring (run by k_trace once the ring's x window is known) (mixed-order scheme of Sect. 4: linear on these two axes, clamped at
 // the edges), giving sub[mu][x] = I/T^3 at the ring's (logT, log g).
 // ---------------------------------------------------------------------------
+// Four-node Lagrange weights on a uniform axis of n >= 4 nodes at position
+// t (node units, clamped to the axis): stencil around the bracketing
+// interval, shifted inward at the axis ends.  Returns the first node.
+__device__ static inline int cubic_uniform(double t, int n, double w[4])
+{
+    t = fmin((double)(n - 1), fmax(0.0, t));
+    int i = (int)floor(t);
+    if (i > n - 2) i = n - 2;
+    int s0 = i - 1;
+    s0 = s0 < 0 ? 0 : (s0 > n - 4 ? n - 4 : s0);
+    const double u = t - s0;
+    w[0] = -(u - 1.0) * (u - 2.0) * (u - 3.0) / 6.0;
+    w[1] = u * (u - 2.0) * (u - 3.0) / 2.0;
+    w[2] = -u * (u - 1.0) * (u - 3.0) / 2.0;
+    w[3] = u * (u - 1.0) * (u - 2.0) / 6.0;
+    return s0;
+}
+
 __device__ static void subtable_ring(const DevSpec &S, const RingRec &g, int xw0, int xw, size_t slot, float *sub)
 {
+    if (S.interp != PPM_INTERP_MIXED) {
+        // strategies (a)-(c): cubic in logT and log g (full x range; generic kernel)
+        double wt[4], wg[4];
+        const int it = cubic_uniform((g.logT - S.T0) / S.hT, S.nT, wt);
+        const int ig = cubic_uniform((g.logg - S.g0) / S.hg, S.ng, wg);
+        const size_t slab = (size_t)S.nmu * S.nx;
+        float w16[16];
+        for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 4; ++c) w16[4 * a + c] = (float)(wt[a] * wg[c]);
+        float *out = sub + slot * slab;
+        for (size_t i = threadIdx.x; i < slab; i += blockDim.x) {
+            float v = 0.0f;
+            for (int a = 0; a < 4; ++a)
+                for (int c = 0; c < 4; ++c)
+                    v += w16[4 * a + c] * S.atm[((size_t)(it + a) * S.ng + ig + c) * slab + i];
+            out[i] = v;
+        }
+        return;
+    }
     double wt1, wg1;
     int it = lin_bracket(g.logT, S.T0, S.hT, S.nT, wt1);
     int ig = lin_bracket(g.logg, S.g0, S.hg, S.ng, wg1);
@@ -451,12 +488,15 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
             }
             float wm[4];
             int m0;
-            if (lo < 3 || lo == nmu - 2) {
+            const bool lin_mu = S.interp == PPM_INTERP_MIXED ? (lo < 3 || lo == nmu - 2)
+                              : (S.interp == PPM_INTERP_CUBIC_LINMU && lo < 3);
+            if (lin_mu) {
                 double t = (mu - axmu[lo]) / (axmu[lo + 1] - axmu[lo]);
                 m0 = lo;
                 wm[0] = (float)(1.0 - t); wm[1] = (float)t; wm[2] = 0.0f; wm[3] = 0.0f;
             } else {
                 m0 = lo - 1;
+                m0 = m0 < 0 ? 0 : (m0 > nmu - 4 ? nmu - 4 : m0);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     double num = 1.0, den = 1.0;
@@ -469,7 +509,7 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
                     wm[q] = (float)(num / den);
                 }
             }
-            const int nrow = (lo < 3 || lo == nmu - 2) ? 2 : 4;
+            const int nrow = lin_mu ? 2 : 4;
             const float *t0 = tab + m0 * nx;
             for (int n = lane; n < nx; n += 64) {
                 float s = wm[0] * t0[n] + wm[1] * t0[nx + n];
@@ -487,7 +527,16 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
                 if (i > nx - 2) i = nx - 2;
                 float f = (float)(t - i);
                 float I;
-                if (i == 0 || i == nx - 2) {
+                if (S.interp != PPM_INTERP_MIXED && (i == 0 || i == nx - 2)) {
+                    // cubic stencil shifted inward at the axis end
+                    const int s0 = i == 0 ? 0 : nx - 4;
+                    const float u = (float)(t - s0);
+                    const float a0 = -(u - 1.0f) * (u - 2.0f) * (u - 3.0f) * (1.0f / 6.0f);
+                    const float a1 = u * (u - 2.0f) * (u - 3.0f) * 0.5f;
+                    const float a2 = -u * (u - 1.0f) * (u - 3.0f) * 0.5f;
+                    const float a3 = u * (u - 1.0f) * (u - 2.0f) * (1.0f / 6.0f);
+                    I = a0 * Sw[s0] + a1 * Sw[s0 + 1] + a2 * Sw[s0 + 2] + a3 * Sw[s0 + 3];
+                } else if (i == 0 || i == nx - 2) {
                     I = Sw[i] + f * (Sw[i + 1] - Sw[i]);
                 } else {
                     float fm1 = f - 1.0f, fm2 = f - 2.0f, fp1 = f + 1.0f;
@@ -497,6 +546,7 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
                     float w3 = fp1 * f * fm1 * (1.0f / 6.0f);
                     I = w0 * Sw[i - 1] + w1 * Sw[i] + w2 * Sw[i + 1] + w3 * Sw[i + 2];
                 }
+                if (S.interp == PPM_INTERP_CUBIC_CLIP) I = fmaxf(0.0f, I);
                 acc[m] += Fp * I;
             }
             wave_sync();

@@ -151,6 +151,41 @@ def atmosphere_table(seed: int = SEED_ATMOS, n_t=35, n_g=11, n_mu=67, n_x=166):
     return np.log10(v), (ax_t, ax_g, ax_mu, ax_x)
 
 
+def atmosphere_table_steep_limb(n_t=35, n_g=11, n_mu=67, n_x=166):
+    """Synthetic table with a limb far steeper than the mu grid resolves,
+    for the interpolation-overshoot diagnostics of Sect. 4: the blackbody
+    factor of atmosphere_table times L(mu) = 1e-6 + tanh(mu / 0.004)^4
+    (rising from ~0 to ~1 across the first five mu nodes) times a mild
+    linear logT / log g trend.  Same axes and layout as atmosphere_table."""
+    ax_t, ax_g, ax_mu, ax_x = atmosphere_axes(n_t, n_g, n_mu, n_x)
+    y = 10.0 ** ax_x
+    bb = y ** 3 * np.exp(-y) / (-np.expm1(-y))
+    pref = 2.0 * K_B_KEV ** 3 / (H_KEVS ** 3 * C_CGS ** 2)
+    trend = 1.0 + 0.1 * (ax_t[:, None, None] - 6.0) + 0.05 * (ax_g[None, :, None] - 14.2)
+    limb = 1e-6 + np.tanh(ax_mu / 0.004) ** 4
+    v = pref * (trend * limb[None, None, :])[..., None] * bb[None, None, None, :]
+    return np.log10(v), (ax_t, ax_g, ax_mu, ax_x)
+
+
+def interp_test_geometry(test: int, n_cells=16, n_phase=64, n_energy=32):
+    """The single small hotspot of the interpolation tests of Sect. 4
+    (Table 3): M = 1.4, R_e = 12 km, 600 Hz, T = 1e6 K, D = 150 pc, spot
+    radius 0.01 rad; test 1: colatitude 1.983 rad seen from i = 0.01 rad,
+    test 2: colatitude pi - 0.01 rad seen from i = 0.964 rad.  Oblate star,
+    steep-limb synthetic table, no absorption."""
+    th, inc = (1.983, 0.01) if test == 1 else (math.pi - 0.01, 0.964)
+    spec = _base_spec(n_spots=1, shape=[SHAPE_CAP, SHAPE_CAP], n_rings=[n_cells, n_cells],
+                      n_phi=[n_cells, n_cells], shape_a=[0.0, 0.0], n_phase=n_phase,
+                      energy=logspace(0.2, 3.0, n_energy), precision="f32")
+    logi, axes = atmosphere_table_steep_limb()
+    spec["atmos_logI"] = logi
+    spec["atmos_axes"] = axes
+    spec["sigma"] = np.zeros(n_energy)
+    spec["rsp"] = gaussian_response(spec["energy"])
+    params = params_vector(1.4, 12.0, inc, 0.0, 0.0, 600.0, 150.0, th, 0.01, 6.0)
+    return spec, params
+
+
 # ------------------------------------------------------- absorption, response
 def sigma_ism(energy_kev: np.ndarray) -> np.ndarray:
     """Stand-in photo-absorption cross-section per H atom [cm^2]."""

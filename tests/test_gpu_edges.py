@@ -129,3 +129,34 @@ def test_call_errors(torch_dev):
     _, cnt, _ = oracle.forward(spec, p)
     got = plan.forward(pt[:1].contiguous()).cpu().numpy()
     assert rel_err(got[0], cnt) < TOL
+
+
+@pytest.mark.parametrize("interp", [0, 1, 2, 3])
+def test_interpolation_strategies(torch_dev, interp):
+    """The four atmosphere interpolation strategies of Sect. 4 (d, a, b, c)
+    against the oracle's implementation of the same strategy."""
+    spec, p = syn.config1(n_cells=12, n_phase=16, n_energy=40)
+    spec = dict(spec, interp=interp)
+    _, cnt, _ = oracle.forward(spec, p)
+    got, _ = run(torch_dev, spec, p)
+    err = rel_err(got[0], cnt)
+    print("strategy %d: err %.2e" % (interp, err))
+    assert err < TOL
+
+
+@pytest.mark.parametrize("test", [1, 2])
+def test_interpolation_test_geometries(torch_dev, test):
+    """The interpolation-test geometries of Sect. 4 on the steep-limb
+    synthetic table: flux before absorption and response, per strategy,
+    against the oracle."""
+    import paper_2510_07764_amd as ppm
+    torch, dev = torch_dev
+    spec, p = syn.interp_test_geometry(test)
+    for mode in (0, 1, 2, 3):
+        s = dict(spec, interp=mode)
+        ft, _, _ = oracle.forward(s, p)
+        plan = ppm.Plan(s, max_batch=1)
+        got = plan.flux(torch.tensor(p[None], dtype=torch.float64, device=dev)).cpu().numpy()[0]
+        err = rel_err(got, ft)
+        print("test %d strategy %d: err %.2e, min/max %.2e" % (test, mode, err, got.min() / got.max()))
+        assert err < TOL

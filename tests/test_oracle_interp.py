@@ -231,3 +231,23 @@ def test_strategy_b_clips_the_cubic_undershoot():
             assert oracle.atmo(spec, lin, lt, lg, m, x, mode=3) >= 0.0
             found += a < 0.0
     assert found > 0
+
+
+@pytest.mark.parametrize("test", [1, 2])
+def test_interpolation_tests_of_sect4_negative_samples(test):
+    """The two small-hotspot geometries of the interpolation tests (Sect. 4,
+    Table 3) on a synthetic steep-limb table: strategy (a) produces negative
+    interpolated intensities where rays graze the limb, (b) counts the same
+    ones and clips them, (c) and (d) produce none.  The flux bins stay
+    positive here (the spot's cells span more than the steep mu range); with
+    the paper's NSX-H table this diagnostic is parity unpinned."""
+    spec, p = syn.interp_test_geometry(test)
+    res = {}
+    for mode in (0, 1, 2, 3):
+        ft, _, d = oracle.forward(dict(spec, interp=mode), p)
+        res[mode] = (d["n_negative"], ft)
+    assert res[1][0] > 0 and res[2][0] == res[1][0]
+    assert res[0][0] == 0 and res[3][0] == 0
+    assert np.all(res[2][1] >= 0.0)
+    # clipping only raises the flux relative to (a)
+    assert np.all(res[2][1] >= res[1][1] - 1e-12 * np.abs(res[1][1]).max())
