@@ -245,9 +245,9 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     pl->precision = sp->precision;
     pl->grad = sp->grad != 0;
 
-    // Gauss-Legendre rules of 32, 48 and 64 nodes, back to back
+    // Gauss-Legendre rules of 20, 24, 32, 48 and 64 nodes, back to back
     std::vector<double> glx, glw;
-    for (int n : {32, 48, 64}) {
+    for (int n : {20, 24, 32, 48, 64}) {
         std::vector<double> x, w;
         gauss_legendre01(n, x, w);
         glx.insert(glx.end(), x.begin(), x.end());

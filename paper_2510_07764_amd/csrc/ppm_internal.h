@@ -17,7 +17,6 @@ constexpr double kKB = 8.617333262e-8;
 constexpr double kH = 4.135667696e-18;
 constexpr double kPc = 3.0856775814913673e18;
 
-constexpr int kMaxQuad = 128;     // Gauss-Legendre nodes of the deflection quadrature
 constexpr int kMaxMu = 128;       // mu nodes held in constant memory
 
 // Static model description as seen by the kernels (device pointers).
