@@ -373,13 +373,21 @@ __global__ __launch_bounds__(256) void k_trace(DevSpec S, const int32_t *list, c
         out[i] = v;
         if (v.y > 0.0) { zlo = fmin(zlo, v.y); zhi = fmax(zhi, v.y); }
     }
-    __shared__ double red_lo[256], red_hi[256];
+    __shared__ double red_lo[4], red_hi[4];
     __shared__ int sh_active, sh_w0, sh_w;
-    red_lo[threadIdx.x] = zlo;
-    red_hi[threadIdx.x] = zhi;
+    // range of z over the block: wave butterflies, then the four waves
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        zlo = fmin(zlo, __shfl_xor(zlo, o, 64));
+        zhi = fmax(zhi, __shfl_xor(zhi, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red_lo[threadIdx.x >> 6] = zlo;
+        red_hi[threadIdx.x >> 6] = zhi;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int t = 1; t < blockDim.x; ++t) { zlo = fmin(zlo, red_lo[t]); zhi = fmax(zhi, red_hi[t]); }
+        for (int t = 1; t < (int)(blockDim.x >> 6); ++t) { zlo = fmin(zlo, red_lo[t]); zhi = fmax(zhi, red_hi[t]); }
         gp->visible = ring_visible ? 1 : 0;
         gp->inv_min = a0;
         gp->inv_max = a1;
@@ -1041,19 +1049,26 @@ __global__ __launch_bounds__(256) void k_loglike_part(const double *counts, cons
     }
 }
 
-__global__ void k_loglike_final(const StarRec *stars, const double *part, const int32_t *bad, int nblk, int B,
-                                 double *logl)
+// one wave per instance: lane-strided partial sums, then a fixed butterfly
+__global__ __launch_bounds__(64) void k_loglike_final(const StarRec *stars, const double *part, const int32_t *bad,
+                                                      int nblk, int B, double *logl)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    const int b = blockIdx.x, lane = threadIdx.x;
     double s = 0.0;
     int nbad = 0;
-    for (int i = 0; i < nblk; ++i) {
+    for (int i = lane; i < nblk; i += 64) {
         s += part[(size_t)b * nblk + i];
         nbad += bad[(size_t)b * nblk + i];
     }
-    if (nbad || stars[b].status != PPM_INST_OK) s = -INFINITY;
-    logl[b] = s;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o, 64);
+        nbad += __shfl_xor(nbad, o, 64);
+    }
+    if (lane == 0) {
+        if (nbad || stars[b].status != PPM_INST_OK) s = -INFINITY;
+        logl[b] = s;
+    }
 }
 
 __global__ void k_status(const StarRec *stars, int B, int32_t *out)
@@ -1165,7 +1180,7 @@ hipError_t launch_loglike(const Workspace &W, const double *counts, int B, int P
 {
     const int nblk = (PC + kLLChunk - 1) / kLLChunk;
     hipLaunchKernelGGL(k_loglike_part, dim3(nblk, B), dim3(256), 0, st, counts, data, PC, W.ll_part, W.ll_bad);
-    hipLaunchKernelGGL(k_loglike_final, dim3((B + 63) / 64), dim3(64), 0, st, W.stars, W.ll_part, W.ll_bad, nblk,
+    hipLaunchKernelGGL(k_loglike_final, dim3(B), dim3(64), 0, st, W.stars, W.ll_part, W.ll_bad, nblk,
                        B, logl);
     return hipGetLastError();
 }
