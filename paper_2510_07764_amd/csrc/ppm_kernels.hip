@@ -693,8 +693,13 @@ __global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const int32_t *li
     float *tab = (float *)(axmu + ((nmu + 1) & ~1));           // sub_stride, 16-byte aligned
     float4 *Qb = (float4 *)(tab + S.sub_stride);               // 4 waves * 64 quads
     float *Sb = (float *)(Qb + 4 * 64);                        // 4 waves * 68
+    double *po = (double *)(Sb + 4 * 68);                      // nfp + 1 phi_o, compact for the search
     const double4 *gtr = trace + ((size_t)b * S.R_tot + r) * (nfp + 1);
-    for (int i = threadIdx.x; i <= nfp; i += blockDim.x) tr[i] = gtr[i];
+    for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
+        const double4 v = gtr[i];
+        tr[i] = v;
+        po[i] = v.z;
+    }
     for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
     // per-ring stride is a multiple of 4 floats: 16-byte aligned rows of float4
     const float4 *gsub = (const float4 *)(sub + ((size_t)b * S.R_tot + r) * (size_t)S.sub_stride);
@@ -738,7 +743,18 @@ __global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const int32_t *li
                 if (!cell_masked(g, off)) {
                     double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
                     double php = (a - floor(a)) + phio0;                    // Eq. (45)
-                    PhaseSample ps = phase_lookup(tr, nfp, php);            // Eq. (46)
+                    int l0 = 0, h0 = nfp;                                   // Eq. (46)
+                    while (h0 - l0 > 1) {
+                        int mid = (l0 + h0) >> 1;
+                        if (po[mid] <= php) l0 = mid; else h0 = mid;
+                    }
+                    const double4 A = tr[l0], Cn = tr[l0 + 1];
+                    double wp = (php - A.z) / (Cn.z - A.z);
+                    wp = fmin(1.0, fmax(0.0, wp));
+                    PhaseSample ps;
+                    ps.F = A.x + wp * (Cn.x - A.x);
+                    ps.z = A.y + wp * (Cn.y - A.y);
+                    ps.mu = A.w + wp * (Cn.w - A.w);
                     if (ps.F != 0.0) {
                         vis = true;
                         double mu = fmin(mu_hi, fmax(mu_lo, ps.mu));
@@ -1086,7 +1102,8 @@ size_t accum_table_lds(const DevSpec &S)
 {
     if (S.fast)
         return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
-             + sizeof(float) * S.sub_stride + sizeof(float4) * 4 * 64 + sizeof(float) * 4 * 68;
+             + sizeof(float) * S.sub_stride + sizeof(float4) * 4 * 64 + sizeof(float) * 4 * 68
+             + sizeof(double) * (S.n_fp + 1);
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * S.nmu + sizeof(float) * S.nmu * S.nx
          + sizeof(float) * 4 * S.nx;
 }
