@@ -464,10 +464,15 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_accum_adj(DevSpec S, const i
     float2 *tab2 = (float2 *)(tab + S.sub_stride);             // sub_stride
     float4 *Nb = (float4 *)(tab2 + S.sub_stride);              // kAdjWaves * 68 node values
     float4 *Qb = Nb + kAdjWaves * 68;                          // kAdjWaves * 4 * 64 quads
+    double *po = (double *)(Qb + kAdjWaves * 4 * 64);          // nfp + 1 phi_o, compact for the search
     const double4 *tg = tangent + slot * (size_t)(nfp + 1) * 5;   // read through the caches in stage C
     {
         const double4 *gtr = trace + slot * (nfp + 1);
-        for (int i = threadIdx.x; i <= nfp; i += blockDim.x) tr[i] = gtr[i];
+        for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
+            const double4 v = gtr[i];
+            tr[i] = v;
+            po[i] = v.z;
+        }
         for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
         const float4 *gs = (const float4 *)(sub + slot * (size_t)S.sub_stride);
         float4 *ts = (float4 *)tab;
@@ -526,7 +531,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_accum_adj(DevSpec S, const i
                     int l0 = 0, h0 = nfp;
                     while (h0 - l0 > 1) {
                         int mid = (l0 + h0) >> 1;
-                        if (tr[mid].z <= php) l0 = mid; else h0 = mid;
+                        if (po[mid] <= php) l0 = mid; else h0 = mid;
                     }
                     const double4 A = tr[l0], Cn = tr[l0 + 1];
                     double w = (php - A.z) / (Cn.z - A.z);
@@ -754,7 +759,7 @@ size_t accum_adj_lds(const DevSpec &S)
 {
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
          + sizeof(float) * S.sub_stride * 3 + sizeof(float4) * kAdjWaves * 68
-         + sizeof(float4) * kAdjWaves * 4 * 64;
+         + sizeof(float4) * kAdjWaves * 4 * 64 + sizeof(double) * (S.n_fp + 1);
 }
 
 hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev,
