@@ -39,8 +39,8 @@ PEAK_FP32_TFLOPS = 157.3
 # of them).  Valid only for the kernel sources the counters were taken on;
 # any change to them reports null until the counters are taken again.
 KERNEL_SOURCES = ("ppm_kernels.hip", "ppm_device.h", "ppm_dual.h", "ppm_internal.h", "ppm_launch.h")
-TRAFFIC = {"sources_sha256": "221e61ff896ddbe90930f0abaac6f778a07c0666ca62f7272a5c4a2f315fe759",
-           "fetch_kib": 4287.48, "write_kib": 33198.96, "fetch_scale": 1.99980, "write_scale": 1.0,
+TRAFFIC = {"sources_sha256": "458d3514046fd6c840785acd66ebef42c670983f116480e8f462ae811940809c",
+           "fetch_kib": 4282.56, "write_kib": 33198.96, "fetch_scale": 1.99980, "write_scale": 1.0,
            "profile": "profiles/k_accum_fast_config1_traffic.md"}
 
 
