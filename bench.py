@@ -41,7 +41,7 @@ PEAK_FP32_TFLOPS = 157.3
 KERNEL_SOURCES = ("ppm_kernels.hip", "ppm_device.h", "ppm_dual.h", "ppm_internal.h", "ppm_launch.h")
 TRAFFIC = {"sources_sha256": "458d3514046fd6c840785acd66ebef42c670983f116480e8f462ae811940809c",
            "fetch_kib": 4282.56, "write_kib": 33198.96, "fetch_scale": 1.99980, "write_scale": 1.0,
-           "profile": "profiles/k_accum_fast_config1_traffic.md"}
+           "phase_tile": 8, "profile": "profiles/k_accum_fast_config1_traffic.md"}
 
 
 def kernel_sources_sha256():
@@ -52,9 +52,13 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def hot_kernel_traffic():
+def hot_kernel_traffic(phase_tile):
+    """HBM bytes per launch of the hot kernel, or None when the counters were
+    taken on other kernel sources or another launch shape."""
     t = TRAFFIC
     if t["sources_sha256"] is None or t["sources_sha256"] != kernel_sources_sha256():
+        return None
+    if phase_tile != t["phase_tile"]:
         return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 
@@ -108,6 +112,9 @@ def main():
                     help="also run device-to-device copies of this many MiB (HBM counter calibration; 0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=128,
                     help="cells per spot of the oracle sample (128: the whole workload; 0: skip)")
+    ap.add_argument("--tiles", default="auto",
+                    help="launch shape of the accumulation kernels: 'auto' (autotuner, per leg) or "
+                         "'F,G' (forward and adjoint phase tiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the batched path shards "
@@ -127,9 +134,21 @@ def main():
     data = np.load(gold)
     data_t = torch.tensor(data, device=dev)
 
+    def tune(plan_, params_, reps):
+        """Autotuned (or fixed) phase tiles of a plan; returns the report."""
+        if args.tiles == "auto":
+            rep = plan_.autotune(params_, reps=reps)
+            return {"chosen": list(rep["chosen"]),
+                    "forward_ms": {str(k): round(v, 4) for k, v in rep["forward"].items()},
+                    "grad_ms": {str(k): round(v, 4) for k, v in rep["grad"].items()}}
+        f, g = (int(v) for v in args.tiles.split(","))
+        plan_.set_tiles(f, g)
+        return {"chosen": [f, g], "fixed": True}
+
     # ---------------- plain: one parameter vector per call
     plan = ppm.Plan(spec, max_batch=1)
     pt = torch.tensor(p[None], dtype=torch.float64, device=dev)
+    tune_plain = tune(plan, pt, 10)
     ll = torch.empty(1, dtype=torch.float64, device=dev)
     for _ in range(args.warmup):
         plan.loglike(pt, data_t, out=ll)
@@ -166,6 +185,7 @@ def main():
         draws = syn.config4_draws(B)
         planb = ppm.Plan(spec, max_batch=B)
         ptb = torch.tensor(draws, dtype=torch.float64, device=dev)
+        tuned = tune(planb, ptb, 3)
         # one direct call with the hot kernel timed (events on the launch stream)
         planb.profile_begin(64)
         planb.loglike(ptb, data_t)
@@ -185,7 +205,7 @@ def main():
         res = {"evals_per_s": B / tb, "batch": B, "ms_per_call": tb * 1e3, "calls": kb,
                "finite": bool(torch.isfinite(out_b).all().item()), "vs_plain": (B / tb) * plain_s,
                "hot_kernel_ms": hms, "hot_kernel_launches": nh, "units": bunits,
-               "roofline_frac": bach / PEAK_FP32_TFLOPS}
+               "roofline_frac": bach / PEAK_FP32_TFLOPS, "tiles": tuned}
         del glb, planb
         return res
 
@@ -199,6 +219,7 @@ def main():
         draws = syn.config4_draws(B)
         plang = ppm.Plan(spec, max_batch=B, grad=True)
         ptg = torch.tensor(draws, dtype=torch.float64, device=dev)
+        tuned_g = tune(plang, ptg, 2)
         glg = ppm.GraphedLogLike(plang, data_t, B, grad=True)
         glg(ptg)
         torch.cuda.synchronize()
@@ -210,7 +231,7 @@ def main():
         tg = (time.perf_counter() - t0) / kg
         grad = {"evals_per_s": B / tg, "batch": B, "ms_per_call": tg * 1e3, "calls": kg,
                 "finite": bool(torch.isfinite(out_g).all().item()),
-                "vs_plain": (B / tg) * plain_s}
+                "vs_plain": (B / tg) * plain_s, "tiles": tuned_g}
         del glg, plang
 
     if args.copy_mib > 0:
@@ -241,11 +262,12 @@ def main():
                    "plain": "one parameter vector per call", "logL": float(ll.item())},
         "plain_graph": {"evals_per_s": 1.0 / plain_graph_s, "ms_per_call": plain_graph_s * 1e3,
                         "matches_direct": graph_ok},
+        "plain_tiles": tune_plain,
         "batched": batched,
         "batched_large": batched_large,
         "grad": grad,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": hot_kernel_traffic(),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": hot_kernel_traffic(plan.tiles[0]),
                      "kernel": "k_accum_fast<4>", "kernel_ms": hot_avg_s * 1e3, "units": units,
                      "flop_per_unit": FLOP_PER_UNIT},
         "cpu_baseline": cpu,

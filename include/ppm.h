@@ -180,6 +180,46 @@ int ppm_visible_pairs(ppm_plan *plan, int B, long long *out, void *stream);
 int ppm_profile_begin(ppm_plan *plan, int max_calls);
 int ppm_profile_end(ppm_plan *plan, double *hot_ms_total, int *n_calls);
 
+/* Launch shape of the two accumulation kernels (the sum of Eq. (47) and its
+ * adjoint): phase_tile output phases per work-group of the forward kernel
+ * (4 waves, 1..256) and phase_tile_grad per work-group of the adjoint kernel
+ * (8 waves, 8..256).  Forward results do not depend on phase_tile: every
+ * phase's sums run in the same order whatever the tile.  The gradient's
+ * per-block partial sums do depend on phase_tile_grad, at the rounding level.
+ * Defaults 8 and 8.  A change applies to later calls; a HIP graph captured
+ * earlier keeps the shape it was captured with.  PPM_ERR_ARG for a null
+ * pointer or a value out of range (the plan is then unchanged). */
+typedef struct ppm_tiles {
+    int32_t phase_tile;
+    int32_t phase_tile_grad;
+} ppm_tiles;
+int ppm_get_tiles(const ppm_plan *plan, ppm_tiles *out);
+int ppm_set_tiles(ppm_plan *plan, const ppm_tiles *tiles);
+
+/* Autotuner of the launch shape.  For each candidate phase tile (forward:
+ * 4, 8, 12, 16, 24, 32; adjoint, gradient plans only: 8, 16, 24, 32;
+ * a candidate that gives the same number of tiles over n_phase as a smaller
+ * one is skipped) it times whole evaluations of the given batch (params_dev,
+ * B, n_cells_host as for ppm_forward): one warm-up call, then `reps` calls
+ * (1..1000) each between two HIP events on `stream`.  It keeps the candidate
+ * with the smallest median time and sets it on the plan; the forward tile is
+ * chosen first and then used while the adjoint tile is timed.  Adjoint calls
+ * run on all-zero data (their cost does not depend on the data) and need
+ * two temporary device buffers, allocated and freed here.  Synchronises the
+ * stream.  On error the plan keeps its previous tiles.  report may be NULL;
+ * otherwise it receives every candidate's median time [ms] and the choice. */
+#define PPM_TUNE_MAX 8
+typedef struct ppm_tune_report {
+    int32_t n_fwd, n_grad;
+    int32_t fwd_tile[PPM_TUNE_MAX];
+    double fwd_ms[PPM_TUNE_MAX];
+    int32_t grad_tile[PPM_TUNE_MAX];
+    double grad_ms[PPM_TUNE_MAX];
+    ppm_tiles chosen;
+} ppm_tune_report;
+int ppm_autotune(ppm_plan *plan, const double *params_dev, int B, const int32_t *n_cells_host, int reps,
+                 void *stream, ppm_tune_report *report);
+
 const char *ppm_status_string(int code);
 const char *ppm_last_error(void);
 int ppm_version(void);

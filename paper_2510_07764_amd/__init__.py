@@ -47,6 +47,20 @@ class _Spec(C.Structure):
                 ("interp", C.c_int32)]
 
 
+class _Tiles(C.Structure):
+    _fields_ = [("phase_tile", C.c_int32), ("phase_tile_grad", C.c_int32)]
+
+
+TUNE_MAX = 8
+
+
+class _TuneReport(C.Structure):
+    _fields_ = [("n_fwd", C.c_int32), ("n_grad", C.c_int32),
+                ("fwd_tile", C.c_int32 * TUNE_MAX), ("fwd_ms", C.c_double * TUNE_MAX),
+                ("grad_tile", C.c_int32 * TUNE_MAX), ("grad_ms", C.c_double * TUNE_MAX),
+                ("chosen", _Tiles)]
+
+
 _VP = C.c_void_p
 _I32P = C.POINTER(C.c_int32)
 _DP = C.POINTER(C.c_double)
@@ -65,6 +79,9 @@ SIGNATURES = {
     "ppm_visible_pairs": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_longlong), _VP]),
     "ppm_profile_begin": (C.c_int, [_VP, C.c_int]),
     "ppm_profile_end": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    "ppm_get_tiles": (C.c_int, [_VP, C.POINTER(_Tiles)]),
+    "ppm_set_tiles": (C.c_int, [_VP, C.POINTER(_Tiles)]),
+    "ppm_autotune": (C.c_int, [_VP, _VP, C.c_int, _I32P, C.c_int, _VP, C.POINTER(_TuneReport)]),
     "ppm_status_string": (C.c_char_p, [C.c_int]),
     "ppm_last_error": (C.c_char_p, []),
     "ppm_version": (C.c_int, []),
@@ -273,6 +290,33 @@ class Plan:
         n = C.c_int()
         _check(lib().ppm_profile_end(self.handle, C.byref(ms), C.byref(n)), "ppm_profile_end")
         return ms.value, n.value
+
+    @property
+    def tiles(self):
+        """(phase_tile, phase_tile_grad): phases per work-group of the forward
+        and of the adjoint accumulation kernels."""
+        t = _Tiles()
+        _check(lib().ppm_get_tiles(self.handle, C.byref(t)), "ppm_get_tiles")
+        return int(t.phase_tile), int(t.phase_tile_grad)
+
+    def set_tiles(self, phase_tile=None, phase_tile_grad=None):
+        cur = self.tiles
+        t = _Tiles(cur[0] if phase_tile is None else int(phase_tile),
+                   cur[1] if phase_tile_grad is None else int(phase_tile_grad))
+        _check(lib().ppm_set_tiles(self.handle, C.byref(t)), "ppm_set_tiles")
+
+    def autotune(self, params, n_cells=None, reps=5, stream=None):
+        """Times every candidate phase tile on this batch (``reps`` calls each,
+        median) and keeps the fastest on the plan.  Returns
+        {"forward": {tile: ms}, "grad": {tile: ms}, "chosen": (fwd, grad)}."""
+        B = self._params(params)
+        keep, nc = self._ncells(n_cells, B)
+        r = _TuneReport()
+        _check(lib().ppm_autotune(self.handle, _dptr(params), B, nc, int(reps), _stream_handle(stream),
+                                  C.byref(r)), "ppm_autotune")
+        return {"forward": {int(r.fwd_tile[i]): float(r.fwd_ms[i]) for i in range(r.n_fwd)},
+                "grad": {int(r.grad_tile[i]): float(r.grad_ms[i]) for i in range(r.n_grad)},
+                "chosen": (int(r.chosen.phase_tile), int(r.chosen.phase_tile_grad))}
 
     def visible_pairs(self, B, stream=None):
         out = C.c_longlong()

@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) void k_subtable_tg(DevSpec S, const int32_t *l
 // ---------------------------------------------------------------------------
 // k_accum_adj: reverse mode of the windowed accumulation (Eq. 47) over
 // energies, per (cell, phase) pair, contracted with the geometry tangents.
-// Block = (ring, tile of kPhaseTile phases), kAdjWaves waves; a wave owns one
+// Block = (ring, tile of S.pt_adj phases), kAdjWaves waves; a wave owns one
 // phase at a time.
 //  stage A  lane = cell: observed-phase lookup (Eqs. 45-46), mu weights and
 //           their mu derivatives (cubic Lagrange; linear in the protected
@@ -450,7 +450,8 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_accum_adj(DevSpec S, const i
                                                    const float *gtil, double *gpart, int n_list)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int n_tile = (S.P + kPhaseTile - 1) / kPhaseTile;
+    const int PT = S.pt_adj;
+    const int n_tile = (S.P + PT - 1) / PT;
     int li, tile;
     if (!xcd_block(n_list, n_tile, li, tile)) return;
     const int ent = list[li], b = ent / S.R_tot, r = ent - b * S.R_tot;
@@ -504,8 +505,8 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_accum_adj(DevSpec S, const i
 #pragma unroll
     for (int q = 0; q < kGradAcc; ++q) U[q] = 0.0;
     double accT = 0.0, accG = 0.0;   // lane-local F_p-weighted logT / log g sums
-    const int k_begin = tile * kPhaseTile;
-    for (int kk = wave; kk < kPhaseTile; kk += kAdjWaves) {
+    const int k_begin = tile * PT;
+    for (int kk = wave; kk < PT; kk += kAdjWaves) {
         const int k = k_begin + kk;
         if (k >= P) break;
         float Gr[EPL];
@@ -774,7 +775,7 @@ hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *param
     hipLaunchKernelGGL(k_trace_tan, dim3(n_list), dim3(256), lds_tt, st, S, list, params, ncells_dev, W.stars,
                        W.rings, W.table, W.table_u, W.trace, W.tangent, W.ringtan);
     hipLaunchKernelGGL(k_subtable_tg, dim3(n_list), dim3(256), 0, st, S, list, W.rings, W.subtg);
-    const int n_tile = (S.P + kPhaseTile - 1) / kPhaseTile;
+    const int n_tile = (S.P + S.pt_adj - 1) / S.pt_adj;
     dim3 grid(xcd_grid(n_list, n_tile));
     size_t lds = accum_adj_lds(S);
     int epl = (S.E + 63) / 64;

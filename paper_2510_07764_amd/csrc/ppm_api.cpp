@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <initializer_list>
 #include <new>
 #include <utility>
 #include <string>
@@ -240,6 +241,8 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     S.C = sp->n_chan;
     S.t_exp = sp->t_exp;
     S.n_alpha = sp->n_alpha;
+    S.pt_fwd = kPhaseTile;
+    S.pt_adj = kPhaseTile;
     pl->max_batch = max_batch;
     pl->max_cells = max_cells;
     pl->precision = sp->precision;
@@ -308,7 +311,7 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         if (sp->grad)
             per_ring += sizeof(double4) * ((size_t)S.n_alpha + (size_t)(S.n_fp + 1) * 5) + sizeof(RingTan)
                       + sizeof(float2) * (size_t)S.sub_stride
-                      + sizeof(double) * kGradAcc * (size_t)((S.P + kPhaseTile - 1) / kPhaseTile);
+                      + sizeof(double) * kGradAcc * (size_t)((S.P + kMinTileGrad - 1) / kMinTileGrad);
         size_t per_inst = per_ring * R + sizeof(double) * (size_t)S.P * S.E
                         + (sp->grad ? (sizeof(double) + sizeof(float)) * (size_t)S.P * S.E : 0);
         size_t budget = (size_t)16 << 30;
@@ -353,7 +356,7 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         ok = ok && W.partial64;
     }
     if (sp->grad) {
-        const size_t n_tile = (S.P + kPhaseTile - 1) / kPhaseTile;
+        const size_t n_tile = (S.P + kMinTileGrad - 1) / kMinTileGrad;
         W.table_u = pl->dalloc<double4>(B * R * S.n_alpha);
         W.tangent = pl->dalloc<double4>(B * R * (S.n_fp + 1) * 5);
         W.ringtan = pl->dalloc<RingTan>(B * R);
@@ -509,6 +512,40 @@ int ppm_loglike(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike reduction");
 }
 
+// One forward + adjoint pass over the batch: per workspace chunk the forward
+// (keeping the pre-absorption flux), then the adjoint of the same instances
+// while their ring scratch is live.  Model counts go to pl->W.counts.
+static hipError_t run_grad(ppm_plan *pl, const double *params, int B, const int32_t *nc, const int32_t *data,
+                           double *grad, hipStream_t st, const char **what)
+{
+    const DevSpec &S = pl->S;
+    for (size_t ci = 0; ci < pl->list_off.size(); ++ci) {
+        int c0 = (int)ci * pl->chunk;
+        int nb = B - c0 < pl->chunk ? B - c0 : pl->chunk;
+        Workspace W = pl->W;
+        W.stars += c0;
+        W.vis_pairs += (size_t)c0 * S.R_tot;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        pl->events(e0, e1);
+        const double *pc = params + (size_t)c0 * PPM_NPARAM;
+        const int32_t *ncc = nc ? nc + c0 : nullptr;
+        double *cc = pl->W.counts + (size_t)c0 * S.P * S.C;
+        hipError_t e = launch_forward(S, W, pc, ncc, nb, pl->d_list + pl->list_off[ci], pl->list_n[ci], st, W.flux,
+                                      cc, e0, e1);
+        if (e != hipSuccess) {
+            *what = "ppm_loglike_grad forward";
+            return e;
+        }
+        e = launch_grad(S, W, pc, ncc, nb, pl->d_list + pl->list_off[ci], pl->list_n[ci], cc, data,
+                        grad + (size_t)c0 * PPM_NGRAD, st);
+        if (e != hipSuccess) {
+            *what = "ppm_loglike_grad adjoint";
+            return e;
+        }
+    }
+    return hipSuccess;
+}
+
 int ppm_loglike_grad(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_cells_host,
                      const int32_t *data_dev, double *logl_dev, double *grad_dev, void *stream)
 {
@@ -518,31 +555,174 @@ int ppm_loglike_grad(ppm_plan *pl, const double *params_dev, int B, const int32_
     int rc = prepare(pl, params_dev, B, n_cells_host, &nc);
     if (rc) return rc;
     if (!data_dev || !logl_dev || !grad_dev) return fail(PPM_ERR_ARG, "null data, logl or grad buffer");
-    const DevSpec &S = pl->S;
     hipStream_t st = (hipStream_t)stream;
-    double *cnt = pl->W.counts;
-    // each workspace pass: forward (keeping the pre-absorption flux), then the
-    // adjoint of the same instances while their ring scratch is live
-    for (size_t ci = 0; ci < pl->list_off.size(); ++ci) {
-        int c0 = (int)ci * pl->chunk;
-        int nb = B - c0 < pl->chunk ? B - c0 : pl->chunk;
-        Workspace W = pl->W;
-        W.stars += c0;
-        W.vis_pairs += (size_t)c0 * S.R_tot;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        pl->events(e0, e1);
-        const double *pc = params_dev + (size_t)c0 * PPM_NPARAM;
-        const int32_t *ncc = nc ? nc + c0 : nullptr;
-        double *cc = cnt + (size_t)c0 * S.P * S.C;
-        hipError_t e = launch_forward(S, W, pc, ncc, nb, pl->d_list + pl->list_off[ci], pl->list_n[ci], st, W.flux,
-                                      cc, e0, e1);
-        if (e != hipSuccess) return hip_fail(e, "ppm_loglike_grad forward");
-        e = launch_grad(S, W, pc, ncc, nb, pl->d_list + pl->list_off[ci], pl->list_n[ci], cc, data_dev,
-                        grad_dev + (size_t)c0 * PPM_NGRAD, st);
-        if (e != hipSuccess) return hip_fail(e, "ppm_loglike_grad adjoint");
-    }
-    hipError_t e = launch_loglike(pl->W, cnt, B, S.P * S.C, data_dev, logl_dev, st);
+    const char *what = "";
+    hipError_t e = run_grad(pl, params_dev, B, nc, data_dev, grad_dev, st, &what);
+    if (e != hipSuccess) return hip_fail(e, what);
+    e = launch_loglike(pl->W, pl->W.counts, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike_grad reduction");
+}
+
+int ppm_get_tiles(const ppm_plan *pl, ppm_tiles *out)
+{
+    if (!pl || !out) return fail(PPM_ERR_ARG, "ppm_get_tiles: null argument");
+    out->phase_tile = pl->S.pt_fwd;
+    out->phase_tile_grad = pl->S.pt_adj;
+    return PPM_OK;
+}
+
+int ppm_set_tiles(ppm_plan *pl, const ppm_tiles *t)
+{
+    if (!pl || !t) return fail(PPM_ERR_ARG, "ppm_set_tiles: null argument");
+    if (t->phase_tile < 1 || t->phase_tile > kMaxTile)
+        return fail(PPM_ERR_ARG, "phase_tile must lie in [1, 256]");
+    if (t->phase_tile_grad < kMinTileGrad || t->phase_tile_grad > kMaxTile)
+        return fail(PPM_ERR_ARG, "phase_tile_grad must lie in [8, 256]");
+    pl->S.pt_fwd = t->phase_tile;
+    pl->S.pt_adj = t->phase_tile_grad;
+    return PPM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct EventSet {
+    std::vector<hipEvent_t> ev;
+    ~EventSet()
+    {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+// Median over `reps` timed calls of run() (one warm-up call first).
+template <typename Run>
+int median_ms(Run &&run, int reps, hipStream_t st, EventSet &es, double *ms)
+{
+    const char *what = "autotune";
+    hipError_t e = run(&what);
+    if (e != hipSuccess) return hip_fail(e, what);
+    e = hipEventRecord(es.ev[0], st);
+    if (e != hipSuccess) return hip_fail(e, "autotune event");
+    for (int i = 0; i < reps; ++i) {
+        e = run(&what);
+        if (e != hipSuccess) return hip_fail(e, what);
+        e = hipEventRecord(es.ev[i + 1], st);
+        if (e != hipSuccess) return hip_fail(e, "autotune event");
+    }
+    e = hipEventSynchronize(es.ev[reps]);
+    if (e != hipSuccess) return hip_fail(e, "autotune sync");
+    std::vector<float> t(reps);
+    for (int i = 0; i < reps; ++i) {
+        e = hipEventElapsedTime(&t[i], es.ev[i], es.ev[i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "autotune elapsed");
+    }
+    std::sort(t.begin(), t.end());
+    *ms = reps % 2 ? t[reps / 2] : 0.5 * (t[reps / 2 - 1] + t[reps / 2]);
+    return PPM_OK;
+}
+
+// Candidates in increasing order, dropping those that tile n_phase into as
+// many tiles as a smaller candidate already does.
+std::vector<int> tile_candidates(std::initializer_list<int> all, int P)
+{
+    std::vector<int> out;
+    int last_tiles = -1;
+    for (int t : all) {
+        int n = (P + t - 1) / t;
+        if (n == last_tiles) continue;
+        out.push_back(t);
+        last_tiles = n;
+    }
+    return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ppm_autotune(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_cells_host, int reps,
+                 void *stream, ppm_tune_report *report)
+{
+    if (reps < 1 || reps > 1000) return fail(PPM_ERR_ARG, "ppm_autotune: reps must lie in [1, 1000]");
+    const int32_t *nc = nullptr;
+    int rc = prepare(pl, params_dev, B, n_cells_host, &nc);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    DevSpec &S = pl->S;
+    const int pt0 = S.pt_fwd, pa0 = S.pt_adj;
+    ppm_tune_report rep;
+    std::memset(&rep, 0, sizeof(rep));
+    EventSet es;
+    es.ev.assign(reps + 1, nullptr);
+    for (auto &e : es.ev) {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return hip_fail(r, "ppm_autotune event");
+    }
+    auto restore = [&](int code) {
+        S.pt_fwd = pt0;
+        S.pt_adj = pa0;
+        return code;
+    };
+    // forward tile
+    double best = 0.0;
+    int best_t = pt0;
+    for (int t : tile_candidates({4, 8, 12, 16, 24, 32}, S.P)) {
+        S.pt_fwd = t;
+        double ms = 0.0;
+        rc = median_ms([&](const char **what) {
+            *what = "ppm_autotune forward";
+            return run_forward(pl, params_dev, B, nc, st, nullptr, pl->W.counts);
+        }, reps, st, es, &ms);
+        if (rc) return restore(rc);
+        rep.fwd_tile[rep.n_fwd] = t;
+        rep.fwd_ms[rep.n_fwd++] = ms;
+        if (rep.n_fwd == 1 || ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    S.pt_fwd = best_t;
+    // adjoint tile (gradient plans)
+    if (pl->grad) {
+        DevBuf data, grad;
+        hipError_t e = hipMalloc(&data.p, sizeof(int32_t) * (size_t)S.P * S.C);
+        if (e == hipSuccess) e = hipMalloc(&grad.p, sizeof(double) * (size_t)B * PPM_NGRAD);
+        if (e == hipSuccess) e = hipMemsetAsync(data.p, 0, sizeof(int32_t) * (size_t)S.P * S.C, st);
+        if (e != hipSuccess) return restore(hip_fail(e, "ppm_autotune temporary buffers"));
+        int best_a = pa0;
+        for (int t : tile_candidates({8, 16, 24, 32}, S.P)) {
+            S.pt_adj = t;
+            double ms = 0.0;
+            rc = median_ms([&](const char **what) {
+                return run_grad(pl, params_dev, B, nc, (const int32_t *)data.p, (double *)grad.p, st, what);
+            }, reps, st, es, &ms);
+            if (rc) return restore(rc);
+            rep.grad_tile[rep.n_grad] = t;
+            rep.grad_ms[rep.n_grad++] = ms;
+            if (rep.n_grad == 1 || ms < best) {
+                best = ms;
+                best_a = t;
+            }
+        }
+        S.pt_adj = best_a;
+        // the temporaries are freed on return: finish the work that reads them
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return restore(hip_fail(e, "ppm_autotune sync"));
+    }
+    rep.chosen.phase_tile = S.pt_fwd;
+    rep.chosen.phase_tile_grad = S.pt_adj;
+    if (report) *report = rep;
+    return PPM_OK;
 }
 
 int ppm_instance_status(ppm_plan *pl, int B, int32_t *status_dev, void *stream)

@@ -31,6 +31,7 @@ struct DevSpec {
     int fast;             // 1: windowed accumulation kernel applies (energy span <= 59 x-intervals)
     int W_max;            // x-node window of the per-ring sub-table
     int sub_stride;       // floats per ring in the sub-table buffer (multiple of 4)
+    int pt_fwd, pt_adj;   // phases per block of the forward / adjoint accumulation kernels
     double tb0, r_span;   // (log10 E_0 - x0)/hx and (log10 E_last - log10 E_0)/hx
     int R_tot;            // ring slots per instance (spot 0 then spot 1)
     int rings_max[2];     // ring slots of each spot

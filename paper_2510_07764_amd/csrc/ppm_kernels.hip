@@ -1120,7 +1120,7 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
     size_t lds_tr = sizeof(double4) * (S.n_alpha + S.n_fp + 1);
     hipLaunchKernelGGL(k_trace, dim3(n_list), dim3(256), lds_tr, st, S, list, W.stars, W.rings, W.table,
                        W.trace, W.sub);
-    const int PT = kPhaseTile;
+    const int PT = S.pt_fwd;
     dim3 grid(xcd_grid(n_list, (S.P + PT - 1) / PT));
     if (S.intensity == PPM_I_TABLE) {
         size_t lds = accum_table_lds(S);

@@ -34,7 +34,9 @@ struct Workspace {
     double *gpart;         // [B][R_tot][n_tile][kGradAcc] per-block adjoint sums
 };
 
-constexpr int kPhaseTile = 8;    // phases per block of the accumulation kernels
+constexpr int kPhaseTile = 8;    // default phases per block of the accumulation kernels
+constexpr int kMinTileGrad = 8;  // smallest adjoint phase tile (sizes the per-block adjoint sums)
+constexpr int kMaxTile = 256;    // largest phase tile either kernel accepts
 constexpr int kGradAcc = 9;      // per-ring adjoint sums of the accumulation kernel
 
 __host__ __device__ int validate_params(const double *p, int n_spots);

@@ -76,3 +76,18 @@ def test_spec_errors_before_device_use():
     e[3] = e[2]
     with pytest.raises(ppm.PPMError, match="increase"):
         ppm.Plan(dict(spec, energy=e))
+
+
+def test_tile_entry_points_reject_null_arguments(L):
+    """The launch-shape and autotuner entry points check their pointers and
+    ranges on the host, before any device work."""
+    import ctypes as C
+    import paper_2510_07764_amd as ppm
+    t = ppm._Tiles(8, 8)
+    assert L.ppm_get_tiles(None, C.byref(t)) == -1
+    assert L.ppm_set_tiles(None, C.byref(t)) == -1
+    r = ppm._TuneReport()
+    assert L.ppm_autotune(None, None, 1, None, 3, None, C.byref(r)) == -1
+    assert L.ppm_autotune(None, None, 1, None, 0, None, C.byref(r)) == -1
+    assert "reps" in L.ppm_last_error().decode()
+    assert C.sizeof(ppm._TuneReport) == 208
