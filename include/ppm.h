@@ -197,7 +197,8 @@ int ppm_get_tiles(const ppm_plan *plan, ppm_tiles *out);
 int ppm_set_tiles(ppm_plan *plan, const ppm_tiles *tiles);
 
 /* Autotuner of the launch shape.  For each candidate phase tile (forward:
- * 4, 8, 12, 16, 24, 32; adjoint, gradient plans only: 8, 16, 24, 32;
+ * 4, 8, 12, 16, 20, 24, 28, 32, 48, 64; adjoint, gradient plans only: 8, 16, 24,
+ * 32;
  * a candidate that gives the same number of tiles over n_phase as a smaller
  * one is skipped) it times whole evaluations of the given batch (params_dev,
  * B, n_cells_host as for ppm_forward): one warm-up call, then `reps` calls
@@ -208,7 +209,7 @@ int ppm_set_tiles(ppm_plan *plan, const ppm_tiles *tiles);
  * two temporary device buffers, allocated and freed here.  Synchronises the
  * stream.  On error the plan keeps its previous tiles.  report may be NULL;
  * otherwise it receives every candidate's median time [ms] and the choice. */
-#define PPM_TUNE_MAX 8
+#define PPM_TUNE_MAX 16
 typedef struct ppm_tune_report {
     int32_t n_fwd, n_grad;
     int32_t fwd_tile[PPM_TUNE_MAX];

@@ -51,7 +51,7 @@ class _Tiles(C.Structure):
     _fields_ = [("phase_tile", C.c_int32), ("phase_tile_grad", C.c_int32)]
 
 
-TUNE_MAX = 8
+TUNE_MAX = 16
 
 
 class _TuneReport(C.Structure):
