@@ -32,16 +32,19 @@ METRIC = "forward+logL evals/sec at config[1], plain vs batched vs +grad, <=1e-4
 FLOP_PER_UNIT = 24.0
 PEAK_FP32_TFLOPS = 157.3
 
-# HBM traffic of the hot kernel per launch (config-1 workload, one vector):
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two rocprofv3 --pmc runs,
-# each scaled by what the same counter reads for a 256 MiB device-to-device
-# copy (FETCH_SIZE reads half the copied bytes on this part, WRITE_SIZE all
-# of them).  Valid only for the kernel sources the counters were taken on;
-# any change to them reports null until the counters are taken again.
+# HBM traffic of the hot kernel per launch (config-1 workload, one vector),
+# per phase tile of the launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+# from rocprofv3 --pmc runs, one counter per run, each scaled by what the same
+# counter reads for a 256 MiB device-to-device copy (FETCH_SIZE reads half the
+# copied bytes on this part, WRITE_SIZE all of them).  Valid only for the
+# kernel sources the counters were taken on and for the tiles listed; any
+# other case reports null until the counters are taken again.
 KERNEL_SOURCES = ("ppm_kernels.hip", "ppm_device.h", "ppm_dual.h", "ppm_internal.h", "ppm_launch.h")
-TRAFFIC = {"sources_sha256": "458d3514046fd6c840785acd66ebef42c670983f116480e8f462ae811940809c",
-           "fetch_kib": 4282.56, "write_kib": 33198.96, "fetch_scale": 1.99980, "write_scale": 1.0,
-           "phase_tile": 8, "profile": "profiles/k_accum_fast_config1_traffic.md"}
+TRAFFIC = {"sources_sha256": "195fc142f80b1780579179b3562fe648b1dd3291e43bbfb83705cd068736b524",
+           "fetch_scale": 1.99980, "write_scale": 1.0,
+           # phase tile -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
+           "by_tile": {8: (4282.85, 33198.96), 12: (4282.26, 33071.07)},
+           "profile": "profiles/k_accum_fast_config1_traffic.md"}
 
 
 def kernel_sources_sha256():
@@ -58,9 +61,10 @@ def hot_kernel_traffic(phase_tile):
     t = TRAFFIC
     if t["sources_sha256"] is None or t["sources_sha256"] != kernel_sources_sha256():
         return None
-    if phase_tile != t["phase_tile"]:
+    if phase_tile not in t["by_tile"]:
         return None
-    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+    fetch_kib, write_kib = t["by_tile"][phase_tile]
+    return (fetch_kib * t["fetch_scale"] + write_kib * t["write_scale"]) * 1024.0
 
 
 def cpu_baseline(sample_cells: int, one_core_cells: int):
