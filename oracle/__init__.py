@@ -105,6 +105,10 @@ def lib():
         L.orc_blackbody.argtypes = [C.c_double, C.c_double]
         L.orc_forward.restype = C.c_int
         L.orc_forward.argtypes = [C.POINTER(Spec), _D, _D, _D, C.POINTER(Diag)]
+        L.orc_forward_map.restype = C.c_int
+        L.orc_forward_map.argtypes = [C.POINTER(Spec), _D, C.c_int, _D, _D, _D, C.POINTER(Diag)]
+        L.orc_healpix_ring.restype = None
+        L.orc_healpix_ring.argtypes = [C.c_int, C.c_int, _D, C.POINTER(C.c_int), _D]
         L.orc_loglike_counts.restype = C.c_double
         L.orc_loglike_counts.argtypes = [_D, C.POINTER(C.c_int), C.c_longlong]
         L.orc_set_threads.restype = None
@@ -173,6 +177,33 @@ def forward(spec: dict | OracleSpec, params, want_counts=True):
     d = Diag()
     lib().orc_forward(C.byref(os_.s), _ptr(p), _ptr(ft), _ptr(cnt) if cnt is not None else None, C.byref(d))
     return ft, cnt, d.as_dict()
+
+
+def forward_map(spec: dict | OracleSpec, params, nside: int, logT_map, want_counts=True):
+    """Full-surface temperature map on HEALPix (Sects. 2.6, 2.8.1):
+    logT_map[12 nside^2] in ring order, non-finite or non-positive entries
+    inactive.  Returns (Ft[P, E], counts[P, C] or None, diag dict)."""
+    os_ = spec if isinstance(spec, OracleSpec) else OracleSpec(spec)
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    m = np.ascontiguousarray(logT_map, dtype=np.float64)
+    assert m.shape == (12 * nside * nside,)
+    ft = np.zeros((os_.n_phase, os_.n_energy))
+    cnt = np.zeros((os_.n_phase, os_.n_chan)) if (want_counts and os_.n_chan) else None
+    d = Diag()
+    rc = lib().orc_forward_map(C.byref(os_.s), _ptr(p), int(nside), _ptr(m), _ptr(ft),
+                               _ptr(cnt) if cnt is not None else None, C.byref(d))
+    assert rc == 0
+    return ft, cnt, d.as_dict()
+
+
+def healpix_ring(nside: int, i: int):
+    """(cos colatitude, pixels, azimuth of the first pixel) of HEALPix ring
+    i = 1 .. 4 nside - 1."""
+    z = C.c_double()
+    n = C.c_int()
+    f = C.c_double()
+    lib().orc_healpix_ring(int(nside), int(i), C.byref(z), C.byref(n), C.byref(f))
+    return z.value, n.value, f.value
 
 
 def loglike_from_counts(counts, data) -> float:

@@ -314,6 +314,29 @@ static double arc_halfwidth(double th, double tc, double z)
    over the spot's colatitude span, N_phi cells per ring over the emitting
    arc(s).  The area element is Eq. (9) (Eq. 6 for a sphere); the per-ring
    quantities are Eqs. (2)-(3), (7), (10)-(11), (18). */
+/* Geometry of the ring at colatitude th (Eqs. 2, 3, 7, 9-11, 18): radius,
+   compactness, surface tilt, log g, surface speed and the largest emission
+   angle of its deflection table. */
+static void ring_geometry(const orc_spec *s, const orc_star *st, double th, orc_ring *g)
+{
+    g->theta = th;
+    double ct = cos(th), sn = sin(th);
+    g->R = st->Re * (1.0 + st->o2 * ct * ct);
+    double dR = -2.0 * st->Re * st->o2 * ct * sn;
+    g->u = st->Rs / g->R;
+    g->f = dR / (g->R * sqrt(1.0 - g->u));
+    g->coseta = 1.0 / sqrt(1.0 + g->f * g->f);
+    g->sineta = g->f / sqrt(1.0 + g->f * g->f);
+    g->logg = log10(st->g0 * gravity_ratio(st, s->mode, th));
+    g->beta = TWO_PI * st->nu * g->R * sn / (C_CGS * sqrt(1.0 - g->u));
+    g->gamma = 1.0 / sqrt(1.0 - g->beta * g->beta);
+    double amax = HALF_PI + fabs(atan(g->f));
+    double acap = orc_alpha_capture(g->u);
+    if (amax > acap - 1e-6) amax = acap - 1e-6;
+    g->alpha_max = amax;
+    g->psi_top = orc_psi(g->u, amax);
+}
+
 int orc_rings(const orc_spec *s, const double *p, int spot, orc_ring *rings)
 {
     orc_star st;
@@ -325,18 +348,8 @@ int orc_rings(const orc_spec *s, const double *p, int spot, orc_ring *rings)
         orc_ring *g = &rings[r];
         double e0 = lo + (hi - lo) * r / nr, e1 = lo + (hi - lo) * (r + 1) / nr;
         double th = 0.5 * (e0 + e1);
-        g->theta = th;
+        ring_geometry(s, &st, th, g);
         g->dcos = cos(e0) - cos(e1);
-        double ct = cos(th), sn = sin(th);
-        g->R = st.Re * (1.0 + st.o2 * ct * ct);
-        double dR = -2.0 * st.Re * st.o2 * ct * sn;
-        g->u = st.Rs / g->R;
-        g->f = dR / (g->R * sqrt(1.0 - g->u));
-        g->coseta = 1.0 / sqrt(1.0 + g->f * g->f);
-        g->sineta = g->f / sqrt(1.0 + g->f * g->f);
-        g->logg = log10(st.g0 * gravity_ratio(&st, s->mode, th));
-        g->beta = TWO_PI * st.nu * g->R * sn / (C_CGS * sqrt(1.0 - g->u));
-        g->gamma = 1.0 / sqrt(1.0 - g->beta * g->beta);
         if (s->shape[spot] == 1) {
             g->dphi_out = arc_halfwidth(th, tc, z);
             g->dphi_in = arc_halfwidth(th, tc, s->shape_a[spot] * z);
@@ -348,13 +361,29 @@ int orc_rings(const orc_spec *s, const double *p, int spot, orc_ring *rings)
         }
         g->w_cell = g->R * g->R * sqrt(1.0 + g->f * g->f) * g->dcos * g->dphi_cell / (st.D * st.D);
         g->n_cells = nphi;
-        double amax = HALF_PI + fabs(atan(g->f));
-        double acap = orc_alpha_capture(g->u);
-        if (amax > acap - 1e-6) amax = acap - 1e-6;
-        g->alpha_max = amax;
-        g->psi_top = orc_psi(g->u, amax);
     }
     return nr;
+}
+
+/* HEALPix ring i = 1 .. 4 nside - 1 (Sect. 2.8.1): cosine of its
+   colatitude, its number of pixels and the azimuth of its first pixel; the
+   pixels of a ring are 2 pi / nphi apart.  Rings south of the equator mirror
+   those north of it. */
+void orc_healpix_ring(int nside, int i, double *z, int *nphi, double *phi_first)
+{
+    int m = i > 2 * nside ? 4 * nside - i : i;   /* northern counterpart */
+    double n = nside;
+    double zz;
+    if (m < nside) {
+        zz = 1.0 - (double)m * m / (3.0 * n * n);
+        *nphi = 4 * m;
+        *phi_first = PI / (2.0 * m) * 0.5;
+    } else {
+        zz = 4.0 / 3.0 - 2.0 * m / (3.0 * n);
+        *nphi = 4 * nside;
+        *phi_first = PI / (2.0 * n) * (1.0 - ((m - nside + 1) % 2) / 2.0);
+    }
+    *z = i > 2 * nside ? -zz : zz;
 }
 
 /* azimuth offset of cell j on ring g relative to the spot centre */
@@ -629,15 +658,21 @@ static void neumaier_add(double *sum, double *comp, double v)
 }
 
 /* Shift-and-add of one ring (Eqs. 45-47) into Ft_sum/Ft_comp [P][E]. */
-static void ring_accumulate(const orc_spec *s, const double *p, int spot, const orc_ring *g,
-                            const double *linI, double *sum, double *comp, orc_diag *diag)
+/* Shift-and-add of one ring (Eqs. 45-47) over the cells given by their
+   azimuths phic[j] (the spot or map longitude including -2 pi Phi) and
+   log10 temperatures logTc[j]: one fine-phase trace for the ring, then per
+   cell, output phase and energy the phase lookup, the intensity at the
+   cell's temperature and a compensated sum into Ft. */
+static void ring_accumulate_cells(const orc_spec *s, const double *p, const orc_ring *g, int ncell,
+                                  const double *phic, const double *logTc, const double *linI,
+                                  double *sum, double *comp, orc_diag *diag)
 {
     int nfp = s->n_fp, P = s->n_phase, E = s->n_energy;
     double *F = malloc(sizeof(double) * 4 * (nfp + 1));
     double *z = F + (nfp + 1), *phio = z + (nfp + 1), *mu = phio + (nfp + 1);
     int inv[2];
     orc_diag local = {0, 0, 0, 0, 0, 0, 0};
-    if (!orc_trace_ring(s, p, g, F, z, phio, mu, inv, &local) || g->w_cell <= 0.0) {
+    if (ncell == 0 || !orc_trace_ring(s, p, g, F, z, phio, mu, inv, &local) || g->w_cell <= 0.0) {
         free(F);
         if (diag) {
 #pragma omp atomic
@@ -645,17 +680,13 @@ static void ring_accumulate(const orc_spec *s, const double *p, int spot, const 
         }
         return;
     }
-    double logT = p[10 + 4 * spot];
-    double T = pow(10.0, logT);
-    double kT = K_B * T;
-    double phis = -TWO_PI * (p[3] + (spot == 1 ? p[15] : 0.0));
-    for (int j = 0; j < g->n_cells; ++j) {
-        double off = cell_offset(s, spot, g, j);
-        if (cell_masked(s, p, spot, g, off)) continue;
-        double phic = phis + off;
+    for (int j = 0; j < ncell; ++j) {
+        double logT = logTc[j];
+        double T = pow(10.0, logT);
+        double kT = K_B * T;
         for (int k = 0; k < P; ++k) {
             double Phik = (k + 0.5) / P;
-            double a = Phik + phic / TWO_PI + 1.0 - phio[0];
+            double a = Phik + phic[j] / TWO_PI + 1.0 - phio[0];
             double php = (a - floor(a)) + phio[0];                     /* Eq. (45) */
             int lo = 0, hi = nfp;                                      /* phio[lo] <= php */
             while (hi - lo > 1) {
@@ -696,16 +727,96 @@ static void ring_accumulate(const orc_spec *s, const double *p, int spot, const 
     }
 }
 
-int orc_forward(const orc_spec *s, const double *p, double *Ft, double *counts, orc_diag *diag)
+/* One spot ring: the unmasked cells at their offsets from the spot centre,
+   all at the spot's temperature. */
+static void ring_accumulate(const orc_spec *s, const double *p, int spot, const orc_ring *g,
+                            const double *linI, double *sum, double *comp, orc_diag *diag)
+{
+    double *phic = malloc(sizeof(double) * 2 * (g->n_cells + 1));
+    double *logTc = phic + g->n_cells + 1;
+    double phis = -TWO_PI * (p[3] + (spot == 1 ? p[15] : 0.0));
+    int n = 0;
+    for (int j = 0; j < g->n_cells; ++j) {
+        double off = cell_offset(s, spot, g, j);
+        if (cell_masked(s, p, spot, g, off)) continue;
+        phic[n] = phis + off;
+        logTc[n] = p[10 + 4 * spot];
+        ++n;
+    }
+    ring_accumulate_cells(s, p, g, n, phic, logTc, linI, sum, comp, diag);
+    free(phic);
+}
+
+/* Runs ring(ctx, r, sum, comp) for r = 0 .. nring-1 (in parallel over
+   rings) and adds the per-ring partials to Ft in a fixed ring order, so that
+   the result does not depend on the thread count. */
+typedef void (*ring_fn)(void *ctx, int r, double *sum, double *comp);
+
+static void sum_rings(const orc_spec *s, int nring, ring_fn ring, void *ctx, double *Ft)
 {
     int P = s->n_phase, E = s->n_energy;
     long long PE = (long long)P * E;
-    double *linI = NULL;
-    if (s->intensity == 1) {
-        long long n = (long long)s->nT * s->ng * s->nmu * s->nx;
-        linI = malloc(sizeof(double) * n);
-        for (long long i = 0; i < n; ++i) linI[i] = pow(10.0, s->logI[i]);
+    double *tot = calloc(2 * PE, sizeof(double));
+    const int CH = 32;
+    double *part = malloc(sizeof(double) * 2 * PE * CH);
+    for (int r0 = 0; r0 < nring; r0 += CH) {
+        int nc = (nring - r0 < CH) ? nring - r0 : CH;
+        memset(part, 0, sizeof(double) * 2 * PE * nc);
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int r = 0; r < nc; ++r) ring(ctx, r0 + r, part + 2 * PE * r, part + 2 * PE * r + PE);
+        for (int r = 0; r < nc; ++r)
+            for (long long i = 0; i < PE; ++i) {
+                neumaier_add(&tot[i], &tot[PE + i], part[2 * PE * r + i]);
+                neumaier_add(&tot[i], &tot[PE + i], part[2 * PE * r + PE + i]);
+            }
     }
+    for (long long i = 0; i < PE; ++i) Ft[i] = tot[i] + tot[PE + i];
+    free(part);
+    free(tot);
+}
+
+/* Eq. (22) absorption and Eq. (55) fold, T_exp / P seconds per phase bin. */
+static void fold_counts(const orc_spec *s, const double *p, const double *Ft, double *counts)
+{
+    int P = s->n_phase, E = s->n_energy, C = s->n_chan;
+    double NH = p[4] * 1e20;
+    for (int k = 0; k < P; ++k)
+        for (int c = 0; c < C; ++c) {
+            double acc = 0.0;
+            for (int e = 0; e < E; ++e) {
+                double att = s->sigma ? exp(-NH * s->sigma[e]) : 1.0;
+                acc += Ft[(long long)k * E + e] * att * s->rsp[(long long)e * C + c];
+            }
+            counts[(long long)k * C + c] = s->t_exp / P * acc;
+        }
+}
+
+static double *linear_table(const orc_spec *s)
+{
+    if (s->intensity != 1) return NULL;
+    long long n = (long long)s->nT * s->ng * s->nmu * s->nx;
+    double *linI = malloc(sizeof(double) * n);
+    for (long long i = 0; i < n; ++i) linI[i] = pow(10.0, s->logI[i]);
+    return linI;
+}
+
+typedef struct {
+    const orc_spec *s;
+    const double *p, *linI;
+    const orc_ring *rings;
+    const int *rspot;
+    orc_diag *diag;
+} spot_ctx;
+
+static void spot_ring(void *c, int r, double *sum, double *comp)
+{
+    spot_ctx *x = (spot_ctx *)c;
+    ring_accumulate(x->s, x->p, x->rspot[r], &x->rings[r], x->linI, sum, comp, x->diag);
+}
+
+int orc_forward(const orc_spec *s, const double *p, double *Ft, double *counts, orc_diag *diag)
+{
+    double *linI = linear_table(s);
     /* ring list over all spots */
     int nring = 0;
     for (int sp = 0; sp < s->n_spots; ++sp) nring += s->n_rings[sp];
@@ -717,39 +828,76 @@ int orc_forward(const orc_spec *s, const double *p, double *Ft, double *counts, 
         for (int r = 0; r < s->n_rings[sp]; ++r) rspot[off + r] = sp;
         off += s->n_rings[sp];
     }
-    double *tot = calloc(2 * PE, sizeof(double));
-    const int CH = 32;
-    double *part = malloc(sizeof(double) * 2 * PE * CH);
-    for (int r0 = 0; r0 < nring; r0 += CH) {
-        int nc = (nring - r0 < CH) ? nring - r0 : CH;
-        memset(part, 0, sizeof(double) * 2 * PE * nc);
-#pragma omp parallel for schedule(dynamic, 1)
-        for (int r = 0; r < nc; ++r)
-            ring_accumulate(s, p, rspot[r0 + r], &rings[r0 + r], linI,
-                            part + 2 * PE * r, part + 2 * PE * r + PE, diag);
-        /* fixed ring order: deterministic for any thread count */
-        for (int r = 0; r < nc; ++r)
-            for (long long i = 0; i < PE; ++i) {
-                neumaier_add(&tot[i], &tot[PE + i], part[2 * PE * r + i]);
-                neumaier_add(&tot[i], &tot[PE + i], part[2 * PE * r + PE + i]);
-            }
+    spot_ctx ctx = {s, p, linI, rings, rspot, diag};
+    sum_rings(s, nring, spot_ring, &ctx, Ft);
+    if (counts) fold_counts(s, p, Ft, counts);
+    free(rings); free(rspot); free(linI);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Full-surface temperature map on HEALPix (Sects. 2.6, 2.8.1)              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const orc_spec *s;
+    const double *p, *linI, *map;
+    int nside;
+    const orc_ring *rings;
+    const long long *first_pix;
+    orc_diag *diag;
+} map_ctx;
+
+static void map_ring(void *c, int r, double *sum, double *comp)
+{
+    map_ctx *x = (map_ctx *)c;
+    const orc_ring *g = &x->rings[r];
+    double zr, phi0;
+    int nphi;
+    orc_healpix_ring(x->nside, r + 1, &zr, &nphi, &phi0);
+    double *phic = malloc(sizeof(double) * 2 * nphi);
+    double *logTc = phic + nphi;
+    int n = 0;
+    for (int j = 0; j < nphi; ++j) {
+        double lt = x->map[x->first_pix[r] + j];
+        if (!(isfinite(lt) && lt > 0.0)) continue;                    /* inactive patch */
+        phic[n] = -TWO_PI * x->p[3] + phi0 + j * (TWO_PI / nphi);
+        logTc[n] = lt;
+        ++n;
     }
-    for (long long i = 0; i < PE; ++i) Ft[i] = tot[i] + tot[PE + i];
-    if (counts) {
-        /* Eq. (22) absorption, Eq. (55) fold, T_exp / P seconds per phase bin */
-        int C = s->n_chan;
-        double NH = p[4] * 1e20;
-        for (int k = 0; k < P; ++k)
-            for (int c = 0; c < C; ++c) {
-                double acc = 0.0;
-                for (int e = 0; e < E; ++e) {
-                    double att = s->sigma ? exp(-NH * s->sigma[e]) : 1.0;
-                    acc += Ft[(long long)k * E + e] * att * s->rsp[(long long)e * C + c];
-                }
-                counts[(long long)k * C + c] = s->t_exp / P * acc;
-            }
+    ring_accumulate_cells(x->s, x->p, g, n, phic, logTc, x->linI, sum, comp, x->diag);
+    free(phic);
+}
+
+int orc_forward_map(const orc_spec *s, const double *p, int nside, const double *logT_map, double *Ft,
+                    double *counts, orc_diag *diag)
+{
+    if (nside < 1) return -1;
+    orc_star st;
+    orc_star_setup(s, p, &st);
+    double *linI = linear_table(s);
+    int nring = 4 * nside - 1;
+    orc_ring *rings = malloc(sizeof(orc_ring) * nring);
+    long long *first = malloc(sizeof(long long) * nring);
+    long long pix = 0;
+    const double area = PI / (3.0 * (double)nside * nside);   /* d cos(theta) d phi of one patch */
+    for (int r = 0; r < nring; ++r) {
+        double zr, phi0;
+        int nphi;
+        orc_healpix_ring(nside, r + 1, &zr, &nphi, &phi0);
+        orc_ring *g = &rings[r];
+        ring_geometry(s, &st, acos(zr), g);
+        g->dcos = 0.0;
+        g->dphi_out = g->dphi_in = 0.0;
+        g->dphi_cell = TWO_PI / nphi;
+        g->w_cell = g->R * g->R * sqrt(1.0 + g->f * g->f) * area / (st.D * st.D);   /* Eq. (9) */
+        g->n_cells = nphi;
+        first[r] = pix;
+        pix += nphi;
     }
-    free(part); free(tot); free(rings); free(rspot); free(linI);
+    map_ctx ctx = {s, p, linI, logT_map, nside, rings, first, diag};
+    sum_rings(s, nring, map_ring, &ctx, Ft);
+    if (counts) fold_counts(s, p, Ft, counts);
+    free(rings); free(first); free(linI);
     return 0;
 }
 

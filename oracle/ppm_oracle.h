@@ -94,6 +94,17 @@ double orc_blackbody(double E_kev, double T_kelvin);
    counts[P][C] (NULL to skip). */
 int orc_forward(const orc_spec *s, const double *p, double *Ft, double *counts, orc_diag *diag);
 double orc_loglike_counts(const double *counts, const int *data, long long n);
+
+/* HEALPix ring i = 1 .. 4 nside - 1 (Sect. 2.8.1): cos(colatitude), pixels
+   on the ring, azimuth of its first pixel (pixels are 2 pi / nphi apart). */
+void orc_healpix_ring(int nside, int i, double *z, int *nphi, double *phi_first);
+/* Forward model of a full-surface temperature map (Sects. 2.6, 2.8.1):
+   logT_map[12 nside^2] holds log10 T [K] per HEALPix patch in ring order
+   (rings from the north pole, pixels by increasing azimuth); a value that is
+   not finite or not positive marks an inactive patch.  Parameter slots 0-6
+   as for spots; the spot slots are ignored.  Returns 0, -1 for nside < 1. */
+int orc_forward_map(const orc_spec *s, const double *p, int nside, const double *logT_map, double *Ft,
+                    double *counts, orc_diag *diag);
 void orc_set_threads(int n);
 
 #ifdef __cplusplus

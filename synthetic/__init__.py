@@ -71,6 +71,7 @@ SHAPE_CAP, SHAPE_ANNULUS, SHAPE_CRESCENT = 0, 1, 2
 
 # seeds of each synthetic input
 SEED_ATMOS, SEED_RESPONSE, SEED_DATA, SEED_BATCH, SEED_RES, SEED_GRAD = 11, 12, 13, 14, 15, 16
+SEED_MAP = 17
 
 
 def logspace(xmin: float, xmax: float, n: int) -> np.ndarray:
@@ -340,6 +341,83 @@ def config4_draws(n=256, seed=SEED_GRAD):
         out[k] = p
         k += 1
     return out
+
+
+# ---------------------------------------------------------------------------
+# Full-surface temperature maps on HEALPix (Sects. 2.6, 2.8.1).  The paper's
+# physics-motivated generator (return-current heating of an off-centred
+# dipole) is not available; smooth synthetic maps with a hot polar-cap-like
+# region with a radial temperature gradient and a cooler arc stand in for it.
+# The patch centres below place those features only; the oracle and the HIP
+# path each compute the HEALPix geometry themselves.
+# ---------------------------------------------------------------------------
+def healpix_centres(nside: int):
+    """(colatitude, azimuth) of every HEALPix patch centre, ring order: rings
+    from the north pole, pixels by increasing azimuth."""
+    th, ph = [], []
+    for i in range(1, 4 * nside):
+        m = min(i, 4 * nside - i)
+        if m < nside:
+            z = 1.0 - m * m / (3.0 * nside * nside)
+            n = 4 * m
+            phi = math.pi / (2.0 * m) * (np.arange(n) + 0.5)
+        else:
+            z = 4.0 / 3.0 - 2.0 * m / (3.0 * nside)
+            n = 4 * nside
+            phi = math.pi / (2.0 * nside) * (np.arange(n) + 1.0 - ((m - nside + 1) % 2) / 2.0)
+        if i > 2 * nside:
+            z = -z
+        th.append(np.full(n, math.acos(z)))
+        ph.append(phi)
+    return np.concatenate(th), np.concatenate(ph)
+
+
+def _angular_distance(th, ph, th0, ph0):
+    c = np.cos(th) * math.cos(th0) + np.sin(th) * math.sin(th0) * np.cos(ph - ph0)
+    return np.arccos(np.clip(c, -1.0, 1.0))
+
+
+def temperature_map(nside: int, kind: str = "hotspots", seed: int = SEED_MAP) -> np.ndarray:
+    """log10 T [K] per HEALPix patch (ring order); 0 marks an inactive patch.
+
+    hotspots  a polar-cap-like region (centre colatitude 0.5 rad, azimuth 0,
+              radius 0.45 rad, logT falling from 6.35 at the centre to 5.95
+              at the rim) and an arc (annulus 0.12-0.30 rad around colatitude
+              2.45 rad, azimuth 2.5 rad, logT 5.95-6.10); the rest inactive;
+    full      every patch active: a smooth background around logT 5.6 with
+              the hotspots on top (the larger of the two);
+    random    seeded: 30% of the patches active with logT uniform in
+              [4.8, 7.0], beyond the table's range on both sides.
+    """
+    th, ph = healpix_centres(nside)
+    if kind == "random":
+        rng = np.random.default_rng(seed)
+        lt = rng.uniform(4.8, 7.0, th.size)
+        return np.where(rng.uniform(size=th.size) < 0.3, lt, 0.0)
+    d1 = _angular_distance(th, ph, 0.5, 0.0)
+    d2 = _angular_distance(th, ph, 2.45, 2.5)
+    hot = np.zeros(th.size)
+    cap = d1 <= 0.45
+    hot[cap] = 6.35 - 0.40 * (d1[cap] / 0.45) ** 2
+    arc = (d2 >= 0.12) & (d2 <= 0.30)
+    hot[arc] = 5.95 + 0.15 * np.sin(math.pi * (d2[arc] - 0.12) / 0.18)
+    if kind == "hotspots":
+        return hot
+    if kind == "full":
+        bg = 5.55 + 0.10 * np.cos(th) ** 2 + 0.05 * np.sin(th) * np.cos(ph - 1.0)
+        return np.maximum(bg, hot)
+    raise ValueError(kind)
+
+
+def map_config(nside: int = 64, kind: str = "full", n_phase: int = 128, n_energy: int = 256):
+    """Full-surface temperature map workload: the config-1 star (oblate,
+    600 Hz, M = 1.4, R_e = 12.5 km, i = 60 deg, 150 pc), the synthetic
+    atmosphere, absorption and response, and a HEALPix map of nside."""
+    spec = _base_spec(n_phase=n_phase, energy=logspace(0.2, 3.0, n_energy), precision="f32", n_side=nside)
+    attach_atmosphere(spec)
+    attach_instrument(spec)
+    params = params_vector(1.4, 12.5, math.radians(60.0), 0.05, 1.0, 600.0, 150.0, 0.0, 0.0, 0.0)
+    return spec, params, temperature_map(nside, kind)
 
 
 def poisson_data(counts: np.ndarray, seed: int = SEED_DATA) -> np.ndarray:
