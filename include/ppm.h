@@ -47,6 +47,8 @@ extern "C" {
 #define PPM_INST_COMPACT 3      /* GM/(R_e c^2) > 0.28: multiple images not modelled (Sect. 6) */
 #define PPM_INST_BAD_SPOT 4     /* spot colatitude outside [0, pi] or radius outside (0, pi] */
 #define PPM_INST_FAST_SPIN 5    /* surface speed beta >= 0.6 somewhere on the star */
+#define PPM_INST_BAD_MAP 6      /* a temperature-map value more than 64 logT table steps
+                                   outside the table's logT range */
 
 enum ppm_mode { PPM_MODE_SD = 0, PPM_MODE_OS = 1 };
 enum ppm_intensity { PPM_I_BLACKBODY = 0, PPM_I_TABLE = 1 };
@@ -88,6 +90,13 @@ enum ppm_interp { PPM_INTERP_MIXED = 0, PPM_INTERP_CUBIC = 1, PPM_INTERP_CUBIC_C
  *              (c: (a) but linear in the protected zone).  (a)-(c) need at
  *              least four nodes on every axis, run on the generic kernel and
  *              have no gradient.
+ *  n_side      0: the spot model above.  > 0 (at most 512): a full-surface
+ *              temperature-map plan (Sects. 2.6, 2.8.1): the surface is the
+ *              12 n_side^2 equal-area HEALPix patches on 4 n_side - 1 rings,
+ *              each with its own temperature given per call to the *_map
+ *              entry points; the spot fields are ignored.  Needs the
+ *              atmosphere table, PPM_F32, the mixed strategy, grad = 0 and an
+ *              energy grid spanning at most 59 x intervals.
  */
 typedef struct {
     int32_t mode, intensity, n_spots;
@@ -105,6 +114,7 @@ typedef struct {
     int32_t precision;
     int32_t grad;
     int32_t interp;
+    int32_t n_side;
 } ppm_spec;
 
 typedef struct ppm_plan ppm_plan;
@@ -153,11 +163,31 @@ int ppm_loglike(ppm_plan *plan, const double *params_dev, int B, const int32_t *
 int ppm_loglike_grad(ppm_plan *plan, const double *params_dev, int B, const int32_t *n_cells_host,
                      const int32_t *data_dev, double *logl_dev, double *grad_dev, void *stream);
 
+/* Forward model of a full-surface temperature map (Sects. 2.6, 2.8.1) for a
+ * plan created with spec->n_side > 0.  map_dev: [B][12 n_side^2] doubles
+ * (device), log10 T [K] per HEALPix patch in ring order (rings from the
+ * north pole, pixels by increasing azimuth; patch j of ring i at azimuth
+ * phi_first(i) + 2 pi j / n(i), rotated by -2 pi Phi); a value that is not
+ * finite or not positive marks a patch that emits nothing.  Temperatures
+ * outside the table's logT axis are clamped for the interpolation on that
+ * axis (Sect. 4) while x = log10(E / kT) uses the patch's own T; a value more
+ * than 64 table steps outside the axis gives the instance PPM_INST_BAD_MAP.
+ * Parameter record slots 0-6 as for spots; the spot slots are ignored.
+ * counts_dev[B][n_phase][n_chan], flux_dev[B][n_phase][n_energy] and the
+ * likelihood as for ppm_forward, ppm_flux and ppm_loglike.  PPM_ERR_ARG on a
+ * spot plan (and the spot entry points return it on a map plan). */
+int ppm_forward_map(ppm_plan *plan, const double *params_dev, int B, const double *map_dev, double *counts_dev,
+                    void *stream);
+int ppm_flux_map(ppm_plan *plan, const double *params_dev, int B, const double *map_dev, double *flux_dev,
+                 void *stream);
+int ppm_loglike_map(ppm_plan *plan, const double *params_dev, int B, const double *map_dev, const int32_t *data_dev,
+                    double *logl_dev, double *counts_dev, void *stream);
+
 /* Per-instance status codes of the last evaluation: status_dev[B] (device). */
 int ppm_instance_status(ppm_plan *plan, int B, int32_t *status_dev, void *stream);
 
 /* Host-side parameter validation with the same rules the device applies;
- * status_host[B]. */
+ * status_host[B].  n_spots 0 checks the star only (temperature maps). */
 int ppm_validate_params(const double *params_host, int B, int n_spots, int32_t *status_host);
 
 /* Introspection for tests: copies to host (synchronising the stream) the
@@ -207,7 +237,7 @@ int ppm_set_tiles(ppm_plan *plan, const ppm_tiles *tiles);
  * chosen first and then used while the adjoint tile is timed.  Adjoint calls
  * run on all-zero data (their cost does not depend on the data) and need
  * two temporary device buffers, allocated and freed here.  Synchronises the
- * stream.  On error the plan keeps its previous tiles.  report may be NULL;
+ * stream.  Spot plans only.  On error the plan keeps its previous tiles.  report may be NULL;
  * otherwise it receives every candidate's median time [ms] and the choice. */
 #define PPM_TUNE_MAX 16
 typedef struct ppm_tune_report {

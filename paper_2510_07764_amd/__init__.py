@@ -24,6 +24,9 @@ MODE_SD, MODE_OS = 0, 1
 I_BLACKBODY, I_TABLE = 0, 1
 F32, F64 = 0, 1
 INTERP_MIXED, INTERP_CUBIC, INTERP_CUBIC_CLIP, INTERP_CUBIC_LINMU = 0, 1, 2, 3
+# per-instance status codes (include/ppm.h)
+(INST_OK, INST_NONFINITE, INST_BAD_STAR, INST_COMPACT, INST_BAD_SPOT, INST_FAST_SPIN,
+ INST_BAD_MAP) = range(7)
 
 _lib = None
 
@@ -44,7 +47,7 @@ class _Spec(C.Structure):
                 ("ax_mu", C.POINTER(C.c_double)), ("ax_x", C.POINTER(C.c_double)),
                 ("log_intensity", C.POINTER(C.c_double)),
                 ("n_alpha", C.c_int32), ("precision", C.c_int32), ("grad", C.c_int32),
-                ("interp", C.c_int32)]
+                ("interp", C.c_int32), ("n_side", C.c_int32)]
 
 
 class _Tiles(C.Structure):
@@ -73,6 +76,9 @@ SIGNATURES = {
     "ppm_flux": (C.c_int, [_VP, _VP, C.c_int, _I32P, _VP, _VP]),
     "ppm_loglike": (C.c_int, [_VP, _VP, C.c_int, _I32P, _VP, _VP, _VP, _VP]),
     "ppm_loglike_grad": (C.c_int, [_VP, _VP, C.c_int, _I32P, _VP, _VP, _VP, _VP]),
+    "ppm_forward_map": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP]),
+    "ppm_flux_map": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP]),
+    "ppm_loglike_map": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP, _VP, _VP]),
     "ppm_instance_status": (C.c_int, [_VP, C.c_int, _VP, _VP]),
     "ppm_validate_params": (C.c_int, [_DP, C.c_int, C.c_int, _I32P]),
     "ppm_debug_ring": (C.c_int, [_VP, C.c_int, C.c_int, _DP, _DP, _DP, _I32P, _VP]),
@@ -174,6 +180,9 @@ class Plan:
         s.precision = F64 if spec.get("precision", "f32") == "f64" else F32
         s.grad = 1 if grad else 0
         s.interp = int(spec.get("interp", 0))
+        s.n_side = int(spec.get("n_side", 0))
+        self.n_side = s.n_side
+        self.n_pix = 12 * s.n_side * s.n_side
         self.spec = spec
         self.n_phase = s.n_phase
         self.n_energy = s.n_energy
@@ -181,7 +190,10 @@ class Plan:
         self.n_fp = s.n_fp
         self.n_alpha = s.n_alpha
         self.max_batch = max_batch
-        self.r_tot = sum(max(spec["n_rings"][i], max_cells) for i in range(min(2, spec["n_spots"])))
+        if s.n_side:
+            self.r_tot = 4 * s.n_side - 1
+        else:
+            self.r_tot = sum(max(spec["n_rings"][i], max_cells) for i in range(min(2, spec["n_spots"])))
         h = C.c_void_p()
         _check(lib().ppm_plan_create(C.byref(s), max_batch, max_cells, C.byref(h)), "ppm_plan_create")
         self.handle = h
@@ -263,6 +275,51 @@ class Plan:
         _check(lib().ppm_loglike_grad(self.handle, _dptr(params), B, nc, _dptr(data), _dptr(out), _dptr(grad),
                                       _stream_handle(stream)), "ppm_loglike_grad")
         return out, grad
+
+    def _map(self, logT_map, B):
+        import torch
+        assert self.n_side > 0, "plan has no temperature map (spec n_side = 0)"
+        assert logT_map.is_cuda and logT_map.dtype == torch.float64 and logT_map.is_contiguous()
+        assert logT_map.numel() == B * self.n_pix
+        return _dptr(logT_map)
+
+    def forward_map(self, params, logT_map, out=None, stream=None):
+        """counts[B, P, C] of full-surface temperature maps: logT_map [B, 12
+        n_side^2] float64 on the device (log10 T per HEALPix patch, ring
+        order; non-finite or non-positive: inactive)."""
+        import torch
+        B = self._params(params)
+        mp = self._map(logT_map, B)
+        if out is None:
+            out = torch.empty((B, self.n_phase, self.n_chan), dtype=torch.float64, device=params.device)
+        _check(lib().ppm_forward_map(self.handle, _dptr(params), B, mp, _dptr(out), _stream_handle(stream)),
+               "ppm_forward_map")
+        return out
+
+    def flux_map(self, params, logT_map, out=None, stream=None):
+        """Flux before absorption and response [B, P, E] of temperature maps."""
+        import torch
+        B = self._params(params)
+        mp = self._map(logT_map, B)
+        if out is None:
+            out = torch.empty((B, self.n_phase, self.n_energy), dtype=torch.float64, device=params.device)
+        _check(lib().ppm_flux_map(self.handle, _dptr(params), B, mp, _dptr(out), _stream_handle(stream)),
+               "ppm_flux_map")
+        return out
+
+    def loglike_map(self, params, logT_map, data, counts=None, out=None, stream=None):
+        """logL[B] of temperature maps; data int32 [P, C] on the device."""
+        import torch
+        B = self._params(params)
+        mp = self._map(logT_map, B)
+        assert data.is_cuda and data.dtype == torch.int32 and data.is_contiguous()
+        assert data.numel() == self.n_phase * self.n_chan
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=params.device)
+        cptr = _dptr(counts) if counts is not None else None
+        _check(lib().ppm_loglike_map(self.handle, _dptr(params), B, mp, _dptr(data), _dptr(out), cptr,
+                                     _stream_handle(stream)), "ppm_loglike_map")
+        return out
 
     def status(self, B, stream=None):
         import torch

@@ -154,7 +154,7 @@ const char *ppm_status_string(int code)
 
 int ppm_validate_params(const double *params_host, int B, int n_spots, int32_t *status_host)
 {
-    if (!params_host || !status_host || B < 1 || n_spots < 1 || n_spots > 2)
+    if (!params_host || !status_host || B < 1 || n_spots < 0 || n_spots > 2)
         return fail(PPM_ERR_ARG, "ppm_validate_params: bad arguments");
     for (int b = 0; b < B; ++b) status_host[b] = validate_params(params_host + (size_t)b * PPM_NPARAM, n_spots);
     return PPM_OK;
@@ -165,13 +165,22 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     if (!sp || !out) return fail(PPM_ERR_ARG, "ppm_plan_create: null pointer");
     *out = nullptr;
     if (max_batch < 1) return fail(PPM_ERR_ARG, "max_batch must be >= 1");
-    if (sp->n_spots < 1 || sp->n_spots > 2) return fail(PPM_ERR_ARG, "n_spots must be 1 or 2");
+    const bool map_plan = sp->n_side != 0;
+    if (map_plan) {
+        if (sp->n_side < 1 || sp->n_side > 512) return fail(PPM_ERR_ARG, "n_side must lie in [1, 512]");
+        if (sp->intensity != PPM_I_TABLE || sp->precision != PPM_F32 || sp->interp != PPM_INTERP_MIXED
+            || sp->grad)
+            return fail(PPM_ERR_UNSUPPORTED,
+                        "temperature maps need the atmosphere table, FP32, the mixed strategy and no gradient");
+        if (max_cells != 0) return fail(PPM_ERR_ARG, "max_cells does not apply to temperature maps");
+    }
+    if (!map_plan && (sp->n_spots < 1 || sp->n_spots > 2)) return fail(PPM_ERR_ARG, "n_spots must be 1 or 2");
     if (sp->mode != PPM_MODE_SD && sp->mode != PPM_MODE_OS) return fail(PPM_ERR_ARG, "bad mode");
     if (sp->intensity != PPM_I_BLACKBODY && sp->intensity != PPM_I_TABLE) return fail(PPM_ERR_ARG, "bad intensity");
     if (sp->precision != PPM_F32 && sp->precision != PPM_F64) return fail(PPM_ERR_ARG, "bad precision");
     if (sp->precision == PPM_F64 && sp->intensity != PPM_I_BLACKBODY)
         return fail(PPM_ERR_UNSUPPORTED, "FP64 precision is implemented for the blackbody model only");
-    for (int s = 0; s < sp->n_spots; ++s) {
+    for (int s = 0; s < (map_plan ? 0 : sp->n_spots); ++s) {
         if (sp->shape[s] < 0 || sp->shape[s] > 2) return fail(PPM_ERR_ARG, "bad spot shape");
         if (sp->n_rings[s] < 1 || sp->n_phi[s] < 1) return fail(PPM_ERR_ARG, "spot grid must be >= 1x1");
         if (sp->shape[s] == PPM_SHAPE_ANNULUS && (sp->n_phi[s] % 2))
@@ -222,17 +231,25 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     S.mode = sp->mode;
     S.intensity = sp->intensity;
     S.interp = sp->interp;
-    S.n_spots = sp->n_spots;
+    S.n_spots = map_plan ? 1 : sp->n_spots;
     for (int s = 0; s < 2; ++s) {
         bool on = s < sp->n_spots;
-        S.shape[s] = on ? sp->shape[s] : 0;
-        S.shape_a[s] = on ? sp->shape_a[s] : 0.0;
-        S.shape_b[s] = on ? sp->shape_b[s] : 0.0;
+        S.shape[s] = on && !map_plan ? sp->shape[s] : 0;
+        S.shape_a[s] = on && !map_plan ? sp->shape_a[s] : 0.0;
+        S.shape_b[s] = on && !map_plan ? sp->shape_b[s] : 0.0;
         S.n_rings_spec[s] = on ? sp->n_rings[s] : 0;
         S.n_phi_spec[s] = on ? sp->n_phi[s] : 0;
         int mx = on ? sp->n_rings[s] : 0;
         if (on && max_cells > mx) mx = max_cells;
         S.rings_max[s] = mx;
+    }
+    if (map_plan) {
+        // the HEALPix rings of the whole surface form one ring list
+        S.n_side = sp->n_side;
+        S.n_pix = 12 * sp->n_side * sp->n_side;
+        S.rings_max[0] = S.n_rings_spec[0] = 4 * sp->n_side - 1;
+        S.n_phi_spec[0] = 4 * sp->n_side;
+        S.rings_max[1] = S.n_rings_spec[1] = S.n_phi_spec[1] = 0;
     }
     S.R_tot = S.rings_max[0] + S.rings_max[1];
     S.n_fp = sp->n_fp;
@@ -287,6 +304,17 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         S.W_max = (int)std::ceil(S.r_span + std::log10(4.0) / S.hx) + 8;
         if (S.W_max > S.nx) S.W_max = S.nx;
         S.fast = (S.r_span <= 59.0 && S.interp == PPM_INTERP_MIXED) ? 1 : 0;
+        if (map_plan) {
+            if (!S.fast) {
+                delete pl;
+                return fail(PPM_ERR_UNSUPPORTED, "temperature maps need an energy grid spanning at most 59 x intervals");
+            }
+            // temperature buckets: the logT intervals plus kMapLow steps either side;
+            // x window: the spot window widened by one logT step of kT
+            S.map_nb = S.nT - 1 + 2 * kMapLow;
+            int wm = S.W_max + (int)std::ceil(S.hT / S.hx) + 2;
+            S.map_wm = (wm + 3) & ~3;
+        }
         if (sp->grad && !S.fast) {
             delete pl;
             return fail(PPM_ERR_UNSUPPORTED, "gradients need an energy grid spanning at most 59 x intervals");
@@ -305,15 +333,17 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     const size_t R = S.R_tot;
     {
         size_t per_ring = sizeof(RingRec) + sizeof(double4) * (S.n_alpha + S.n_fp + 1)
-                        + (S.intensity == PPM_I_TABLE ? sizeof(float) * (size_t)S.sub_stride
+                        + (S.intensity == PPM_I_TABLE ? sizeof(float) * (map_plan ? 0 : (size_t)S.sub_stride)
                                                       + sizeof(float) * (size_t)S.P * S.E
                                                       : sizeof(double) * (size_t)S.P * S.E);
+        if (map_plan) per_ring += sizeof(int32_t) * (size_t)(S.map_nb + 1);
         if (sp->grad)
             per_ring += sizeof(double4) * ((size_t)S.n_alpha + (size_t)(S.n_fp + 1) * 5) + sizeof(RingTan)
                       + sizeof(float2) * (size_t)S.sub_stride
                       + sizeof(double) * kGradAcc * (size_t)((S.P + kMinTileGrad - 1) / kMinTileGrad);
         size_t per_inst = per_ring * R + sizeof(double) * (size_t)S.P * S.E
-                        + (sp->grad ? (sizeof(double) + sizeof(float)) * (size_t)S.P * S.E : 0);
+                        + (sp->grad ? (sizeof(double) + sizeof(float)) * (size_t)S.P * S.E : 0)
+                        + (map_plan ? sizeof(MapCell) * (size_t)S.n_pix : 0);
         size_t budget = (size_t)16 << 30;
         size_t c = budget / per_inst;
         if (c < 1) c = 1;
@@ -340,10 +370,17 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
            && pl->d_list
            && S.glx && S.glw && S.energy && S.rsp32;
     if (S.intensity == PPM_I_TABLE) {
-        W.sub = pl->dalloc<float>(B * R * (size_t)S.sub_stride);
+        if (map_plan) {
+            W.mcell = pl->dalloc<MapCell>(B * (size_t)S.n_pix);
+            W.mgrp = pl->dalloc<int32_t>(B * R * (size_t)(S.map_nb + 1));
+            ok = ok && W.mcell && W.mgrp;
+        } else {
+            W.sub = pl->dalloc<float>(B * R * (size_t)S.sub_stride);
+            ok = ok && W.sub;
+        }
         W.partial32 = pl->dalloc<float>(B * R * S.P * S.E);
         W.fold_in32 = pl->dalloc<float>(B * S.P * S.E);
-        ok = ok && W.sub && W.partial32 && W.fold_in32 && S.atm && S.ax_mu;
+        ok = ok && W.partial32 && W.fold_in32 && S.atm && S.ax_mu;
     } else {
         W.partial64 = pl->dalloc<double>(B * R * S.P * S.E);
         if (sp->precision == PPM_F64) {
@@ -372,7 +409,11 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         delete pl;
         return fail(PPM_ERR_ALLOC, "device allocation or upload failed");
     }
-    if (S.intensity == PPM_I_TABLE) {
+    if (map_plan && accum_map_lds(S) > 160 * 1024) {
+        delete pl;
+        return fail(PPM_ERR_UNSUPPORTED, "temperature-map working set does not fit in LDS");
+    }
+    if (S.intensity == PPM_I_TABLE && !map_plan) {
         size_t lds = accum_table_lds(S);
         if (lds > 160 * 1024) {
             delete pl;
@@ -393,9 +434,12 @@ void ppm_plan_destroy(ppm_plan *plan) { delete plan; }
 // list of live (instance, ring) slots when they change: chunk by chunk,
 // instances with larger grids first so the longest blocks start early.
 static int prepare(ppm_plan *pl, const double *params, int B, const int32_t *ncells_host,
-                   const int32_t **ncells_dev)
+                   const int32_t **ncells_dev, bool map_call = false)
 {
     if (!pl || !params) return fail(PPM_ERR_ARG, "null plan or params");
+    if ((pl->S.n_side > 0) != map_call)
+        return fail(PPM_ERR_ARG, map_call ? "plan has no temperature map (spec n_side = 0)"
+                                          : "temperature-map plan: use the *_map entry points");
     if (B < 1 || B > pl->max_batch) return fail(PPM_ERR_BATCH, "batch outside [1, max_batch]");
     const DevSpec &S = pl->S;
     *ncells_dev = nullptr;
@@ -473,6 +517,65 @@ static hipError_t run_forward(ppm_plan *pl, const double *params, int B, const i
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// One forward pass of a temperature-map plan over the batch, chunk by chunk.
+static hipError_t run_forward_map(ppm_plan *pl, const double *params, int B, const double *map, hipStream_t st,
+                                  double *flux, double *counts)
+{
+    const DevSpec &S = pl->S;
+    for (size_t ci = 0; ci < pl->list_off.size(); ++ci) {
+        int c0 = (int)ci * pl->chunk;
+        int nb = B - c0 < pl->chunk ? B - c0 : pl->chunk;
+        Workspace W = pl->W;
+        W.stars += c0;
+        W.vis_pairs += (size_t)c0 * S.R_tot;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        pl->events(e0, e1);
+        hipError_t e = launch_forward_map(S, W, params + (size_t)c0 * PPM_NPARAM, map + (size_t)c0 * S.n_pix, nb,
+                                          pl->d_list + pl->list_off[ci], pl->list_n[ci], st,
+                                          flux ? flux + (size_t)c0 * S.P * S.E : nullptr,
+                                          counts + (size_t)c0 * S.P * S.C, e0, e1);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int ppm_forward_map(ppm_plan *pl, const double *params_dev, int B, const double *map_dev, double *counts_dev,
+                    void *stream)
+{
+    const int32_t *nc = nullptr;
+    int rc = prepare(pl, params_dev, B, nullptr, &nc, true);
+    if (rc) return rc;
+    if (!map_dev || !counts_dev) return fail(PPM_ERR_ARG, "null map or counts buffer");
+    hipError_t e = run_forward_map(pl, params_dev, B, map_dev, (hipStream_t)stream, nullptr, counts_dev);
+    return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_forward_map launch");
+}
+
+int ppm_flux_map(ppm_plan *pl, const double *params_dev, int B, const double *map_dev, double *flux_dev,
+                 void *stream)
+{
+    const int32_t *nc = nullptr;
+    int rc = prepare(pl, params_dev, B, nullptr, &nc, true);
+    if (rc) return rc;
+    if (!map_dev || !flux_dev) return fail(PPM_ERR_ARG, "null map or flux buffer");
+    hipError_t e = run_forward_map(pl, params_dev, B, map_dev, (hipStream_t)stream, flux_dev, pl->W.counts);
+    return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_flux_map launch");
+}
+
+int ppm_loglike_map(ppm_plan *pl, const double *params_dev, int B, const double *map_dev, const int32_t *data_dev,
+                    double *logl_dev, double *counts_dev, void *stream)
+{
+    const int32_t *nc = nullptr;
+    int rc = prepare(pl, params_dev, B, nullptr, &nc, true);
+    if (rc) return rc;
+    if (!map_dev || !data_dev || !logl_dev) return fail(PPM_ERR_ARG, "null map, data or logl buffer");
+    double *cnt = counts_dev ? counts_dev : pl->W.counts;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = run_forward_map(pl, params_dev, B, map_dev, st, nullptr, cnt);
+    if (e != hipSuccess) return hip_fail(e, "ppm_loglike_map forward");
+    e = launch_loglike(pl->W, cnt, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
+    return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike_map reduction");
 }
 
 int ppm_forward(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_cells_host,

@@ -203,6 +203,36 @@ __device__ inline double cell_offset(const RingRec &g, int j)
     return -g.dphi_out + (j + 0.5) * g.dphi_cell;
 }
 
+// HEALPix ring i = 1 .. 4 nside - 1 (Sect. 2.8.1): cos(colatitude), pixels on
+// the ring and the azimuth of its first pixel (pixels 2 pi / n apart); rings
+// south of the equator mirror their northern counterparts.
+__host__ __device__ inline void healpix_ring(int nside, int i, double &z, int &n, double &first)
+{
+    const int m = i > 2 * nside ? 4 * nside - i : i;
+    const double ns = nside;
+    double zz;
+    if (m < nside) {
+        zz = 1.0 - (double)m * m / (3.0 * ns * ns);
+        n = 4 * m;
+        first = kPi / (4.0 * m);
+    } else {
+        zz = 4.0 / 3.0 - 2.0 * m / (3.0 * ns);
+        n = 4 * nside;
+        first = kPi / (2.0 * ns) * ((m - nside) % 2 == 0 ? 0.5 : 1.0);
+    }
+    z = i > 2 * nside ? -zz : zz;
+}
+
+// index of the first pixel of HEALPix ring i in ring order
+__host__ __device__ inline long long healpix_first_pixel(int nside, int i)
+{
+    const long long N = nside;
+    if (i < nside) return 2LL * i * (i - 1);
+    if (i <= 3 * nside) return 2LL * N * (N - 1) + 4LL * N * (i - nside);
+    const long long m = 4LL * N - i;
+    return 12LL * N * N - 2LL * m * (m + 1);
+}
+
 __device__ inline bool cell_masked(const RingRec &g, double off)
 {
     if (g.shape != PPM_SHAPE_CRESCENT) return false;

@@ -32,6 +32,10 @@ struct DevSpec {
     int W_max;            // x-node window of the per-ring sub-table
     int sub_stride;       // floats per ring in the sub-table buffer (multiple of 4)
     int pt_fwd, pt_adj;   // phases per block of the forward / adjoint accumulation kernels
+    int n_side;           // temperature-map plan: HEALPix resolution (0: spot model)
+    int n_pix;            // patches of a map (12 n_side^2)
+    int map_nb;           // temperature buckets of a map ring (logT steps, with margins)
+    int map_wm;           // x nodes of a bucket's slab window
     double tb0, r_span;   // (log10 E_0 - x0)/hx and (log10 E_last - log10 E_0)/hx
     int R_tot;            // ring slots per instance (spot 0 then spot 1)
     int rings_max[2];     // ring slots of each spot
@@ -66,6 +70,19 @@ struct RingRec {
     double zmin, zmax;           // range of the fine-phase redshift factor z
     int xw0, xw;                 // x-node window [xw0, xw0 + xw) of the ring's sub-table
 };
+
+// One active patch of a temperature-map ring, sorted by temperature bucket:
+// cell index on the ring, logT interpolation weight between the bucket's
+// two table nodes, (T / 10^6 K)^3 and log10(k T / keV).
+struct MapCell {
+    double lkT;
+    float t, T3;
+    int j, pad;
+};
+
+// Temperature buckets of map rings: bucket q holds logT in
+// [T0 + (q - kMapLow) hT, T0 + (q - kMapLow + 1) hT).
+constexpr int kMapLow = 64;
 
 // Ring-level tangents along the five local directions of a ring's geometry
 // (M, R_e, inclination, the ring's spot colatitude and angular radius).

@@ -46,7 +46,9 @@ __host__ __device__ int validate_params(const double *p, int n_spots)
 }
 
 // ---------------------------------------------------------------------------
-// k_setup: star (Eqs. 7, 8, 11) and spot rings (Eqs. 2, 3, 9, 10, 18)
+// k_setup: star (Eqs. 7, 8, 11) and spot rings (Eqs. 2, 3, 9, 10, 18), or
+// for a temperature-map plan the HEALPix rings of the whole surface
+// (Sect. 2.8.1; patch solid angle pi / (3 n_side^2))
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_setup(DevSpec S, const double *params, const int32_t *n_cells, StarRec *stars,
                         RingRec *rings, int32_t *vis_pairs)
@@ -56,7 +58,7 @@ __global__ __launch_bounds__(64) void k_setup(DevSpec S, const double *params, c
     __shared__ StarRec st;
     if (threadIdx.x == 0) {
         StarRec s;
-        s.status = validate_params(p, S.n_spots);
+        s.status = validate_params(p, S.n_side > 0 ? 0 : S.n_spots);
         s.GM = p[0] * kGMsun;
         s.Re = p[1] * 1e5;
         s.Rs = 2.0 * s.GM / (kC * kC);
@@ -92,11 +94,20 @@ __global__ __launch_bounds__(64) void k_setup(DevSpec S, const double *params, c
         bool live = st.status == PPM_INST_OK && spot < S.n_spots && lr < nr;
         double tc = p[8 + 4 * spot], z = p[9 + 4 * spot];
         if (!live) { tc = 0.5; z = 0.1; }
-        double lo = fmax(0.0, tc - z), hi = fmin(kPi, tc + z);
-        double e0 = lo + (hi - lo) * lr / nr, e1 = lo + (hi - lo) * (lr + 1) / nr;
-        double th = 0.5 * (e0 + e1);
+        double th, hp_first = 0.0;
+        int hp_n = 0;
+        if (S.n_side > 0) {
+            double zr;
+            healpix_ring(S.n_side, r + 1, zr, hp_n, hp_first);
+            th = acos(zr);
+            g.dcos = 0.0;
+        } else {
+            double lo = fmax(0.0, tc - z), hi = fmin(kPi, tc + z);
+            double e0 = lo + (hi - lo) * lr / nr, e1 = lo + (hi - lo) * (lr + 1) / nr;
+            th = 0.5 * (e0 + e1);
+            g.dcos = cos(e0) - cos(e1);
+        }
         g.theta = th;
-        g.dcos = cos(e0) - cos(e1);
         double ct = cos(th), sn = sin(th);
         g.R = st.Re * (1.0 + st.o2 * ct * ct);                    // Eq. (7)
         double dR = -2.0 * st.Re * st.o2 * ct * sn;
@@ -109,14 +120,20 @@ __global__ __launch_bounds__(64) void k_setup(DevSpec S, const double *params, c
         g.beta = kTwoPi * st.nu * g.R * sn / (kC * g.sq1u);        // Eq. (18)
         g.gamma = 1.0 / sqrt(1.0 - g.beta * g.beta);
         g.dphi_out = arc_halfwidth(th, tc, z);
-        if (g.shape == PPM_SHAPE_ANNULUS) {
+        if (S.n_side > 0) {
+            // cell j at azimuth first + j * 2 pi / n (cell_offset of a cap ring)
+            g.dphi_cell = kTwoPi / hp_n;
+            g.dphi_out = 0.5 * g.dphi_cell - hp_first;
+            g.dphi_in = 0.0;
+        } else if (g.shape == PPM_SHAPE_ANNULUS) {
             g.dphi_in = arc_halfwidth(th, tc, S.shape_a[spot] * z);
             g.dphi_cell = (g.dphi_out - g.dphi_in) / (0.5 * np);
         } else {
             g.dphi_in = 0.0;
             g.dphi_cell = 2.0 * g.dphi_out / np;
         }
-        g.w_cell = g.R * g.R * sqrt(1.0 + g.f * g.f) * g.dcos * g.dphi_cell / (st.D * st.D);  // Eq. (9)
+        const double patch = S.n_side > 0 ? kPi / (3.0 * S.n_side * (double)S.n_side) : g.dcos * g.dphi_cell;
+        g.w_cell = g.R * g.R * sqrt(1.0 + g.f * g.f) * patch / (st.D * st.D);  // Eq. (9)
         double acap;
         {
             double v = 1.5 * g.u * sqrt(3.0 * (1.0 - g.u));
@@ -127,13 +144,15 @@ __global__ __launch_bounds__(64) void k_setup(DevSpec S, const double *params, c
         g.alpha_max = amax;
         g.cdt_obl = cdt_oblate(st.Re, st.Rs, g.R) / g.R;
         g.phi_spot = -kTwoPi * (p[3] + (spot == 1 ? p[15] : 0.0));
-        g.logT = p[10 + 4 * spot];
+        // map rings: per-patch temperatures, 10^6 K is the reference the
+        // accumulation scales by
+        g.logT = S.n_side > 0 ? 6.0 : p[10 + 4 * spot];
         g.T = pow(10.0, g.logT);
         g.kT = kKB * g.T;
         double sgn = (tc >= kHalfPi) ? 1.0 : -1.0;
         g.tm = tc - sgn * S.shape_b[spot] * z;
         g.cos_zm = cos(S.shape_a[spot] * z);
-        if (live) g.n_cells = np;
+        if (live) g.n_cells = S.n_side > 0 ? hp_n : np;
         rings[(size_t)b * S.R_tot + r] = g;
         vis_pairs[(size_t)b * S.R_tot + r] = 0;
     }
@@ -394,7 +413,7 @@ __global__ __launch_bounds__(256) void k_trace(DevSpec S, const int32_t *list, c
         int active = (ring_visible && g.w_cell > 0.0) ? 1 : 0;
         gp->zmin = zlo;
         gp->zmax = zhi;
-        if (active && S.intensity == PPM_I_TABLE) {
+        if (active && S.intensity == PPM_I_TABLE && S.n_side == 0) {
             // x nodes any (cell, phase, energy) of this ring can touch, plus the
             // cubic stencil: t = (log10(z E / kT) - x0) / hx
             double lkt = log10(g.kT) / S.hx;
@@ -422,7 +441,8 @@ __global__ __launch_bounds__(256) void k_trace(DevSpec S, const int32_t *list, c
     }
     __syncthreads();
     // the ring's (logT, log g) collapse of the atmosphere table
-    if (sh_active && S.intensity == PPM_I_TABLE) subtable_ring(S, g, sh_w0, sh_w, (size_t)b * S.R_tot + r, sub);
+    if (sh_active && S.intensity == PPM_I_TABLE && S.n_side == 0)
+        subtable_ring(S, g, sh_w0, sh_w, (size_t)b * S.R_tot + r, sub);
 }
 
 
@@ -1108,18 +1128,43 @@ size_t accum_table_lds(const DevSpec &S)
          + sizeof(float) * 4 * S.nx;
 }
 
-hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *params,
-                          const int32_t *ncells_dev, int B, const int32_t *list, int n_list, hipStream_t st,
-                          double *flux_out, double *counts_out, hipEvent_t ev_hot0, hipEvent_t ev_hot1)
+void launch_setup(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev, int B,
+                  hipStream_t st)
 {
-    const bool want_flux_f64 = flux_out != nullptr;
     hipLaunchKernelGGL(k_setup, dim3((S.R_tot + 63) / 64, B), dim3(64), 0, st, S, params, ncells_dev, W.stars,
                        W.rings, W.vis_pairs);
+}
+
+void launch_table_trace(const DevSpec &S, const Workspace &W, const int32_t *list, int n_list, hipStream_t st)
+{
     hipLaunchKernelGGL(k_table, dim3(n_list, (S.n_alpha + 63) / 64), dim3(64), 0, st, S, list, W.stars, W.rings,
                        W.table);
     size_t lds_tr = sizeof(double4) * (S.n_alpha + S.n_fp + 1);
     hipLaunchKernelGGL(k_trace, dim3(n_list), dim3(256), lds_tr, st, S, list, W.stars, W.rings, W.table,
                        W.trace, W.sub);
+}
+
+// FP32 ring partials -> per-instance FP64 sum, absorption, MFMA fold
+void launch_reduce_fold32(const DevSpec &S, const Workspace &W, int B, hipStream_t st, double *flux_out,
+                          double *counts_out)
+{
+    if ((S.E & 3) == 0)
+        hipLaunchKernelGGL(k_reduce4, dim3(S.P, (S.E + 255) / 256, B), dim3(512), S.R_tot, st, S, W.stars,
+                           W.rings, W.partial32, flux_out, W.fold_in32);
+    else
+        hipLaunchKernelGGL((k_reduce<float, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S,
+                           W.stars, W.rings, W.partial32, flux_out, W.fold_in32);
+    hipLaunchKernelGGL(k_fold_f32, dim3((S.C + 15) / 16, (B * S.P + 15) / 16), dim3(256), 0, st,
+                       W.fold_in32, S.rsp32, counts_out, B * S.P, S.C, S.E);
+}
+
+hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *params,
+                          const int32_t *ncells_dev, int B, const int32_t *list, int n_list, hipStream_t st,
+                          double *flux_out, double *counts_out, hipEvent_t ev_hot0, hipEvent_t ev_hot1)
+{
+    const bool want_flux_f64 = flux_out != nullptr;
+    launch_setup(S, W, params, ncells_dev, B, st);
+    launch_table_trace(S, W, list, n_list, st);
     const int PT = S.pt_fwd;
     dim3 grid(xcd_grid(n_list, (S.P + PT - 1) / PT));
     if (S.intensity == PPM_I_TABLE) {
@@ -1152,14 +1197,7 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
             hipLaunchKernelGGL(k_accum_table<8>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
                                W.partial32, W.vis_pairs, PT, n_list);
         if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
-        if ((S.E & 3) == 0)
-            hipLaunchKernelGGL(k_reduce4, dim3(S.P, (S.E + 255) / 256, B), dim3(512), S.R_tot, st, S, W.stars,
-                               W.rings, W.partial32, want_flux_f64 ? flux_out : nullptr, W.fold_in32);
-        else
-            hipLaunchKernelGGL((k_reduce<float, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S,
-                               W.stars, W.rings, W.partial32, want_flux_f64 ? flux_out : nullptr, W.fold_in32);
-        hipLaunchKernelGGL(k_fold_f32, dim3((S.C + 15) / 16, (B * S.P + 15) / 16), dim3(256), 0, st,
-                           W.fold_in32, S.rsp32, counts_out, B * S.P, S.C, S.E);
+        launch_reduce_fold32(S, W, B, st, want_flux_f64 ? flux_out : nullptr, counts_out);
     } else {
         size_t lds = sizeof(double4) * (S.n_fp + 1);
         int epl = (S.E + 63) / 64;

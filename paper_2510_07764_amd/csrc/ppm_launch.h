@@ -32,6 +32,9 @@ struct Workspace {
     float *gtil;           // [B][P][E] adjoint of the flux divided by E
     double *nh_part;       // [B][P] N_H gradient per phase
     double *gpart;         // [B][R_tot][n_tile][kGradAcc] per-block adjoint sums
+    // temperature-map plans only
+    MapCell *mcell;        // [B][n_pix] active patches, per ring sorted by temperature bucket
+    int32_t *mgrp;         // [B][R_tot][map_nb + 1] bucket offsets within the ring's patches
 };
 
 constexpr int kPhaseTile = 8;    // default phases per block of the accumulation kernels
@@ -45,6 +48,16 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
                           const int32_t *ncells_dev, int B, const int32_t *list, int n_list, hipStream_t st,
                           double *flux_out, double *counts_out, hipEvent_t ev_hot0 = nullptr,
                           hipEvent_t ev_hot1 = nullptr);
+void launch_setup(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev, int B,
+                  hipStream_t st);
+void launch_table_trace(const DevSpec &S, const Workspace &W, const int32_t *list, int n_list, hipStream_t st);
+void launch_reduce_fold32(const DevSpec &S, const Workspace &W, int B, hipStream_t st, double *flux_out,
+                          double *counts_out);
+hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double *params, const double *map, int B,
+                              const int32_t *list, int n_list, hipStream_t st, double *flux_out, double *counts_out,
+                              hipEvent_t ev_hot0 = nullptr, hipEvent_t ev_hot1 = nullptr);
+size_t accum_map_lds(const DevSpec &S);
+constexpr int kMapWaves = 8;     // waves per block of the map accumulation kernel, one phase each
 hipError_t launch_loglike(const Workspace &W, const double *counts, int B, int PC, const int32_t *data,
                           double *logl, hipStream_t st);
 hipError_t launch_status(const Workspace &W, int B, int32_t *out, hipStream_t st);

@@ -1,0 +1,374 @@
+// Full-surface temperature maps on HEALPix (Sects. 2.6, 2.8.1): the whole
+// stellar surface is divided into 12 n_side^2 equal-area patches on
+// 4 n_side - 1 iso-latitude rings, each patch with its own temperature
+// (inactive patches emit nothing).  The ring machinery of the spot model
+// (setup, FP64 deflection table, fine-phase trace, ring reduction, fold)
+// is shared; what differs is that the (logT, log g) collapse of the
+// atmosphere table can no longer be done once per ring.
+//
+//   k_map_sort    per ring: buckets the active patches by logT table
+//                 interval (stable counting sort), so that patches sharing
+//                 the two logT nodes of their linear interpolation are
+//                 processed together
+//   k_accum_map   shift-and-add (Eq. 47) per (ring, 8 phases), one phase
+//                 per wave: for each bucket, the two logT slabs collapsed
+//                 in log g over the bucket's x window go to LDS, then the
+//                 windowed scheme of the spot kernel with the logT weight
+//                 applied inside the mu contraction
+// Section and equation numbers refer to arXiv:2510.07764.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ppm_internal.h"
+#include "ppm_device.h"
+#include "ppm_launch.h"
+#include "../../include/ppm.h"
+
+namespace ppm {
+
+// bucket of a map value: -1 inactive patch (not finite or not positive),
+// -2 further than kMapLow table steps outside the logT axis
+__device__ inline int map_bucket(const DevSpec &S, double lt)
+{
+    if (!(isfinite(lt) && lt > 0.0)) return -1;
+    const double u = floor((lt - S.T0) / S.hT);
+    if (u < -kMapLow || u >= S.map_nb - kMapLow) return -2;
+    return (int)u + kMapLow;
+}
+
+// ---------------------------------------------------------------------------
+// k_map_sort: one block per (instance, ring).  Pass 1 histograms the ring's
+// active patches over the temperature buckets, the offsets go to grp; pass 2
+// places each patch at its bucket offset plus its rank among the earlier
+// patches of the same bucket (stable, so the accumulation order over patches
+// is fixed).  A ring without active patches is switched off (n_cells = 0)
+// before the table and trace kernels run.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_map_sort(DevSpec S, const int32_t *list, const double *map, StarRec *stars,
+                                                  RingRec *rings, MapCell *cells, int32_t *grp)
+{
+    const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
+    RingRec *gp = rings + (size_t)b * S.R_tot + r;
+    const int n = gp->n_cells;   // pixels of the ring; 0 when the instance is not evaluated
+    const int NB = S.map_nb;
+    extern __shared__ int lds_i[];
+    int *cnt = lds_i, *run = lds_i + NB, *qch = run + NB;   // NB, NB, blockDim.x
+    __shared__ int bad, total;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < NB; q += blockDim.x) cnt[q] = 0;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    const long long pix0 = healpix_first_pixel(S.n_side, r + 1);
+    const double *mrow = map + (size_t)b * S.n_pix + pix0;
+    for (int j = tid; j < n; j += blockDim.x) {
+        const int q = map_bucket(S, mrow[j]);
+        if (q >= 0) atomicAdd(&cnt[q], 1);
+        else if (q == -2) bad = 1;
+    }
+    __syncthreads();
+    int32_t *gr = grp + ((size_t)b * S.R_tot + r) * (NB + 1);
+    if (tid == 0) {
+        int acc = 0;
+        for (int q = 0; q < NB; ++q) {
+            run[q] = acc;
+            gr[q] = acc;
+            acc += cnt[q];
+        }
+        gr[NB] = acc;
+        total = acc;
+    }
+    __syncthreads();
+    MapCell *out = cells + (size_t)b * S.n_pix + pix0;
+    for (int j0 = 0; j0 < n; j0 += blockDim.x) {
+        const int j = j0 + tid;
+        const double lt = j < n ? mrow[j] : 0.0;
+        const int q = j < n ? map_bucket(S, lt) : -1;
+        qch[tid] = q;
+        __syncthreads();
+        if (q >= 0) {
+            int rank = 0;
+            for (int t = 0; t < tid; ++t) rank += qch[t] == q;
+            const int u = q - kMapLow;
+            const int it = u < 0 ? 0 : (u > S.nT - 2 ? S.nT - 2 : u);
+            double w = (lt - S.T0) / S.hT - it;     // linear in logT, clamped at the axis ends
+            w = fmin(1.0, fmax(0.0, w));
+            MapCell c;
+            c.lkT = log10(kKB) + lt;
+            c.t = (float)w;
+            c.T3 = (float)pow(10.0, 3.0 * (lt - 6.0));
+            c.j = j;
+            c.pad = 0;
+            out[run[q] + rank] = c;
+        }
+        __syncthreads();
+        for (int qq = tid; qq < NB; qq += blockDim.x) {
+            int c = 0;
+            for (int t = 0; t < (int)blockDim.x; ++t) c += qch[t] == qq;
+            run[qq] += c;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (total == 0) gp->n_cells = 0;
+        if (bad && stars[b].status == PPM_INST_OK) stars[b].status = PPM_INST_BAD_MAP;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_accum_map: block = (ring, 8 output phases), 8 waves, wave w owns phase
+// 8 * tile + w and EPL consecutive energies per lane.  Per temperature
+// bucket (logT nodes it, it + 1 after clamping):
+//   staging  sl0, sl1 = table slabs at logT nodes it and it + 1, linear in
+//            the ring's log g, over the x window the bucket's patches can
+//            reach (redshift range of the ring, bucket's kT range, energy
+//            span and the cubic stencil);
+//   stage A  lane = patch: observed-phase lookup (Eqs. 45-46), mu weights of
+//            the mixed scheme pre-scaled by F_p (T / 10^6 K)^3, logT weight,
+//            x position of the first energy;
+//   stage B  per visible pair: mu contraction of both slabs and their logT
+//            blend at x node I0 - 1 + lane, cubic coefficients of interval
+//            I0 + lane (linear in the first and last table interval, zero
+//            outside), per energy one quad read and a Horner step.
+// ---------------------------------------------------------------------------
+template <int EPL>
+__global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const int32_t *list, const RingRec *rings,
+                                                             const double4 *trace, const MapCell *cells,
+                                                             const int32_t *grp, float *partial, int32_t *vis_pairs,
+                                                             int n_list)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    constexpr int PT = kMapWaves;
+    const int n_tile = (S.P + PT - 1) / PT;
+    int li, tile;
+    if (!xcd_block(n_list, n_tile, li, tile)) return;
+    const int ent = list[li], b = ent / S.R_tot, r = ent - b * S.R_tot;
+    const size_t slot = (size_t)b * S.R_tot + r;
+    const RingRec g = rings[slot];
+    if (!g.active) return;
+    const int nfp = S.n_fp, nmu = S.nmu, nx = S.nx, E = S.E, P = S.P, WM = S.map_wm, NB = S.map_nb;
+    double4 *tr = (double4 *)lds_raw;                          // nfp + 1
+    double *po = (double *)(tr + nfp + 1);                     // nfp + 1, padded to even
+    double *axmu = po + ((nfp + 2) & ~1);                      // nmu, padded to even
+    float *sl0 = (float *)(axmu + ((nmu + 1) & ~1));           // nmu * WM
+    float *sl1 = sl0 + nmu * WM;                               // nmu * WM
+    float4 *Qb = (float4 *)(sl1 + nmu * WM);                   // kMapWaves * 64 quads (WM % 4 == 0)
+    float *Sb = (float *)(Qb + kMapWaves * 64);                // kMapWaves * 68
+    const int tid = threadIdx.x;
+    const double4 *gtr = trace + slot * (nfp + 1);
+    for (int i = tid; i <= nfp; i += blockDim.x) {
+        const double4 v = gtr[i];
+        tr[i] = v;
+        po[i] = v.z;
+    }
+    for (int i = tid; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
+    const int wave = tid >> 6, lane = tid & 63;
+    float4 *Qw = Qb + wave * 64;
+    float *Sw = Sb + wave * 68;
+    if (lane < 4) Sw[64 + lane] = 0.0f;
+    const double ihx = 1.0 / S.hx;
+    float tbr[EPL];
+#pragma unroll
+    for (int m = 0; m < EPL; ++m) {
+        int e = lane * EPL + m;
+        tbr[m] = e < E ? (float)((log10(S.energy[e]) - log10(S.energy[0])) * ihx) : 0.0f;
+    }
+    const double mu_lo = S.ax_mu[0], mu_hi = S.ax_mu[nmu - 1];
+    const double inv2pi = 1.0 / kTwoPi;
+    const double phio0 = gtr[0].z;
+    const int k = tile * PT + wave;
+    const bool kval = k < P;
+    const double Phik = (k + 0.5) / P;
+    double wg1;
+    const int ig = lin_bracket(g.logg, S.g0, S.hg, S.ng, wg1);
+    const float fg1 = (float)wg1, fg0 = (float)(1.0 - wg1);
+    const double lz_lo = log10(g.zmin), lz_hi = log10(g.zmax);
+    const double lkb = log10(kKB);
+    const int32_t *gr = grp + slot * (NB + 1);
+    const MapCell *cl = cells + (size_t)b * S.n_pix + healpix_first_pixel(S.n_side, r + 1);
+    const size_t slab = (size_t)nmu * nx;
+    float acc[EPL];
+#pragma unroll
+    for (int m = 0; m < EPL; ++m) acc[m] = 0.0f;
+    int npairs = 0;
+    for (int q = 0; q < NB; ++q) {
+        const int c_beg = gr[q], c_end = gr[q + 1];
+        if (c_end == c_beg) continue;
+        const int u = q - kMapLow;
+        const int it = u < 0 ? 0 : (u > S.nT - 2 ? S.nT - 2 : u);
+        // x window of the bucket: t = (log10(z E / kT) - x0) / hx over the
+        // ring's z range, the bucket's kT range and the energy grid
+        const double lkt_lo = lkb + S.T0 + u * S.hT, lkt_hi = lkt_lo + S.hT;
+        const double tlo = (lz_lo - lkt_hi) * ihx + S.tb0, thi = (lz_hi - lkt_lo) * ihx + S.tb0 + S.r_span;
+        int w0 = (int)floor(tlo) - 2, w1 = (int)floor(thi) + 3;
+        w0 = w0 < 0 ? 0 : w0;
+        w1 = w1 > nx - 1 ? nx - 1 : w1;
+        int xw = w1 - w0 + 1;
+        xw = xw < 0 ? 0 : (xw > WM ? WM : xw);
+        __syncthreads();   // the previous bucket's slabs are no longer read (and the trace is staged)
+        const float *a00 = S.atm + ((size_t)it * S.ng + ig) * slab, *a01 = a00 + slab;
+        const float *a10 = S.atm + ((size_t)(it + 1) * S.ng + ig) * slab, *a11 = a10 + slab;
+        for (int i = tid; i < nmu * xw; i += blockDim.x) {
+            const int m = i / xw, c = i - m * xw;
+            const size_t o = (size_t)m * nx + w0 + c;
+            sl0[m * WM + c] = fg0 * a00[o] + fg1 * a01[o];
+            sl1[m * WM + c] = fg0 * a10[o] + fg1 * a11[o];
+        }
+        __syncthreads();
+        if (!kval) continue;
+        for (int c0 = c_beg; c0 < c_end; c0 += 64) {
+            // ---------------- stage A: one (patch, phase) pair per lane
+            const int cc = c0 + lane;
+            bool vis = false;
+            float w0f = 0.f, w1f = 0.f, w2f = 0.f, w3f = 0.f, fr = 0.f, tw = 0.f;
+            int I0 = 0, m0 = 0;
+            if (cc < c_end) {
+                const MapCell mc = cl[cc];
+                const double off = cell_offset(g, mc.j);
+                double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
+                double php = (a - floor(a)) + phio0;                    // Eq. (45)
+                int l0 = 0, h0 = nfp;                                   // Eq. (46)
+                while (h0 - l0 > 1) {
+                    int mid = (l0 + h0) >> 1;
+                    if (po[mid] <= php) l0 = mid; else h0 = mid;
+                }
+                const double4 A = tr[l0], Cn = tr[l0 + 1];
+                double wp = (php - A.z) / (Cn.z - A.z);
+                wp = fmin(1.0, fmax(0.0, wp));
+                const double Fp = A.x + wp * (Cn.x - A.x);
+                if (Fp != 0.0) {
+                    vis = true;
+                    const double zp = A.y + wp * (Cn.y - A.y);
+                    const double mu = fmin(mu_hi, fmax(mu_lo, A.w + wp * (Cn.w - A.w)));
+                    int lo = 0, hi = nmu - 1;
+                    while (hi - lo > 1) {
+                        int mid = (lo + hi) >> 1;
+                        if (axmu[mid] <= mu) lo = mid; else hi = mid;
+                    }
+                    double w[4] = {0.0, 0.0, 0.0, 0.0};
+                    if (lo < 3 || lo == nmu - 2) {
+                        double t = (mu - axmu[lo]) / (axmu[lo + 1] - axmu[lo]);
+                        m0 = lo < nmu - 4 ? lo : nmu - 4;
+                        w[lo - m0] = 1.0 - t;
+                        w[lo + 1 - m0] = t;
+                    } else {
+                        m0 = lo - 1;
+#pragma unroll
+                        for (int q4 = 0; q4 < 4; ++q4) {
+                            double num = 1.0, den = 1.0;
+#pragma unroll
+                            for (int s2 = 0; s2 < 4; ++s2) {
+                                if (s2 == q4) continue;
+                                num *= mu - axmu[m0 + s2];
+                                den *= axmu[m0 + q4] - axmu[m0 + s2];
+                            }
+                            w[q4] = num / den;
+                        }
+                    }
+                    const double sc = Fp * (double)mc.T3;
+                    w0f = (float)(w[0] * sc);
+                    w1f = (float)(w[1] * sc);
+                    w2f = (float)(w[2] * sc);
+                    w3f = (float)(w[3] * sc);
+                    tw = mc.t;
+                    const double T0 = log10(zp) * ihx + S.tb0 - mc.lkT * ihx;
+                    const double fl = floor(T0);
+                    I0 = (int)fl;
+                    fr = (float)(T0 - fl);
+                }
+            }
+            uint64_t mask = __ballot(vis);
+            npairs += __popcll(mask);
+            // ---------------- stage B: the visible pairs one after another
+            while (mask) {
+                const int p = __ffsll((unsigned long long)mask) - 1;
+                mask &= mask - 1;
+                const float pw0 = readlane_f(w0f, p), pw1 = readlane_f(w1f, p), pw2 = readlane_f(w2f, p),
+                            pw3 = readlane_f(w3f, p), pfr = readlane_f(fr, p), ptw = readlane_f(tw, p);
+                const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
+                const int col = pI0 - 1 + lane - w0;
+                float Sv = 0.0f;
+                if (col >= 0 && col < xw) {
+                    const float *t0 = sl0 + pm0 * WM + col, *t1 = sl1 + pm0 * WM + col;
+                    const float v0 = pw0 * t0[0] + pw1 * t0[WM] + pw2 * t0[2 * WM] + pw3 * t0[3 * WM];
+                    const float v1 = pw0 * t1[0] + pw1 * t1[WM] + pw2 * t1[2 * WM] + pw3 * t1[3 * WM];
+                    Sv = v0 + ptw * (v1 - v0);
+                }
+                Sw[lane] = Sv;
+                wave_sync();
+                const float s1 = Sw[lane + 1], s2 = Sw[lane + 2], s3 = Sw[lane + 3];
+                const int gi = pI0 + lane;
+                float4 qd = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (gi >= 0 && gi <= nx - 2) {
+                    if (gi == 0 || gi == nx - 2) {
+                        qd = make_float4(s1, s2 - s1, 0.f, 0.f);
+                    } else {
+                        const float c2 = 0.5f * (Sv + s2) - s1;
+                        const float c3 = (s3 - Sv) * (1.0f / 6.0f) + 0.5f * (s1 - s2);
+                        qd = make_float4(s1, s2 - s1 - c2 - c3, c2, c3);
+                    }
+                }
+                Qw[lane] = qd;
+                wave_sync();
+#pragma unroll
+                for (int m = 0; m < EPL; ++m) {
+                    const float t = pfr + tbr[m];
+                    const float f = __builtin_amdgcn_fractf(t);
+                    const float4 qv = Qw[(int)t];
+                    acc[m] += qv.x + f * (qv.y + f * (qv.z + f * qv.w));
+                }
+                wave_sync();
+            }
+        }
+    }
+    if (kval) {
+        const double scale = g.w_cell * g.T * g.T * g.T;   // g.T = 10^6 K, the patches' reference
+        float *out = partial + (slot * P + k) * E;
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) {
+            int e = lane * EPL + m;
+            if (e < E) out[e] = (float)(acc[m] * (scale / S.energy[e]));
+        }
+    }
+    if (lane == 0 && npairs) atomicAdd(&vis_pairs[slot], npairs);
+}
+
+size_t accum_map_lds(const DevSpec &S)
+{
+    return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.n_fp + 2) & ~1) + sizeof(double) * ((S.nmu + 1) & ~1)
+         + sizeof(float) * 2 * (size_t)S.nmu * S.map_wm + sizeof(float4) * kMapWaves * 64
+         + sizeof(float) * kMapWaves * 68;
+}
+
+hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double *params, const double *map, int B,
+                              const int32_t *list, int n_list, hipStream_t st, double *flux_out, double *counts_out,
+                              hipEvent_t ev_hot0, hipEvent_t ev_hot1)
+{
+    launch_setup(S, W, params, nullptr, B, st);
+    hipLaunchKernelGGL(k_map_sort, dim3(n_list), dim3(256), sizeof(int) * (2 * S.map_nb + 256), st, S, list, map,
+                       W.stars, W.rings, W.mcell, W.mgrp);
+    launch_table_trace(S, W, list, n_list, st);
+    const int n_tile = (S.P + kMapWaves - 1) / kMapWaves;
+    dim3 grid(xcd_grid(n_list, n_tile));
+    const size_t lds = accum_map_lds(S);
+    const int epl = (S.E + 63) / 64;
+    if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
+    if (epl <= 1)
+        hipLaunchKernelGGL(k_accum_map<1>, grid, dim3(64 * kMapWaves), lds, st, S, list, W.rings, W.trace, W.mcell,
+                           W.mgrp, W.partial32, W.vis_pairs, n_list);
+    else if (epl <= 2)
+        hipLaunchKernelGGL(k_accum_map<2>, grid, dim3(64 * kMapWaves), lds, st, S, list, W.rings, W.trace, W.mcell,
+                           W.mgrp, W.partial32, W.vis_pairs, n_list);
+    else if (epl <= 4)
+        hipLaunchKernelGGL(k_accum_map<4>, grid, dim3(64 * kMapWaves), lds, st, S, list, W.rings, W.trace, W.mcell,
+                           W.mgrp, W.partial32, W.vis_pairs, n_list);
+    else
+        hipLaunchKernelGGL(k_accum_map<8>, grid, dim3(64 * kMapWaves), lds, st, S, list, W.rings, W.trace, W.mcell,
+                           W.mgrp, W.partial32, W.vis_pairs, n_list);
+    if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
+    launch_reduce_fold32(S, W, B, st, flux_out, counts_out);
+    return hipGetLastError();
+}
+
+}  // namespace ppm

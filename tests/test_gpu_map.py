@@ -1,0 +1,159 @@
+"""GPU parity of full-surface temperature maps on HEALPix (Sects. 2.6,
+2.8.1; ``ppm_forward_map`` / ``ppm_flux_map`` / ``ppm_loglike_map`` through
+the C ABI) against the FP64 CPU oracle.
+
+Bar as in the spot parity tests: per phase-channel (phase-energy) bin at or
+above 1e-6 of the peak, |gpu - oracle| / oracle <= 1e-4; visible-pair counts
+exact.  Maps: smooth hotspots, every patch active with hotspots on top, and
+seeded random temperatures reaching beyond the table's logT range on both
+sides (clamped interpolation, x from the patch's own temperature).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch, torch.device("cuda:0")
+
+
+def rel_err(got, ref, floor=1e-6):
+    sel = ref >= floor * ref.max()
+    return float(np.max(np.abs(got[sel] - ref[sel]) / ref[sel])), int(sel.sum())
+
+
+def gpu_map(torch_dev, spec, params, maps, what="counts"):
+    import paper_2510_07764_amd as ppm
+    torch, dev = torch_dev
+    p = np.atleast_2d(params)
+    m = np.atleast_2d(maps)
+    plan = ppm.Plan(spec, max_batch=p.shape[0])
+    pt = torch.tensor(p, dtype=torch.float64, device=dev)
+    mt = torch.tensor(m, dtype=torch.float64, device=dev)
+    out = plan.forward_map(pt, mt) if what == "counts" else plan.flux_map(pt, mt)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), plan, pt, mt
+
+
+@pytest.mark.parametrize("nside,kind,P,E", [(8, "hotspots", 32, 256), (16, "full", 36, 256),
+                                            (8, "random", 24, 64), (4, "full", 16, 37)])
+def test_map_parity(torch_dev, nside, kind, P, E):
+    spec, p, m = syn.map_config(nside, kind, n_phase=P, n_energy=E)
+    print(f"map parity nside {nside} {kind} P {P} E {E}", flush=True)
+    ft, cnt, diag = oracle.forward_map(spec, p, nside, m)
+    got, plan, _, _ = gpu_map(torch_dev, spec, p, m)
+    err, n = rel_err(got[0], cnt)
+    assert plan.status(1).cpu().numpy().tolist() == [0]
+    vp = plan.visible_pairs(1)
+    print(f"  counts max rel err {err:.3e} over {n} bins; visible pairs {vp} vs {diag['n_visible_pairs']}; "
+          f"clamped logT {diag['n_clamp_T']}", flush=True)
+    assert err < TOL
+    assert vp == diag["n_visible_pairs"]
+    fl, _, _, _ = gpu_map(torch_dev, spec, p, m, what="flux")
+    err2, _ = rel_err(fl[0], ft)
+    assert err2 < TOL
+
+
+def test_map_batch_status_and_empty(torch_dev):
+    """One batch: a hotspot map, the same map with one value far beyond the
+    table (instance status BAD_MAP, logL -inf), an empty map (zero counts,
+    logL 0 against all-zero data) and a rotated star; each valid instance
+    equals its single-instance evaluation bit for bit."""
+    import paper_2510_07764_amd as ppm
+    torch, dev = torch_dev
+    nside = 8
+    spec, p, m = syn.map_config(nside, "hotspots", n_phase=16, n_energy=64)
+    bad = m.copy()
+    bad[np.flatnonzero(m)[0]] = 20.0
+    q = p.copy()
+    q[3] = 0.3
+    params = np.stack([p, p, p, q])
+    maps = np.stack([m, bad, np.zeros_like(m), m])
+    got, plan, pt, mt = gpu_map(torch_dev, spec, params, maps)
+    st = plan.status(4).cpu().numpy().tolist()
+    assert st == [ppm.INST_OK, ppm.INST_BAD_MAP, ppm.INST_OK, ppm.INST_OK]
+    data = torch.zeros((16, spec["rsp"].shape[1]), dtype=torch.int32, device=dev)
+    ll = plan.loglike_map(pt, mt, data).cpu().numpy()
+    assert ll[1] == -math.inf
+    assert ll[2] == 0.0 and np.all(got[2] == 0.0)
+    for b in (0, 3):
+        one, _, _, _ = gpu_map(torch_dev, spec, params[b], maps[b])
+        assert np.array_equal(one[0], got[b]), b
+    _, cnt, _ = oracle.forward_map(spec, q, nside, m)
+    assert rel_err(got[3], cnt)[0] < TOL
+
+
+def test_map_multi_pass_batch(torch_dev):
+    """Batch split over workspace passes (two instances per pass)."""
+    torch, dev = torch_dev
+    nside = 4
+    spec, p, m = syn.map_config(nside, "full", n_phase=16, n_energy=32)
+    params = np.stack([p] * 5)
+    params[:, 3] = np.linspace(0.0, 0.4, 5)
+    maps = np.stack([m, syn.temperature_map(nside, "random"), m, m[::-1].copy(), m])
+    os.environ["PPM_MAX_CHUNK"] = "2"
+    try:
+        got, _, _, _ = gpu_map(torch_dev, spec, params, maps)
+    finally:
+        del os.environ["PPM_MAX_CHUNK"]
+    for b in range(5):
+        one, _, _, _ = gpu_map(torch_dev, spec, params[b], maps[b])
+        assert np.array_equal(one[0], got[b]), b
+
+
+def test_map_loglike_against_oracle(torch_dev):
+    torch, dev = torch_dev
+    nside = 8
+    spec, p, m = syn.map_config(nside, "full", n_phase=16, n_energy=64)
+    _, cnt, _ = oracle.forward_map(spec, p, nside, m)
+    data = syn.poisson_data(cnt)
+    ll_ref = oracle.loglike_from_counts(cnt, data)
+    got, plan, pt, mt = gpu_map(torch_dev, spec, p, m)
+    ll = plan.loglike_map(pt, mt, torch.tensor(data, device=dev)).item()
+    assert abs(ll - ll_ref) <= TOL * np.abs(data - cnt).sum()
+
+
+def test_map_entry_point_guards(torch_dev):
+    import paper_2510_07764_amd as ppm
+    torch, dev = torch_dev
+    spec, p, m = syn.map_config(4, n_phase=8, n_energy=16)
+    plan = ppm.Plan(spec, max_batch=1)
+    pt = torch.tensor(p[None], dtype=torch.float64, device=dev)
+    with pytest.raises(ppm.PPMError, match="_map entry points"):
+        plan.forward(pt)
+    with pytest.raises(ppm.PPMError, match="_map entry points"):
+        plan.autotune(pt, reps=1)
+    sspec, sp = syn.config1(n_cells=8, n_phase=8, n_energy=16)
+    splan = ppm.Plan(sspec, max_batch=1)
+    spt = torch.tensor(sp[None], dtype=torch.float64, device=dev)
+    splan.n_side = 4   # bypass the binding's own check to reach the library's
+    splan.n_pix = 12 * 16
+    with pytest.raises(ppm.PPMError, match="no temperature map"):
+        splan.forward_map(spt, torch.tensor(m[None], dtype=torch.float64, device=dev))
+    with pytest.raises(ppm.PPMError, match="n_side"):
+        ppm.Plan(dict(spec, n_side=600))
+    with pytest.raises(ppm.PPMError, match="temperature maps need"):
+        ppm.Plan(dict(spec, interp=ppm.INTERP_CUBIC))
+
+
+def test_map_full_size_golden(torch_dev):
+    """Full-surface map at n_side 64 (49,152 patches, all active), 128
+    phases, 256 energies, 300 channels, against stored oracle counts."""
+    ref = np.load(os.path.join(HERE, "golden", "map64_counts.npy"))
+    spec, p, m = syn.map_config(64, "full")
+    got, plan, _, _ = gpu_map(torch_dev, spec, p, m)
+    err, n = rel_err(got[0], ref)
+    print(f"map n_side 64 full: counts max rel err {err:.3e} over {n} bins", flush=True)
+    assert err < TOL
