@@ -30,6 +30,10 @@ METRIC = "forward+logL evals/sec at config[1], plain vs batched vs +grad, <=1e-4
 # dot 7, scale and accumulate 2; plus the mu contraction of the ~63 x nodes
 # an energy window touches (8 FLOP each) amortised over 256 energies (~2).
 FLOP_PER_UNIT = 24.0
+# Temperature-map accumulation: the same per-energy work plus the second
+# logT slab in the mu contraction (8 FLOP) and the logT blend (2 FLOP) at
+# each of the ~63 x nodes of a pair, amortised over 256 energies (~2.5).
+FLOP_PER_UNIT_MAP = 26.5
 PEAK_FP32_TFLOPS = 157.3
 
 # HBM traffic of the hot kernel per launch (config-1 workload, one vector),
@@ -116,6 +120,9 @@ def main():
                     help="also run device-to-device copies of this many MiB (HBM counter calibration; 0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=128,
                     help="cells per spot of the oracle sample (128: the whole workload; 0: skip)")
+    ap.add_argument("--map-nside", type=int, default=64,
+                    help="HEALPix n_side of the full-surface temperature-map leg (0: skip)")
+    ap.add_argument("--map-batch", type=int, default=32, help="vectors per call in the batched map leg (0: skip)")
     ap.add_argument("--tiles", default="auto",
                     help="launch shape of the accumulation kernels: 'auto' (autotuner, per leg) or "
                          "'F,G' (forward and adjoint phase tiles)")
@@ -238,6 +245,61 @@ def main():
                 "vs_plain": (B / tg) * plain_s, "tiles": tuned_g}
         del glg, plang
 
+    # ---------------- full-surface temperature map (HEALPix), one vector per call,
+    # then a batch of maps (the same map, parameter draws of the batched leg)
+    tmap = None
+    if args.map_nside > 0:
+        mspec, mp, mm = syn.map_config(args.map_nside, "full")
+        mplan = ppm.Plan(mspec, max_batch=max(1, args.map_batch))
+        mpt = torch.tensor(mp[None], dtype=torch.float64, device=dev)
+        mmt = torch.tensor(mm[None], dtype=torch.float64, device=dev)
+        mll = torch.empty(1, dtype=torch.float64, device=dev)
+        mtune = None
+        if args.tiles == "auto":
+            r = mplan.autotune_map(mpt, mmt, reps=5)
+            mtune = {"chosen": r["chosen"][0], "forward_ms": {str(k): round(v, 4) for k, v in r["forward"].items()}}
+        for _ in range(args.warmup):
+            mplan.loglike_map(mpt, mmt, data_t, out=mll)
+        torch.cuda.synchronize()
+        mplan.profile_begin(args.steps)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            mplan.loglike_map(mpt, mmt, data_t, out=mll)
+        torch.cuda.synchronize()
+        map_s = (time.perf_counter() - t0) / args.steps
+        mhot, mn = mplan.profile_end()
+        munits = mplan.visible_pairs(1) * mplan.n_energy
+        mhot_s = mhot / max(mn, 1) * 1e-3
+        mach = munits * FLOP_PER_UNIT_MAP / mhot_s / 1e12
+        tmap = {"workload": f"full-surface map, HEALPix n_side {args.map_nside} "
+                            f"({12 * args.map_nside ** 2} patches, all active), config-1 star and instrument",
+                "evals_per_s": 1.0 / map_s, "ms_per_call": map_s * 1e3,
+                "kernel": "k_accum_map<4>", "kernel_ms": mhot_s * 1e3, "units": munits,
+                "flop_per_unit": FLOP_PER_UNIT_MAP, "achieved": mach, "frac": mach / PEAK_FP32_TFLOPS,
+                "logL": float(mll.item()), "tiles": mtune}
+        if args.map_batch > 1:
+            Bm = args.map_batch
+            mptb = torch.tensor(np.tile(mp, (Bm, 1)), dtype=torch.float64, device=dev)
+            mptb[:, 3] = torch.linspace(0.0, 0.5, Bm, dtype=torch.float64)
+            mmtb = mmt.repeat(Bm, 1).contiguous()
+            mllb = torch.empty(Bm, dtype=torch.float64, device=dev)
+            mtune_b = None
+            if args.tiles == "auto":
+                r = mplan.autotune_map(mptb, mmtb, reps=2)
+                mtune_b = {"chosen": r["chosen"][0],
+                           "forward_ms": {str(k): round(v, 4) for k, v in r["forward"].items()}}
+            mplan.loglike_map(mptb, mmtb, data_t, out=mllb)
+            torch.cuda.synchronize()
+            kmb = max(2, args.steps // 10)
+            t0 = time.perf_counter()
+            for _ in range(kmb):
+                mplan.loglike_map(mptb, mmtb, data_t, out=mllb)
+            torch.cuda.synchronize()
+            tmb = (time.perf_counter() - t0) / kmb
+            tmap["batched"] = {"batch": Bm, "evals_per_s": Bm / tmb, "ms_per_call": tmb * 1e3,
+                               "finite": bool(torch.isfinite(mllb).all().item()), "tiles": mtune_b}
+        del mplan
+
     if args.copy_mib > 0:
         # plain copy kernel of known size: reads and writes copy_mib MiB each
         src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
@@ -270,6 +332,7 @@ def main():
         "batched": batched,
         "batched_large": batched_large,
         "grad": grad,
+        "map": tmap,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": hot_kernel_traffic(plan.tiles[0]),
                      "kernel": "k_accum_fast<4>", "kernel_ms": hot_avg_s * 1e3, "units": units,

@@ -216,6 +216,7 @@ int ppm_profile_end(ppm_plan *plan, double *hot_ms_total, int *n_calls);
  * (8 waves, 8..256).  Forward results do not depend on phase_tile: every
  * phase's sums run in the same order whatever the tile.  The gradient's
  * per-block partial sums do depend on phase_tile_grad, at the rounding level.
+ * Temperature-map plans use phase_tile rounded down to 8, 16 or 32 (8 waves).
  * Defaults 8 and 8.  A change applies to later calls; a HIP graph captured
  * earlier keeps the shape it was captured with.  PPM_ERR_ARG for a null
  * pointer or a value out of range (the plan is then unchanged). */
@@ -250,6 +251,10 @@ typedef struct ppm_tune_report {
 } ppm_tune_report;
 int ppm_autotune(ppm_plan *plan, const double *params_dev, int B, const int32_t *n_cells_host, int reps,
                  void *stream, ppm_tune_report *report);
+/* The same for a temperature-map plan over map_dev (as for ppm_forward_map):
+ * candidates 8, 16 and 32 phases per work-group of the map kernel. */
+int ppm_autotune_map(ppm_plan *plan, const double *params_dev, int B, const double *map_dev, int reps,
+                     void *stream, ppm_tune_report *report);
 
 const char *ppm_status_string(int code);
 const char *ppm_last_error(void);

@@ -88,6 +88,7 @@ SIGNATURES = {
     "ppm_get_tiles": (C.c_int, [_VP, C.POINTER(_Tiles)]),
     "ppm_set_tiles": (C.c_int, [_VP, C.POINTER(_Tiles)]),
     "ppm_autotune": (C.c_int, [_VP, _VP, C.c_int, _I32P, C.c_int, _VP, C.POINTER(_TuneReport)]),
+    "ppm_autotune_map": (C.c_int, [_VP, _VP, C.c_int, _VP, C.c_int, _VP, C.POINTER(_TuneReport)]),
     "ppm_status_string": (C.c_char_p, [C.c_int]),
     "ppm_last_error": (C.c_char_p, []),
     "ppm_version": (C.c_int, []),
@@ -373,6 +374,17 @@ class Plan:
                                   C.byref(r)), "ppm_autotune")
         return {"forward": {int(r.fwd_tile[i]): float(r.fwd_ms[i]) for i in range(r.n_fwd)},
                 "grad": {int(r.grad_tile[i]): float(r.grad_ms[i]) for i in range(r.n_grad)},
+                "chosen": (int(r.chosen.phase_tile), int(r.chosen.phase_tile_grad))}
+
+    def autotune_map(self, params, logT_map, reps=5, stream=None):
+        """Autotuner of a temperature-map plan (phase tiles 8, 16, 32);
+        returns {"forward": {tile: ms}, "chosen": (fwd, grad)}."""
+        B = self._params(params)
+        mp = self._map(logT_map, B)
+        r = _TuneReport()
+        _check(lib().ppm_autotune_map(self.handle, _dptr(params), B, mp, int(reps), _stream_handle(stream),
+                                      C.byref(r)), "ppm_autotune_map")
+        return {"forward": {int(r.fwd_tile[i]): float(r.fwd_ms[i]) for i in range(r.n_fwd)},
                 "chosen": (int(r.chosen.phase_tile), int(r.chosen.phase_tile_grad))}
 
     def visible_pairs(self, B, stream=None):

@@ -828,6 +828,52 @@ int ppm_autotune(ppm_plan *pl, const double *params_dev, int B, const int32_t *n
     return PPM_OK;
 }
 
+int ppm_autotune_map(ppm_plan *pl, const double *params_dev, int B, const double *map_dev, int reps, void *stream,
+                     ppm_tune_report *report)
+{
+    if (reps < 1 || reps > 1000) return fail(PPM_ERR_ARG, "ppm_autotune_map: reps must lie in [1, 1000]");
+    const int32_t *nc = nullptr;
+    int rc = prepare(pl, params_dev, B, nullptr, &nc, true);
+    if (rc) return rc;
+    if (!map_dev) return fail(PPM_ERR_ARG, "null map");
+    hipStream_t st = (hipStream_t)stream;
+    DevSpec &S = pl->S;
+    const int pt0 = S.pt_fwd;
+    ppm_tune_report rep;
+    std::memset(&rep, 0, sizeof(rep));
+    EventSet es;
+    es.ev.assign(reps + 1, nullptr);
+    for (auto &e : es.ev) {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return hip_fail(r, "ppm_autotune_map event");
+    }
+    double best = 0.0;
+    int best_t = pt0;
+    for (int t : tile_candidates({8, 16, 32}, S.P)) {
+        S.pt_fwd = t;
+        double ms = 0.0;
+        rc = median_ms([&](const char **what) {
+            *what = "ppm_autotune_map forward";
+            return run_forward_map(pl, params_dev, B, map_dev, st, nullptr, pl->W.counts);
+        }, reps, st, es, &ms);
+        if (rc) {
+            S.pt_fwd = pt0;
+            return rc;
+        }
+        rep.fwd_tile[rep.n_fwd] = t;
+        rep.fwd_ms[rep.n_fwd++] = ms;
+        if (rep.n_fwd == 1 || ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    S.pt_fwd = best_t;
+    rep.chosen.phase_tile = S.pt_fwd;
+    rep.chosen.phase_tile_grad = S.pt_adj;
+    if (report) *report = rep;
+    return PPM_OK;
+}
+
 int ppm_instance_status(ppm_plan *pl, int B, int32_t *status_dev, void *stream)
 {
     if (!pl || !status_dev) return fail(PPM_ERR_ARG, "null argument");

@@ -10,8 +10,8 @@
 //                 interval (stable counting sort), so that patches sharing
 //                 the two logT nodes of their linear interpolation are
 //                 processed together
-//   k_accum_map   shift-and-add (Eq. 47) per (ring, 8 phases), one phase
-//                 per wave: for each bucket, the two logT slabs collapsed
+//   k_accum_map   shift-and-add (Eq. 47) per (ring, 8, 16 or 32 phases),
+//                 8 waves: for each bucket, the two logT slabs collapsed
 //                 in log g over the bucket's x window go to LDS, then the
 //                 windowed scheme of the spot kernel with the logT weight
 //                 applied inside the mu contraction
@@ -117,9 +117,10 @@ __global__ __launch_bounds__(256) void k_map_sort(DevSpec S, const int32_t *list
 }
 
 // ---------------------------------------------------------------------------
-// k_accum_map: block = (ring, 8 output phases), 8 waves, wave w owns phase
-// 8 * tile + w and EPL consecutive energies per lane.  Per temperature
-// bucket (logT nodes it, it + 1 after clamping):
+// k_accum_map: block = (ring, 8 KPW output phases), 8 waves, wave w owns
+// phases 8 KPW tile + w + 8 q (q < KPW) and EPL consecutive energies per
+// lane; the staged slabs of a bucket serve all of the block's phases.  Per
+// temperature bucket (logT nodes it, it + 1 after clamping):
 //   staging  sl0, sl1 = table slabs at logT nodes it and it + 1, linear in
 //            the ring's log g, over the x window the bucket's patches can
 //            reach (redshift range of the ring, bucket's kT range, energy
@@ -132,14 +133,14 @@ __global__ __launch_bounds__(256) void k_map_sort(DevSpec S, const int32_t *list
 //            I0 + lane (linear in the first and last table interval, zero
 //            outside), per energy one quad read and a Horner step.
 // ---------------------------------------------------------------------------
-template <int EPL>
+template <int EPL, int KPW>
 __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const int32_t *list, const RingRec *rings,
                                                              const double4 *trace, const MapCell *cells,
                                                              const int32_t *grp, float *partial, int32_t *vis_pairs,
                                                              int n_list)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    constexpr int PT = kMapWaves;
+    constexpr int PT = kMapWaves * KPW;
     const int n_tile = (S.P + PT - 1) / PT;
     int li, tile;
     if (!xcd_block(n_list, n_tile, li, tile)) return;
@@ -177,9 +178,8 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     const double mu_lo = S.ax_mu[0], mu_hi = S.ax_mu[nmu - 1];
     const double inv2pi = 1.0 / kTwoPi;
     const double phio0 = gtr[0].z;
-    const int k = tile * PT + wave;
-    const bool kval = k < P;
-    const double Phik = (k + 0.5) / P;
+    const int k_first = tile * PT + wave;
+    const bool kval = k_first < P;
     double wg1;
     const int ig = lin_bracket(g.logg, S.g0, S.hg, S.ng, wg1);
     const float fg1 = (float)wg1, fg0 = (float)(1.0 - wg1);
@@ -188,9 +188,11 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     const int32_t *gr = grp + slot * (NB + 1);
     const MapCell *cl = cells + (size_t)b * S.n_pix + healpix_first_pixel(S.n_side, r + 1);
     const size_t slab = (size_t)nmu * nx;
-    float acc[EPL];
+    float acc[KPW][EPL];
 #pragma unroll
-    for (int m = 0; m < EPL; ++m) acc[m] = 0.0f;
+    for (int kq = 0; kq < KPW; ++kq)
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) acc[kq][m] = 0.0f;
     int npairs = 0;
     for (int q = 0; q < NB; ++q) {
         const int c_beg = gr[q], c_end = gr[q + 1];
@@ -217,118 +219,127 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
         }
         __syncthreads();
         if (!kval) continue;
-        for (int c0 = c_beg; c0 < c_end; c0 += 64) {
-            // ---------------- stage A: one (patch, phase) pair per lane
-            const int cc = c0 + lane;
-            bool vis = false;
-            float w0f = 0.f, w1f = 0.f, w2f = 0.f, w3f = 0.f, fr = 0.f, tw = 0.f;
-            int I0 = 0, m0 = 0;
-            if (cc < c_end) {
-                const MapCell mc = cl[cc];
-                const double off = cell_offset(g, mc.j);
-                double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
-                double php = (a - floor(a)) + phio0;                    // Eq. (45)
-                int l0 = 0, h0 = nfp;                                   // Eq. (46)
-                while (h0 - l0 > 1) {
-                    int mid = (l0 + h0) >> 1;
-                    if (po[mid] <= php) l0 = mid; else h0 = mid;
-                }
-                const double4 A = tr[l0], Cn = tr[l0 + 1];
-                double wp = (php - A.z) / (Cn.z - A.z);
-                wp = fmin(1.0, fmax(0.0, wp));
-                const double Fp = A.x + wp * (Cn.x - A.x);
-                if (Fp != 0.0) {
-                    vis = true;
-                    const double zp = A.y + wp * (Cn.y - A.y);
-                    const double mu = fmin(mu_hi, fmax(mu_lo, A.w + wp * (Cn.w - A.w)));
-                    int lo = 0, hi = nmu - 1;
-                    while (hi - lo > 1) {
-                        int mid = (lo + hi) >> 1;
-                        if (axmu[mid] <= mu) lo = mid; else hi = mid;
+#pragma unroll
+        for (int kq = 0; kq < KPW; ++kq) {
+            const int k = k_first + kMapWaves * kq;
+            if (k >= P) break;
+            const double Phik = (k + 0.5) / P;
+            for (int c0 = c_beg; c0 < c_end; c0 += 64) {
+                // ---------------- stage A: one (patch, phase) pair per lane
+                const int cc = c0 + lane;
+                bool vis = false;
+                float w0f = 0.f, w1f = 0.f, w2f = 0.f, w3f = 0.f, fr = 0.f, tw = 0.f;
+                int I0 = 0, m0 = 0;
+                if (cc < c_end) {
+                    const MapCell mc = cl[cc];
+                    const double off = cell_offset(g, mc.j);
+                    double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
+                    double php = (a - floor(a)) + phio0;                    // Eq. (45)
+                    int l0 = 0, h0 = nfp;                                   // Eq. (46)
+                    while (h0 - l0 > 1) {
+                        int mid = (l0 + h0) >> 1;
+                        if (po[mid] <= php) l0 = mid; else h0 = mid;
                     }
-                    double w[4] = {0.0, 0.0, 0.0, 0.0};
-                    if (lo < 3 || lo == nmu - 2) {
-                        double t = (mu - axmu[lo]) / (axmu[lo + 1] - axmu[lo]);
-                        m0 = lo < nmu - 4 ? lo : nmu - 4;
-                        w[lo - m0] = 1.0 - t;
-                        w[lo + 1 - m0] = t;
-                    } else {
-                        m0 = lo - 1;
+                    const double4 A = tr[l0], Cn = tr[l0 + 1];
+                    double wp = (php - A.z) / (Cn.z - A.z);
+                    wp = fmin(1.0, fmax(0.0, wp));
+                    const double Fp = A.x + wp * (Cn.x - A.x);
+                    if (Fp != 0.0) {
+                        vis = true;
+                        const double zp = A.y + wp * (Cn.y - A.y);
+                        const double mu = fmin(mu_hi, fmax(mu_lo, A.w + wp * (Cn.w - A.w)));
+                        int lo = 0, hi = nmu - 1;
+                        while (hi - lo > 1) {
+                            int mid = (lo + hi) >> 1;
+                            if (axmu[mid] <= mu) lo = mid; else hi = mid;
+                        }
+                        double w[4] = {0.0, 0.0, 0.0, 0.0};
+                        if (lo < 3 || lo == nmu - 2) {
+                            double t = (mu - axmu[lo]) / (axmu[lo + 1] - axmu[lo]);
+                            m0 = lo < nmu - 4 ? lo : nmu - 4;
+                            w[lo - m0] = 1.0 - t;
+                            w[lo + 1 - m0] = t;
+                        } else {
+                            m0 = lo - 1;
 #pragma unroll
-                        for (int q4 = 0; q4 < 4; ++q4) {
-                            double num = 1.0, den = 1.0;
+                            for (int q4 = 0; q4 < 4; ++q4) {
+                                double num = 1.0, den = 1.0;
 #pragma unroll
-                            for (int s2 = 0; s2 < 4; ++s2) {
-                                if (s2 == q4) continue;
-                                num *= mu - axmu[m0 + s2];
-                                den *= axmu[m0 + q4] - axmu[m0 + s2];
+                                for (int s2 = 0; s2 < 4; ++s2) {
+                                    if (s2 == q4) continue;
+                                    num *= mu - axmu[m0 + s2];
+                                    den *= axmu[m0 + q4] - axmu[m0 + s2];
+                                }
+                                w[q4] = num / den;
                             }
-                            w[q4] = num / den;
+                        }
+                        const double sc = Fp * (double)mc.T3;
+                        w0f = (float)(w[0] * sc);
+                        w1f = (float)(w[1] * sc);
+                        w2f = (float)(w[2] * sc);
+                        w3f = (float)(w[3] * sc);
+                        tw = mc.t;
+                        const double T0 = log10(zp) * ihx + S.tb0 - mc.lkT * ihx;
+                        const double fl = floor(T0);
+                        I0 = (int)fl;
+                        fr = (float)(T0 - fl);
+                    }
+                }
+                uint64_t mask = __ballot(vis);
+                npairs += __popcll(mask);
+                // ---------------- stage B: the visible pairs one after another
+                while (mask) {
+                    const int p = __ffsll((unsigned long long)mask) - 1;
+                    mask &= mask - 1;
+                    const float pw0 = readlane_f(w0f, p), pw1 = readlane_f(w1f, p), pw2 = readlane_f(w2f, p),
+                                pw3 = readlane_f(w3f, p), pfr = readlane_f(fr, p), ptw = readlane_f(tw, p);
+                    const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
+                    const int col = pI0 - 1 + lane - w0;
+                    float Sv = 0.0f;
+                    if (col >= 0 && col < xw) {
+                        const float *t0 = sl0 + pm0 * WM + col, *t1 = sl1 + pm0 * WM + col;
+                        const float v0 = pw0 * t0[0] + pw1 * t0[WM] + pw2 * t0[2 * WM] + pw3 * t0[3 * WM];
+                        const float v1 = pw0 * t1[0] + pw1 * t1[WM] + pw2 * t1[2 * WM] + pw3 * t1[3 * WM];
+                        Sv = v0 + ptw * (v1 - v0);
+                    }
+                    Sw[lane] = Sv;
+                    wave_sync();
+                    const float s1 = Sw[lane + 1], s2 = Sw[lane + 2], s3 = Sw[lane + 3];
+                    const int gi = pI0 + lane;
+                    float4 qd = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (gi >= 0 && gi <= nx - 2) {
+                        if (gi == 0 || gi == nx - 2) {
+                            qd = make_float4(s1, s2 - s1, 0.f, 0.f);
+                        } else {
+                            const float c2 = 0.5f * (Sv + s2) - s1;
+                            const float c3 = (s3 - Sv) * (1.0f / 6.0f) + 0.5f * (s1 - s2);
+                            qd = make_float4(s1, s2 - s1 - c2 - c3, c2, c3);
                         }
                     }
-                    const double sc = Fp * (double)mc.T3;
-                    w0f = (float)(w[0] * sc);
-                    w1f = (float)(w[1] * sc);
-                    w2f = (float)(w[2] * sc);
-                    w3f = (float)(w[3] * sc);
-                    tw = mc.t;
-                    const double T0 = log10(zp) * ihx + S.tb0 - mc.lkT * ihx;
-                    const double fl = floor(T0);
-                    I0 = (int)fl;
-                    fr = (float)(T0 - fl);
-                }
-            }
-            uint64_t mask = __ballot(vis);
-            npairs += __popcll(mask);
-            // ---------------- stage B: the visible pairs one after another
-            while (mask) {
-                const int p = __ffsll((unsigned long long)mask) - 1;
-                mask &= mask - 1;
-                const float pw0 = readlane_f(w0f, p), pw1 = readlane_f(w1f, p), pw2 = readlane_f(w2f, p),
-                            pw3 = readlane_f(w3f, p), pfr = readlane_f(fr, p), ptw = readlane_f(tw, p);
-                const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
-                const int col = pI0 - 1 + lane - w0;
-                float Sv = 0.0f;
-                if (col >= 0 && col < xw) {
-                    const float *t0 = sl0 + pm0 * WM + col, *t1 = sl1 + pm0 * WM + col;
-                    const float v0 = pw0 * t0[0] + pw1 * t0[WM] + pw2 * t0[2 * WM] + pw3 * t0[3 * WM];
-                    const float v1 = pw0 * t1[0] + pw1 * t1[WM] + pw2 * t1[2 * WM] + pw3 * t1[3 * WM];
-                    Sv = v0 + ptw * (v1 - v0);
-                }
-                Sw[lane] = Sv;
-                wave_sync();
-                const float s1 = Sw[lane + 1], s2 = Sw[lane + 2], s3 = Sw[lane + 3];
-                const int gi = pI0 + lane;
-                float4 qd = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (gi >= 0 && gi <= nx - 2) {
-                    if (gi == 0 || gi == nx - 2) {
-                        qd = make_float4(s1, s2 - s1, 0.f, 0.f);
-                    } else {
-                        const float c2 = 0.5f * (Sv + s2) - s1;
-                        const float c3 = (s3 - Sv) * (1.0f / 6.0f) + 0.5f * (s1 - s2);
-                        qd = make_float4(s1, s2 - s1 - c2 - c3, c2, c3);
-                    }
-                }
-                Qw[lane] = qd;
-                wave_sync();
+                    Qw[lane] = qd;
+                    wave_sync();
 #pragma unroll
-                for (int m = 0; m < EPL; ++m) {
-                    const float t = pfr + tbr[m];
-                    const float f = __builtin_amdgcn_fractf(t);
-                    const float4 qv = Qw[(int)t];
-                    acc[m] += qv.x + f * (qv.y + f * (qv.z + f * qv.w));
+                    for (int m = 0; m < EPL; ++m) {
+                        const float t = pfr + tbr[m];
+                        const float f = __builtin_amdgcn_fractf(t);
+                        const float4 qv = Qw[(int)t];
+                        acc[kq][m] += qv.x + f * (qv.y + f * (qv.z + f * qv.w));
+                    }
+                    wave_sync();
                 }
-                wave_sync();
             }
         }
     }
-    if (kval) {
-        const double scale = g.w_cell * g.T * g.T * g.T;   // g.T = 10^6 K, the patches' reference
+    const double scale = g.w_cell * g.T * g.T * g.T;   // g.T = 10^6 K, the patches' reference
+#pragma unroll
+    for (int kq = 0; kq < KPW; ++kq) {
+        const int k = k_first + kMapWaves * kq;
+        if (k >= P) break;
         float *out = partial + (slot * P + k) * E;
 #pragma unroll
         for (int m = 0; m < EPL; ++m) {
             int e = lane * EPL + m;
-            if (e < E) out[e] = (float)(acc[m] * (scale / S.energy[e]));
+            if (e < E) out[e] = (float)(acc[kq][m] * (scale / S.energy[e]));
         }
     }
     if (lane == 0 && npairs) atomicAdd(&vis_pairs[slot], npairs);
@@ -349,23 +360,31 @@ hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double
     hipLaunchKernelGGL(k_map_sort, dim3(n_list), dim3(256), sizeof(int) * (2 * S.map_nb + 256), st, S, list, map,
                        W.stars, W.rings, W.mcell, W.mgrp);
     launch_table_trace(S, W, list, n_list, st);
-    const int n_tile = (S.P + kMapWaves - 1) / kMapWaves;
+    const int kpw = S.pt_fwd >= 4 * kMapWaves ? 4 : (S.pt_fwd >= 2 * kMapWaves ? 2 : 1);
+    const int n_tile = (S.P + kMapWaves * kpw - 1) / (kMapWaves * kpw);
     dim3 grid(xcd_grid(n_list, n_tile));
     const size_t lds = accum_map_lds(S);
     const int epl = (S.E + 63) / 64;
     if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
+#define PPM_MAP_LAUNCH(E_, K_)                                                                                   \
+    hipLaunchKernelGGL((k_accum_map<E_, K_>), grid, dim3(64 * kMapWaves), lds, st, S, list, W.rings, W.trace,   \
+                       W.mcell, W.mgrp, W.partial32, W.vis_pairs, n_list)
+#define PPM_MAP_KPW(E_)                          \
+    do {                                         \
+        if (kpw == 1) PPM_MAP_LAUNCH(E_, 1);     \
+        else if (kpw == 2) PPM_MAP_LAUNCH(E_, 2); \
+        else PPM_MAP_LAUNCH(E_, 4);              \
+    } while (0)
     if (epl <= 1)
-        hipLaunchKernelGGL(k_accum_map<1>, grid, dim3(64 * kMapWaves), lds, st, S, list, W.rings, W.trace, W.mcell,
-                           W.mgrp, W.partial32, W.vis_pairs, n_list);
+        PPM_MAP_KPW(1);
     else if (epl <= 2)
-        hipLaunchKernelGGL(k_accum_map<2>, grid, dim3(64 * kMapWaves), lds, st, S, list, W.rings, W.trace, W.mcell,
-                           W.mgrp, W.partial32, W.vis_pairs, n_list);
+        PPM_MAP_KPW(2);
     else if (epl <= 4)
-        hipLaunchKernelGGL(k_accum_map<4>, grid, dim3(64 * kMapWaves), lds, st, S, list, W.rings, W.trace, W.mcell,
-                           W.mgrp, W.partial32, W.vis_pairs, n_list);
+        PPM_MAP_KPW(4);
     else
-        hipLaunchKernelGGL(k_accum_map<8>, grid, dim3(64 * kMapWaves), lds, st, S, list, W.rings, W.trace, W.mcell,
-                           W.mgrp, W.partial32, W.vis_pairs, n_list);
+        PPM_MAP_KPW(8);
+#undef PPM_MAP_KPW
+#undef PPM_MAP_LAUNCH
     if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
     launch_reduce_fold32(S, W, B, st, flux_out, counts_out);
     return hipGetLastError();

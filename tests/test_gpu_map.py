@@ -157,3 +157,25 @@ def test_map_full_size_golden(torch_dev):
     err, n = rel_err(got[0], ref)
     print(f"map n_side 64 full: counts max rel err {err:.3e} over {n} bins", flush=True)
     assert err < TOL
+
+
+def test_map_tiles_bitwise_and_autotune(torch_dev):
+    """8, 16 and 32 phases per work-group give identical counts (each phase
+    summed by one wave in a fixed order); the autotuner keeps the fastest."""
+    import paper_2510_07764_amd as ppm
+    torch, dev = torch_dev
+    nside = 8
+    spec, p, m = syn.map_config(nside, "full", n_phase=40, n_energy=256)
+    plan = ppm.Plan(spec, max_batch=2)
+    pt = torch.tensor(np.stack([p, p]), dtype=torch.float64, device=dev)
+    pt[1, 3] = 0.2
+    mt = torch.tensor(np.stack([m, syn.temperature_map(nside, "random")]), dtype=torch.float64, device=dev)
+    ref = plan.forward_map(pt, mt).cpu().numpy()
+    for t in (16, 32, 8):
+        plan.set_tiles(phase_tile=t)
+        assert np.array_equal(plan.forward_map(pt, mt).cpu().numpy(), ref), t
+    rep = plan.autotune_map(pt, mt, reps=2)
+    assert sorted(rep["forward"]) == [8, 16, 32]
+    assert rep["forward"][rep["chosen"][0]] == min(rep["forward"].values())
+    assert plan.tiles[0] == rep["chosen"][0]
+    assert np.array_equal(plan.forward_map(pt, mt).cpu().numpy(), ref)
