@@ -44,10 +44,10 @@ PEAK_FP32_TFLOPS = 157.3
 # kernel sources the counters were taken on and for the tiles listed; any
 # other case reports null until the counters are taken again.
 KERNEL_SOURCES = ("ppm_kernels.hip", "ppm_device.h", "ppm_dual.h", "ppm_internal.h", "ppm_launch.h")
-TRAFFIC = {"sources_sha256": "195fc142f80b1780579179b3562fe648b1dd3291e43bbfb83705cd068736b524",
+TRAFFIC = {"sources_sha256": "0a133ba7fad0db37b570c4c81d38c4540b5948e9de15cf8eb08e88bcb5484237",
            "fetch_scale": 1.99980, "write_scale": 1.0,
            # phase tile -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-           "by_tile": {8: (4282.85, 33198.96), 12: (4282.26, 33071.07)},
+           "by_tile": {8: (4284.38, 33198.96), 12: (4284.20, 33071.07)},
            "profile": "profiles/k_accum_fast_config1_traffic.md"}
 
 
@@ -123,6 +123,7 @@ def main():
     ap.add_argument("--map-nside", type=int, default=64,
                     help="HEALPix n_side of the full-surface temperature-map leg (0: skip)")
     ap.add_argument("--map-batch", type=int, default=32, help="vectors per call in the batched map leg (0: skip)")
+    ap.add_argument("--map-tile", default="auto", help="phase tile of the map legs: 'auto' or 8, 16, 32")
     ap.add_argument("--tiles", default="auto",
                     help="launch shape of the accumulation kernels: 'auto' (autotuner, per leg) or "
                          "'F,G' (forward and adjoint phase tiles)")
@@ -255,9 +256,12 @@ def main():
         mmt = torch.tensor(mm[None], dtype=torch.float64, device=dev)
         mll = torch.empty(1, dtype=torch.float64, device=dev)
         mtune = None
-        if args.tiles == "auto":
+        if args.map_tile == "auto":
             r = mplan.autotune_map(mpt, mmt, reps=5)
             mtune = {"chosen": r["chosen"][0], "forward_ms": {str(k): round(v, 4) for k, v in r["forward"].items()}}
+        else:
+            mplan.set_tiles(phase_tile=int(args.map_tile))
+            mtune = {"chosen": int(args.map_tile), "fixed": True}
         for _ in range(args.warmup):
             mplan.loglike_map(mpt, mmt, data_t, out=mll)
         torch.cuda.synchronize()
@@ -283,8 +287,8 @@ def main():
             mptb[:, 3] = torch.linspace(0.0, 0.5, Bm, dtype=torch.float64)
             mmtb = mmt.repeat(Bm, 1).contiguous()
             mllb = torch.empty(Bm, dtype=torch.float64, device=dev)
-            mtune_b = None
-            if args.tiles == "auto":
+            mtune_b = {"chosen": mplan.tiles[0], "fixed": True}
+            if args.map_tile == "auto":
                 r = mplan.autotune_map(mptb, mmtb, reps=2)
                 mtune_b = {"chosen": r["chosen"][0],
                            "forward_ms": {str(k): round(v, 4) for k, v in r["forward"].items()}}
