@@ -444,7 +444,7 @@ __device__ inline void offset_coeffs(const RingRec &g, int j, double &ca, double
 constexpr int kAdjWaves = 8;   // waves per block of k_accum_adj
 
 template <int EPL>
-__global__ __launch_bounds__(64 * kAdjWaves) void k_accum_adj(DevSpec S, const int32_t *list, const RingRec *rings,
+__global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, const int32_t *list, const RingRec *rings,
                                                    const RingTan *ringtan, const double4 *trace,
                                                    const double4 *tangent, const float *sub, const float2 *subtg,
                                                    const float *gtil, double *gpart, int n_list)
@@ -462,11 +462,11 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_accum_adj(DevSpec S, const i
     double4 *tr = (double4 *)lds_raw;                          // nfp + 1
     double *axmu = (double *)(tr + nfp + 1);                   // nmu (padded to 16 bytes)
     float *tab = (float *)(axmu + ((nmu + 1) & ~1));           // sub_stride
-    float2 *tab2 = (float2 *)(tab + S.sub_stride);             // sub_stride
-    float4 *Nb = (float4 *)(tab2 + S.sub_stride);              // kAdjWaves * 68 node values
+    float4 *Nb = (float4 *)(tab + S.sub_stride);               // kAdjWaves * 68 node values
     float4 *Qb = Nb + kAdjWaves * 68;                          // kAdjWaves * 4 * 64 quads
     double *po = (double *)(Qb + kAdjWaves * 4 * 64);          // nfp + 1 phi_o, compact for the search
     const double4 *tg = tangent + slot * (size_t)(nfp + 1) * 5;   // read through the caches in stage C
+    const float2 *tab2 = subtg + slot * (size_t)S.sub_stride;      // logT / log g planes, read through L2
     {
         const double4 *gtr = trace + slot * (nfp + 1);
         for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
@@ -478,9 +478,6 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_accum_adj(DevSpec S, const i
         const float4 *gs = (const float4 *)(sub + slot * (size_t)S.sub_stride);
         float4 *ts = (float4 *)tab;
         for (int i = threadIdx.x; i < S.sub_stride / 4; i += blockDim.x) ts[i] = gs[i];
-        const float4 *gs2 = (const float4 *)(subtg + slot * (size_t)S.sub_stride);
-        float4 *ts2 = (float4 *)tab2;
-        for (int i = threadIdx.x; i < S.sub_stride / 2; i += blockDim.x) ts2[i] = gs2[i];
     }
     __syncthreads();
 
@@ -759,7 +756,7 @@ __global__ __launch_bounds__(64) void k_grad_final(DevSpec S, const StarRec *sta
 size_t accum_adj_lds(const DevSpec &S)
 {
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
-         + sizeof(float) * S.sub_stride * 3 + sizeof(float4) * kAdjWaves * 68
+         + sizeof(float) * S.sub_stride + sizeof(float4) * kAdjWaves * 68
          + sizeof(float4) * kAdjWaves * 4 * 64 + sizeof(double) * (S.n_fp + 1);
 }
 
