@@ -211,11 +211,13 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
         __syncthreads();   // the previous bucket's slabs are no longer read (and the trace is staged)
         const float *a00 = S.atm + ((size_t)it * S.ng + ig) * slab, *a01 = a00 + slab;
         const float *a10 = S.atm + ((size_t)(it + 1) * S.ng + ig) * slab, *a11 = a10 + slab;
-        for (int i = tid; i < nmu * xw; i += blockDim.x) {
-            const int m = i / xw, c = i - m * xw;
-            const size_t o = (size_t)m * nx + w0 + c;
-            sl0[m * WM + c] = fg0 * a00[o] + fg1 * a01[o];
-            sl1[m * WM + c] = fg0 * a10[o] + fg1 * a11[o];
+        // wave w stages rows w, w + 8, ...; lanes walk the row's columns
+        for (int m = wave; m < nmu; m += kMapWaves) {
+            const size_t o = (size_t)m * nx + w0;
+            for (int c = lane; c < xw; c += 64) {
+                sl0[m * WM + c] = fg0 * a00[o + c] + fg1 * a01[o + c];
+                sl1[m * WM + c] = fg0 * a10[o + c] + fg1 * a11[o + c];
+            }
         }
         __syncthreads();
         if (!kval) continue;
