@@ -124,6 +124,9 @@ def main():
                     help="HEALPix n_side of the full-surface temperature-map leg (0: skip)")
     ap.add_argument("--map-batch", type=int, default=32, help="vectors per call in the batched map leg (0: skip)")
     ap.add_argument("--map-tile", default="auto", help="phase tile of the map legs: 'auto' or 8, 16, 32")
+    ap.add_argument("--pt-chains", type=int, default=64, help="chains per temperature of the sampler leg (0: skip)")
+    ap.add_argument("--pt-temps", type=int, default=4, help="temperatures of the sampler leg")
+    ap.add_argument("--pt-steps", type=int, default=20, help="timed steps of the sampler leg")
     ap.add_argument("--tiles", default="auto",
                     help="launch shape of the accumulation kernels: 'auto' (autotuner, per leg) or "
                          "'F,G' (forward and adjoint phase tiles)")
@@ -246,6 +249,36 @@ def main():
                 "vs_plain": (B / tg) * plain_s, "tiles": tuned_g}
         del glg, plang
 
+    # ---------------- GPU-resident parallel-tempered sampler on workload 1: every
+    # step one batched likelihood call of chains x temperatures proposals
+    ptleg = None
+    if args.pt_chains > 0:
+        Cc, Tt = args.pt_chains, args.pt_temps
+        betas = [0.5 ** t for t in range(Tt)]
+        free = list(syn.GRAD_SLOTS)
+        lo = [p[s] * 0.9 if p[s] > 0 else -0.5 for s in free]
+        hi = [p[s] * 1.1 if p[s] > 0 else 0.5 for s in free]
+        steps = [max(abs(p[s]), 0.05) * 2e-3 for s in free]
+        pplan = ppm.Plan(spec, max_batch=Cc * Tt)
+        ptune = tune(pplan, torch.tensor(syn.config4_draws(Cc * Tt), dtype=torch.float64, device=dev), 2)
+        sampler = ppm.PTSampler(Cc, betas, free, lo, hi, steps, seed=2025, swap_every=1)
+        start = torch.tensor(np.tile(p, (Tt, Cc, 1)), dtype=torch.float64, device=dev)
+        sampler.set_state(start)
+        sampler.run(pplan, data_t, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, chain_l = sampler.run(pplan, data_t, args.pt_steps)
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - t0) / args.pt_steps
+        _, _, nacc, nsw, _ = sampler.state()
+        ptleg = {"chains": Cc, "temperatures": Tt, "steps": args.pt_steps, "ms_per_step": tp * 1e3,
+                 "steps_per_s": 1.0 / tp, "loglike_evals_per_s": Cc * Tt / tp,
+                 "accept_rate": float(nacc.sum().item()) / ((args.pt_steps + 2) * Cc * Tt),
+                 "swap_rate": (float(nsw.sum().item()) / ((args.pt_steps + 2) * Cc * max(Tt - 1, 1) / 2)
+                               if Tt > 1 else None),
+                 "finite": bool(torch.isfinite(chain_l).all().item()), "tiles": ptune}
+        del sampler, pplan
+
     # ---------------- full-surface temperature map (HEALPix), one vector per call,
     # then a batch of maps (the same map, parameter draws of the batched leg)
     tmap = None
@@ -337,6 +370,7 @@ def main():
         "batched_large": batched_large,
         "grad": grad,
         "map": tmap,
+        "sampler": ptleg,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": hot_kernel_traffic(plan.tiles[0]),
                      "kernel": "k_accum_fast<4>", "kernel_ms": hot_avg_s * 1e3, "units": units,

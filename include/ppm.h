@@ -256,6 +256,70 @@ int ppm_autotune(ppm_plan *plan, const double *params_dev, int B, const int32_t 
 int ppm_autotune_map(ppm_plan *plan, const double *params_dev, int B, const double *map_dev, int reps,
                      void *stream, ppm_tune_report *report);
 
+/*
+ * GPU-resident parallel-tempered Metropolis sampler (the inference layer
+ * named in Sect. 7): C chains at each of T inverse temperatures, every step
+ * one batched likelihood call of the T*C proposals, all on the device with
+ * no host synchronisation.
+ *   move     theta'_j = theta_j + step[j] / sqrt(beta_t) z_j on the free
+ *            slots (z standard normal), accepted when theta' lies in the
+ *            uniform prior box [lo, hi] and log u < beta_t (L' - L)
+ *            (an invalid proposal has L' = -inf and is rejected);
+ *   swap     after every swap_every-th step n, for each chain the pairs
+ *            (t, t+1) with t of parity (n / swap_every) mod 2 exchange
+ *            states when log u < (beta_t - beta_{t+1}) (L_{t+1} - L_t).
+ * Random numbers: Philox4x32-10 (Salmon et al. 2011) with counter
+ * (n mod 2^32, n div 2^32, t*C + c, purpose << 16 | k), key (seed mod 2^32,
+ * seed div 2^32), purpose 0 proposal (k = pair of free slots, Box-Muller of
+ * two 53-bit uniforms taken from words (0,1) and (2,3)), 1 acceptance, 2 swap.
+ * Layouts (device, caller-owned): state and proposals [T][C][16] doubles
+ * (slots not free are carried unchanged), log-likelihoods [T][C],
+ * acceptance counts [T][C] int32, swap counts [T-1][C] int32 (pair t).
+ * The sampler owns its state and scratch (allocated at creation); its calls
+ * are asynchronous on the given stream, and it must not be used from two
+ * streams at once.
+ */
+#define PPM_PT_MAX_TEMPS 64
+typedef struct ppm_pt_config {
+    int32_t n_chains;               /* C >= 1 */
+    int32_t n_temps;                /* T in [1, 64] */
+    int32_t n_free;                 /* free slots, 1 .. 16 */
+    int32_t free_slot[16];          /* their places in the parameter record, distinct, 0 .. 15 */
+    double lo[16], hi[16];          /* uniform prior box per free slot, lo < hi */
+    double step[16];                /* proposal standard deviation at beta = 1, > 0 */
+    double beta[PPM_PT_MAX_TEMPS];  /* inverse temperatures in (0, 1], strictly decreasing */
+    uint64_t seed;
+    int32_t swap_every;             /* swap round after every k-th step; 0: no swaps */
+} ppm_pt_config;
+
+typedef struct ppm_pt ppm_pt;
+
+/* Creates a sampler (validates the configuration, allocates its device
+ * state).  PPM_ERR_ARG on an invalid configuration. */
+int ppm_pt_create(const ppm_pt_config *cfg, ppm_pt **out);
+void ppm_pt_destroy(ppm_pt *pt);
+/* Sets the state [T][C][16] and its log-likelihoods [T][C] (logl_dev NULL:
+ * -inf, so that the first finite proposals are accepted), the step counter
+ * n, and zeroes the acceptance and swap counts. */
+int ppm_pt_set_state(ppm_pt *pt, const double *params_dev, const double *logl_dev, int64_t step, void *stream);
+/* Proposals of the current step into prop_dev [T][C][16]. */
+int ppm_pt_propose(ppm_pt *pt, double *prop_dev, void *stream);
+/* Acceptance of the current step's proposals given their log-likelihoods
+ * prop_logl_dev [T][C], then the swap round when due; advances the step
+ * counter. */
+int ppm_pt_accept(ppm_pt *pt, const double *prop_dev, const double *prop_logl_dev, void *stream);
+/* n_steps steps of propose -> ppm_loglike(plan, T*C proposals, data_dev) ->
+ * accept, all launched on the stream without synchronisation.  chain_dev
+ * [n_steps][C][16] and chain_logl_dev [n_steps][C] (either may be NULL)
+ * receive the cold chains (t = 0) after each step.  The plan must be a spot
+ * plan with max_batch >= T*C. */
+int ppm_pt_run(ppm_pt *pt, ppm_plan *plan, const int32_t *data_dev, int n_steps, double *chain_dev,
+               double *chain_logl_dev, void *stream);
+/* Copies the state, its log-likelihoods and the counts (device pointers,
+ * each may be NULL) and returns the step counter (host). */
+int ppm_pt_get_state(ppm_pt *pt, double *params_dev, double *logl_dev, int32_t *n_accept_dev, int32_t *n_swap_dev,
+                     int64_t *step, void *stream);
+
 const char *ppm_status_string(int code);
 const char *ppm_last_error(void);
 int ppm_version(void);

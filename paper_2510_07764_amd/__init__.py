@@ -64,6 +64,16 @@ class _TuneReport(C.Structure):
                 ("chosen", _Tiles)]
 
 
+PT_MAX_TEMPS = 64
+
+
+class _PTConfig(C.Structure):
+    _fields_ = [("n_chains", C.c_int32), ("n_temps", C.c_int32), ("n_free", C.c_int32),
+                ("free_slot", C.c_int32 * 16), ("lo", C.c_double * 16), ("hi", C.c_double * 16),
+                ("step", C.c_double * 16), ("beta", C.c_double * PT_MAX_TEMPS), ("seed", C.c_uint64),
+                ("swap_every", C.c_int32)]
+
+
 _VP = C.c_void_p
 _I32P = C.POINTER(C.c_int32)
 _DP = C.POINTER(C.c_double)
@@ -89,6 +99,13 @@ SIGNATURES = {
     "ppm_set_tiles": (C.c_int, [_VP, C.POINTER(_Tiles)]),
     "ppm_autotune": (C.c_int, [_VP, _VP, C.c_int, _I32P, C.c_int, _VP, C.POINTER(_TuneReport)]),
     "ppm_autotune_map": (C.c_int, [_VP, _VP, C.c_int, _VP, C.c_int, _VP, C.POINTER(_TuneReport)]),
+    "ppm_pt_create": (C.c_int, [C.POINTER(_PTConfig), C.POINTER(_VP)]),
+    "ppm_pt_destroy": (None, [_VP]),
+    "ppm_pt_set_state": (C.c_int, [_VP, _VP, _VP, C.c_int64, _VP]),
+    "ppm_pt_propose": (C.c_int, [_VP, _VP, _VP]),
+    "ppm_pt_accept": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "ppm_pt_run": (C.c_int, [_VP, _VP, _VP, C.c_int, _VP, _VP, _VP]),
+    "ppm_pt_get_state": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_int64), _VP]),
     "ppm_status_string": (C.c_char_p, [C.c_int]),
     "ppm_last_error": (C.c_char_p, []),
     "ppm_version": (C.c_int, []),
@@ -437,6 +454,92 @@ class GraphedLogLike:
         self.params.copy_(params)
         self.graph.replay()
         return (self.out, self.grad) if self.with_grad else self.out
+
+
+class PTSampler:
+    """GPU-resident parallel-tempered Metropolis sampler (``ppm_pt_*``):
+    n_chains chains at each inverse temperature of ``betas``, random-walk
+    moves on the parameter-record slots ``free_slots`` with standard
+    deviations ``steps`` (at beta = 1) inside the prior box [lo, hi]."""
+
+    def __init__(self, n_chains, betas, free_slots, lo, hi, steps, seed=0, swap_every=1):
+        c = _PTConfig()
+        c.n_chains = int(n_chains)
+        c.n_temps = len(betas)
+        c.n_free = len(free_slots)
+        for j, sl in enumerate(free_slots):
+            c.free_slot[j] = int(sl)
+            c.lo[j] = float(lo[j])
+            c.hi[j] = float(hi[j])
+            c.step[j] = float(steps[j])
+        for t, b in enumerate(betas):
+            c.beta[t] = float(b)
+        c.seed = int(seed)
+        c.swap_every = int(swap_every)
+        self.C, self.T = c.n_chains, c.n_temps
+        h = C.c_void_p()
+        _check(lib().ppm_pt_create(C.byref(c), C.byref(h)), "ppm_pt_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ppm_pt_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, params, logl=None, step=0, stream=None):
+        """params [T, C, 16], logl [T, C] (None: -inf), float64 on the device."""
+        import torch
+        assert params.is_cuda and params.dtype == torch.float64 and params.is_contiguous()
+        assert params.numel() == self.T * self.C * NPARAM
+        lp = None
+        if logl is not None:
+            assert logl.dtype == torch.float64 and logl.is_contiguous() and logl.numel() == self.T * self.C
+            lp = _dptr(logl)
+        _check(lib().ppm_pt_set_state(self.handle, _dptr(params), lp, int(step), _stream_handle(stream)),
+               "ppm_pt_set_state")
+
+    def propose(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.T, self.C, NPARAM), dtype=torch.float64, device="cuda")
+        _check(lib().ppm_pt_propose(self.handle, _dptr(out), _stream_handle(stream)), "ppm_pt_propose")
+        return out
+
+    def accept(self, prop, prop_logl, stream=None):
+        _check(lib().ppm_pt_accept(self.handle, _dptr(prop), _dptr(prop_logl), _stream_handle(stream)),
+               "ppm_pt_accept")
+
+    def run(self, plan: Plan, data, n_steps, chain=None, chain_logl=None, stream=None):
+        """n_steps of propose -> plan.loglike -> accept; returns the cold
+        chains [n_steps, C, 16] and their logL [n_steps, C]."""
+        import torch
+        if chain is None:
+            chain = torch.empty((n_steps, self.C, NPARAM), dtype=torch.float64, device="cuda")
+        if chain_logl is None:
+            chain_logl = torch.empty((n_steps, self.C), dtype=torch.float64, device="cuda")
+        _check(lib().ppm_pt_run(self.handle, plan.handle, _dptr(data), int(n_steps), _dptr(chain), _dptr(chain_logl),
+                                _stream_handle(stream)), "ppm_pt_run")
+        return chain, chain_logl
+
+    def state(self, stream=None):
+        """(params [T, C, 16], logl [T, C], accept counts [T, C], swap
+        counts [T-1, C], step)."""
+        import torch
+        p = torch.empty((self.T, self.C, NPARAM), dtype=torch.float64, device="cuda")
+        ll = torch.empty((self.T, self.C), dtype=torch.float64, device="cuda")
+        na = torch.empty((self.T, self.C), dtype=torch.int32, device="cuda")
+        ns = torch.zeros((max(self.T - 1, 1), self.C), dtype=torch.int32, device="cuda")
+        st = C.c_int64()
+        _check(lib().ppm_pt_get_state(self.handle, _dptr(p), _dptr(ll), _dptr(na),
+                                      _dptr(ns) if self.T > 1 else None, C.byref(st), _stream_handle(stream)),
+               "ppm_pt_get_state")
+        return p, ll, na, ns[: self.T - 1], st.value
 
 
 def _autograd_function():

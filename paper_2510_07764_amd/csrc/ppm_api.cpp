@@ -81,6 +81,12 @@ bool uniform_axis(const double *a, int n, double &x0, double &h)
 
 }  // namespace
 
+namespace ppm {
+// error reporting shared with the other host sources of the library
+int api_fail(int code, const char *msg) { return fail(code, msg); }
+int api_hip_fail(hipError_t e, const char *where) { return hip_fail(e, where); }
+}  // namespace ppm
+
 struct ppm_plan {
     DevSpec S;
     Workspace W;

@@ -67,5 +67,7 @@ hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *param
 size_t accum_table_lds(const DevSpec &S);
 size_t accum_adj_lds(const DevSpec &S);
 int loglike_blocks(int PC);
+int api_fail(int code, const char *msg);           // sets ppm_last_error, returns code
+int api_hip_fail(hipError_t e, const char *where);  // sets ppm_last_error, returns PPM_ERR_HIP
 
 }  // namespace ppm

@@ -91,3 +91,33 @@ def test_tile_entry_points_reject_null_arguments(L):
     assert L.ppm_autotune(None, None, 1, None, 0, None, C.byref(r)) == -1
     assert "reps" in L.ppm_last_error().decode()
     assert C.sizeof(ppm._TuneReport) == 8 + 2 * 16 * (4 + 8) + 8
+
+
+def test_sampler_configuration_errors(L):
+    """ppm_pt_create validates its configuration before any device call."""
+    import ctypes as C
+    import paper_2510_07764_amd as ppm
+
+    def cfg(**kw):
+        c = ppm._PTConfig()
+        c.n_chains, c.n_temps, c.n_free, c.swap_every = 4, 3, 2, 1
+        c.free_slot[0], c.free_slot[1] = 0, 1
+        for j in range(2):
+            c.lo[j], c.hi[j], c.step[j] = 0.0, 1.0, 0.1
+        for t, b in enumerate((1.0, 0.5, 0.25)):
+            c.beta[t] = b
+        for k, v in kw.items():
+            if isinstance(v, tuple):
+                getattr(c, k)[v[0]] = v[1]
+            else:
+                setattr(c, k, v)
+        return c
+
+    h = C.c_void_p()
+    for bad, msg in ((cfg(n_temps=0), "n_temps"), (cfg(n_temps=65), "n_temps"), (cfg(n_free=0), "n_free"),
+                     (cfg(free_slot=(1, 0)), "distinct"), (cfg(free_slot=(1, 16)), "distinct"),
+                     (cfg(hi=(0, 0.0)), "lo < hi"), (cfg(step=(1, 0.0)), "steps"),
+                     (cfg(beta=(1, 1.0)), "decrease"), (cfg(beta=(0, 1.5)), "beta"), (cfg(n_chains=0), "n_chains"),
+                     (cfg(swap_every=-1), "swap_every")):
+        assert L.ppm_pt_create(C.byref(bad), C.byref(h)) == -1
+        assert msg in L.ppm_last_error().decode(), (msg, L.ppm_last_error())
