@@ -320,6 +320,41 @@ int ppm_pt_run(ppm_pt *pt, ppm_plan *plan, const int32_t *data_dev, int n_steps,
 int ppm_pt_get_state(ppm_pt *pt, double *params_dev, double *logl_dev, int32_t *n_accept_dev, int32_t *n_swap_dev,
                      int64_t *step, void *stream);
 
+/*
+ * Instrument pipeline of Sect. 2.8.4 (host functions, no device work).
+ * ppm_arf_read / ppm_rmf_read read OGIP FITS files (CAL/GEN/92-002): the
+ * ARF's SPECRESP extension (ENERG_LO, ENERG_HI [keV], SPECRESP [cm^2]) and
+ * the RMF's MATRIX (or SPECRESP MATRIX) extension (ENERG_LO, ENERG_HI, N_GRP,
+ * F_CHAN, N_CHAN, MATRIX, fixed-width or variable-length columns; first
+ * channel from TLMIN of F_CHAN, default 1; channel count from DETCHANS or the
+ * EBOUNDS rows) and EBOUNDS (E_MIN, E_MAX).  Two calls: with every output
+ * array NULL only the sizes are returned; then arrays of n_energy
+ * (e_lo, e_hi, area), n_energy x n_chan row-major (matrix, dense probabilities)
+ * and n_chan (ch_lo, ch_hi; may be NULL).  PPM_ERR_ARG for an unreadable file
+ * or a missing extension or column (see ppm_last_error).
+ *
+ * ppm_response_build: RSP[i][c] = sum_e DS[i][e] A[e] R[e][c] for the model
+ * energies e_model[n_model] (increasing), where DS[i][e] is the integral of
+ * the piecewise-linear hat function of model energy i (constant beyond the
+ * grid's ends) over the fine bin [e_lo[e], e_hi[e]]; area NULL means A = 1.
+ * rsp[n_model][n_chan] in the units of A times keV, ready for
+ * ppm_spec.rsp.  Absorption is not folded in: it stays exp(-N_H sigma) per
+ * evaluation with N_H a parameter.
+ *
+ * ppm_sigma_from_table: the cross-section per H atom at energies e[n] from a
+ * transmission table (e_tab increasing, att_tab in (0, 1]) at the reference
+ * column nh_ref [cm^-2], linear in energy between table nodes and constant
+ * beyond them: sigma = -ln(transmission) / nh_ref, so that exp(-N_H sigma) is
+ * the table value to the power N_H / nh_ref.
+ */
+int ppm_arf_read(const char *path, int32_t *n_energy, double *e_lo, double *e_hi, double *area);
+int ppm_rmf_read(const char *path, int32_t *n_energy, int32_t *n_chan, double *e_lo, double *e_hi, double *matrix,
+                 double *ch_lo, double *ch_hi);
+int ppm_response_build(int32_t n_model, const double *e_model, int32_t n_fine, const double *e_lo, const double *e_hi,
+                       const double *area, int32_t n_chan, const double *matrix, double *rsp);
+int ppm_sigma_from_table(int32_t n_tab, const double *e_tab, const double *att_tab, double nh_ref, int32_t n,
+                         const double *e, double *sigma);
+
 const char *ppm_status_string(int code);
 const char *ppm_last_error(void);
 int ppm_version(void);

@@ -106,6 +106,10 @@ SIGNATURES = {
     "ppm_pt_accept": (C.c_int, [_VP, _VP, _VP, _VP]),
     "ppm_pt_run": (C.c_int, [_VP, _VP, _VP, C.c_int, _VP, _VP, _VP]),
     "ppm_pt_get_state": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_int64), _VP]),
+    "ppm_arf_read": (C.c_int, [C.c_char_p, _I32P, _DP, _DP, _DP]),
+    "ppm_rmf_read": (C.c_int, [C.c_char_p, _I32P, _I32P, _DP, _DP, _DP, _DP, _DP]),
+    "ppm_response_build": (C.c_int, [C.c_int32, _DP, C.c_int32, _DP, _DP, _DP, C.c_int32, _DP, _DP]),
+    "ppm_sigma_from_table": (C.c_int, [C.c_int32, _DP, _DP, C.c_double, C.c_int32, _DP, _DP]),
     "ppm_status_string": (C.c_char_p, [C.c_int]),
     "ppm_last_error": (C.c_char_p, []),
     "ppm_version": (C.c_int, []),
@@ -141,6 +145,56 @@ def validate_params(params: np.ndarray, n_spots: int) -> np.ndarray:
     out = np.zeros(p.shape[0], dtype=np.int32)
     _check(lib().ppm_validate_params(p.ctypes.data_as(_DP), p.shape[0], n_spots, out.ctypes.data_as(_I32P)),
            "ppm_validate_params")
+    return out
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def read_arf(path):
+    """OGIP ARF -> (e_lo, e_hi, area) [keV, keV, cm^2]."""
+    n = C.c_int32()
+    _check(lib().ppm_arf_read(os.fsencode(path), C.byref(n), None, None, None), "ppm_arf_read")
+    lo, hi, a = (np.zeros(n.value) for _ in range(3))
+    _check(lib().ppm_arf_read(os.fsencode(path), C.byref(n), lo.ctypes.data_as(_DP), hi.ctypes.data_as(_DP),
+                              a.ctypes.data_as(_DP)), "ppm_arf_read")
+    return lo, hi, a
+
+
+def read_rmf(path):
+    """OGIP RMF -> (e_lo, e_hi, matrix [n_energy, n_chan], ch_lo, ch_hi)."""
+    ne, nc = C.c_int32(), C.c_int32()
+    _check(lib().ppm_rmf_read(os.fsencode(path), C.byref(ne), C.byref(nc), None, None, None, None, None),
+           "ppm_rmf_read")
+    lo, hi = np.zeros(ne.value), np.zeros(ne.value)
+    m = np.zeros((ne.value, nc.value))
+    cl, ch = np.full(nc.value, np.nan), np.full(nc.value, np.nan)
+    _check(lib().ppm_rmf_read(os.fsencode(path), C.byref(ne), C.byref(nc), lo.ctypes.data_as(_DP),
+                              hi.ctypes.data_as(_DP), m.ctypes.data_as(_DP), cl.ctypes.data_as(_DP),
+                              ch.ctypes.data_as(_DP)), "ppm_rmf_read")
+    return lo, hi, m, cl, ch
+
+
+def build_response(e_model, e_lo, e_hi, area, matrix):
+    """RSP [n_model, n_chan] = DS (A R) for ppm_spec.rsp (Sect. 2.8.4)."""
+    em, lo, hi, mt = _f64(e_model), _f64(e_lo), _f64(e_hi), _f64(matrix)
+    ar = None if area is None else _f64(area)
+    out = np.zeros((em.size, mt.shape[1]))
+    _check(lib().ppm_response_build(em.size, em.ctypes.data_as(_DP), lo.size, lo.ctypes.data_as(_DP),
+                                    hi.ctypes.data_as(_DP), None if ar is None else ar.ctypes.data_as(_DP),
+                                    mt.shape[1], mt.ctypes.data_as(_DP), out.ctypes.data_as(_DP)),
+           "ppm_response_build")
+    return out
+
+
+def sigma_from_table(e_tab, att_tab, nh_ref, energy):
+    """Cross-section per H atom [cm^2] from a transmission table at nh_ref."""
+    et, at, e = _f64(e_tab), _f64(att_tab), _f64(energy)
+    out = np.zeros(e.size)
+    _check(lib().ppm_sigma_from_table(et.size, et.ctypes.data_as(_DP), at.ctypes.data_as(_DP), float(nh_ref),
+                                      e.size, e.ctypes.data_as(_DP), out.ctypes.data_as(_DP)),
+           "ppm_sigma_from_table")
     return out
 
 
