@@ -97,6 +97,9 @@ enum ppm_interp { PPM_INTERP_MIXED = 0, PPM_INTERP_CUBIC = 1, PPM_INTERP_CUBIC_C
  *              entry points; the spot fields are ignored.  Needs the
  *              atmosphere table, PPM_F32, the mixed strategy, grad = 0 and an
  *              energy grid spanning at most 59 x intervals.
+ *  background  NULL, or [n_phase][n_chan] expected background counts per bin
+ *              (Sect. 7): the likelihood and its gradient use model counts
+ *              plus background; ppm_forward's counts stay the model's own.
  */
 typedef struct {
     int32_t mode, intensity, n_spots;
@@ -115,6 +118,7 @@ typedef struct {
     int32_t grad;
     int32_t interp;
     int32_t n_side;
+    const double *background;
 } ppm_spec;
 
 typedef struct ppm_plan ppm_plan;

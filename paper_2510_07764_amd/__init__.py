@@ -47,7 +47,7 @@ class _Spec(C.Structure):
                 ("ax_mu", C.POINTER(C.c_double)), ("ax_x", C.POINTER(C.c_double)),
                 ("log_intensity", C.POINTER(C.c_double)),
                 ("n_alpha", C.c_int32), ("precision", C.c_int32), ("grad", C.c_int32),
-                ("interp", C.c_int32), ("n_side", C.c_int32)]
+                ("interp", C.c_int32), ("n_side", C.c_int32), ("background", C.POINTER(C.c_double))]
 
 
 class _Tiles(C.Structure):
@@ -253,6 +253,11 @@ class Plan:
         s.grad = 1 if grad else 0
         s.interp = int(spec.get("interp", 0))
         s.n_side = int(spec.get("n_side", 0))
+        bg = spec.get("background")
+        if bg is not None:
+            bg = np.asarray(bg, dtype=np.float64)
+            assert bg.shape == (s.n_phase, s.n_chan), bg.shape
+        s.background = arr(bg)
         self.n_side = s.n_side
         self.n_pix = 12 * s.n_side * s.n_side
         self.spec = spec

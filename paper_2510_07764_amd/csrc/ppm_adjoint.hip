@@ -52,7 +52,8 @@ __global__ __launch_bounds__(256) void k_fold_bwd(DevSpec S, const StarRec *star
     const int32_t *d = data + (size_t)k * C;
     for (int c = threadIdx.x; c < C; c += blockDim.x) {
         const int dc = d[c];
-        gm[c] = dc == 0 ? -1.0 : dc / m[c] - 1.0;     // d/dm of d ln m - m
+        const double mc = S.bkg ? m[c] + S.bkg[(size_t)k * C + c] : m[c];   // model plus background
+        gm[c] = dc == 0 ? -1.0 : dc / mc - 1.0;       // d/dm of d ln m - m
     }
     __syncthreads();
     const StarRec st = stars[b];

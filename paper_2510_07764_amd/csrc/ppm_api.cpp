@@ -284,6 +284,18 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     S.glw = pl->upload(glw.data(), glw.size());
     S.energy = pl->upload(sp->energy_kev, S.E);
     if (sp->sigma_cm2) S.sigma = pl->upload(sp->sigma_cm2, S.E);
+    if (sp->background) {
+        for (size_t i = 0; i < (size_t)S.P * S.C; ++i)
+            if (!(sp->background[i] >= 0.0) || !std::isfinite(sp->background[i])) {
+                delete pl;
+                return fail(PPM_ERR_ARG, "background counts must be finite and >= 0");
+            }
+        S.bkg = pl->upload(sp->background, (size_t)S.P * S.C);
+        if (!S.bkg) {
+            delete pl;
+            return fail(PPM_ERR_ALLOC, "background upload failed");
+        }
+    }
     {
         size_t n = (size_t)S.E * S.C;
         std::vector<float> r32(n);
@@ -580,7 +592,7 @@ int ppm_loglike_map(ppm_plan *pl, const double *params_dev, int B, const double 
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = run_forward_map(pl, params_dev, B, map_dev, st, nullptr, cnt);
     if (e != hipSuccess) return hip_fail(e, "ppm_loglike_map forward");
-    e = launch_loglike(pl->W, cnt, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
+    e = launch_loglike(pl->W, cnt, pl->S.bkg, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike_map reduction");
 }
 
@@ -617,7 +629,7 @@ int ppm_loglike(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = run_forward(pl, params_dev, B, nc, st, nullptr, cnt);
     if (e != hipSuccess) return hip_fail(e, "ppm_loglike forward");
-    e = launch_loglike(pl->W, cnt, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
+    e = launch_loglike(pl->W, cnt, pl->S.bkg, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike reduction");
 }
 
@@ -668,7 +680,7 @@ int ppm_loglike_grad(ppm_plan *pl, const double *params_dev, int B, const int32_
     const char *what = "";
     hipError_t e = run_grad(pl, params_dev, B, nc, data_dev, grad_dev, st, &what);
     if (e != hipSuccess) return hip_fail(e, what);
-    e = launch_loglike(pl->W, pl->W.counts, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
+    e = launch_loglike(pl->W, pl->W.counts, pl->S.bkg, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike_grad reduction");
 }
 

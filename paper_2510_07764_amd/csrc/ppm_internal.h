@@ -47,6 +47,7 @@ struct DevSpec {
     const float *rsp32;     // [E][C]
     const double *rsp64;    // [E][C]
     const double *rspT64;   // [C][E] (gradient plans: backward fold)
+    const double *bkg;      // [P][C] background counts per bin (nullptr: none)
     const float *atm;       // [nT][ng][nmu][nx] linear I/T^3
     const double *ax_mu;    // [nmu]
     const double *glx, *glw;  // Gauss-Legendre on [0, 1], n_quad nodes

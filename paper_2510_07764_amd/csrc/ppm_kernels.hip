@@ -1052,8 +1052,8 @@ __global__ __launch_bounds__(256) void k_fold_f64(const double *A, const double 
 // ---------------------------------------------------------------------------
 constexpr int kLLChunk = 512;    // bins per block of the first likelihood stage
 
-__global__ __launch_bounds__(256) void k_loglike_part(const double *counts, const int32_t *data, int PC,
-                                                      double *part, int32_t *bad)
+__global__ __launch_bounds__(256) void k_loglike_part(const double *counts, const double *bkg, const int32_t *data,
+                                                      int PC, double *part, int32_t *bad)
 {
     const int b = blockIdx.y, blk = blockIdx.x;
     __shared__ double red[256];
@@ -1064,7 +1064,7 @@ __global__ __launch_bounds__(256) void k_loglike_part(const double *counts, cons
     const int i0 = blk * kLLChunk, i1 = min(PC, i0 + kLLChunk);
     for (int i = i0 + threadIdx.x; i < i1; i += 256) {
         int d = data[i];
-        double mi = m[i];
+        double mi = bkg ? m[i] + bkg[i] : m[i];   // model plus background counts
         if (d == 0) { s -= mi; continue; }
         if (!(mi > 0.0)) { ++nbad; continue; }
         s += d * log(mi) - mi - lgamma(d + 1.0);
@@ -1230,11 +1230,11 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
     return hipGetLastError();
 }
 
-hipError_t launch_loglike(const Workspace &W, const double *counts, int B, int PC, const int32_t *data,
-                          double *logl, hipStream_t st)
+hipError_t launch_loglike(const Workspace &W, const double *counts, const double *bkg, int B, int PC,
+                          const int32_t *data, double *logl, hipStream_t st)
 {
     const int nblk = (PC + kLLChunk - 1) / kLLChunk;
-    hipLaunchKernelGGL(k_loglike_part, dim3(nblk, B), dim3(256), 0, st, counts, data, PC, W.ll_part, W.ll_bad);
+    hipLaunchKernelGGL(k_loglike_part, dim3(nblk, B), dim3(256), 0, st, counts, bkg, data, PC, W.ll_part, W.ll_bad);
     hipLaunchKernelGGL(k_loglike_final, dim3(B), dim3(64), 0, st, W.stars, W.ll_part, W.ll_bad, nblk,
                        B, logl);
     return hipGetLastError();

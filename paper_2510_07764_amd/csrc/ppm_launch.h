@@ -58,8 +58,8 @@ hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double
                               hipEvent_t ev_hot0 = nullptr, hipEvent_t ev_hot1 = nullptr);
 size_t accum_map_lds(const DevSpec &S);
 constexpr int kMapWaves = 8;     // waves per block of the map accumulation kernel, one phase each
-hipError_t launch_loglike(const Workspace &W, const double *counts, int B, int PC, const int32_t *data,
-                          double *logl, hipStream_t st);
+hipError_t launch_loglike(const Workspace &W, const double *counts, const double *bkg, int B, int PC,
+                          const int32_t *data, double *logl, hipStream_t st);
 hipError_t launch_status(const Workspace &W, int B, int32_t *out, hipStream_t st);
 hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev,
                        int B, const int32_t *list, int n_list, const double *counts, const int32_t *data,
