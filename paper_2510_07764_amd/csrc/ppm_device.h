@@ -74,38 +74,41 @@ __device__ inline void gl_rule(const DevSpec &S, int n, const double *&x, const 
 // cos(alpha) -> 0; 20/24/32/48/64 nodes for cos(alpha) >= 0.5/0.2/0.05/1e-3
 // and below keep the relative error of all three integrals below 1e-12 for
 // u in [0.15, 0.64] (against a 128-node rule).
+// With q0, qs the quadrature runs over the nodes q0, q0 + qs, ... only and the
+// terms that are not quadrature sums come from q0 = 0 only, so that summing
+// the results of q0 = 0 .. qs-1 gives the full values (lanes of one ray).
 template <class U>
-__device__ void bend_out(const DevSpec &S, const U &u, double alpha, U &psi, U &dpsi, U &tp)
+__device__ void bend_out(const DevSpec &S, const U &u, double alpha, U &psi, U &dpsi, U &tp, int q0 = 0, int qs = 1)
 {
     const U sq = sqrt(1.0 - u);
-    if (alpha <= 0.0) { psi = U(0.0); dpsi = 1.0 / sq; tp = U(0.0); return; }
+    if (alpha <= 0.0) { psi = U(0.0); dpsi = q0 == 0 ? 1.0 / sq : U(0.0); tp = U(0.0); return; }
     double c = cos(alpha), s = sin(alpha);
-    const U q0 = 2.0 - u / (1.0 - u);
+    const U qa = 2.0 - u / (1.0 - u);
     const double *gx, *gw;
     if (c < 1e-9) {
         // tangent ray: x/sqrt(x^2 s^2 q) = 1/(s sqrt q), regular on [0, 1]
         gl_rule(S, 32, gx, gw);
         U I1 = U(0.0), IT = U(0.0);
-        for (int q = 0; q < 32; ++q) {
+        for (int q = q0; q < 32; q += qs) {
             double x = gx[q], w = gw[q];
             U rq = sqrt(q_s2(x, u));
             I1 += w / rq;
             IT += w / (rq * (1.0 + x * s * rq));
         }
         psi = 2.0 / sq * I1;
-        dpsi = 2.0 / (sq * q0);
+        dpsi = q0 == 0 ? 2.0 / (sq * qa) : U(0.0);
         tp = 2.0 * s / (1.0 - u) * IT;
         return;
     }
     const int n = c >= 0.5 ? 20 : (c >= 0.2 ? 24 : (c >= 0.05 ? 32 : (c >= 1e-3 ? 48 : 64)));
     gl_rule(S, n, gx, gw);
-    U A = c / (s * sqrt(q0));
+    U A = c / (s * sqrt(qa));
     U L = asinh(1.0 / A);
     const U w = u / (1.0 - u);        // q(x) = 2 - x^2 - w (1 - x^2)^2
     const U hA = 0.5 * A, hAL = 0.5 * A * L;
     const double s2 = s * s, c2 = c * c;
     U I1 = U(0.0), I3 = U(0.0), IT = U(0.0);
-    for (int q = 0; q < n; ++q) {
+    for (int q = q0; q < n; q += qs) {
         U ex = exp(L * gx[q]);
         U iex = 1.0 / ex;
         U x = hA * (ex - iex);
@@ -126,7 +129,7 @@ __device__ void bend_out(const DevSpec &S, const U &u, double alpha, U &psi, U &
 
 // psi(v, pi/2), c dt_p/R (v, pi/2) and their v-derivatives (periastron leg)
 template <class U>
-__device__ void grazing(const DevSpec &S, const U &v, U &ph, U &dph, U &th, U &dth)
+__device__ void grazing(const DevSpec &S, const U &v, U &ph, U &dph, U &th, U &dth, int q0 = 0, int qs = 1)
 {
     U J = U(0.0), J3 = U(0.0), K = U(0.0), K1 = U(0.0);
     const double *gx, *gw;
@@ -137,7 +140,7 @@ __device__ void grazing(const DevSpec &S, const U &v, U &ph, U &dph, U &th, U &d
     const int n = vv <= 0.6 ? 20 : (vv <= 0.64 ? 24 : (vv <= 0.66 ? 32 : 48));
     gl_rule(S, n, gx, gw);
     const U vw = v / (1.0 - v);
-    for (int q = 0; q < n; ++q) {
+    for (int q = q0; q < n; q += qs) {
         double x = gx[q], w = gw[q];
         double t = 1.0 - x * x, tt = t * t;
         U Q = 2.0 - x * x - vw * tt;

@@ -22,6 +22,8 @@
 
 namespace ppm {
 
+constexpr int kTableSplit = 8;   // lanes per deflection-table node in k_table
+
 // ---------------------------------------------------------------------------
 // parameter validation (host and device share these rules)
 // ---------------------------------------------------------------------------
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(64) void k_setup(DevSpec S, const double *params, c
 // sqrt(q0)), which resolves the boundary layer of width ~cos(alpha) at
 // x -> 0 for near-grazing rays.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_table(DevSpec S, const int32_t *list, const StarRec *stars, const RingRec *rings, double4 *table)
+__global__ __launch_bounds__(256) void k_table(DevSpec S, const int32_t *list, const StarRec *stars, const RingRec *rings, double4 *table)
 {
     const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
     const RingRec g = rings[(size_t)b * S.R_tot + r];
@@ -176,39 +178,54 @@ __global__ __launch_bounds__(64) void k_table(DevSpec S, const int32_t *list, co
     const double u = g.u;
     const double dal = g.alpha_max / (S.n_alpha - 1);
     double4 *tab = table + ((size_t)b * S.R_tot + r) * S.n_alpha;
-    for (int j = blockIdx.y * blockDim.x + threadIdx.x; j < S.n_alpha; j += gridDim.y * blockDim.x) {
-        double a = dal * j;
-        if (j == S.n_alpha - 1) a = g.alpha_max;
-        double psi, dpsi, T, dT;
-        if (a <= kHalfPi) {
-            double tp;
-            bend_out(S, u, a, psi, dpsi, tp);
-            T = tp + g.cdt_obl;
-            dT = dpsi * sin(a) / g.sq1u;          // d(c dt)/d psi = b (impact parameter)
-        } else {
-            // inward ray through a periastron at rho R (Eqs. 13, 14, 17)
-            double be = kPi - a;
-            double psb, dpsb, tpb;
-            bend_out(S, u, be, psb, dpsb, tpb);
-            double sa = sin(a), ca = cos(a);
-            double kk = sqrt(3.0 * (1.0 - u));
-            double arg = 3.0 * u * kk / (2.0 * sa);
-            if (arg > 1.0) arg = 1.0;
-            double rho = -2.0 * sa / kk * cos((acos(arg) + kTwoPi) / 3.0);
-            double k = sa * sa / (1.0 - u), kp = 2.0 * sa * ca / (1.0 - u);
-            double rhop = kp * (rho - u) / (3.0 * rho * rho - k);
-            double v = u / rho, vp = -u * rhop / (rho * rho);
-            double ph, dph, th, dth;
-            grazing(S, v, ph, dph, th, dth);
-            psi = 2.0 * ph - psb;
-            dpsi = 2.0 * dph * vp + dpsb;
-            double Rp = rho * g.R;
-            double cdtp = cdt_oblate(st.Re, st.Rs, Rp) / g.R;
-            T = 2.0 * rho * th - tpb + 2.0 * cdtp - g.cdt_obl;
-            double dtpb = dpsb * sin(be) / g.sq1u;
-            dT = 2.0 * rhop * th + 2.0 * rho * dth * vp + dtpb - 2.0 * rhop * rho / (rho - u);
+    // kTableSplit lanes per node, each summing every kTableSplit-th quadrature
+    // node; the lanes' results add up to the node's values
+    const int kq = threadIdx.x % kTableSplit;
+    const int per_block = blockDim.x / kTableSplit;
+    for (int j0 = blockIdx.y * per_block; j0 < S.n_alpha; j0 += gridDim.y * per_block) {
+        const int j = j0 + (int)threadIdx.x / kTableSplit;
+        double psi = 0.0, dpsi = 0.0, T = 0.0, dT = 0.0;
+        if (j < S.n_alpha) {
+            double a = dal * j;
+            if (j == S.n_alpha - 1) a = g.alpha_max;
+            const bool lead = kq == 0;
+            if (a <= kHalfPi) {
+                double tp;
+                bend_out(S, u, a, psi, dpsi, tp, kq, kTableSplit);
+                T = tp + (lead ? g.cdt_obl : 0.0);
+                dT = dpsi * sin(a) / g.sq1u;          // d(c dt)/d psi = b (impact parameter)
+            } else {
+                // inward ray through a periastron at rho R (Eqs. 13, 14, 17)
+                double be = kPi - a;
+                double psb, dpsb, tpb;
+                bend_out(S, u, be, psb, dpsb, tpb, kq, kTableSplit);
+                double sa = sin(a), ca = cos(a);
+                double kk = sqrt(3.0 * (1.0 - u));
+                double arg = 3.0 * u * kk / (2.0 * sa);
+                if (arg > 1.0) arg = 1.0;
+                double rho = -2.0 * sa / kk * cos((acos(arg) + kTwoPi) / 3.0);
+                double k = sa * sa / (1.0 - u), kp = 2.0 * sa * ca / (1.0 - u);
+                double rhop = kp * (rho - u) / (3.0 * rho * rho - k);
+                double v = u / rho, vp = -u * rhop / (rho * rho);
+                double ph, dph, th, dth;
+                grazing(S, v, ph, dph, th, dth, kq, kTableSplit);
+                psi = 2.0 * ph - psb;
+                dpsi = 2.0 * dph * vp + dpsb;
+                double Rp = rho * g.R;
+                double cdtp = cdt_oblate(st.Re, st.Rs, Rp) / g.R;
+                T = 2.0 * rho * th - tpb + (lead ? 2.0 * cdtp - g.cdt_obl : 0.0);
+                double dtpb = dpsb * sin(be) / g.sq1u;
+                dT = 2.0 * rhop * th + 2.0 * rho * dth * vp + dtpb - (lead ? 2.0 * rhop * rho / (rho - u) : 0.0);
+            }
         }
-        tab[j] = make_double4(psi, dpsi, T, dT);
+#pragma unroll
+        for (int o = 1; o < kTableSplit; o <<= 1) {
+            psi += __shfl_xor(psi, o, 64);
+            dpsi += __shfl_xor(dpsi, o, 64);
+            T += __shfl_xor(T, o, 64);
+            dT += __shfl_xor(dT, o, 64);
+        }
+        if (j < S.n_alpha && kq == 0) tab[j] = make_double4(psi, dpsi, T, dT);
     }
 }
 
@@ -1137,8 +1154,9 @@ void launch_setup(const DevSpec &S, const Workspace &W, const double *params, co
 
 void launch_table_trace(const DevSpec &S, const Workspace &W, const int32_t *list, int n_list, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_table, dim3(n_list, (S.n_alpha + 63) / 64), dim3(64), 0, st, S, list, W.stars, W.rings,
-                       W.table);
+    const int nodes_per_block = 256 / kTableSplit;
+    hipLaunchKernelGGL(k_table, dim3(n_list, (S.n_alpha + nodes_per_block - 1) / nodes_per_block), dim3(256), 0, st, S,
+                       list, W.stars, W.rings, W.table);
     size_t lds_tr = sizeof(double4) * (S.n_alpha + S.n_fp + 1);
     hipLaunchKernelGGL(k_trace, dim3(n_list), dim3(256), lds_tr, st, S, list, W.stars, W.rings, W.table,
                        W.trace, W.sub);
