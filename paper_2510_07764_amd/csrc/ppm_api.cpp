@@ -345,7 +345,7 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         S.ax_mu = pl->upload(sp->ax_mu, S.nmu);
     }
     // workspace: per-instance outputs for max_batch instances, ring-level
-    // scratch for `chunk` instances (a 16 GiB budget bounds the chunk)
+    // scratch for `chunk` instances (a 64 GiB budget of the 288 GB bounds the chunk)
     Workspace &W = pl->W;
     std::memset(&W, 0, sizeof(W));
     const size_t R = S.R_tot;
@@ -362,7 +362,7 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         size_t per_inst = per_ring * R + sizeof(double) * (size_t)S.P * S.E
                         + (sp->grad ? (sizeof(double) + sizeof(float)) * (size_t)S.P * S.E : 0)
                         + (map_plan ? sizeof(MapCell) * (size_t)S.n_pix : 0);
-        size_t budget = (size_t)16 << 30;
+        size_t budget = (size_t)64 << 30;
         size_t c = budget / per_inst;
         if (c < 1) c = 1;
         // PPM_MAX_CHUNK caps the instances per workspace pass (tests use it to
