@@ -44,10 +44,10 @@ PEAK_FP32_TFLOPS = 157.3
 # kernel sources the counters were taken on and for the tiles listed; any
 # other case reports null until the counters are taken again.
 KERNEL_SOURCES = ("ppm_kernels.hip", "ppm_device.h", "ppm_dual.h", "ppm_internal.h", "ppm_launch.h")
-TRAFFIC = {"sources_sha256": "0a133ba7fad0db37b570c4c81d38c4540b5948e9de15cf8eb08e88bcb5484237",
+TRAFFIC = {"sources_sha256": "10559f9747c7dd5fbdc10a1b6c2e3805fa3fab51bd9a5e6107e34790ca806f6a",
            "fetch_scale": 1.99980, "write_scale": 1.0,
            # phase tile -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-           "by_tile": {8: (4284.38, 33198.96), 12: (4284.20, 33071.07)},
+           "by_tile": {8: (4288.45, 33198.96), 12: (4288.30, 33071.07)},
            "profile": "profiles/k_accum_fast_config1_traffic.md"}
 
 
