@@ -232,8 +232,8 @@ int ppm_get_tiles(const ppm_plan *plan, ppm_tiles *out);
 int ppm_set_tiles(ppm_plan *plan, const ppm_tiles *tiles);
 
 /* Autotuner of the launch shape.  For each candidate phase tile (forward:
- * 4, 8, 12, 16, 20, 24, 28, 32, 48, 64; adjoint, gradient plans only: 8, 16, 24,
- * 32;
+ * 4, 8, 12, 16, 20, 24, 28, 32, 48, 64, 96, 128; adjoint, gradient plans only: 8,
+ * 16, 24, 32;
  * a candidate that gives the same number of tiles over n_phase as a smaller
  * one is skipped) it times whole evaluations of the given batch (params_dev,
  * B, n_cells_host as for ppm_forward): one warm-up call, then `reps` calls

@@ -797,7 +797,7 @@ int ppm_autotune(ppm_plan *pl, const double *params_dev, int B, const int32_t *n
     // forward tile
     double best = 0.0;
     int best_t = pt0;
-    for (int t : tile_candidates({4, 8, 12, 16, 20, 24, 28, 32, 48, 64}, S.P)) {
+    for (int t : tile_candidates({4, 8, 12, 16, 20, 24, 28, 32, 48, 64, 96, 128}, S.P)) {
         S.pt_fwd = t;
         double ms = 0.0;
         rc = median_ms([&](const char **what) {

@@ -610,9 +610,11 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
 
 // ---------------------------------------------------------------------------
 // k_accum_fast: shift-and-add with the mixed-order atmosphere table (Eq. 47),
-// windowed formulation.  Block = (ring, tile of PT phases), 4 waves; a wave
-// owns one phase at a time and EPL consecutive energies per lane (FP32
-// accumulators in registers, fixed summation order over cells).
+// windowed formulation.  Block = (ring, tile of PT phases), NW waves; a wave
+// owns one phase at a time and EPL energies per lane, 64 apart (FP32
+// accumulators in registers, fixed summation order over cells; neighbouring
+// lanes then read neighbouring or equal interval quads, which keeps the quad
+// reads free of LDS bank conflicts).
 //  stage A  lane = cell: FP64 observed-phase lookup (Eqs. 45-46), mu
 //           weights (cubic Lagrange; linear in the protected small-mu zone
 //           and the last interval) pre-scaled by F_p, and the x position
@@ -714,9 +716,10 @@ __device__ __forceinline__ void pairs_general(uint64_t mask, float w0, float w1,
     }
 }
 
-template <int EPL>
-__global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const int32_t *list, const RingRec *rings, const double4 *trace,
-                                                    const float *sub, float *partial, int32_t *vis_pairs, int PT, int n_list)
+template <int EPL, int NW>
+__global__ __launch_bounds__(64 * NW, NW == 8 ? 6 : 4) void k_accum_fast(DevSpec S, const int32_t *list, const RingRec *rings,
+                                                    const double4 *trace, const float *sub, float *partial,
+                                                    int32_t *vis_pairs, int PT, int n_list)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     int li, tile;
@@ -728,9 +731,9 @@ __global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const int32_t *li
     double4 *tr = (double4 *)lds_raw;                          // nfp + 1
     double *axmu = (double *)(tr + nfp + 1);                   // nmu (padded to 16 bytes)
     float *tab = (float *)(axmu + ((nmu + 1) & ~1));           // sub_stride, 16-byte aligned
-    float4 *Qb = (float4 *)(tab + S.sub_stride);               // 4 waves * 64 quads
-    float *Sb = (float *)(Qb + 4 * 64);                        // 4 waves * 68
-    double *po = (double *)(Sb + 4 * 68);                      // nfp + 1 phi_o, compact for the search
+    float4 *Qb = (float4 *)(tab + S.sub_stride);               // NW waves * 64 quads
+    float *Sb = (float *)(Qb + NW * 64);                       // NW waves * 68
+    double *po = (double *)(Sb + NW * 68);                     // nfp + 1 phi_o, compact for the search
     const double4 *gtr = trace + ((size_t)b * S.R_tot + r) * (nfp + 1);
     for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
         const double4 v = gtr[i];
@@ -755,14 +758,14 @@ __global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const int32_t *li
     float tbr[EPL];
 #pragma unroll
     for (int m = 0; m < EPL; ++m) {
-        int e = lane * EPL + m;
+        int e = lane + 64 * m;
         tbr[m] = e < E ? (float)((log10(S.energy[e]) - log10(S.energy[0])) * ihx) : 0.0f;
     }
     const double mu_lo = axmu[0], mu_hi = axmu[nmu - 1];
     const int xw0 = g.xw0, xw = g.xw;
     int npairs = 0;
     const int k_begin = tile * PT;
-    for (int kk = wave; kk < PT; kk += 4) {
+    for (int kk = wave; kk < PT; kk += NW) {
         const int k = k_begin + kk;
         if (k >= P) break;
         float acc[EPL];
@@ -841,23 +844,10 @@ __global__ __launch_bounds__(256) void k_accum_fast(DevSpec S, const int32_t *li
         }
         const double scale = g.w_cell * g.T * g.T * g.T;
         float *out = partial + (((size_t)b * S.R_tot + r) * P + k) * E;
-        if (EPL == 4 && (E & 3) == 0) {
-            // one 16-byte store per lane: whole cache lines, no read for ownership
-            const int e = lane * 4;
-            if (e < E) {
-                float4 v;
-                v.x = (float)(acc[0] * (scale / S.energy[e]));
-                v.y = (float)(acc[1 % EPL] * (scale / S.energy[e + 1]));
-                v.z = (float)(acc[2 % EPL] * (scale / S.energy[e + 2]));
-                v.w = (float)(acc[3 % EPL] * (scale / S.energy[e + 3]));
-                *(float4 *)(out + e) = v;
-            }
-        } else {
 #pragma unroll
-            for (int m = 0; m < EPL; ++m) {
-                int e = lane * EPL + m;
-                if (e < E) out[e] = (float)(acc[m] * (scale / S.energy[e]));
-            }
+        for (int m = 0; m < EPL; ++m) {
+            int e = lane + 64 * m;
+            if (e < E) out[e] = (float)(acc[m] * (scale / S.energy[e]));
         }
     }
     if (lane == 0 && npairs) atomicAdd(&vis_pairs[(size_t)b * S.R_tot + r], npairs);
@@ -1139,7 +1129,7 @@ size_t accum_table_lds(const DevSpec &S)
 {
     if (S.fast)
         return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
-             + sizeof(float) * S.sub_stride + sizeof(float4) * 4 * 64 + sizeof(float) * 4 * 68
+             + sizeof(float) * S.sub_stride + sizeof(float4) * kFwdWaves * 64 + sizeof(float) * kFwdWaves * 68
              + sizeof(double) * (S.n_fp + 1);
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * S.nmu + sizeof(float) * S.nmu * S.nx
          + sizeof(float) * 4 * S.nx;
@@ -1191,16 +1181,16 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
         int epl = (S.E + 63) / 64;
         if (S.fast) {
             if (epl <= 1)
-                hipLaunchKernelGGL(k_accum_fast<1>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
+                hipLaunchKernelGGL((k_accum_fast<1, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, list, W.rings, W.trace, W.sub,
                                    W.partial32, W.vis_pairs, PT, n_list);
             else if (epl <= 2)
-                hipLaunchKernelGGL(k_accum_fast<2>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
+                hipLaunchKernelGGL((k_accum_fast<2, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, list, W.rings, W.trace, W.sub,
                                    W.partial32, W.vis_pairs, PT, n_list);
             else if (epl <= 4)
-                hipLaunchKernelGGL(k_accum_fast<4>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
+                hipLaunchKernelGGL((k_accum_fast<4, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, list, W.rings, W.trace, W.sub,
                                    W.partial32, W.vis_pairs, PT, n_list);
             else
-                hipLaunchKernelGGL(k_accum_fast<8>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
+                hipLaunchKernelGGL((k_accum_fast<8, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, list, W.rings, W.trace, W.sub,
                                    W.partial32, W.vis_pairs, PT, n_list);
         } else if (epl <= 1)
             hipLaunchKernelGGL(k_accum_table<1>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,

@@ -41,6 +41,10 @@ constexpr int kPhaseTile = 8;    // default phases per block of the accumulation
 constexpr int kMinTileGrad = 8;  // smallest adjoint phase tile (sizes the per-block adjoint sums)
 constexpr int kMaxTile = 256;    // largest phase tile either kernel accepts
 constexpr int kGradAcc = 9;      // per-ring adjoint sums of the accumulation kernel
+#ifndef PPM_FWD_WAVES
+#define PPM_FWD_WAVES 8
+#endif
+constexpr int kFwdWaves = PPM_FWD_WAVES;  // waves per block of the forward accumulation kernel
 
 __host__ __device__ int validate_params(const double *p, int n_spots);
 

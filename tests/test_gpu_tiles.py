@@ -117,8 +117,8 @@ def test_autotune_picks_a_candidate_and_keeps_results(torch_dev):
     ref = plan.forward(q).cpu().numpy()
     rep = plan.autotune(q, reps=3)
     print("autotune report:", rep, flush=True)
-    # 32 phases: candidates 4, 8, 12, 16, 20, 24, 28, 32, 48, 64 give 8, 4, 3, 2, 2, 2, 2, 1, 1, 1
-    # tiles; those repeating a smaller candidate's count are dropped
+    # 32 phases: candidates 4, 8, 12, 16, 20, 24, 28, 32, 48, 64, 96, 128 give 8, 4, 3, 2, 2, 2, 2,
+    # 1, 1, 1, 1, 1 tiles; those repeating a smaller candidate's count are dropped
     assert sorted(rep["forward"]) == [4, 8, 12, 16, 32]
     assert sorted(rep["grad"]) == [8, 16, 32]
     assert all(v > 0 for v in rep["forward"].values()) and all(v > 0 for v in rep["grad"].values())
