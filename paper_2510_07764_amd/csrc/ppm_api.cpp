@@ -343,6 +343,33 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         for (size_t i = 0; i < n; ++i) lin[i] = (float)std::pow(10.0, sp->log_intensity[i]);
         S.atm = pl->upload(lin.data(), n);
         S.ax_mu = pl->upload(sp->ax_mu, S.nmu);
+        const double *a = sp->ax_mu;
+        const int nm = S.nmu;
+        std::vector<double> cf(4 * (size_t)nm, 0.0);
+        for (int lo = 0; lo < nm - 1; ++lo) {
+            double *c = &cf[4 * (size_t)lo];
+            if (lo < 3 || lo == nm - 2) {
+                c[0] = 1.0 / (a[lo + 1] - a[lo]);
+                continue;
+            }
+            const int m0 = lo - 1;
+            for (int q = 0; q < 4; ++q) {
+                double den = 1.0;
+                for (int s = 0; s < 4; ++s)
+                    if (s != q) den *= a[m0 + q] - a[m0 + s];
+                c[q] = 1.0 / den;
+            }
+        }
+        S.mu_coef = pl->upload(cf.data(), cf.size());
+        S.mu_nb = 4 * nm;
+        S.mu_ibw = S.mu_nb / (a[nm - 1] - a[0]);
+        std::vector<int16_t> mb(S.mu_nb);
+        for (int b = 0, l = 0; b < S.mu_nb; ++b) {
+            const double edge = a[0] + b / S.mu_ibw;
+            while (l < nm - 2 && a[l + 1] <= edge) ++l;
+            mb[b] = (int16_t)l;
+        }
+        S.mu_bucket = pl->upload(mb.data(), mb.size());
     }
     // workspace: per-instance outputs for max_batch instances, ring-level
     // scratch for `chunk` instances (a 64 GiB budget of the 288 GB bounds the chunk)
@@ -398,7 +425,7 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         }
         W.partial32 = pl->dalloc<float>(B * R * S.P * S.E);
         W.fold_in32 = pl->dalloc<float>(B * S.P * S.E);
-        ok = ok && W.partial32 && W.fold_in32 && S.atm && S.ax_mu;
+        ok = ok && W.partial32 && W.fold_in32 && S.atm && S.ax_mu && S.mu_coef && S.mu_bucket;
     } else {
         W.partial64 = pl->dalloc<double>(B * R * S.P * S.E);
         if (sp->precision == PPM_F64) {

@@ -50,6 +50,15 @@ struct DevSpec {
     const double *bkg;      // [P][C] background counts per bin (nullptr: none)
     const float *atm;       // [nT][ng][nmu][nx] linear I/T^3
     const double *ax_mu;    // [nmu]
+    // mu-axis lookup of the windowed kernel: per interval l (a_l <= mu < a_{l+1})
+    // the linear 1/(a_{l+1} - a_l) (l < 3, l = nmu - 2) or the four inverse
+    // denominators of the cubic Lagrange weights on nodes l-1 .. l+2; and
+    // mu_nb equal buckets over [a_0, a_{nmu-1}], each with the largest l
+    // whose node lies at or below the bucket's lower edge
+    const double *mu_coef;  // [nmu][4]
+    const int16_t *mu_bucket;   // [mu_nb]
+    int mu_nb;
+    double mu_ibw;          // mu_nb / (a_{nmu-1} - a_0)
     const double *glx, *glw;  // Gauss-Legendre on [0, 1], n_quad nodes
 };
 

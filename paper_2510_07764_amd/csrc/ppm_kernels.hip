@@ -734,6 +734,11 @@ __global__ __launch_bounds__(64 * NW, NW == 8 ? 6 : 4) void k_accum_fast(DevSpec
     float4 *Qb = (float4 *)(tab + S.sub_stride);               // NW waves * 64 quads
     float *Sb = (float *)(Qb + NW * 64);                       // NW waves * 68
     double *po = (double *)(Sb + NW * 68);                     // nfp + 1 phi_o, compact for the search
+    double *ipo = po + nfp + 1;                                // nfp: 1 / (phi_o[i+1] - phi_o[i])
+    double *mcf = ipo + nfp + 1;                               // nmu * 4 mu-interval coefficients
+    int16_t *pbk = (int16_t *)(mcf + 4 * nmu);                 // 2 nfp phase buckets
+    int16_t *mbk = pbk + 2 * nfp;                              // mu_nb mu buckets
+    const int n_pb = 2 * nfp;
     const double4 *gtr = trace + ((size_t)b * S.R_tot + r) * (nfp + 1);
     for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
         const double4 v = gtr[i];
@@ -741,10 +746,25 @@ __global__ __launch_bounds__(64 * NW, NW == 8 ? 6 : 4) void k_accum_fast(DevSpec
         po[i] = v.z;
     }
     for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
+    for (int i = threadIdx.x; i < 4 * nmu; i += blockDim.x) mcf[i] = S.mu_coef[i];
+    for (int i = threadIdx.x; i < S.mu_nb; i += blockDim.x) mbk[i] = S.mu_bucket[i];
     // per-ring stride is a multiple of 4 floats: 16-byte aligned rows of float4
     const float4 *gsub = (const float4 *)(sub + ((size_t)b * S.R_tot + r) * (size_t)S.sub_stride);
     float4 *tab4 = (float4 *)tab;
     for (int i = threadIdx.x; i < S.sub_stride / 4; i += blockDim.x) tab4[i] = gsub[i];
+    __syncthreads();
+    // phase buckets: bucket q covers phi_o[0] + [q, q + 1) / (2 nfp) and holds
+    // the largest i < nfp with phi_o[i] at or below its lower edge
+    for (int q = threadIdx.x; q < n_pb; q += blockDim.x) {
+        const double edge = po[0] + (double)q / n_pb;
+        int l0 = 0, h0 = nfp;
+        while (h0 - l0 > 1) {
+            int mid = (l0 + h0) >> 1;
+            if (po[mid] <= edge) l0 = mid; else h0 = mid;
+        }
+        pbk[q] = (int16_t)l0;
+    }
+    for (int i = threadIdx.x; i < nfp; i += blockDim.x) ipo[i] = 1.0 / (po[i + 1] - po[i]);
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -783,13 +803,14 @@ __global__ __launch_bounds__(64 * NW, NW == 8 ? 6 : 4) void k_accum_fast(DevSpec
                 if (!cell_masked(g, off)) {
                     double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
                     double php = (a - floor(a)) + phio0;                    // Eq. (45)
-                    int l0 = 0, h0 = nfp;                                   // Eq. (46)
-                    while (h0 - l0 > 1) {
-                        int mid = (l0 + h0) >> 1;
-                        if (po[mid] <= php) l0 = mid; else h0 = mid;
-                    }
+                    // Eq. (46): fine interval [phi_o[l0], phi_o[l0+1]) holding php, from
+                    // its bucket and a bounded scan (phi_o increases)
+                    int q = (int)((php - phio0) * n_pb);
+                    int l0 = pbk[q < n_pb - 1 ? q : n_pb - 1];
+                    while (l0 > 0 && po[l0] > php) --l0;
+                    while (l0 < nfp - 1 && po[l0 + 1] <= php) ++l0;
                     const double4 A = tr[l0], Cn = tr[l0 + 1];
-                    double wp = (php - A.z) / (Cn.z - A.z);
+                    double wp = (php - A.z) * ipo[l0];
                     wp = fmin(1.0, fmax(0.0, wp));
                     PhaseSample ps;
                     ps.F = A.x + wp * (Cn.x - A.x);
@@ -798,35 +819,37 @@ __global__ __launch_bounds__(64 * NW, NW == 8 ? 6 : 4) void k_accum_fast(DevSpec
                     if (ps.F != 0.0) {
                         vis = true;
                         double mu = fmin(mu_hi, fmax(mu_lo, ps.mu));
-                        int lo = 0, hi = nmu - 1;
-                        while (hi - lo > 1) {
-                            int mid = (lo + hi) >> 1;
-                            if (axmu[mid] <= mu) lo = mid; else hi = mid;
-                        }
-                        double w[4] = {0.0, 0.0, 0.0, 0.0};
+                        // mu interval [a_lo, a_lo+1) from its bucket and a bounded scan
+                        int qm = (int)((mu - mu_lo) * S.mu_ibw);
+                        int lo = mbk[qm < S.mu_nb - 1 ? qm : S.mu_nb - 1];
+                        while (lo > 0 && axmu[lo] > mu) --lo;
+                        while (lo < nmu - 2 && axmu[lo + 1] <= mu) ++lo;
+                        const double *cf = mcf + 4 * lo;
+                        double v0, v1, v2, v3;
                         if (lo < 3 || lo == nmu - 2) {
-                            double t = (mu - axmu[lo]) / (axmu[lo + 1] - axmu[lo]);
+                            // linear on [a_lo, a_lo+1]; node lo sits at slot lo - m0 of 0..2
+                            const double t = (mu - axmu[lo]) * cf[0];
                             m0 = lo < nmu - 4 ? lo : nmu - 4;
-                            w[lo - m0] = 1.0 - t;
-                            w[lo + 1 - m0] = t;
+                            const int sl = lo - m0;
+                            v0 = sl == 0 ? 1.0 - t : 0.0;
+                            v1 = sl == 0 ? t : (sl == 1 ? 1.0 - t : 0.0);
+                            v2 = sl == 1 ? t : (sl == 2 ? 1.0 - t : 0.0);
+                            v3 = sl == 2 ? t : 0.0;
                         } else {
+                            // cubic Lagrange on nodes lo-1 .. lo+2, inverse denominators cf
                             m0 = lo - 1;
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                double num = 1.0, den = 1.0;
-#pragma unroll
-                                for (int s2 = 0; s2 < 4; ++s2) {
-                                    if (s2 == q) continue;
-                                    num *= mu - axmu[m0 + s2];
-                                    den *= axmu[m0 + q] - axmu[m0 + s2];
-                                }
-                                w[q] = num / den;
-                            }
+                            const double d0 = mu - axmu[m0], d1 = mu - axmu[m0 + 1], d2 = mu - axmu[m0 + 2],
+                                         d3 = mu - axmu[m0 + 3];
+                            const double p01 = d0 * d1, p23 = d2 * d3;
+                            v0 = d1 * p23 * cf[0];
+                            v1 = d0 * p23 * cf[1];
+                            v2 = p01 * d3 * cf[2];
+                            v3 = p01 * d2 * cf[3];
                         }
-                        w0 = (float)(w[0] * ps.F);
-                        w1 = (float)(w[1] * ps.F);
-                        w2 = (float)(w[2] * ps.F);
-                        w3 = (float)(w[3] * ps.F);
+                        w0 = (float)(v0 * ps.F);
+                        w1 = (float)(v1 * ps.F);
+                        w2 = (float)(v2 * ps.F);
+                        w3 = (float)(v3 * ps.F);
                         double T0 = log10(ps.z) * ihx + tbk;
                         double fl = floor(T0);
                         I0 = (int)fl;
@@ -1130,7 +1153,8 @@ size_t accum_table_lds(const DevSpec &S)
     if (S.fast)
         return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
              + sizeof(float) * S.sub_stride + sizeof(float4) * kFwdWaves * 64 + sizeof(float) * kFwdWaves * 68
-             + sizeof(double) * (S.n_fp + 1);
+             + sizeof(double) * 2 * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
+             + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb);
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * S.nmu + sizeof(float) * S.nmu * S.nx
          + sizeof(float) * 4 * S.nx;
 }
