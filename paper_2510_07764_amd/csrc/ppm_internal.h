@@ -62,6 +62,15 @@ struct DevSpec {
     const double *glx, *glw;  // Gauss-Legendre on [0, 1], n_quad nodes
 };
 
+// LDS copy of a ring's sub-table in the windowed kernel: x-major, the nmu
+// values of one x node adjacent, node stride nmu | 1 (odd, so 64 lanes on
+// consecutive nodes hit distinct banks); floats, rounded up to 16 bytes
+__host__ __device__ inline int fast_tab_stride(int nmu) { return nmu | 1; }
+__host__ __device__ inline int fast_tab_floats(const DevSpec &S)
+{
+    return (fast_tab_stride(S.nmu) * S.W_max + 3) & ~3;
+}
+
 struct StarRec {
     double GM, Rs, Re, x, Obar, o2, g0, D, nu, si, ci, NH;
     int status;

@@ -635,7 +635,7 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
 // and last table interval: every interval is cubic, no selects.
 template <int EPL>
 __device__ __forceinline__ void pairs_interior(uint64_t mask, float w0, float w1, float w2, float w3, float fr,
-                                               int pk, int lane, const float *tab, int W, int xw0, float *Sw,
+                                               int pk, int lane, const float *tab, int W, int NMP, int xw0, float *Sw,
                                                float4 *Qw, const float (&tbr)[EPL], float (&acc)[EPL])
 {
     while (mask) {
@@ -648,8 +648,9 @@ __device__ __forceinline__ void pairs_interior(uint64_t mask, float w0, float w1
         // mu contraction at x node I0 - 1 + lane (columns past the window hold zeros)
         int col = pI0 - 1 + lane - xw0;
         col = col < W - 1 ? col : W - 1;
-        const float *t0 = tab + pm0 * W + col;
-        const float Sv = pw0 * t0[0] + pw1 * t0[W] + pw2 * t0[2 * W] + pw3 * t0[3 * W];
+        // 24-bit multiply-add on byte offsets (full-rate, unlike a 32-bit multiply)
+        const float *t0 = (const float *)((const char *)(tab + pm0) + __umul24((unsigned)col, 4u * NMP));
+        const float Sv = pw0 * t0[0] + pw1 * t0[1] + pw2 * t0[2] + pw3 * t0[3];
         Sw[lane] = Sv;
         wave_sync();
         const float s1 = Sw[lane + 1], s2 = Sw[lane + 2], s3 = Sw[lane + 3];
@@ -672,7 +673,7 @@ __device__ __forceinline__ void pairs_interior(uint64_t mask, float w0, float w1
 // leave the table (zero contribution).
 template <int EPL>
 __device__ __forceinline__ void pairs_general(uint64_t mask, float w0, float w1, float w2, float w3, float fr,
-                                              int I0, int m0, int lane, const float *tab, int W, int xw0, int xw,
+                                              int I0, int m0, int lane, const float *tab, int NMP, int xw0, int xw,
                                               int nx, float *Sw, float4 *Qw, const float (&tbr)[EPL],
                                               float (&acc)[EPL])
 {
@@ -685,8 +686,8 @@ __device__ __forceinline__ void pairs_general(uint64_t mask, float w0, float w1,
         const int col = pI0 - 1 + lane - xw0;
         float Sv = 0.0f;
         if (col >= 0 && col < xw) {
-            const float *t0 = tab + pm0 * W + col;
-            Sv = pw0 * t0[0] + pw1 * t0[W] + pw2 * t0[2 * W] + pw3 * t0[3 * W];
+            const float *t0 = (const float *)((const char *)(tab + pm0) + __umul24((unsigned)col, 4u * NMP));
+            Sv = pw0 * t0[0] + pw1 * t0[1] + pw2 * t0[2] + pw3 * t0[3];
         }
         Sw[lane] = Sv;
         wave_sync();
@@ -730,8 +731,9 @@ __global__ __launch_bounds__(64 * NW, NW == 8 ? 6 : 4) void k_accum_fast(DevSpec
     const int nfp = S.n_fp, nmu = S.nmu, nx = S.nx, E = S.E, P = S.P, W = S.W_max;
     double4 *tr = (double4 *)lds_raw;                          // nfp + 1
     double *axmu = (double *)(tr + nfp + 1);                   // nmu (padded to 16 bytes)
-    float *tab = (float *)(axmu + ((nmu + 1) & ~1));           // sub_stride, 16-byte aligned
-    float4 *Qb = (float4 *)(tab + S.sub_stride);               // NW waves * 64 quads
+    float *tab = (float *)(axmu + ((nmu + 1) & ~1));           // x-major sub-table, 16-byte aligned
+    const int NMP = fast_tab_stride(nmu);
+    float4 *Qb = (float4 *)(tab + fast_tab_floats(S));         // NW waves * 64 quads
     float *Sb = (float *)(Qb + NW * 64);                       // NW waves * 68
     double *po = (double *)(Sb + NW * 68);                     // nfp + 1 phi_o, compact for the search
     double *ipo = po + nfp + 1;                                // nfp: 1 / (phi_o[i+1] - phi_o[i])
@@ -748,10 +750,22 @@ __global__ __launch_bounds__(64 * NW, NW == 8 ? 6 : 4) void k_accum_fast(DevSpec
     for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
     for (int i = threadIdx.x; i < 4 * nmu; i += blockDim.x) mcf[i] = S.mu_coef[i];
     for (int i = threadIdx.x; i < S.mu_nb; i += blockDim.x) mbk[i] = S.mu_bucket[i];
-    // per-ring stride is a multiple of 4 floats: 16-byte aligned rows of float4
+    // the ring's sub-table ([nmu][W] in HBM, per-ring stride a multiple of 4
+    // floats) transposed into the x-major LDS layout
     const float4 *gsub = (const float4 *)(sub + ((size_t)b * S.R_tot + r) * (size_t)S.sub_stride);
-    float4 *tab4 = (float4 *)tab;
-    for (int i = threadIdx.x; i < S.sub_stride / 4; i += blockDim.x) tab4[i] = gsub[i];
+    for (int i = threadIdx.x; i < S.sub_stride / 4; i += blockDim.x) {
+        const float4 v = gsub[i];
+        const float vk[4] = {v.x, v.y, v.z, v.w};
+        int m = (4 * i) / W, c = 4 * i - m * W;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (m < nmu) tab[c * NMP + m] = vk[k];
+            if (++c == W) {
+                c = 0;
+                ++m;
+            }
+        }
+    }
     __syncthreads();
     // phase buckets: bucket q covers phi_o[0] + [q, q + 1) / (2 nfp) and holds
     // the largest i < nfp with phi_o[i] at or below its lower edge
@@ -861,9 +875,9 @@ __global__ __launch_bounds__(64 * NW, NW == 8 ? 6 : 4) void k_accum_fast(DevSpec
             npairs += __popcll(mask);
             // ---------------- stage B: the visible pairs one after another
             if (g.interior)
-                pairs_interior<EPL>(mask, w0, w1, w2, w3, fr, (I0 << 8) | m0, lane, tab, W, xw0, Sw, Qw, tbr, acc);
+                pairs_interior<EPL>(mask, w0, w1, w2, w3, fr, (I0 << 8) | m0, lane, tab, W, NMP, xw0, Sw, Qw, tbr, acc);
             else
-                pairs_general<EPL>(mask, w0, w1, w2, w3, fr, I0, m0, lane, tab, W, xw0, xw, nx, Sw, Qw, tbr, acc);
+                pairs_general<EPL>(mask, w0, w1, w2, w3, fr, I0, m0, lane, tab, NMP, xw0, xw, nx, Sw, Qw, tbr, acc);
         }
         const double scale = g.w_cell * g.T * g.T * g.T;
         float *out = partial + (((size_t)b * S.R_tot + r) * P + k) * E;
@@ -1152,7 +1166,7 @@ size_t accum_table_lds(const DevSpec &S)
 {
     if (S.fast)
         return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
-             + sizeof(float) * S.sub_stride + sizeof(float4) * kFwdWaves * 64 + sizeof(float) * kFwdWaves * 68
+             + sizeof(float) * fast_tab_floats(S) + sizeof(float4) * kFwdWaves * 64 + sizeof(float) * kFwdWaves * 68
              + sizeof(double) * 2 * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
              + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb);
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * S.nmu + sizeof(float) * S.nmu * S.nx
