@@ -718,7 +718,7 @@ __device__ __forceinline__ void pairs_general(uint64_t mask, float w0, float w1,
 }
 
 template <int EPL, int NW>
-__global__ __launch_bounds__(64 * NW, NW == 8 ? 6 : 4) void k_accum_fast(DevSpec S, const int32_t *list, const RingRec *rings,
+__global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec S, const int32_t *list, const RingRec *rings,
                                                     const double4 *trace, const float *sub, float *partial,
                                                     int32_t *vis_pairs, int PT, int n_list)
 {

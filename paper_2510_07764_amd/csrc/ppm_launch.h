@@ -42,7 +42,7 @@ constexpr int kMinTileGrad = 8;  // smallest adjoint phase tile (sizes the per-b
 constexpr int kMaxTile = 256;    // largest phase tile either kernel accepts
 constexpr int kGradAcc = 9;      // per-ring adjoint sums of the accumulation kernel
 #ifndef PPM_FWD_WAVES
-#define PPM_FWD_WAVES 8
+#define PPM_FWD_WAVES 12
 #endif
 constexpr int kFwdWaves = PPM_FWD_WAVES;  // waves per block of the forward accumulation kernel
 
