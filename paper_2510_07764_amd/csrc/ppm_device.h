@@ -110,17 +110,17 @@ __device__ void bend_out(const DevSpec &S, const U &u, double alpha, U &psi, U &
     U I1 = U(0.0), I3 = U(0.0), IT = U(0.0);
     for (int q = q0; q < n; q += qs) {
         U ex = exp(L * gx[q]);
-        U iex = 1.0 / ex;
+        U iex = rcp_nr(ex);
         U x = hA * (ex - iex);
         U dx = hAL * (ex + iex) * gw[q];
         U x2 = x * x, t = 1.0 - x2;
         U D = c2 + x2 * s2 * (2.0 - x2 - w * t * t);
-        U r = sqrt(D);
-        U ir = 1.0 / r;
+        U ir = rsqrt_nr(D);
+        U r = D * ir;
         U xr = x * ir * dx;
         I1 += xr;
         I3 += xr * ir * ir;
-        IT += xr / (1.0 + r);
+        IT += xr * rcp_nr(1.0 + r);
     }
     psi = 2.0 * s / sq * I1;
     dpsi = 2.0 * c / sq * I3;
@@ -144,12 +144,12 @@ __device__ void grazing(const DevSpec &S, const U &v, U &ph, U &dph, U &th, U &d
         double x = gx[q], w = gw[q];
         double t = 1.0 - x * x, tt = t * t;
         U Q = 2.0 - x * x - vw * tt;
-        U rq = sqrt(Q);
-        U irq = 1.0 / rq;
+        U irq = rsqrt_nr(Q);
+        U rq = Q * irq;
         J += w * irq;
         J3 += w * tt * (irq * irq * irq);
         U gq = rq + x * Q;
-        U igq = 1.0 / gq;
+        U igq = rcp_nr(gq);
         K += w * igq;
         K1 += w * (0.5 * irq + x) * tt * (igq * igq);
     }

@@ -190,6 +190,36 @@ template <int N> __device__ inline Dual<N> &operator+=(Dual<N> &a, const Dual<N>
 template <int N> __device__ inline Dual<N> &operator-=(Dual<N> &a, const Dual<N> &b) { return a = a - b; }
 template <int N> __device__ inline Dual<N> &operator*=(Dual<N> &a, const Dual<N> &b) { return a = a * b; }
 
+// 1/x and 1/sqrt(x) for positive finite x: the hardware estimate refined by
+// two Newton steps (within about an ulp of the correctly rounded result, at
+// half the instructions of an IEEE division or square root)
+__device__ inline double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ inline double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+template <int N> __device__ inline Dual<N> rcp_nr(const Dual<N> &a)
+{
+    const double r = rcp_nr(a.v);
+    return chain(a, r, -r * r);
+}
+template <int N> __device__ inline Dual<N> rsqrt_nr(const Dual<N> &a)
+{
+    const double y = rsqrt_nr(a.v);
+    return chain(a, y, -0.5 * y * y * y);
+}
+
 __device__ inline double value(double x) { return x; }
 template <int N> __device__ inline double value(const Dual<N> &x) { return x.v; }
 

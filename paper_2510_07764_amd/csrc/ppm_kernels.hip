@@ -22,7 +22,7 @@
 
 namespace ppm {
 
-constexpr int kTableSplit = 8;   // lanes per deflection-table node in k_table
+constexpr int kTableSplit = 2;   // lanes per deflection-table node in k_table
 
 // ---------------------------------------------------------------------------
 // parameter validation (host and device share these rules)
@@ -189,17 +189,20 @@ __global__ __launch_bounds__(256) void k_table(DevSpec S, const int32_t *list, c
             double a = dal * j;
             if (j == S.n_alpha - 1) a = g.alpha_max;
             const bool lead = kq == 0;
-            if (a <= kHalfPi) {
-                double tp;
-                bend_out(S, u, a, psi, dpsi, tp, kq, kTableSplit);
-                T = tp + (lead ? g.cdt_obl : 0.0);
-                dT = dpsi * sin(a) / g.sq1u;          // d(c dt)/d psi = b (impact parameter)
+            // one outgoing-ray quadrature per node: at alpha, or for an inward
+            // ray at pi - alpha (its outgoing leg from the periastron)
+            const bool inward = a > kHalfPi;
+            double psb, dpsb, tpb;
+            bend_out(S, u, inward ? kPi - a : a, psb, dpsb, tpb, kq, kTableSplit);
+            const double sa = sin(a);
+            if (!inward) {
+                psi = psb;
+                dpsi = dpsb;
+                T = tpb + (lead ? g.cdt_obl : 0.0);
+                dT = dpsb * sa / g.sq1u;               // d(c dt)/d psi = b (impact parameter)
             } else {
                 // inward ray through a periastron at rho R (Eqs. 13, 14, 17)
-                double be = kPi - a;
-                double psb, dpsb, tpb;
-                bend_out(S, u, be, psb, dpsb, tpb, kq, kTableSplit);
-                double sa = sin(a), ca = cos(a);
+                double ca = cos(a);
                 double kk = sqrt(3.0 * (1.0 - u));
                 double arg = 3.0 * u * kk / (2.0 * sa);
                 if (arg > 1.0) arg = 1.0;
@@ -214,7 +217,7 @@ __global__ __launch_bounds__(256) void k_table(DevSpec S, const int32_t *list, c
                 double Rp = rho * g.R;
                 double cdtp = cdt_oblate(st.Re, st.Rs, Rp) / g.R;
                 T = 2.0 * rho * th - tpb + (lead ? 2.0 * cdtp - g.cdt_obl : 0.0);
-                double dtpb = dpsb * sin(be) / g.sq1u;
+                double dtpb = dpsb * sa / g.sq1u;
                 dT = 2.0 * rhop * th + 2.0 * rho * dth * vp + dtpb - (lead ? 2.0 * rhop * rho / (rho - u) : 0.0);
             }
         }
