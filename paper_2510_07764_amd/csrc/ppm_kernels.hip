@@ -22,7 +22,8 @@
 
 namespace ppm {
 
-constexpr int kTableSplit = 2;   // lanes per deflection-table node in k_table
+constexpr int kTableSplit = 2;     // lanes per deflection-table node in k_table
+constexpr int kTraceThreads = 512; // threads per ring block of k_trace
 
 // ---------------------------------------------------------------------------
 // parameter validation (host and device share these rules)
@@ -290,14 +291,23 @@ __device__ static void subtable_ring(const DevSpec &S, const RingRec &g, int xw0
         // window [xw0, xw0 + W_max) of every mu row, row stride W_max
         const int W = S.W_max;
         float *out = sub + slot * (size_t)S.sub_stride;
-        for (int i = threadIdx.x; i < S.nmu * W; i += blockDim.x) {
-            int m = i / W, c = i - m * W;
-            float v = 0.0f;
-            if (c < xw) {
-                size_t o = (size_t)m * S.nx + xw0 + c;
-                v = w00 * s00[o] + w01 * s01[o] + w10 * s10[o] + w11 * s11[o];
+        // four elements per thread per round: sixteen independent loads in flight
+        const int n = S.nmu * W, step = blockDim.x;
+        for (int i0 = threadIdx.x; i0 < n; i0 += 4 * step) {
+            float v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int i = i0 + k * step;
+                const int m = i / W, c = i - m * W;
+                v[k] = 0.0f;
+                if (i < n && c < xw) {
+                    const size_t o = (size_t)m * S.nx + xw0 + c;
+                    v[k] = w00 * s00[o] + w01 * s01[o] + w10 * s10[o] + w11 * s11[o];
+                }
             }
-            out[i] = v;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (i0 + k * step < n) out[i0 + k * step] = v[k];
         }
         return;
     }
@@ -309,7 +319,7 @@ __device__ static void subtable_ring(const DevSpec &S, const RingRec &g, int xw0
 // ---------------------------------------------------------------------------
 // k_trace: pseudo-patch light curve of one ring (Sect. 2.8.3, Eqs. 38-44)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_trace(DevSpec S, const int32_t *list, const StarRec *stars, RingRec *rings, const double4 *table,
+__global__ __launch_bounds__(kTraceThreads) void k_trace(DevSpec S, const int32_t *list, const StarRec *stars, RingRec *rings, const double4 *table,
                         double4 *trace, float *sub)
 {
     extern __shared__ double4 lds_tab[];
@@ -412,7 +422,7 @@ __global__ __launch_bounds__(256) void k_trace(DevSpec S, const int32_t *list, c
         out[i] = v;
         if (v.y > 0.0) { zlo = fmin(zlo, v.y); zhi = fmax(zhi, v.y); }
     }
-    __shared__ double red_lo[4], red_hi[4];
+    __shared__ double red_lo[kTraceThreads / 64], red_hi[kTraceThreads / 64];
     __shared__ int sh_active, sh_w0, sh_w;
     // range of z over the block: wave butterflies, then the four waves
 #pragma unroll
@@ -999,11 +1009,13 @@ __global__ __launch_bounds__(256) void k_reduce(DevSpec S, const StarRec *stars,
 
 // FP32 partials with E % 4 == 0: a thread owns four consecutive energies and
 // reads them with 16-byte loads; eight ring groups per block.
-__global__ __launch_bounds__(512) void k_reduce4(DevSpec S, const StarRec *stars, const RingRec *rings,
+constexpr int kReduceGroups = 16;   // waves of k_reduce4, each summing every 16th ring
+
+__global__ __launch_bounds__(64 * kReduceGroups) void k_reduce4(DevSpec S, const StarRec *stars, const RingRec *rings,
                                                  const float *partial, double *flux, float *fold_in)
 {
     extern __shared__ unsigned char act[];
-    __shared__ double4 red[8][64];
+    __shared__ double4 red[kReduceGroups][64];
     const int k = blockIdx.x, b = blockIdx.z;
     const int E = S.E, P = S.P, R = S.R_tot;
     const int el = threadIdx.x & 63, grp = threadIdx.x >> 6;
@@ -1014,7 +1026,8 @@ __global__ __launch_bounds__(512) void k_reduce4(DevSpec S, const StarRec *stars
     if (e < E) {
         const float *base = partial + ((size_t)b * R * P + k) * E + e;
         const size_t rs = (size_t)P * E;
-        for (int r = grp; r < R; r += 8) {
+#pragma unroll 4
+        for (int r = grp; r < R; r += kReduceGroups) {
             if (!act[r]) continue;
             const float4 v = *(const float4 *)(base + r * rs);
             s0 += (double)v.x;
@@ -1027,7 +1040,7 @@ __global__ __launch_bounds__(512) void k_reduce4(DevSpec S, const StarRec *stars
     __syncthreads();
     if (grp == 0 && e < E) {
         double t[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int g2 = 0; g2 < 8; ++g2) {
+        for (int g2 = 0; g2 < kReduceGroups; ++g2) {
             const double4 v = red[g2][el];
             t[0] += v.x; t[1] += v.y; t[2] += v.z; t[3] += v.w;
         }
@@ -1189,7 +1202,7 @@ void launch_table_trace(const DevSpec &S, const Workspace &W, const int32_t *lis
     hipLaunchKernelGGL(k_table, dim3(n_list, (S.n_alpha + nodes_per_block - 1) / nodes_per_block), dim3(256), 0, st, S,
                        list, W.stars, W.rings, W.table);
     size_t lds_tr = sizeof(double4) * (S.n_alpha + S.n_fp + 1);
-    hipLaunchKernelGGL(k_trace, dim3(n_list), dim3(256), lds_tr, st, S, list, W.stars, W.rings, W.table,
+    hipLaunchKernelGGL(k_trace, dim3(n_list), dim3(kTraceThreads), lds_tr, st, S, list, W.stars, W.rings, W.table,
                        W.trace, W.sub);
 }
 
@@ -1198,7 +1211,7 @@ void launch_reduce_fold32(const DevSpec &S, const Workspace &W, int B, hipStream
                           double *counts_out)
 {
     if ((S.E & 3) == 0)
-        hipLaunchKernelGGL(k_reduce4, dim3(S.P, (S.E + 255) / 256, B), dim3(512), S.R_tot, st, S, W.stars,
+        hipLaunchKernelGGL(k_reduce4, dim3(S.P, (S.E + 255) / 256, B), dim3(64 * kReduceGroups), S.R_tot, st, S, W.stars,
                            W.rings, W.partial32, flux_out, W.fold_in32);
     else
         hipLaunchKernelGGL((k_reduce<float, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S,
