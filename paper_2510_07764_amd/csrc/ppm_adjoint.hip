@@ -494,7 +494,7 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
     float tbr[EPL];
 #pragma unroll
     for (int m = 0; m < EPL; ++m) {
-        int e = lane * EPL + m;
+        int e = lane + 64 * m;     // energies 64 apart: neighbouring lanes read neighbouring quads
         tbr[m] = e < E ? (float)((log10(S.energy[e]) - log10(S.energy[0])) * ihx) : 0.0f;
     }
     const double mu_lo = axmu[0], mu_hi = axmu[nmu - 1];
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
         float Gr[EPL];
 #pragma unroll
         for (int m = 0; m < EPL; ++m) {
-            int e = lane * EPL + m;
+            int e = lane + 64 * m;
             Gr[m] = e < E ? gtil[((size_t)b * P + k) * E + e] : 0.0f;
         }
         const double Phik = (k + 0.5) / P;
