@@ -466,6 +466,11 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
     float4 *Nb = (float4 *)(tab + S.sub_stride);               // kAdjWaves * 68 node values
     float4 *Qb = Nb + kAdjWaves * 68;                          // kAdjWaves * 4 * 64 quads
     double *po = (double *)(Qb + kAdjWaves * 4 * 64);          // nfp + 1 phi_o, compact for the search
+    double *ipo = po + nfp + 1;                                // nfp: 1 / (phi_o[i+1] - phi_o[i])
+    double *mcf = ipo + nfp + 1;                               // nmu * 4 mu-interval coefficients
+    int16_t *pbk = (int16_t *)(mcf + 4 * nmu);                 // 2 nfp phase buckets
+    int16_t *mbk = pbk + 2 * nfp;                              // mu_nb mu buckets
+    const int n_pb = 2 * nfp;
     const double4 *tg = tangent + slot * (size_t)(nfp + 1) * 5;   // read through the caches in stage C
     const float2 *tab2 = subtg + slot * (size_t)S.sub_stride;      // logT / log g planes, read through L2
     {
@@ -476,10 +481,24 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
             po[i] = v.z;
         }
         for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
+        for (int i = threadIdx.x; i < 4 * nmu; i += blockDim.x) mcf[i] = S.mu_coef[i];
+        for (int i = threadIdx.x; i < S.mu_nb; i += blockDim.x) mbk[i] = S.mu_bucket[i];
         const float4 *gs = (const float4 *)(sub + slot * (size_t)S.sub_stride);
         float4 *ts = (float4 *)tab;
         for (int i = threadIdx.x; i < S.sub_stride / 4; i += blockDim.x) ts[i] = gs[i];
     }
+    __syncthreads();
+    // phase buckets and inverse spacings of phi_o, as in the forward kernel
+    for (int q = threadIdx.x; q < n_pb; q += blockDim.x) {
+        const double edge = po[0] + (double)q / n_pb;
+        int l0 = 0, h0 = nfp;
+        while (h0 - l0 > 1) {
+            int mid = (l0 + h0) >> 1;
+            if (po[mid] <= edge) l0 = mid; else h0 = mid;
+        }
+        pbk[q] = (int16_t)l0;
+    }
+    for (int i = threadIdx.x; i < nfp; i += blockDim.x) ipo[i] = 1.0 / (po[i + 1] - po[i]);
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -527,13 +546,12 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
                 if (!cell_masked(g, off)) {
                     double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
                     double php = (a - floor(a)) + phio0;                    // Eq. (45)
-                    int l0 = 0, h0 = nfp;
-                    while (h0 - l0 > 1) {
-                        int mid = (l0 + h0) >> 1;
-                        if (po[mid] <= php) l0 = mid; else h0 = mid;
-                    }
+                    int q = (int)((php - phio0) * n_pb);                   // bucket, bounded scan
+                    int l0 = pbk[q < n_pb - 1 ? q : n_pb - 1];
+                    while (l0 > 0 && po[l0] > php) --l0;
+                    while (l0 < nfp - 1 && po[l0 + 1] <= php) ++l0;
                     const double4 A = tr[l0], Cn = tr[l0 + 1];
-                    double w = (php - A.z) / (Cn.z - A.z);
+                    double w = (php - A.z) * ipo[l0];
                     w = fmin(1.0, fmax(0.0, w));
                     const double Fp = A.x + w * (Cn.x - A.x);                // Eq. (46)
                     if (Fp != 0.0) {
@@ -545,40 +563,44 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
                         const double mup = A.w + w * (Cn.w - A.w);
                         mu_clamped = !(mup > mu_lo && mup < mu_hi);
                         const double mu = fmin(mu_hi, fmax(mu_lo, mup));
-                        int ml = 0, mh = nmu - 1;
-                        while (mh - ml > 1) {
-                            int mid = (ml + mh) >> 1;
-                            if (axmu[mid] <= mu) ml = mid; else mh = mid;
-                        }
-                        double wv[4] = {0.0, 0.0, 0.0, 0.0}, dv[4] = {0.0, 0.0, 0.0, 0.0};
+                        int qm = (int)((mu - mu_lo) * S.mu_ibw);               // bucket, bounded scan
+                        int ml = mbk[qm < S.mu_nb - 1 ? qm : S.mu_nb - 1];
+                        while (ml > 0 && axmu[ml] > mu) --ml;
+                        while (ml < nmu - 2 && axmu[ml + 1] <= mu) ++ml;
+                        const double *cf = mcf + 4 * ml;
+                        double wa, wb, wc, wd, da, db, dc, dd;
                         if (ml < 3 || ml == nmu - 2) {
-                            const double hmu = axmu[ml + 1] - axmu[ml];
-                            const double t = (mu - axmu[ml]) / hmu;
+                            // linear on [a_ml, a_ml+1]; node ml at slot ml - m0 of 0..2
+                            const double ih = cf[0];
+                            const double t = (mu - axmu[ml]) * ih;
                             m0 = ml < nmu - 4 ? ml : nmu - 4;
-                            wv[ml - m0] = 1.0 - t;
-                            wv[ml + 1 - m0] = t;
-                            dv[ml - m0] = -1.0 / hmu;
-                            dv[ml + 1 - m0] = 1.0 / hmu;
+                            const int sl = ml - m0;
+                            wa = sl == 0 ? 1.0 - t : 0.0;
+                            wb = sl == 0 ? t : (sl == 1 ? 1.0 - t : 0.0);
+                            wc = sl == 1 ? t : (sl == 2 ? 1.0 - t : 0.0);
+                            wd = sl == 2 ? t : 0.0;
+                            da = sl == 0 ? -ih : 0.0;
+                            db = sl == 0 ? ih : (sl == 1 ? -ih : 0.0);
+                            dc = sl == 1 ? ih : (sl == 2 ? -ih : 0.0);
+                            dd = sl == 2 ? ih : 0.0;
                         } else {
+                            // cubic Lagrange on nodes ml-1 .. ml+2 and its mu derivative
                             m0 = ml - 1;
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                double num = 1.0, den = 1.0, dnum = 0.0;
-#pragma unroll
-                                for (int s2 = 0; s2 < 4; ++s2) {
-                                    if (s2 == q) continue;
-                                    const double fac = mu - axmu[m0 + s2];
-                                    dnum = dnum * fac + num;       // product rule, running
-                                    num *= fac;
-                                    den *= axmu[m0 + q] - axmu[m0 + s2];
-                                }
-                                wv[q] = num / den;
-                                dv[q] = dnum / den;
-                            }
+                            const double d0 = mu - axmu[m0], d1 = mu - axmu[m0 + 1], d2 = mu - axmu[m0 + 2],
+                                         d3 = mu - axmu[m0 + 3];
+                            const double p01 = d0 * d1, p23 = d2 * d3, s01 = d0 + d1, s23 = d2 + d3;
+                            wa = d1 * p23 * cf[0];
+                            wb = d0 * p23 * cf[1];
+                            wc = p01 * d3 * cf[2];
+                            wd = p01 * d2 * cf[3];
+                            da = (p23 + d1 * s23) * cf[0];
+                            db = (p23 + d0 * s23) * cf[1];
+                            dc = (p01 + d3 * s01) * cf[2];
+                            dd = (p01 + d2 * s01) * cf[3];
                         }
-                        if (mu_clamped) dv[0] = dv[1] = dv[2] = dv[3] = 0.0;
-                        w0 = (float)wv[0]; w1 = (float)wv[1]; w2 = (float)wv[2]; w3 = (float)wv[3];
-                        v0 = (float)dv[0]; v1 = (float)dv[1]; v2 = (float)dv[2]; v3 = (float)dv[3];
+                        if (mu_clamped) da = db = dc = dd = 0.0;
+                        w0 = (float)wa; w1 = (float)wb; w2 = (float)wc; w3 = (float)wd;
+                        v0 = (float)da; v1 = (float)db; v2 = (float)dc; v3 = (float)dd;
                         const double T0 = log10(zp) * ihx + tbk;
                         const double fl = floor(T0);
                         I0 = (int)fl;
@@ -758,7 +780,8 @@ size_t accum_adj_lds(const DevSpec &S)
 {
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
          + sizeof(float) * S.sub_stride + sizeof(float4) * kAdjWaves * 68
-         + sizeof(float4) * kAdjWaves * 4 * 64 + sizeof(double) * (S.n_fp + 1);
+         + sizeof(float4) * kAdjWaves * 4 * 64 + sizeof(double) * 2 * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
+         + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb);
 }
 
 hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev,
