@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_map_sort(DevSpec S, const int32_t *list
 
 // ---------------------------------------------------------------------------
 // k_accum_map: block = (ring, 8 KPW output phases), 8 waves, wave w owns
-// phases 8 KPW tile + w + 8 q (q < KPW) and EPL consecutive energies per
+// phases 8 KPW tile + w + 8 q (q < KPW) and EPL energies, 64 apart, per
 // lane; the staged slabs of a bucket serve all of the block's phases.  Per
 // temperature bucket (logT nodes it, it + 1 after clamping):
 //   staging  sl0, sl1 = table slabs at logT nodes it and it + 1, linear in
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     float tbr[EPL];
 #pragma unroll
     for (int m = 0; m < EPL; ++m) {
-        int e = lane * EPL + m;
+        int e = lane + 64 * m;     // energies 64 apart: neighbouring lanes read neighbouring quads
         tbr[m] = e < E ? (float)((log10(S.energy[e]) - log10(S.energy[0])) * ihx) : 0.0f;
     }
     const double mu_lo = S.ax_mu[0], mu_hi = S.ax_mu[nmu - 1];
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
         float *out = partial + (slot * P + k) * E;
 #pragma unroll
         for (int m = 0; m < EPL; ++m) {
-            int e = lane * EPL + m;
+            int e = lane + 64 * m;
             if (e < E) out[e] = (float)(acc[kq][m] * (scale / S.energy[e]));
         }
     }
