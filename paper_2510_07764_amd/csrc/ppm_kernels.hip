@@ -53,63 +53,91 @@ __host__ __device__ int validate_params(const double *p, int n_spots)
 // for a temperature-map plan the HEALPix rings of the whole surface
 // (Sect. 2.8.1; patch solid angle pi / (3 n_side^2))
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_setup(DevSpec S, const double *params, const int32_t *n_cells, StarRec *stars,
+__device__ inline StarRec make_star(const DevSpec &S, const double *p)
+{
+    StarRec s;
+    s.status = validate_params(p, S.n_side > 0 ? 0 : S.n_spots);
+    s.GM = p[0] * kGMsun;
+    s.Re = p[1] * 1e5;
+    s.Rs = 2.0 * s.GM / (kC * kC);
+    s.x = s.GM / (kC * kC * s.Re);
+    s.Obar = kTwoPi * p[5] * sqrt(s.Re * s.Re * s.Re / s.GM);
+    s.o2 = (S.mode == PPM_MODE_OS) ? s.Obar * s.Obar * (-0.788 + 1.030 * s.x) : 0.0;
+    s.g0 = s.GM / (s.Re * s.Re) / sqrt(1.0 - s.Rs / s.Re);
+    s.D = p[6] * kPc;
+    s.nu = p[5];
+    s.si = sin(p[2]);
+    s.ci = cos(p[2]);
+    s.NH = p[4] * 1e20;
+    s.pad = 0;
+    return s;
+}
+
+// Block = 64 rings, four waves; lane = ring.  The waves share a ring's
+// transcendental work, each on its own SIMD: wave 0 the shape and velocity
+// chain (Eqs. 2, 3, 7, 18) and the ray limits, wave 1 the outer arc
+// half-width, wave 2 the inner one and the crescent mask radius, wave 3 the
+// colatitude band, surface gravity (Eqs. 10, 11) and temperature; wave 0
+// takes the others' results from LDS and writes the record.  Every thread
+// evaluates the star record itself (identical values).
+__global__ __launch_bounds__(256) void k_setup(DevSpec S, const double *params, const int32_t *n_cells, StarRec *stars,
                         RingRec *rings, int32_t *vis_pairs)
 {
     const int b = blockIdx.y;
-    const double *p = params + (size_t)b * PPM_NPARAM;
-    __shared__ StarRec st;
-    if (threadIdx.x == 0) {
-        StarRec s;
-        s.status = validate_params(p, S.n_side > 0 ? 0 : S.n_spots);
-        s.GM = p[0] * kGMsun;
-        s.Re = p[1] * 1e5;
-        s.Rs = 2.0 * s.GM / (kC * kC);
-        s.x = s.GM / (kC * kC * s.Re);
-        s.Obar = kTwoPi * p[5] * sqrt(s.Re * s.Re * s.Re / s.GM);
-        s.o2 = (S.mode == PPM_MODE_OS) ? s.Obar * s.Obar * (-0.788 + 1.030 * s.x) : 0.0;
-        s.g0 = s.GM / (s.Re * s.Re) / sqrt(1.0 - s.Rs / s.Re);
-        s.D = p[6] * kPc;
-        s.nu = p[5];
-        s.si = sin(p[2]);
-        s.ci = cos(p[2]);
-        s.NH = p[4] * 1e20;
-        s.pad = 0;
-        st = s;
-        if (blockIdx.x == 0) stars[b] = s;
-    }
-    __syncthreads();
+    // the whole parameter vector in registers first: validation and setup
+    // then wait for one round of independent loads, not a chain of them
+    double p[PPM_NPARAM];
+#pragma unroll
+    for (int i = 0; i < PPM_NPARAM; ++i) p[i] = params[(size_t)b * PPM_NPARAM + i];
+    const StarRec st = make_star(S, p);
+    if (blockIdx.x == 0 && threadIdx.x == 0) stars[b] = st;
+    const int role = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = blockIdx.x * 64 + lane;
+    const int rr = r < S.R_tot ? r : S.R_tot - 1;      // threads past the end mirror the last ring
     const int ncell_override = n_cells ? n_cells[b] : 0;
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < S.R_tot; r += gridDim.x * blockDim.x) {
-        RingRec g;
-        int spot = (r < S.rings_max[0]) ? 0 : 1;
-        int lr = spot == 0 ? r : r - S.rings_max[0];
-        int nr = ncell_override > 0 ? ncell_override : S.n_rings_spec[spot];
-        int np = ncell_override > 0 ? ncell_override : S.n_phi_spec[spot];
+    const int spot = (rr < S.rings_max[0]) ? 0 : 1;
+    const int lr = spot == 0 ? rr : rr - S.rings_max[0];
+    const int nr = ncell_override > 0 ? ncell_override : S.n_rings_spec[spot];
+    const int np = ncell_override > 0 ? ncell_override : S.n_phi_spec[spot];
+    const bool live = st.status == PPM_INST_OK && spot < S.n_spots && lr < nr;
+    double tc = p[8 + 4 * spot], z = p[9 + 4 * spot];
+    if (!live) { tc = 0.5; z = 0.1; }
+    double th, hp_first = 0.0, e0 = 0.0, e1 = 0.0;
+    int hp_n = 0;
+    if (S.n_side > 0) {
+        double zr;
+        healpix_ring(S.n_side, rr + 1, zr, hp_n, hp_first);
+        th = acos(zr);
+    } else {
+        double lo = fmax(0.0, tc - z), hi = fmin(kPi, tc + z);
+        e0 = lo + (hi - lo) * lr / nr;
+        e1 = lo + (hi - lo) * (lr + 1) / nr;
+        th = 0.5 * (e0 + e1);
+    }
+    const int shape = S.shape[spot];
+    // results of waves 1-3 per ring: outer, inner half-width, cos(mask radius),
+    // cos band difference, log g, T
+    __shared__ double xo[6][64];
+    RingRec g;
+    double acap = 0.0;
+    if (role == 1) {
+        xo[0][lane] = arc_halfwidth(th, tc, z);
+    } else if (role == 2) {
+        xo[1][lane] = (S.n_side == 0 && shape == PPM_SHAPE_ANNULUS) ? arc_halfwidth(th, tc, S.shape_a[spot] * z) : 0.0;
+        xo[2][lane] = cos(S.shape_a[spot] * z);
+    } else if (role == 3) {
+        xo[3][lane] = S.n_side > 0 ? 0.0 : cos(e0) - cos(e1);
+        xo[4][lane] = log10(st.g0 * gravity_ratio(st, S.mode, th));   // Eqs. (10), (11)
+        xo[5][lane] = pow(10.0, S.n_side > 0 ? 6.0 : p[10 + 4 * spot]);
+    } else {
         g.spot = spot;
-        g.shape = S.shape[spot];
+        g.shape = shape;
         g.active = 0;
         g.visible = 0;
         g.inv_min = 0;
         g.inv_max = -1;
         g.interior = 0;
         g.n_cells = 0;
-        bool live = st.status == PPM_INST_OK && spot < S.n_spots && lr < nr;
-        double tc = p[8 + 4 * spot], z = p[9 + 4 * spot];
-        if (!live) { tc = 0.5; z = 0.1; }
-        double th, hp_first = 0.0;
-        int hp_n = 0;
-        if (S.n_side > 0) {
-            double zr;
-            healpix_ring(S.n_side, r + 1, zr, hp_n, hp_first);
-            th = acos(zr);
-            g.dcos = 0.0;
-        } else {
-            double lo = fmax(0.0, tc - z), hi = fmin(kPi, tc + z);
-            double e0 = lo + (hi - lo) * lr / nr, e1 = lo + (hi - lo) * (lr + 1) / nr;
-            th = 0.5 * (e0 + e1);
-            g.dcos = cos(e0) - cos(e1);
-        }
         g.theta = th;
         double ct = cos(th), sn = sin(th);
         g.R = st.Re * (1.0 + st.o2 * ct * ct);                    // Eq. (7)
@@ -119,25 +147,8 @@ __global__ __launch_bounds__(64) void k_setup(DevSpec S, const double *params, c
         g.f = dR / (g.R * g.sq1u);                                 // Eq. (2)
         g.coseta = 1.0 / sqrt(1.0 + g.f * g.f);                    // Eq. (3)
         g.sineta = g.f / sqrt(1.0 + g.f * g.f);
-        g.logg = log10(st.g0 * gravity_ratio(st, S.mode, th));     // Eqs. (10), (11)
         g.beta = kTwoPi * st.nu * g.R * sn / (kC * g.sq1u);        // Eq. (18)
         g.gamma = 1.0 / sqrt(1.0 - g.beta * g.beta);
-        g.dphi_out = arc_halfwidth(th, tc, z);
-        if (S.n_side > 0) {
-            // cell j at azimuth first + j * 2 pi / n (cell_offset of a cap ring)
-            g.dphi_cell = kTwoPi / hp_n;
-            g.dphi_out = 0.5 * g.dphi_cell - hp_first;
-            g.dphi_in = 0.0;
-        } else if (g.shape == PPM_SHAPE_ANNULUS) {
-            g.dphi_in = arc_halfwidth(th, tc, S.shape_a[spot] * z);
-            g.dphi_cell = (g.dphi_out - g.dphi_in) / (0.5 * np);
-        } else {
-            g.dphi_in = 0.0;
-            g.dphi_cell = 2.0 * g.dphi_out / np;
-        }
-        const double patch = S.n_side > 0 ? kPi / (3.0 * S.n_side * (double)S.n_side) : g.dcos * g.dphi_cell;
-        g.w_cell = g.R * g.R * sqrt(1.0 + g.f * g.f) * patch / (st.D * st.D);  // Eq. (9)
-        double acap;
         {
             double v = 1.5 * g.u * sqrt(3.0 * (1.0 - g.u));
             acap = v >= 1.0 ? kHalfPi : kPi - asin(v);
@@ -150,15 +161,34 @@ __global__ __launch_bounds__(64) void k_setup(DevSpec S, const double *params, c
         // map rings: per-patch temperatures, 10^6 K is the reference the
         // accumulation scales by
         g.logT = S.n_side > 0 ? 6.0 : p[10 + 4 * spot];
-        g.T = pow(10.0, g.logT);
-        g.kT = kKB * g.T;
         double sgn = (tc >= kHalfPi) ? 1.0 : -1.0;
         g.tm = tc - sgn * S.shape_b[spot] * z;
-        g.cos_zm = cos(S.shape_a[spot] * z);
-        if (live) g.n_cells = S.n_side > 0 ? hp_n : np;
-        rings[(size_t)b * S.R_tot + r] = g;
-        vis_pairs[(size_t)b * S.R_tot + r] = 0;
     }
+    __syncthreads();                                   // waves 1-3 have written their results
+    if (role != 0 || r >= S.R_tot) return;
+    g.dcos = xo[3][lane];
+    g.logg = xo[4][lane];
+    g.dphi_out = xo[0][lane];
+    if (S.n_side > 0) {
+        // cell j at azimuth first + j * 2 pi / n (cell_offset of a cap ring)
+        g.dphi_cell = kTwoPi / hp_n;
+        g.dphi_out = 0.5 * g.dphi_cell - hp_first;
+        g.dphi_in = 0.0;
+    } else if (g.shape == PPM_SHAPE_ANNULUS) {
+        g.dphi_in = xo[1][lane];
+        g.dphi_cell = (g.dphi_out - g.dphi_in) / (0.5 * np);
+    } else {
+        g.dphi_in = 0.0;
+        g.dphi_cell = 2.0 * g.dphi_out / np;
+    }
+    const double patch = S.n_side > 0 ? kPi / (3.0 * S.n_side * (double)S.n_side) : g.dcos * g.dphi_cell;
+    g.w_cell = g.R * g.R * sqrt(1.0 + g.f * g.f) * patch / (st.D * st.D);  // Eq. (9)
+    g.T = xo[5][lane];
+    g.kT = kKB * g.T;
+    g.cos_zm = xo[2][lane];
+    if (live) g.n_cells = S.n_side > 0 ? hp_n : np;
+    rings[(size_t)b * S.R_tot + r] = g;
+    vis_pairs[(size_t)b * S.R_tot + r] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1074,11 +1104,23 @@ __global__ __launch_bounds__(256) void k_fold_f32(const float *A, const float *B
     const int kb = wave * kq, ke = min(K, kb + kq);
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     const bool mrow = (m0 + li) < M, ncol = (n0 + li) < N;
-    for (int k0 = kb; k0 < ke; k0 += 4) {
-        const int k = k0 + lk;
-        float a = (mrow && k < ke) ? A[(size_t)(m0 + li) * K + k] : 0.0f;
-        float bv = (ncol && k < ke) ? B[(size_t)k * N + n0 + li] : 0.0f;
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
+    // sixteen K steps at a time: all their operands loaded first (in-bounds
+    // addresses, zero where outside), then the MFMAs in K order
+    constexpr int kSteps = 16;
+    for (int kc = kb; kc < ke; kc += 4 * kSteps) {
+        float av[kSteps], bv[kSteps];
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) {
+            const int k = kc + 4 * s + lk;
+            const bool oka = mrow && k < ke, okb = ncol && k < ke;
+            const float va = A[oka ? (size_t)(m0 + li) * K + k : 0];
+            const float vb = B[okb ? (size_t)k * N + n0 + li : 0];
+            av[s] = oka ? va : 0.0f;
+            bv[s] = okb ? vb : 0.0f;
+        }
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s)
+            if (kc + 4 * s < ke) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc, 0, 0, 0);
     }
     part[wave][l] = acc;
     __syncthreads();
@@ -1192,7 +1234,7 @@ size_t accum_table_lds(const DevSpec &S)
 void launch_setup(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev, int B,
                   hipStream_t st)
 {
-    hipLaunchKernelGGL(k_setup, dim3((S.R_tot + 63) / 64, B), dim3(64), 0, st, S, params, ncells_dev, W.stars,
+    hipLaunchKernelGGL(k_setup, dim3((S.R_tot + 63) / 64, B), dim3(256), 0, st, S, params, ncells_dev, W.stars,
                        W.rings, W.vis_pairs);
 }
 
