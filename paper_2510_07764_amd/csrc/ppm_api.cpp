@@ -280,6 +280,8 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         glw.insert(glw.end(), w.begin(), w.end());
     }
     S.n_quad = (int)glx.size();
+    S.Pd = (double)S.P;
+    S.fpb = 2.0 * S.n_fp;
     S.glx = pl->upload(glx.data(), glx.size());
     S.glw = pl->upload(glw.data(), glw.size());
     S.energy = pl->upload(sp->energy_kev, S.E);
@@ -319,6 +321,18 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         // for surface speeds below 0.6 c) and the cubic stencil.
         S.tb0 = (std::log10(sp->energy_kev[0]) - S.x0) / S.hx;
         S.r_span = (std::log10(sp->energy_kev[S.E - 1]) - std::log10(sp->energy_kev[0])) / S.hx;
+        S.ihx = 1.0 / S.hx;
+        S.ixl = (float)(1.0 / (S.hx * std::log(10.0)));
+        {
+            std::vector<float> tbe(S.E);
+            for (int e = 0; e < S.E; ++e)
+                tbe[e] = (float)((std::log10(sp->energy_kev[e]) - std::log10(sp->energy_kev[0])) * S.ihx);
+            S.tbe = pl->upload(tbe.data(), tbe.size());
+            if (!S.tbe) {
+                delete pl;
+                return fail(PPM_ERR_ALLOC, "device allocation or upload failed");
+            }
+        }
         S.W_max = (int)std::ceil(S.r_span + std::log10(4.0) / S.hx) + 8;
         if (S.W_max > S.nx) S.W_max = S.nx;
         S.fast = (S.r_span <= 59.0 && S.interp == PPM_INTERP_MIXED) ? 1 : 0;
@@ -362,6 +376,8 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         }
         S.mu_coef = pl->upload(cf.data(), cf.size());
         S.mu_nb = 4 * nm;
+        S.mu_lo = a[0];
+        S.mu_hi = a[nm - 1];
         S.mu_ibw = S.mu_nb / (a[nm - 1] - a[0]);
         std::vector<int16_t> mb(S.mu_nb);
         for (int b = 0, l = 0; b < S.mu_nb; ++b) {

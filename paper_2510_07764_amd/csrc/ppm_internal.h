@@ -37,6 +37,11 @@ struct DevSpec {
     int map_nb;           // temperature buckets of a map ring (logT steps, with margins)
     int map_wm;           // x nodes of a bucket's slab window
     double tb0, r_span;   // (log10 E_0 - x0)/hx and (log10 E_last - log10 E_0)/hx
+    double ihx;           // 1 / hx
+    float ixl;            // 1 / (hx ln 10): x nodes per unit of ln z
+    double mu_lo, mu_hi;  // first and last mu node
+    double Pd, fpb;       // n_phase and 2 n_fp (the phase buckets) as doubles
+    const float *tbe;     // [E] (log10 E_e - log10 E_0)/hx, the energies' x offsets
     int R_tot;            // ring slots per instance (spot 0 then spot 1)
     int rings_max[2];     // ring slots of each spot
     int n_rings_spec[2], n_phi_spec[2];   // default grid of each spot
@@ -88,6 +93,7 @@ struct RingRec {
     int visible, inv_min, inv_max, interior;   // interior: the ring never reaches the x-axis edge intervals
     double zmin, zmax;           // range of the fine-phase redshift factor z
     int xw0, xw;                 // x-node window [xw0, xw0 + xw) of the ring's sub-table
+    double tbk;                  // (log10(E_0 / kT) - x0)/hx: x position of E_0 at z = 1
 };
 
 // One active patch of a temperature-map ring, sorted by temperature bucket:

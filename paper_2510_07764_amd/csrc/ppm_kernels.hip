@@ -477,6 +477,7 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace(DevSpec S, const int32_
             // x nodes any (cell, phase, energy) of this ring can touch, plus the
             // cubic stencil: t = (log10(z E / kT) - x0) / hx
             double lkt = log10(g.kT) / S.hx;
+            gp->tbk = S.tb0 - lkt;
             double tlo = log10(zlo) / S.hx + S.tb0 - lkt;
             double thi = log10(zhi) / S.hx + S.tb0 + S.r_span - lkt;
             int w0 = (int)floor(tlo) - 2, w1 = (int)floor(thi) + 3;
@@ -674,6 +675,26 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
 // intervals (checked at plan creation).
 // ---------------------------------------------------------------------------
 
+// x shift log10(1 + t) / hx of an interpolated redshift z_A (1 + t), with
+// ixl = 1 / (hx ln 10): FP64 halvings (1 + t = (1 + t')^2, t' = t / (1 +
+// sqrt(1 + t))) down to |t| <= 1/16, then ln(1 + t) = 2 atanh(s), s = t / (2
+// + t), from its series in FP32 (|s| <= 1/31: s (1 + s^2/3 + s^4/5) is within
+// 2e-10 relative).  Its error stays below the FP32 rounding of the x
+// fraction it feeds.
+__device__ inline float x_shift(double t, float ixl)
+{
+    int k = 0;
+    while (fabs(t) > 0.0625 && k < 64) {     // |t'| < |t| / 2 for t > 0; capped for t near -1
+        const double u = 1.0 + t;
+        t = t * rcp_nr(1.0 + u * rsqrt_nr(u));
+        ++k;
+    }
+    const float tf = (float)t;
+    const float s = tf * __builtin_amdgcn_rcpf(2.0f + tf), s2 = s * s;
+    const float l = 2.0f * s * (1.0f + s2 * (1.0f / 3.0f + s2 * (1.0f / 5.0f)));
+    return ldexpf(l, k) * ixl;
+}
+
 // Stage B of k_accum_fast for rings whose x window stays clear of the first
 // and last table interval: every interval is cubic, no selects.
 template <int EPL>
@@ -785,9 +806,12 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     int16_t *mbk = pbk + 2 * nfp;                              // mu_nb mu buckets
     const int n_pb = 2 * nfp;
     const double4 *gtr = trace + ((size_t)b * S.R_tot + r) * (nfp + 1);
+    // LDS trace per fine-phase sample i: (F, z_{i+1}/z_i - 1, x position of
+    // E_0 at z_i, mu); phi_o in po
     for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
         const double4 v = gtr[i];
-        tr[i] = v;
+        const double zn = i < nfp ? gtr[i + 1].y : v.y;
+        tr[i] = make_double4(v.x, zn / v.y - 1.0, log10(v.y) * S.ihx + g.tbk, v.w);
         po[i] = v.z;
     }
     for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
@@ -828,17 +852,15 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     float4 *Qw = Qb + wave * 64;
     float *Sw = Sb + wave * 68;
     if (lane < 4) Sw[64 + lane] = 0.0f;
-    const double phio0 = tr[0].z;
+    const double phio0 = gtr[0].z;                 // phi_o of sample 0 (tr holds x positions)
     const double inv2pi = 1.0 / kTwoPi;
-    const double tbk = S.tb0 - log10(g.kT) / S.hx;   // (log10(E_0/kT) - x0)/hx
-    const double ihx = 1.0 / S.hx;
     float tbr[EPL];
 #pragma unroll
     for (int m = 0; m < EPL; ++m) {
         int e = lane + 64 * m;
-        tbr[m] = e < E ? (float)((log10(S.energy[e]) - log10(S.energy[0])) * ihx) : 0.0f;
+        tbr[m] = e < E ? S.tbe[e] : 0.0f;
     }
-    const double mu_lo = axmu[0], mu_hi = axmu[nmu - 1];
+    const double mu_lo = S.mu_lo, mu_hi = S.mu_hi;
     const int xw0 = g.xw0, xw = g.xw;
     int npairs = 0;
     const int k_begin = tile * PT;
@@ -848,7 +870,7 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
         float acc[EPL];
 #pragma unroll
         for (int m = 0; m < EPL; ++m) acc[m] = 0.0f;
-        const double Phik = (k + 0.5) / P;
+        const double Phik = (k + 0.5) / S.Pd;
         for (int c0 = 0; c0 < g.n_cells; c0 += 64) {
             // ---------------- stage A: one (cell, phase) pair per lane
             const int j = c0 + lane;
@@ -862,16 +884,15 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
                     double php = (a - floor(a)) + phio0;                    // Eq. (45)
                     // Eq. (46): fine interval [phi_o[l0], phi_o[l0+1]) holding php, from
                     // its bucket and a bounded scan (phi_o increases)
-                    int q = (int)((php - phio0) * n_pb);
+                    int q = (int)((php - phio0) * S.fpb);
                     int l0 = pbk[q < n_pb - 1 ? q : n_pb - 1];
                     while (l0 > 0 && po[l0] > php) --l0;
                     while (l0 < nfp - 1 && po[l0 + 1] <= php) ++l0;
                     const double4 A = tr[l0], Cn = tr[l0 + 1];
-                    double wp = (php - A.z) * ipo[l0];
+                    double wp = (php - po[l0]) * ipo[l0];
                     wp = fmin(1.0, fmax(0.0, wp));
                     PhaseSample ps;
                     ps.F = A.x + wp * (Cn.x - A.x);
-                    ps.z = A.y + wp * (Cn.y - A.y);
                     ps.mu = A.w + wp * (Cn.w - A.w);
                     if (ps.F != 0.0) {
                         vis = true;
@@ -907,7 +928,8 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
                         w1 = (float)(v1 * ps.F);
                         w2 = (float)(v2 * ps.F);
                         w3 = (float)(v3 * ps.F);
-                        double T0 = log10(ps.z) * ihx + tbk;
+                        // x position at the interpolated z = z_A (1 + wp q_A)
+                        const double T0 = A.z + (double)x_shift(wp * A.y, S.ixl);
                         double fl = floor(T0);
                         I0 = (int)fl;
                         fr = (float)(T0 - fl);
