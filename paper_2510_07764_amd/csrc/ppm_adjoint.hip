@@ -477,7 +477,8 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
         const double4 *gtr = trace + slot * (nfp + 1);
         for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
             const double4 v = gtr[i];
-            tr[i] = v;
+            // (F, z, x position of E_0 at z, mu); phi_o in po
+            tr[i] = make_double4(v.x, v.y, log10(v.y) * S.ihx + g.tbk, v.w);
             po[i] = v.z;
         }
         for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
@@ -506,17 +507,16 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
     float4 *Qw = Qb + wave * 4 * 64;
     if (lane < 4) Nw[64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
     const RingTan rt = ringtan[slot];
-    const double phio0 = tr[0].z;
+    const double phio0 = trace[slot * (nfp + 1)].z;        // phi_o of sample 0
     const double inv2pi = 1.0 / kTwoPi;
-    const double tbk = S.tb0 - log10(g.kT) / S.hx;
-    const double ihx = 1.0 / S.hx;
+    const double ihx = S.ihx;
     float tbr[EPL];
 #pragma unroll
     for (int m = 0; m < EPL; ++m) {
         int e = lane + 64 * m;     // energies 64 apart: neighbouring lanes read neighbouring quads
-        tbr[m] = e < E ? (float)((log10(S.energy[e]) - log10(S.energy[0])) * ihx) : 0.0f;
+        tbr[m] = e < E ? S.tbe[e] : 0.0f;
     }
-    const double mu_lo = axmu[0], mu_hi = axmu[nmu - 1];
+    const double mu_lo = S.mu_lo, mu_hi = S.mu_hi;
     const int xw0 = g.xw0, xw = g.xw;
     double U[kGradAcc];
 #pragma unroll
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
             int e = lane + 64 * m;
             Gr[m] = e < E ? gtil[((size_t)b * P + k) * E + e] : 0.0f;
         }
-        const double Phik = (k + 0.5) / P;
+        const double Phik = (k + 0.5) / S.Pd;
         for (int c0 = 0; c0 < g.n_cells; c0 += 64) {
             // ---------------- stage A: one (cell, phase) pair per lane
             const int j = c0 + lane;
@@ -546,12 +546,12 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
                 if (!cell_masked(g, off)) {
                     double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
                     double php = (a - floor(a)) + phio0;                    // Eq. (45)
-                    int q = (int)((php - phio0) * n_pb);                   // bucket, bounded scan
+                    int q = (int)((php - phio0) * S.fpb);                  // bucket, bounded scan
                     int l0 = pbk[q < n_pb - 1 ? q : n_pb - 1];
                     while (l0 > 0 && po[l0] > php) --l0;
                     while (l0 < nfp - 1 && po[l0 + 1] <= php) ++l0;
                     const double4 A = tr[l0], Cn = tr[l0 + 1];
-                    double w = (php - A.z) * ipo[l0];
+                    double w = (php - po[l0]) * ipo[l0];
                     w = fmin(1.0, fmax(0.0, w));
                     const double Fp = A.x + w * (Cn.x - A.x);                // Eq. (46)
                     if (Fp != 0.0) {
@@ -601,7 +601,8 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
                         if (mu_clamped) da = db = dc = dd = 0.0;
                         w0 = (float)wa; w1 = (float)wb; w2 = (float)wc; w3 = (float)wd;
                         v0 = (float)da; v1 = (float)db; v2 = (float)dc; v3 = (float)dd;
-                        const double T0 = log10(zp) * ihx + tbk;
+                        // x position at zp = z_A (1 + t): sample position plus the shift
+                        const double T0 = A.z + (double)x_shift(w * (Cn.y - A.y) * rcp_nr(A.y), S.ixl);
                         const double fl = floor(T0);
                         I0 = (int)fl;
                         fr = (float)(T0 - fl);
@@ -683,7 +684,7 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
             // ---------------- stage C: chain rule per pair, FP64
             if (vis) {
                 const double4 A = tr[lo], Cn = tr[lo + 1];
-                const double dph = Cn.z - A.z;
+                const double dph = po[lo + 1] - po[lo];
                 const double w = wph;
                 const double Fp = A.x + w * (Cn.x - A.x), zp = A.y + w * (Cn.y - A.y);
                 const double S0 = R0, Sx = (double)R1 * ihx, Sm = R2;

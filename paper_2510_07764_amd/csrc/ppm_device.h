@@ -182,6 +182,26 @@ __device__ inline void dhermite(const T &t, T &d00, T &d10, T &d01, T &d11)
 }
 
 
+// x shift log10(1 + t) / hx of an interpolated redshift z_A (1 + t), with
+// ixl = 1 / (hx ln 10): FP64 halvings (1 + t = (1 + t')^2, t' = t / (1 +
+// sqrt(1 + t))) down to |t| <= 1/16, then ln(1 + t) = 2 atanh(s), s = t / (2
+// + t), from its series in FP32 (|s| <= 1/31: s (1 + s^2/3 + s^4/5) is within
+// 2e-10 relative).  Its error stays below the FP32 rounding of the x
+// fraction it feeds.
+__device__ inline float x_shift(double t, float ixl)
+{
+    int k = 0;
+    while (fabs(t) > 0.0625 && k < 64) {     // |t'| < |t| / 2 for t > 0; capped for t near -1
+        const double u = 1.0 + t;
+        t = t * rcp_nr(1.0 + u * rsqrt_nr(u));
+        ++k;
+    }
+    const float tf = (float)t;
+    const float s = tf * __builtin_amdgcn_rcpf(2.0f + tf), s2 = s * s;
+    const float l = 2.0f * s * (1.0f + s2 * (1.0f / 3.0f + s2 * (1.0f / 5.0f)));
+    return ldexpf(l, k) * ixl;
+}
+
 __device__ inline int lin_bracket(double v, double v0, double h, int n, double &w1)
 {
     double t = (v - v0) / h;
