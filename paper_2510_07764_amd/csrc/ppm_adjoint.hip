@@ -798,21 +798,26 @@ hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *param
                        W.rings, W.table, W.table_u, W.trace, W.tangent, W.ringtan);
     hipLaunchKernelGGL(k_subtable_tg, dim3(n_list), dim3(256), 0, st, S, list, W.rings, W.subtg);
     const int n_tile = (S.P + S.pt_adj - 1) / S.pt_adj;
-    dim3 grid(xcd_grid(n_list, n_tile));
     size_t lds = accum_adj_lds(S);
     int epl = (S.E + 63) / 64;
-    if (epl <= 1)
-        hipLaunchKernelGGL(k_accum_adj<1>, grid, dim3(64 * kAdjWaves), lds, st, S, list, W.rings, W.ringtan, W.trace,
-                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n_list);
-    else if (epl <= 2)
-        hipLaunchKernelGGL(k_accum_adj<2>, grid, dim3(64 * kAdjWaves), lds, st, S, list, W.rings, W.ringtan, W.trace,
-                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n_list);
-    else if (epl <= 4)
-        hipLaunchKernelGGL(k_accum_adj<4>, grid, dim3(64 * kAdjWaves), lds, st, S, list, W.rings, W.ringtan, W.trace,
-                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n_list);
-    else
-        hipLaunchKernelGGL(k_accum_adj<8>, grid, dim3(64 * kAdjWaves), lds, st, S, list, W.rings, W.ringtan, W.trace,
-                           W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n_list);
+    const int step = max_list_per_launch(n_tile, 64 * kAdjWaves);
+    for (int off = 0; off < n_list; off += step) {
+        const int32_t *sl = list + off;
+        const int n = n_list - off < step ? n_list - off : step;
+        dim3 grid(xcd_grid(n, n_tile));
+        if (epl <= 1)
+            hipLaunchKernelGGL(k_accum_adj<1>, grid, dim3(64 * kAdjWaves), lds, st, S, sl, W.rings, W.ringtan, W.trace,
+                               W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n);
+        else if (epl <= 2)
+            hipLaunchKernelGGL(k_accum_adj<2>, grid, dim3(64 * kAdjWaves), lds, st, S, sl, W.rings, W.ringtan, W.trace,
+                               W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n);
+        else if (epl <= 4)
+            hipLaunchKernelGGL(k_accum_adj<4>, grid, dim3(64 * kAdjWaves), lds, st, S, sl, W.rings, W.ringtan, W.trace,
+                               W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n);
+        else
+            hipLaunchKernelGGL(k_accum_adj<8>, grid, dim3(64 * kAdjWaves), lds, st, S, sl, W.rings, W.ringtan, W.trace,
+                               W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n);
+    }
     hipLaunchKernelGGL(k_grad_final, dim3(B), dim3(64), 0, st, S, W.stars, W.rings, W.ringtan, W.gpart, n_tile,
                        W.nh_part, grad);
     return hipGetLastError();

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include "ppm_internal.h"
 #include "ppm_dual.h"
@@ -291,6 +292,21 @@ constexpr int kXcds = 8;
 __host__ __device__ inline int xcd_grid(int n_list, int n_tile)
 {
     return kXcds * n_tile * ((n_list + kXcds - 1) / kXcds);
+}
+
+// work-list entries one accumulation launch may take: its grid of n_tile
+// blocks per entry, `threads` each, stays below 2^32 threads (a launch
+// limit); a multiple of the XCD count.  PPM_MAX_LAUNCH_THREADS lowers the
+// limit (tests use it to split launches on small workloads).
+inline int max_list_per_launch(int n_tile, int threads)
+{
+    long long lim = 4294967295LL;
+    if (const char *env = std::getenv("PPM_MAX_LAUNCH_THREADS")) {
+        const long long v = std::strtoll(env, nullptr, 10);
+        if (v >= 1 && v < lim) lim = v;
+    }
+    const long long m = lim / ((long long)n_tile * threads);
+    return m < kXcds ? kXcds : (int)((m / kXcds) * kXcds);
 }
 
 __device__ inline bool xcd_block(int n_list, int n_tile, int &li, int &tile)

@@ -1272,54 +1272,66 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
     launch_setup(S, W, params, ncells_dev, B, st);
     launch_table_trace(S, W, list, n_list, st);
     const int PT = S.pt_fwd;
-    dim3 grid(xcd_grid(n_list, (S.P + PT - 1) / PT));
+    const int n_tile = (S.P + PT - 1) / PT;
     if (S.intensity == PPM_I_TABLE) {
         size_t lds = accum_table_lds(S);
         if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
         int epl = (S.E + 63) / 64;
-        if (S.fast) {
-            if (epl <= 1)
-                hipLaunchKernelGGL((k_accum_fast<1, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, list, W.rings, W.trace, W.sub,
-                                   W.partial32, W.vis_pairs, PT, n_list);
+        const int step = max_list_per_launch(n_tile, S.fast ? 64 * kFwdWaves : 256);
+        for (int off = 0; off < n_list; off += step) {
+            const int32_t *sl = list + off;
+            const int n = n_list - off < step ? n_list - off : step;
+            dim3 grid(xcd_grid(n, n_tile));
+            if (S.fast) {
+                if (epl <= 1)
+                    hipLaunchKernelGGL((k_accum_fast<1, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, sl, W.rings, W.trace, W.sub,
+                                       W.partial32, W.vis_pairs, PT, n);
+                else if (epl <= 2)
+                    hipLaunchKernelGGL((k_accum_fast<2, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, sl, W.rings, W.trace, W.sub,
+                                       W.partial32, W.vis_pairs, PT, n);
+                else if (epl <= 4)
+                    hipLaunchKernelGGL((k_accum_fast<4, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, sl, W.rings, W.trace, W.sub,
+                                       W.partial32, W.vis_pairs, PT, n);
+                else
+                    hipLaunchKernelGGL((k_accum_fast<8, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, sl, W.rings, W.trace, W.sub,
+                                       W.partial32, W.vis_pairs, PT, n);
+            } else if (epl <= 1)
+                hipLaunchKernelGGL(k_accum_table<1>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.sub,
+                                   W.partial32, W.vis_pairs, PT, n);
             else if (epl <= 2)
-                hipLaunchKernelGGL((k_accum_fast<2, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, list, W.rings, W.trace, W.sub,
-                                   W.partial32, W.vis_pairs, PT, n_list);
+                hipLaunchKernelGGL(k_accum_table<2>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.sub,
+                                   W.partial32, W.vis_pairs, PT, n);
             else if (epl <= 4)
-                hipLaunchKernelGGL((k_accum_fast<4, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, list, W.rings, W.trace, W.sub,
-                                   W.partial32, W.vis_pairs, PT, n_list);
+                hipLaunchKernelGGL(k_accum_table<4>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.sub,
+                                   W.partial32, W.vis_pairs, PT, n);
             else
-                hipLaunchKernelGGL((k_accum_fast<8, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, list, W.rings, W.trace, W.sub,
-                                   W.partial32, W.vis_pairs, PT, n_list);
-        } else if (epl <= 1)
-            hipLaunchKernelGGL(k_accum_table<1>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
-                               W.partial32, W.vis_pairs, PT, n_list);
-        else if (epl <= 2)
-            hipLaunchKernelGGL(k_accum_table<2>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
-                               W.partial32, W.vis_pairs, PT, n_list);
-        else if (epl <= 4)
-            hipLaunchKernelGGL(k_accum_table<4>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
-                               W.partial32, W.vis_pairs, PT, n_list);
-        else
-            hipLaunchKernelGGL(k_accum_table<8>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.sub,
-                               W.partial32, W.vis_pairs, PT, n_list);
+                hipLaunchKernelGGL(k_accum_table<8>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.sub,
+                                   W.partial32, W.vis_pairs, PT, n);
+        }
         if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
         launch_reduce_fold32(S, W, B, st, want_flux_f64 ? flux_out : nullptr, counts_out);
     } else {
         size_t lds = sizeof(double4) * (S.n_fp + 1);
         int epl = (S.E + 63) / 64;
         if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
-        if (epl <= 1)
-            hipLaunchKernelGGL(k_accum_bb<1>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.partial64,
-                               W.vis_pairs, PT, n_list);
-        else if (epl <= 2)
-            hipLaunchKernelGGL(k_accum_bb<2>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.partial64,
-                               W.vis_pairs, PT, n_list);
-        else if (epl <= 4)
-            hipLaunchKernelGGL(k_accum_bb<4>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.partial64,
-                               W.vis_pairs, PT, n_list);
-        else
-            hipLaunchKernelGGL(k_accum_bb<8>, grid, dim3(256), lds, st, S, list, W.rings, W.trace, W.partial64,
-                               W.vis_pairs, PT, n_list);
+        const int step = max_list_per_launch(n_tile, 256);
+        for (int off = 0; off < n_list; off += step) {
+            const int32_t *sl = list + off;
+            const int n = n_list - off < step ? n_list - off : step;
+            dim3 grid(xcd_grid(n, n_tile));
+            if (epl <= 1)
+                hipLaunchKernelGGL(k_accum_bb<1>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.partial64,
+                                   W.vis_pairs, PT, n);
+            else if (epl <= 2)
+                hipLaunchKernelGGL(k_accum_bb<2>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.partial64,
+                                   W.vis_pairs, PT, n);
+            else if (epl <= 4)
+                hipLaunchKernelGGL(k_accum_bb<4>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.partial64,
+                                   W.vis_pairs, PT, n);
+            else
+                hipLaunchKernelGGL(k_accum_bb<8>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.partial64,
+                                   W.vis_pairs, PT, n);
+        }
         if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
         if (S.rsp64) {
             hipLaunchKernelGGL((k_reduce<double, double>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S, W.stars,

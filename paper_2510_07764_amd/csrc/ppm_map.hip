@@ -364,27 +364,32 @@ hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double
     launch_table_trace(S, W, list, n_list, st);
     const int kpw = S.pt_fwd >= 4 * kMapWaves ? 4 : (S.pt_fwd >= 2 * kMapWaves ? 2 : 1);
     const int n_tile = (S.P + kMapWaves * kpw - 1) / (kMapWaves * kpw);
-    dim3 grid(xcd_grid(n_list, n_tile));
     const size_t lds = accum_map_lds(S);
     const int epl = (S.E + 63) / 64;
     if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
 #define PPM_MAP_LAUNCH(E_, K_)                                                                                   \
-    hipLaunchKernelGGL((k_accum_map<E_, K_>), grid, dim3(64 * kMapWaves), lds, st, S, list, W.rings, W.trace,   \
-                       W.mcell, W.mgrp, W.partial32, W.vis_pairs, n_list)
+    hipLaunchKernelGGL((k_accum_map<E_, K_>), grid, dim3(64 * kMapWaves), lds, st, S, sl, W.rings, W.trace,     \
+                       W.mcell, W.mgrp, W.partial32, W.vis_pairs, n)
 #define PPM_MAP_KPW(E_)                          \
     do {                                         \
         if (kpw == 1) PPM_MAP_LAUNCH(E_, 1);     \
         else if (kpw == 2) PPM_MAP_LAUNCH(E_, 2); \
         else PPM_MAP_LAUNCH(E_, 4);              \
     } while (0)
-    if (epl <= 1)
-        PPM_MAP_KPW(1);
-    else if (epl <= 2)
-        PPM_MAP_KPW(2);
-    else if (epl <= 4)
-        PPM_MAP_KPW(4);
-    else
-        PPM_MAP_KPW(8);
+    const int step = max_list_per_launch(n_tile, 64 * kMapWaves);
+    for (int off = 0; off < n_list; off += step) {
+        const int32_t *sl = list + off;
+        const int n = n_list - off < step ? n_list - off : step;
+        dim3 grid(xcd_grid(n, n_tile));
+        if (epl <= 1)
+            PPM_MAP_KPW(1);
+        else if (epl <= 2)
+            PPM_MAP_KPW(2);
+        else if (epl <= 4)
+            PPM_MAP_KPW(4);
+        else
+            PPM_MAP_KPW(8);
+    }
 #undef PPM_MAP_KPW
 #undef PPM_MAP_LAUNCH
     if (ev_hot1) (void)hipEventRecord(ev_hot1, st);

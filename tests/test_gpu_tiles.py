@@ -95,6 +95,46 @@ def test_gradient_across_adjoint_tiles(torch_dev):
         assert err < 1e-11, (fwd, adj, err)
 
 
+def test_split_launches_bit_identical(torch_dev):
+    """An accumulation launch is split over sub-ranges of the work list when
+    its grid would pass the 2^32-thread launch limit (a batch of 1,024
+    workload-1 vectors at phase tile 4).  Forced here on a small batch by
+    lowering the limit (PPM_MAX_LAUNCH_THREADS): forward counts, logL and the
+    gradient, and a temperature-map forward, are bit-identical to the
+    unsplit launches (every block writes only its own ring's outputs)."""
+    import os
+    import paper_2510_07764_amd as ppm
+    torch, dev = torch_dev
+    spec, p = syn.config1(n_cells=16, n_phase=32, n_energy=64)
+    _, cnt, _ = oracle.forward(oracle.OracleSpec(spec), p)
+    data = torch.tensor(syn.poisson_data(cnt), device=dev)
+    q = torch.tensor(syn.config4_draws(4), dtype=torch.float64, device=dev)
+    plan = ppm.Plan(spec, max_batch=4, grad=True)
+    plan.set_tiles(phase_tile=4, phase_tile_grad=8)
+    mspec, mp, mm = syn.map_config(4, "full", n_phase=32, n_energy=64)
+    mplan = ppm.Plan(mspec, max_batch=2)
+    mpt = torch.tensor(np.stack([mp, mp]), dtype=torch.float64, device=dev)
+    mpt[1, 3] = 0.25
+    mmt = torch.tensor(np.stack([mm, mm[::-1].copy()]), dtype=torch.float64, device=dev)
+
+    def run():
+        c = plan.forward(q).cpu().numpy()
+        ll, g = plan.loglike_grad(q, data)
+        mc = mplan.forward_map(mpt, mmt).cpu().numpy()
+        torch.cuda.synchronize()
+        return c, ll.cpu().numpy(), g.cpu().numpy(), mc
+
+    ref = run()
+    # 8 work-list entries per forward launch (8 tiles x 768 threads each)
+    os.environ["PPM_MAX_LAUNCH_THREADS"] = str(8 * 8 * 768)
+    try:
+        got = run()
+    finally:
+        del os.environ["PPM_MAX_LAUNCH_THREADS"]
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+
 def test_set_tiles_rejects_out_of_range(torch_dev):
     import paper_2510_07764_amd as ppm
     spec, _ = syn.config1(n_cells=8, n_phase=16, n_energy=32)
