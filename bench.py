@@ -44,10 +44,10 @@ PEAK_FP32_TFLOPS = 157.3
 # kernel sources the counters were taken on and for the tiles listed; any
 # other case reports null until the counters are taken again.
 KERNEL_SOURCES = ("ppm_kernels.hip", "ppm_device.h", "ppm_dual.h", "ppm_internal.h", "ppm_launch.h")
-TRAFFIC = {"sources_sha256": "10559f9747c7dd5fbdc10a1b6c2e3805fa3fab51bd9a5e6107e34790ca806f6a",
+TRAFFIC = {"sources_sha256": "8e573b491de9d45e963653bf885acdf4e6e31cc553741e8adf7f4bff2db37401",
            "fetch_scale": 1.99980, "write_scale": 1.0,
            # phase tile -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-           "by_tile": {8: (4288.45, 33198.96), 12: (4288.30, 33071.07)},
+           "by_tile": {32: (4266.32, 33128.73), 64: (4259.80, 32960.00), 128: (4260.34, 32864.00)},
            "profile": "profiles/k_accum_fast_config1_traffic.md"}
 
 
@@ -321,7 +321,7 @@ def main():
         tmap = {"workload": f"full-surface map, HEALPix n_side {args.map_nside} "
                             f"({12 * args.map_nside ** 2} patches, all active), config-1 star and instrument",
                 "evals_per_s": 1.0 / map_s, "ms_per_call": map_s * 1e3,
-                "kernel": "k_accum_map<4>", "kernel_ms": mhot_s * 1e3, "units": munits,
+                "kernel": "k_accum_map", "kernel_ms": mhot_s * 1e3, "units": munits,
                 "flop_per_unit": FLOP_PER_UNIT_MAP, "achieved": mach, "frac": mach / PEAK_FP32_TFLOPS,
                 "logL": float(mll.item()), "tiles": mtune}
         if args.map_batch > 1:
@@ -383,7 +383,7 @@ def main():
         "sampler": ptleg,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": hot_kernel_traffic(plan.tiles[0]),
-                     "kernel": "k_accum_fast<4>", "kernel_ms": hot_avg_s * 1e3, "units": units,
+                     "kernel": "k_accum_fast<4, 12>", "kernel_ms": hot_avg_s * 1e3, "units": units,
                      "flop_per_unit": FLOP_PER_UNIT},
         "cpu_baseline": cpu,
     }
