@@ -9,7 +9,10 @@ the C ABI, against the FP64 oracle (bar: 1e-4 relative per bin at or above
 * the spherical (S+D) star with the atmosphere table;
 * pole-on observer (a flat light curve), a spot centred on the pole, a
   single cell per spot with one phase and one energy;
-* argument errors of the evaluation calls.
+* argument errors of the evaluation calls;
+* coarse fine-phase traces on a fast spinner, where the redshift changes by
+  more than 1/16 between fine samples (the windowed kernel's x positions
+  then take their halving path, and phase buckets hold several samples).
 """
 import math
 
@@ -206,3 +209,34 @@ def test_grad_per_instance_grids(torch_dev):
         l1, g1 = pl.loglike_grad(pt[i:i + 1].contiguous(), dt)
         np.testing.assert_allclose(g[i].cpu().numpy(), g1[0].cpu().numpy(), rtol=1e-6, atol=1e-9 * g1.abs().max().item())
         assert abs(ll[i].item() - l1[0].item()) <= 1e-9 * abs(l1[0].item())
+
+
+def _max_z_step(spec, params):
+    """Largest relative redshift step between fine samples with flux (oracle)."""
+    os_ = oracle.OracleSpec(spec)
+    qm = 0.0
+    for spot in (0, 1):
+        for g in oracle.rings(os_, params, spot):
+            tr = oracle.trace_ring(os_, params, g)
+            if not tr["visible"]:
+                continue
+            z, F = np.asarray(tr["z"]), np.asarray(tr["F"])
+            lit = (F[:-1] != 0) | (F[1:] != 0)
+            step = np.abs(z[1:] / z[:-1] - 1.0)[lit]
+            if step.size:
+                qm = max(qm, float(step.max()))
+    return qm
+
+
+@pytest.mark.parametrize("n_fp,nu", [(8, 600.0), (12, 716.0)])
+def test_coarse_trace_fast_spin(torch_dev, n_fp, nu):
+    spec, p = syn.config1(n_cells=16, n_phase=32, n_energy=64)
+    spec = dict(spec, n_fp=n_fp)
+    p = p.copy()
+    p[5] = nu
+    assert _max_z_step(spec, p) > 1.0 / 16.0      # the halving path is reached
+    _, cnt, _ = oracle.forward(oracle.OracleSpec(spec), p)
+    got, _ = run(torch_dev, spec, p)
+    err = rel_err(got[0], cnt)
+    print(f"n_fp {n_fp}, {nu} Hz: max rel err {err:.3e}", flush=True)
+    assert err < TOL
