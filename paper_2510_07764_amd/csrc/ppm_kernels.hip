@@ -678,15 +678,17 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
 // Stage B of k_accum_fast for rings whose x window stays clear of the first
 // and last table interval: every interval is cubic, no selects.
 template <int EPL>
-__device__ __forceinline__ void pairs_interior(uint64_t mask, float w0, float w1, float w2, float w3, float fr,
-                                               int pk, int lane, const float *tab, int W, int NMP, int xw0, float *Sw,
-                                               float4 *Qw, const float (&tbr)[EPL], float (&acc)[EPL])
+__device__ __forceinline__ void pairs_interior(uint64_t mask, const float4 *Pp, float fr, int pk, int lane, const float *tab,
+                                               int W, int NMP, int xw0, float *Sw, float4 *Qw,
+                                               const float (&tbr)[EPL], float (&acc)[EPL])
 {
     while (mask) {
         const int p = __ffsll((unsigned long long)mask) - 1;
         mask &= mask - 1;
-        const float pw0 = readlane_f(w0, p), pw1 = readlane_f(w1, p), pw2 = readlane_f(w2, p),
-                    pw3 = readlane_f(w3, p), pfr = readlane_f(fr, p);
+        // the pair's mu weights, broadcast from its lane's LDS record
+        const float4 pw = Pp[p];
+        const float pfr = readlane_f(fr, p);
+        const float pw0 = pw.x, pw1 = pw.y, pw2 = pw.z, pw3 = pw.w;
         const int ppk = __builtin_amdgcn_readlane(pk, p);
         const int pI0 = ppk >> 8, pm0 = ppk & 255;
         // mu contraction at x node I0 - 1 + lane (columns past the window hold zeros)
@@ -716,7 +718,7 @@ __device__ __forceinline__ void pairs_interior(uint64_t mask, float w0, float w1
 // Stage B for rings that may reach the edge intervals (linear there) or
 // leave the table (zero contribution).
 template <int EPL>
-__device__ __forceinline__ void pairs_general(uint64_t mask, float w0, float w1, float w2, float w3, float fr,
+__device__ __forceinline__ void pairs_general(uint64_t mask, const float4 *Pp, float fr,
                                               int I0, int m0, int lane, const float *tab, int NMP, int xw0, int xw,
                                               int nx, float *Sw, float4 *Qw, const float (&tbr)[EPL],
                                               float (&acc)[EPL])
@@ -724,8 +726,9 @@ __device__ __forceinline__ void pairs_general(uint64_t mask, float w0, float w1,
     while (mask) {
         const int p = __ffsll((unsigned long long)mask) - 1;
         mask &= mask - 1;
-        const float pw0 = readlane_f(w0, p), pw1 = readlane_f(w1, p), pw2 = readlane_f(w2, p),
-                    pw3 = readlane_f(w3, p), pfr = readlane_f(fr, p);
+        const float4 pw = Pp[p];
+        const float pfr = readlane_f(fr, p);
+        const float pw0 = pw.x, pw1 = pw.y, pw2 = pw.z, pw3 = pw.w;
         const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
         const int col = pI0 - 1 + lane - xw0;
         float Sv = 0.0f;
@@ -779,7 +782,8 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     const int NMP = fast_tab_stride(nmu);
     float4 *Qb = (float4 *)(tab + fast_tab_floats(S));         // NW waves * 64 quads
     float *Sb = (float *)(Qb + NW * 64);                       // NW waves * 68
-    double *po = (double *)(Sb + NW * 68);                     // nfp + 1 phi_o, compact for the search
+    float4 *Pb = (float4 *)(Sb + NW * 68);                     // NW waves * 64 pair mu weights
+    double *po = (double *)(Pb + NW * 64);                     // nfp + 1 phi_o, compact for the search
     double *ipo = po + nfp + 1;                                // nfp: 1 / (phi_o[i+1] - phi_o[i])
     double *mcf = ipo + nfp + 1;                               // nmu * 4 mu-interval coefficients
     int16_t *pbk = (int16_t *)(mcf + 4 * nmu);                 // 2 nfp phase buckets
@@ -831,6 +835,7 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float4 *Qw = Qb + wave * 64;
     float *Sw = Sb + wave * 68;
+    float4 *Pw = Pb + wave * 64;
     if (lane < 4) Sw[64 + lane] = 0.0f;
     const double phio0 = gtr[0].z;                 // phi_o of sample 0 (tr holds x positions)
     const double inv2pi = 1.0 / kTwoPi;
@@ -918,11 +923,13 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
             }
             uint64_t mask = __ballot(vis);
             npairs += __popcll(mask);
+            Pw[lane] = make_float4(w0, w1, w2, w3);
+            wave_sync();
             // ---------------- stage B: the visible pairs one after another
             if (g.interior)
-                pairs_interior<EPL>(mask, w0, w1, w2, w3, fr, (I0 << 8) | m0, lane, tab, W, NMP, xw0, Sw, Qw, tbr, acc);
+                pairs_interior<EPL>(mask, Pw, fr, (I0 << 8) | m0, lane, tab, W, NMP, xw0, Sw, Qw, tbr, acc);
             else
-                pairs_general<EPL>(mask, w0, w1, w2, w3, fr, I0, m0, lane, tab, NMP, xw0, xw, nx, Sw, Qw, tbr, acc);
+                pairs_general<EPL>(mask, Pw, fr, I0, m0, lane, tab, NMP, xw0, xw, nx, Sw, Qw, tbr, acc);
         }
         const double scale = g.w_cell * g.T * g.T * g.T;
         float *out = partial + (((size_t)b * S.R_tot + r) * P + k) * E;
@@ -1227,6 +1234,7 @@ size_t accum_table_lds(const DevSpec &S)
     if (S.fast)
         return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
              + sizeof(float) * fast_tab_floats(S) + sizeof(float4) * kFwdWaves * 64 + sizeof(float) * kFwdWaves * 68
+             + sizeof(float4) * kFwdWaves * 64
              + sizeof(double) * 2 * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
              + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb);
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * S.nmu + sizeof(float) * S.nmu * S.nx
