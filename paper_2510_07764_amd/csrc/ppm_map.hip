@@ -156,26 +156,48 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     float *sl1 = sl0 + nmu * WM;                               // nmu * WM
     float4 *Qb = (float4 *)(sl1 + nmu * WM);                   // kMapWaves * 64 quads (WM % 4 == 0)
     float *Sb = (float *)(Qb + kMapWaves * 64);                // kMapWaves * 68
+    double *ipo = (double *)(Sb + kMapWaves * 68);             // nfp: 1 / (phi_o[i+1] - phi_o[i])
+    double *mcf = ipo + nfp + 1;                               // nmu * 4 mu-interval coefficients
+    int16_t *pbk = (int16_t *)(mcf + 4 * nmu);                 // 2 nfp phase buckets
+    int16_t *mbk = pbk + 2 * nfp;                              // mu_nb mu buckets
+    const int n_pb = 2 * nfp;
     const int tid = threadIdx.x;
     const double4 *gtr = trace + slot * (nfp + 1);
+    // LDS trace per fine-phase sample i: (F, z_{i+1}/z_i - 1, x position of
+    // E_0 at z_i and kT = 1 keV, mu); phi_o in po
     for (int i = tid; i <= nfp; i += blockDim.x) {
         const double4 v = gtr[i];
-        tr[i] = v;
+        const double zn = i < nfp ? gtr[i + 1].y : v.y;
+        tr[i] = make_double4(v.x, zn / v.y - 1.0, log10(v.y) * S.ihx + S.tb0, v.w);
         po[i] = v.z;
     }
     for (int i = tid; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
+    for (int i = tid; i < 4 * nmu; i += blockDim.x) mcf[i] = S.mu_coef[i];
+    for (int i = tid; i < S.mu_nb; i += blockDim.x) mbk[i] = S.mu_bucket[i];
+    __syncthreads();
+    // phase buckets and inverse spacings of phi_o, as in the spot kernel
+    for (int q = tid; q < n_pb; q += blockDim.x) {
+        const double edge = po[0] + (double)q / n_pb;
+        int l0 = 0, h0 = nfp;
+        while (h0 - l0 > 1) {
+            int mid = (l0 + h0) >> 1;
+            if (po[mid] <= edge) l0 = mid; else h0 = mid;
+        }
+        pbk[q] = (int16_t)l0;
+    }
+    for (int i = tid; i < nfp; i += blockDim.x) ipo[i] = 1.0 / (po[i + 1] - po[i]);
     const int wave = tid >> 6, lane = tid & 63;
     float4 *Qw = Qb + wave * 64;
     float *Sw = Sb + wave * 68;
     if (lane < 4) Sw[64 + lane] = 0.0f;
-    const double ihx = 1.0 / S.hx;
+    const double ihx = S.ihx;
     float tbr[EPL];
 #pragma unroll
     for (int m = 0; m < EPL; ++m) {
         int e = lane + 64 * m;     // energies 64 apart: neighbouring lanes read neighbouring quads
-        tbr[m] = e < E ? (float)((log10(S.energy[e]) - log10(S.energy[0])) * ihx) : 0.0f;
+        tbr[m] = e < E ? S.tbe[e] : 0.0f;
     }
-    const double mu_lo = S.ax_mu[0], mu_hi = S.ax_mu[nmu - 1];
+    const double mu_lo = S.mu_lo, mu_hi = S.mu_hi;
     const double inv2pi = 1.0 / kTwoPi;
     const double phio0 = gtr[0].z;
     const int k_first = tile * PT + wave;
@@ -225,7 +247,7 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
         for (int kq = 0; kq < KPW; ++kq) {
             const int k = k_first + kMapWaves * kq;
             if (k >= P) break;
-            const double Phik = (k + 0.5) / P;
+            const double Phik = (k + 0.5) / S.Pd;
             for (int c0 = c_beg; c0 < c_end; c0 += 64) {
                 // ---------------- stage A: one (patch, phase) pair per lane
                 const int cc = c0 + lane;
@@ -237,51 +259,49 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
                     const double off = cell_offset(g, mc.j);
                     double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
                     double php = (a - floor(a)) + phio0;                    // Eq. (45)
-                    int l0 = 0, h0 = nfp;                                   // Eq. (46)
-                    while (h0 - l0 > 1) {
-                        int mid = (l0 + h0) >> 1;
-                        if (po[mid] <= php) l0 = mid; else h0 = mid;
-                    }
+                    int qb = (int)((php - phio0) * S.fpb);                 // Eq. (46): bucket, bounded scan
+                    int l0 = pbk[qb < n_pb - 1 ? qb : n_pb - 1];
+                    while (l0 > 0 && po[l0] > php) --l0;
+                    while (l0 < nfp - 1 && po[l0 + 1] <= php) ++l0;
                     const double4 A = tr[l0], Cn = tr[l0 + 1];
-                    double wp = (php - A.z) / (Cn.z - A.z);
+                    double wp = (php - po[l0]) * ipo[l0];
                     wp = fmin(1.0, fmax(0.0, wp));
                     const double Fp = A.x + wp * (Cn.x - A.x);
                     if (Fp != 0.0) {
                         vis = true;
-                        const double zp = A.y + wp * (Cn.y - A.y);
                         const double mu = fmin(mu_hi, fmax(mu_lo, A.w + wp * (Cn.w - A.w)));
-                        int lo = 0, hi = nmu - 1;
-                        while (hi - lo > 1) {
-                            int mid = (lo + hi) >> 1;
-                            if (axmu[mid] <= mu) lo = mid; else hi = mid;
-                        }
-                        double w[4] = {0.0, 0.0, 0.0, 0.0};
+                        int qm = (int)((mu - mu_lo) * S.mu_ibw);               // bucket, bounded scan
+                        int lo = mbk[qm < S.mu_nb - 1 ? qm : S.mu_nb - 1];
+                        while (lo > 0 && axmu[lo] > mu) --lo;
+                        while (lo < nmu - 2 && axmu[lo + 1] <= mu) ++lo;
+                        const double *cf = mcf + 4 * lo;
+                        double v0, v1, v2, v3;
                         if (lo < 3 || lo == nmu - 2) {
-                            double t = (mu - axmu[lo]) / (axmu[lo + 1] - axmu[lo]);
+                            const double t = (mu - axmu[lo]) * cf[0];
                             m0 = lo < nmu - 4 ? lo : nmu - 4;
-                            w[lo - m0] = 1.0 - t;
-                            w[lo + 1 - m0] = t;
+                            const int sl = lo - m0;
+                            v0 = sl == 0 ? 1.0 - t : 0.0;
+                            v1 = sl == 0 ? t : (sl == 1 ? 1.0 - t : 0.0);
+                            v2 = sl == 1 ? t : (sl == 2 ? 1.0 - t : 0.0);
+                            v3 = sl == 2 ? t : 0.0;
                         } else {
                             m0 = lo - 1;
-#pragma unroll
-                            for (int q4 = 0; q4 < 4; ++q4) {
-                                double num = 1.0, den = 1.0;
-#pragma unroll
-                                for (int s2 = 0; s2 < 4; ++s2) {
-                                    if (s2 == q4) continue;
-                                    num *= mu - axmu[m0 + s2];
-                                    den *= axmu[m0 + q4] - axmu[m0 + s2];
-                                }
-                                w[q4] = num / den;
-                            }
+                            const double d0 = mu - axmu[m0], d1 = mu - axmu[m0 + 1], d2 = mu - axmu[m0 + 2],
+                                         d3 = mu - axmu[m0 + 3];
+                            const double p01 = d0 * d1, p23 = d2 * d3;
+                            v0 = d1 * p23 * cf[0];
+                            v1 = d0 * p23 * cf[1];
+                            v2 = p01 * d3 * cf[2];
+                            v3 = p01 * d2 * cf[3];
                         }
                         const double sc = Fp * (double)mc.T3;
-                        w0f = (float)(w[0] * sc);
-                        w1f = (float)(w[1] * sc);
-                        w2f = (float)(w[2] * sc);
-                        w3f = (float)(w[3] * sc);
+                        w0f = (float)(v0 * sc);
+                        w1f = (float)(v1 * sc);
+                        w2f = (float)(v2 * sc);
+                        w3f = (float)(v3 * sc);
                         tw = mc.t;
-                        const double T0 = log10(zp) * ihx + S.tb0 - mc.lkT * ihx;
+                        // x position at zp = z_A (1 + wp q_A) and the patch's kT
+                        const double T0 = A.z + (double)x_shift(wp * A.y, S.ixl) - mc.lkT * ihx;
                         const double fl = floor(T0);
                         I0 = (int)fl;
                         fr = (float)(T0 - fl);
@@ -351,7 +371,8 @@ size_t accum_map_lds(const DevSpec &S)
 {
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.n_fp + 2) & ~1) + sizeof(double) * ((S.nmu + 1) & ~1)
          + sizeof(float) * 2 * (size_t)S.nmu * S.map_wm + sizeof(float4) * kMapWaves * 64
-         + sizeof(float) * kMapWaves * 68;
+         + sizeof(float) * kMapWaves * 68 + sizeof(double) * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
+         + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb);
 }
 
 hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double *params, const double *map, int B,
