@@ -426,8 +426,16 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     W.counts = pl->dalloc<double>(BM * S.P * S.C);
     W.ll_part = pl->dalloc<double>(BM * loglike_blocks(S.P * S.C));
     W.ll_bad = pl->dalloc<int32_t>(BM * loglike_blocks(S.P * S.C));
+    {
+        std::vector<double> lf(kLogFact);
+        for (int d = 0; d < kLogFact; ++d) lf[d] = std::lgamma(d + 1.0);
+        W.lfact = pl->upload(lf.data(), lf.size());
+        std::vector<unsigned> z(BM, 0u);
+        W.ll_done = pl->upload(z.data(), z.size());
+    }
     pl->d_list = pl->dalloc<int32_t>(BM * R);
     bool ok = W.stars && W.rings && W.table && W.trace && W.vis_pairs && W.ncells && W.counts && W.ll_part && W.ll_bad
+              && W.lfact && W.ll_done
            && pl->d_list
            && S.glx && S.glw && S.energy && S.rsp32;
     if (S.intensity == PPM_I_TABLE) {

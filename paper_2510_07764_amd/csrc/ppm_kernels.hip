@@ -1163,12 +1163,18 @@ __global__ __launch_bounds__(256) void k_fold_f64(const double *A, const double 
 // ---------------------------------------------------------------------------
 constexpr int kLLChunk = 512;    // bins per block of the first likelihood stage
 
-__global__ __launch_bounds__(256) void k_loglike_part(const double *counts, const double *bkg, const int32_t *data,
-                                                      int PC, double *part, int32_t *bad)
+// Block = kLLChunk bins of one instance: per-block sums, then the block that
+// finishes last for the instance (a per-instance counter) adds the block sums
+// in block order (wave 0: lane-strided sums, then a fixed butterfly) and
+// resets the counter for the next call.
+__global__ __launch_bounds__(256) void k_loglike(const StarRec *stars, const double *counts, const double *bkg,
+                                                 const int32_t *data, const double *lfact, int PC, double *part,
+                                                 int32_t *bad, unsigned *done, double *logl)
 {
-    const int b = blockIdx.y, blk = blockIdx.x;
+    const int b = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
     __shared__ double red[256];
     __shared__ int nb[256];
+    __shared__ bool last;
     double s = 0.0;
     int nbad = 0;
     const double *m = counts + (size_t)b * PC;
@@ -1178,7 +1184,7 @@ __global__ __launch_bounds__(256) void k_loglike_part(const double *counts, cons
         double mi = bkg ? m[i] + bkg[i] : m[i];   // model plus background counts
         if (d == 0) { s -= mi; continue; }
         if (!(mi > 0.0)) { ++nbad; continue; }
-        s += d * log(mi) - mi - lgamma(d + 1.0);
+        s += d * log(mi) - mi - ((unsigned)d < (unsigned)kLogFact ? lfact[d] : lgamma(d + 1.0));   // log d!, tabulated for 0 <= d < kLogFact
     }
     red[threadIdx.x] = s;
     nb[threadIdx.x] = nbad;
@@ -1191,30 +1197,32 @@ __global__ __launch_bounds__(256) void k_loglike_part(const double *counts, cons
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        part[(size_t)b * gridDim.x + blk] = red[0];
-        bad[(size_t)b * gridDim.x + blk] = nb[0];
+        part[(size_t)b * nblk + blk] = red[0];
+        bad[(size_t)b * nblk + blk] = nb[0];
+        __threadfence();                                   // the block sum is visible before the count
+        last = atomicAdd(&done[b], 1u) == (unsigned)(nblk - 1);
     }
-}
-
-// one wave per instance: lane-strided partial sums, then a fixed butterfly
-__global__ __launch_bounds__(64) void k_loglike_final(const StarRec *stars, const double *part, const int32_t *bad,
-                                                      int nblk, int B, double *logl)
-{
-    const int b = blockIdx.x, lane = threadIdx.x;
-    double s = 0.0;
-    int nbad = 0;
-    for (int i = lane; i < nblk; i += 64) {
-        s += part[(size_t)b * nblk + i];
-        nbad += bad[(size_t)b * nblk + i];
+    __syncthreads();
+    if (!last || threadIdx.x >= 64) return;
+    __threadfence();                                       // every block's sum is visible to this one
+    const volatile double *vp = part + (size_t)b * nblk;
+    const volatile int32_t *vb = bad + (size_t)b * nblk;
+    const int lane = threadIdx.x;
+    double t = 0.0;
+    int tb = 0;
+    for (int q = lane; q < nblk; q += 64) {
+        t += vp[q];
+        tb += vb[q];
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        s += __shfl_xor(s, o, 64);
-        nbad += __shfl_xor(nbad, o, 64);
+        t += __shfl_xor(t, o, 64);
+        tb += __shfl_xor(tb, o, 64);
     }
     if (lane == 0) {
-        if (nbad || stars[b].status != PPM_INST_OK) s = -INFINITY;
-        logl[b] = s;
+        if (tb || stars[b].status != PPM_INST_OK) t = -INFINITY;
+        logl[b] = t;
+        done[b] = 0u;
     }
 }
 
@@ -1360,9 +1368,8 @@ hipError_t launch_loglike(const Workspace &W, const double *counts, const double
                           const int32_t *data, double *logl, hipStream_t st)
 {
     const int nblk = (PC + kLLChunk - 1) / kLLChunk;
-    hipLaunchKernelGGL(k_loglike_part, dim3(nblk, B), dim3(256), 0, st, counts, bkg, data, PC, W.ll_part, W.ll_bad);
-    hipLaunchKernelGGL(k_loglike_final, dim3(B), dim3(64), 0, st, W.stars, W.ll_part, W.ll_bad, nblk,
-                       B, logl);
+    hipLaunchKernelGGL(k_loglike, dim3(nblk, B), dim3(256), 0, st, W.stars, counts, bkg, data, W.lfact, PC, W.ll_part,
+                       W.ll_bad, W.ll_done, logl);
     return hipGetLastError();
 }
 

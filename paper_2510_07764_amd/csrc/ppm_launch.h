@@ -23,6 +23,8 @@ struct Workspace {
     int32_t *ncells;       // [B] per-instance grid override
     double *ll_part;       // [B][loglike_blocks] first-stage likelihood sums
     int32_t *ll_bad;       // [B][loglike_blocks] bins with m <= 0 and d > 0
+    double *lfact;         // [kLogFact] log d! for the first kLogFact counts
+    unsigned *ll_done;     // [B] blocks of the likelihood kernel done per instance (zero between calls)
     // gradient plans only
     double4 *table_u;      // [B][R_tot][n_alpha] d/du (psi, psi', T, T') at fixed alpha
     double4 *tangent;      // [B][R_tot][n_fp + 1][5] tangents of (F, z, phi_o, mu)
@@ -41,6 +43,7 @@ constexpr int kPhaseTile = 8;    // default phases per block of the accumulation
 constexpr int kMinTileGrad = 8;  // smallest adjoint phase tile (sizes the per-block adjoint sums)
 constexpr int kMaxTile = 256;    // largest phase tile either kernel accepts
 constexpr int kGradAcc = 9;      // per-ring adjoint sums of the accumulation kernel
+constexpr int kLogFact = 1024;   // counts whose log d! comes from a table
 #ifndef PPM_FWD_WAVES
 #define PPM_FWD_WAVES 12
 #endif
