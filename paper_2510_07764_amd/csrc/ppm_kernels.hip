@@ -488,8 +488,10 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace(DevSpec S, const int32_
             if (w > S.W_max) w = S.W_max;   // cannot happen for surface speeds below 0.6 c
             gp->xw0 = w0;
             gp->xw = w;
-            // every interval used lies in [floor(tlo), floor(thi)]
-            gp->interior = (floor(tlo) >= 1.0 && floor(thi) <= S.nx - 3) ? 1 : 0;
+            // every interval used lies in [floor(tlo), floor(thi)], up to one interval
+            // of slip from the rounding of a pair's x position: clear of the axis ends
+            // with that margin, every interval is cubic and every column in the window
+            gp->interior = (floor(tlo) >= 2.0 && floor(thi) <= S.nx - 4) ? 1 : 0;
         } else {
             gp->xw0 = 0;
             gp->xw = 0;
