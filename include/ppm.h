@@ -236,9 +236,11 @@ int ppm_set_tiles(ppm_plan *plan, const ppm_tiles *tiles);
  * 16, 24, 32;
  * a candidate that gives the same number of tiles over n_phase as a smaller
  * one is skipped) it times whole evaluations of the given batch (params_dev,
- * B, n_cells_host as for ppm_forward): one warm-up call, then `reps` calls
- * (1..1000) each between two HIP events on `stream`.  It keeps the candidate
- * with the smallest median time and sets it on the plan; the forward tile is
+ * B, n_cells_host as for ppm_forward), each between two HIP events on
+ * `stream`: about 100 ms of untimed warm-up evaluations first (the device
+ * clock ramps up under load), then every candidate once per repetition, in
+ * turn, for `reps` repetitions (1..1000).  It keeps the candidate with the
+ * smallest median time and sets it on the plan; the forward tile is
  * chosen first and then used while the adjoint tile is timed.  Adjoint calls
  * run on all-zero data (their cost does not depend on the data) and need
  * two temporary device buffers, allocated and freed here.  Synchronises the

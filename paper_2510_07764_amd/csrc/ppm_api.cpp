@@ -776,30 +776,60 @@ struct DevBuf {
     }
 };
 
-// Median over `reps` timed calls of run() (one warm-up call first).
-template <typename Run>
-int median_ms(Run &&run, int reps, hipStream_t st, EventSet &es, double *ms)
+// Per-candidate medians of `reps` timed calls of run() (set(c) selects
+// candidate c).  The device is first kept busy for about 100 ms with the
+// first candidate (its clock ramps up under load, and drops again when idle),
+// and the candidates are then timed in turn, repetition by repetition, so that
+// any remaining drift reaches every candidate alike.
+template <typename Set, typename Run>
+int time_candidates(const std::vector<int> &cands, Set &&set, Run &&run, int reps, hipStream_t st,
+                    std::vector<double> &med)
 {
+    const int nc = (int)cands.size();
+    EventSet es;
+    es.ev.assign(2 * (size_t)nc * reps + 2, nullptr);
+    for (auto &e : es.ev) {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return hip_fail(r, "autotune event");
+    }
     const char *what = "autotune";
-    hipError_t e = run(&what);
+    set(cands[0]);
+    hipError_t e = hipEventRecord(es.ev[0], st);
+    if (e == hipSuccess) e = run(&what);
+    if (e == hipSuccess) e = hipEventRecord(es.ev[1], st);
+    if (e == hipSuccess) e = hipEventSynchronize(es.ev[1]);
     if (e != hipSuccess) return hip_fail(e, what);
-    e = hipEventRecord(es.ev[0], st);
-    if (e != hipSuccess) return hip_fail(e, "autotune event");
-    for (int i = 0; i < reps; ++i) {
+    float t0 = 0.0f;
+    e = hipEventElapsedTime(&t0, es.ev[0], es.ev[1]);
+    if (e != hipSuccess) return hip_fail(e, "autotune elapsed");
+    int warm = t0 > 0.0f ? (int)std::ceil(100.0 / t0) : 1;
+    warm = warm < 1 ? 1 : (warm > 500 ? 500 : warm);
+    for (int i = 0; i < warm; ++i) {
         e = run(&what);
         if (e != hipSuccess) return hip_fail(e, what);
-        e = hipEventRecord(es.ev[i + 1], st);
-        if (e != hipSuccess) return hip_fail(e, "autotune event");
     }
-    e = hipEventSynchronize(es.ev[reps]);
+    for (int r = 0; r < reps; ++r)
+        for (int c = 0; c < nc; ++c) {
+            set(cands[c]);
+            hipEvent_t *ev = &es.ev[2 + 2 * ((size_t)r * nc + c)];
+            e = hipEventRecord(ev[0], st);
+            if (e == hipSuccess) e = run(&what);
+            if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+            if (e != hipSuccess) return hip_fail(e, what);
+        }
+    e = hipEventSynchronize(es.ev.back());
     if (e != hipSuccess) return hip_fail(e, "autotune sync");
+    med.assign(nc, 0.0);
     std::vector<float> t(reps);
-    for (int i = 0; i < reps; ++i) {
-        e = hipEventElapsedTime(&t[i], es.ev[i], es.ev[i + 1]);
-        if (e != hipSuccess) return hip_fail(e, "autotune elapsed");
+    for (int c = 0; c < nc; ++c) {
+        for (int r = 0; r < reps; ++r) {
+            hipEvent_t *ev = &es.ev[2 + 2 * ((size_t)r * nc + c)];
+            e = hipEventElapsedTime(&t[r], ev[0], ev[1]);
+            if (e != hipSuccess) return hip_fail(e, "autotune elapsed");
+        }
+        std::sort(t.begin(), t.end());
+        med[c] = reps % 2 ? t[reps / 2] : 0.5 * (t[reps / 2 - 1] + t[reps / 2]);
     }
-    std::sort(t.begin(), t.end());
-    *ms = reps % 2 ? t[reps / 2] : 0.5 * (t[reps / 2 - 1] + t[reps / 2]);
     return PPM_OK;
 }
 
@@ -834,33 +864,27 @@ int ppm_autotune(ppm_plan *pl, const double *params_dev, int B, const int32_t *n
     const int pt0 = S.pt_fwd, pa0 = S.pt_adj;
     ppm_tune_report rep;
     std::memset(&rep, 0, sizeof(rep));
-    EventSet es;
-    es.ev.assign(reps + 1, nullptr);
-    for (auto &e : es.ev) {
-        hipError_t r = hipEventCreate(&e);
-        if (r != hipSuccess) return hip_fail(r, "ppm_autotune event");
-    }
     auto restore = [&](int code) {
         S.pt_fwd = pt0;
         S.pt_adj = pa0;
         return code;
     };
     // forward tile
+    const std::vector<int> fc = tile_candidates({4, 8, 12, 16, 20, 24, 28, 32, 48, 64, 96, 128}, S.P);
+    std::vector<double> fms;
+    rc = time_candidates(fc, [&](int t) { S.pt_fwd = t; }, [&](const char **what) {
+        *what = "ppm_autotune forward";
+        return run_forward(pl, params_dev, B, nc, st, nullptr, pl->W.counts);
+    }, reps, st, fms);
+    if (rc) return restore(rc);
     double best = 0.0;
     int best_t = pt0;
-    for (int t : tile_candidates({4, 8, 12, 16, 20, 24, 28, 32, 48, 64, 96, 128}, S.P)) {
-        S.pt_fwd = t;
-        double ms = 0.0;
-        rc = median_ms([&](const char **what) {
-            *what = "ppm_autotune forward";
-            return run_forward(pl, params_dev, B, nc, st, nullptr, pl->W.counts);
-        }, reps, st, es, &ms);
-        if (rc) return restore(rc);
-        rep.fwd_tile[rep.n_fwd] = t;
-        rep.fwd_ms[rep.n_fwd++] = ms;
-        if (rep.n_fwd == 1 || ms < best) {
-            best = ms;
-            best_t = t;
+    for (size_t c = 0; c < fc.size(); ++c) {
+        rep.fwd_tile[rep.n_fwd] = fc[c];
+        rep.fwd_ms[rep.n_fwd++] = fms[c];
+        if (c == 0 || fms[c] < best) {
+            best = fms[c];
+            best_t = fc[c];
         }
     }
     S.pt_fwd = best_t;
@@ -872,18 +896,18 @@ int ppm_autotune(ppm_plan *pl, const double *params_dev, int B, const int32_t *n
         if (e == hipSuccess) e = hipMemsetAsync(data.p, 0, sizeof(int32_t) * (size_t)S.P * S.C, st);
         if (e != hipSuccess) return restore(hip_fail(e, "ppm_autotune temporary buffers"));
         int best_a = pa0;
-        for (int t : tile_candidates({8, 16, 24, 32}, S.P)) {
-            S.pt_adj = t;
-            double ms = 0.0;
-            rc = median_ms([&](const char **what) {
-                return run_grad(pl, params_dev, B, nc, (const int32_t *)data.p, (double *)grad.p, st, what);
-            }, reps, st, es, &ms);
-            if (rc) return restore(rc);
-            rep.grad_tile[rep.n_grad] = t;
-            rep.grad_ms[rep.n_grad++] = ms;
-            if (rep.n_grad == 1 || ms < best) {
-                best = ms;
-                best_a = t;
+        const std::vector<int> gc = tile_candidates({8, 16, 24, 32}, S.P);
+        std::vector<double> gms;
+        rc = time_candidates(gc, [&](int t) { S.pt_adj = t; }, [&](const char **what) {
+            return run_grad(pl, params_dev, B, nc, (const int32_t *)data.p, (double *)grad.p, st, what);
+        }, reps, st, gms);
+        if (rc) return restore(rc);
+        for (size_t c = 0; c < gc.size(); ++c) {
+            rep.grad_tile[rep.n_grad] = gc[c];
+            rep.grad_ms[rep.n_grad++] = gms[c];
+            if (c == 0 || gms[c] < best) {
+                best = gms[c];
+                best_a = gc[c];
             }
         }
         S.pt_adj = best_a;
@@ -910,30 +934,24 @@ int ppm_autotune_map(ppm_plan *pl, const double *params_dev, int B, const double
     const int pt0 = S.pt_fwd;
     ppm_tune_report rep;
     std::memset(&rep, 0, sizeof(rep));
-    EventSet es;
-    es.ev.assign(reps + 1, nullptr);
-    for (auto &e : es.ev) {
-        hipError_t r = hipEventCreate(&e);
-        if (r != hipSuccess) return hip_fail(r, "ppm_autotune_map event");
+    const std::vector<int> mc = tile_candidates({8, 16, 32}, S.P);
+    std::vector<double> mms;
+    rc = time_candidates(mc, [&](int t) { S.pt_fwd = t; }, [&](const char **what) {
+        *what = "ppm_autotune_map forward";
+        return run_forward_map(pl, params_dev, B, map_dev, st, nullptr, pl->W.counts);
+    }, reps, st, mms);
+    if (rc) {
+        S.pt_fwd = pt0;
+        return rc;
     }
     double best = 0.0;
     int best_t = pt0;
-    for (int t : tile_candidates({8, 16, 32}, S.P)) {
-        S.pt_fwd = t;
-        double ms = 0.0;
-        rc = median_ms([&](const char **what) {
-            *what = "ppm_autotune_map forward";
-            return run_forward_map(pl, params_dev, B, map_dev, st, nullptr, pl->W.counts);
-        }, reps, st, es, &ms);
-        if (rc) {
-            S.pt_fwd = pt0;
-            return rc;
-        }
-        rep.fwd_tile[rep.n_fwd] = t;
-        rep.fwd_ms[rep.n_fwd++] = ms;
-        if (rep.n_fwd == 1 || ms < best) {
-            best = ms;
-            best_t = t;
+    for (size_t c = 0; c < mc.size(); ++c) {
+        rep.fwd_tile[rep.n_fwd] = mc[c];
+        rep.fwd_ms[rep.n_fwd++] = mms[c];
+        if (c == 0 || mms[c] < best) {
+            best = mms[c];
+            best_t = mc[c];
         }
     }
     S.pt_fwd = best_t;
