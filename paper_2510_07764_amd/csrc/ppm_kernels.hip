@@ -792,6 +792,11 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     int16_t *mbk = pbk + 2 * nfp;                              // mu_nb mu buckets
     const int n_pb = 2 * nfp;
     const double4 *gtr = trace + ((size_t)b * S.R_tot + r) * (nfp + 1);
+    // phases of the tile go to the waves as they finish (waves start on
+    // phases 0 .. NW-1); each phase is done by one wave, so the sums do not
+    // depend on the assignment
+    __shared__ int k_next;
+    if (threadIdx.x == 0) k_next = NW;
     // LDS trace per fine-phase sample i: (F, z_{i+1}/z_i - 1, x position of
     // E_0 at z_i, mu); phi_o in po
     for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
@@ -851,7 +856,7 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     const int xw0 = g.xw0, xw = g.xw;
     int npairs = 0;
     const int k_begin = tile * PT;
-    for (int kk = wave; kk < PT; kk += NW) {
+    for (int kk = wave; kk < PT;) {
         const int k = k_begin + kk;
         if (k >= P) break;
         float acc[EPL];
@@ -940,6 +945,9 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
             int e = lane + 64 * m;
             if (e < E) out[e] = (float)(acc[m] * (scale / S.energy[e]));
         }
+        int nk = 0;
+        if (lane == 0) nk = atomicAdd(&k_next, 1);
+        kk = __builtin_amdgcn_readfirstlane(nk);
     }
     if (lane == 0 && npairs) atomicAdd(&vis_pairs[(size_t)b * S.R_tot + r], npairs);
 }
