@@ -392,18 +392,20 @@ __device__ inline float dpp_mov(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
 }
 
-// sum over the 64 lanes, returned uniform: DPP within rows of 16 lanes
-// (quad swaps, half-row and row mirrors), row broadcasts 15 and 31 across
-// rows, the total read from lane 63
-__device__ inline float wave_total(float v)
+// sum over the 64 lanes, in every lane: DPP butterflies within rows of 16
+// lanes (quad swaps, half-row and row mirrors), then swaps of rows 0/1 and 2/3
+// (swizzle, xor 16) and of the two halves (lane permute, xor 32).  Every lane
+// adds the same operands, so all lanes hold the same bits: for lane 63 the
+// order is (R3 + R2) + (R1 + R0) over the row sums R.
+__device__ inline float wave_allsum(float v, int bp32)
 {
     v += dpp_mov<0xB1>(v);
     v += dpp_mov<0x4E>(v);
     v += dpp_mov<0x141>(v);
     v += dpp_mov<0x140>(v);
-    v += dpp_mov<0x142, 0xa>(v);
-    v += dpp_mov<0x143, 0xc>(v);
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+    v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+    v += __int_as_float(__builtin_amdgcn_ds_bpermute(bp32, __float_as_int(v)));
+    return v;
 }
 
 __device__ inline double wave_sum_d(double v)
@@ -439,6 +441,112 @@ __device__ inline void offset_coeffs(const RingRec &g, int j, double &ca, double
     } else {
         ca = -1.0 + (2.0 * j + 1.0) / g.n_cells;
         cb = 0.0;
+    }
+}
+
+// Stage B of k_accum_adj for the visible pairs (mask) of one 64-cell group;
+// the pair's lane keeps its three energy sums in R0, R1, R2.  The wave totals
+// of a pair are taken while the next pair's table rows load (their latency is
+// the loop's longest chain), the last pair's after the loop.  INTERIOR: the
+// ring's x window stays one interval clear of the table's first and last
+// intervals (every interval an energy can use is cubic and every stencil
+// column lies in the window; columns past it hold zeros), so the bounds tests
+// drop out.
+template <int EPL, bool INTERIOR>
+__device__ __forceinline__ void adj_pairs(uint64_t mask, const float (&wv)[8], float fr, float Fpf, int I0, int m0,
+                                          int lane, int bp32, const float *tab, const float2 *tab2, int W, int xw0,
+                                          int xw, int nx, float4 *Nw, float4 *Qw, const float (&tbr)[EPL],
+                                          const float (&Gr)[EPL], float &R0, float &R1, float &R2, double &accT,
+                                          double &accG)
+{
+    float ps0 = 0.f, psx = 0.f, psm = 0.f;   // lane sums of the previous pair
+    int pp = -1;                            // its lane (none yet)
+    while (mask) {
+        const int p = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const float pw0 = readlane_f(wv[0], p), pw1 = readlane_f(wv[1], p), pw2 = readlane_f(wv[2], p),
+                    pw3 = readlane_f(wv[3], p);
+        const float pv0 = readlane_f(wv[4], p), pv1 = readlane_f(wv[5], p), pv2 = readlane_f(wv[6], p),
+                    pv3 = readlane_f(wv[7], p);
+        const float pfr = readlane_f(fr, p), pF = readlane_f(Fpf, p);
+        const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
+        // the pair's four mu rows of the table and of its logT / log g planes at
+        // x node pI0 - 1 + lane (zero outside the window)
+        int col = pI0 - 1 + lane - xw0;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        float2 b0 = make_float2(0.f, 0.f), b1 = b0, b2 = b0, b3 = b0;
+        if (INTERIOR || (col >= 0 && col < xw)) {
+            if (INTERIOR) col = col < W - 1 ? col : W - 1;
+            const float *t0 = tab + pm0 * W + col;
+            const float2 *u0 = tab2 + pm0 * W + col;
+            a0 = t0[0]; a1 = t0[W]; a2 = t0[2 * W]; a3 = t0[3 * W];
+            b0 = u0[0]; b1 = u0[W]; b2 = u0[2 * W]; b3 = u0[3 * W];
+        }
+        {
+            const float t0 = wave_allsum(ps0, bp32), t1 = wave_allsum(psx, bp32), t2 = wave_allsum(psm, bp32);
+            const bool mine = lane == pp;
+            R0 = mine ? t0 : R0;
+            R1 = mine ? t1 : R1;
+            R2 = mine ? t2 : R2;
+        }
+        float4 nv;
+        nv.x = pw0 * a0 + pw1 * a1 + pw2 * a2 + pw3 * a3;
+        nv.y = pv0 * a0 + pv1 * a1 + pv2 * a2 + pv3 * a3;
+        nv.z = pw0 * b0.x + pw1 * b1.x + pw2 * b2.x + pw3 * b3.x;
+        nv.w = pw0 * b0.y + pw1 * b1.y + pw2 * b2.y + pw3 * b3.y;
+        Nw[lane] = nv;
+        wave_sync();
+        {
+            const float4 n1 = Nw[lane + 1], n2 = Nw[lane + 2], n3 = Nw[lane + 3];
+            float4 q0, q1, q2, q3;
+            const int gi = pI0 + lane;
+            if (INTERIOR || (gi >= 1 && gi <= nx - 3)) {
+                q0 = cubic_quad(nv.x, n1.x, n2.x, n3.x);
+                q1 = cubic_quad(nv.y, n1.y, n2.y, n3.y);
+                q2 = cubic_quad(nv.z, n1.z, n2.z, n3.z);
+                q3 = cubic_quad(nv.w, n1.w, n2.w, n3.w);
+            } else if (gi == 0 || gi == nx - 2) {
+                q0 = make_float4(n1.x, n2.x - n1.x, 0.f, 0.f);
+                q1 = make_float4(n1.y, n2.y - n1.y, 0.f, 0.f);
+                q2 = make_float4(n1.z, n2.z - n1.z, 0.f, 0.f);
+                q3 = make_float4(n1.w, n2.w - n1.w, 0.f, 0.f);
+            } else {
+                q0 = q1 = q2 = q3 = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            Qw[lane] = q0;
+            Qw[64 + lane] = q1;
+            Qw[128 + lane] = q2;
+            Qw[192 + lane] = q3;
+        }
+        wave_sync();
+        float s0 = 0.f, sx = 0.f, sm = 0.f, sT = 0.f, sg = 0.f;
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) {
+            const float t = pfr + tbr[m];
+            const float f = __builtin_amdgcn_fractf(t);
+            const int ix = (int)t;
+            const float4 qa = Qw[ix], qm = Qw[64 + ix], qt = Qw[128 + ix], qg = Qw[192 + ix];
+            const float G = Gr[m];
+            s0 += G * horner(qa, f);
+            sx += G * (qa.y + f * (2.0f * qa.z + 3.0f * f * qa.w));
+            sm += G * horner(qm, f);
+            sT += G * horner(qt, f);
+            sg += G * horner(qg, f);
+        }
+        wave_sync();
+        accT += (double)(pF * sT);
+        accG += (double)(pF * sg);
+        ps0 = s0;
+        psx = sx;
+        psm = sm;
+        pp = p;
+    }
+    if (pp >= 0) {
+        const float t0 = wave_allsum(ps0, bp32), t1 = wave_allsum(psx, bp32), t2 = wave_allsum(psm, bp32);
+        const bool mine = lane == pp;
+        R0 = mine ? t0 : R0;
+        R1 = mine ? t1 : R1;
+        R2 = mine ? t2 : R2;
     }
 }
 
@@ -506,6 +614,7 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
     float4 *Nw = Nb + wave * 68;
     float4 *Qw = Qb + wave * 4 * 64;
     if (lane < 4) Nw[64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int bp32 = (lane ^ 32) << 2;                     // byte address of the xor-32 partner
     const RingTan rt = ringtan[slot];
     const double phio0 = trace[slot * (nfp + 1)].z;        // phi_o of sample 0
     const double inv2pi = 1.0 / kTwoPi;
@@ -612,75 +721,13 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
             const uint64_t vmask = __ballot(vis);
             // ---------------- stage B: the visible pairs one after another
             float R0 = 0.f, R1 = 0.f, R2 = 0.f;
-            uint64_t mask = vmask;
-            while (mask) {
-                const int p = __ffsll((unsigned long long)mask) - 1;
-                mask &= mask - 1;
-                const float pw0 = readlane_f(w0, p), pw1 = readlane_f(w1, p), pw2 = readlane_f(w2, p),
-                            pw3 = readlane_f(w3, p);
-                const float pv0 = readlane_f(v0, p), pv1 = readlane_f(v1, p), pv2 = readlane_f(v2, p),
-                            pv3 = readlane_f(v3, p);
-                const float pfr = readlane_f(fr, p), pF = readlane_f(Fpf, p);
-                const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
-                const int col = pI0 - 1 + lane - xw0;
-                float4 nv = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (col >= 0 && col < xw) {
-                    const float *t0 = tab + pm0 * W + col;
-                    const float2 *u0 = tab2 + pm0 * W + col;
-                    const float a0 = t0[0], a1 = t0[W], a2 = t0[2 * W], a3 = t0[3 * W];
-                    const float2 b0 = u0[0], b1 = u0[W], b2 = u0[2 * W], b3 = u0[3 * W];
-                    nv.x = pw0 * a0 + pw1 * a1 + pw2 * a2 + pw3 * a3;
-                    nv.y = pv0 * a0 + pv1 * a1 + pv2 * a2 + pv3 * a3;
-                    nv.z = pw0 * b0.x + pw1 * b1.x + pw2 * b2.x + pw3 * b3.x;
-                    nv.w = pw0 * b0.y + pw1 * b1.y + pw2 * b2.y + pw3 * b3.y;
-                }
-                Nw[lane] = nv;
-                wave_sync();
-                {
-                    const float4 n1 = Nw[lane + 1], n2 = Nw[lane + 2], n3 = Nw[lane + 3];
-                    const int gi = pI0 + lane;
-                    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0, q3 = q0;
-                    if (gi >= 0 && gi <= nx - 2) {
-                        if (gi == 0 || gi == nx - 2) {
-                            q0 = make_float4(n1.x, n2.x - n1.x, 0.f, 0.f);
-                            q1 = make_float4(n1.y, n2.y - n1.y, 0.f, 0.f);
-                            q2 = make_float4(n1.z, n2.z - n1.z, 0.f, 0.f);
-                            q3 = make_float4(n1.w, n2.w - n1.w, 0.f, 0.f);
-                        } else {
-                            q0 = cubic_quad(nv.x, n1.x, n2.x, n3.x);
-                            q1 = cubic_quad(nv.y, n1.y, n2.y, n3.y);
-                            q2 = cubic_quad(nv.z, n1.z, n2.z, n3.z);
-                            q3 = cubic_quad(nv.w, n1.w, n2.w, n3.w);
-                        }
-                    }
-                    Qw[lane] = q0;
-                    Qw[64 + lane] = q1;
-                    Qw[128 + lane] = q2;
-                    Qw[192 + lane] = q3;
-                }
-                wave_sync();
-                float s0 = 0.f, sx = 0.f, sm = 0.f, sT = 0.f, sg = 0.f;
-#pragma unroll
-                for (int m = 0; m < EPL; ++m) {
-                    const float t = pfr + tbr[m];
-                    const float f = __builtin_amdgcn_fractf(t);
-                    const int ix = (int)t;
-                    const float4 qa = Qw[ix], qm = Qw[64 + ix], qt = Qw[128 + ix], qg = Qw[192 + ix];
-                    const float G = Gr[m];
-                    s0 += G * horner(qa, f);
-                    sx += G * (qa.y + f * (2.0f * qa.z + 3.0f * f * qa.w));
-                    sm += G * horner(qm, f);
-                    sT += G * horner(qt, f);
-                    sg += G * horner(qg, f);
-                }
-                wave_sync();
-                accT += (double)(pF * sT);
-                accG += (double)(pF * sg);
-                s0 = wave_total(s0);
-                sx = wave_total(sx);
-                sm = wave_total(sm);
-                if (lane == p) { R0 = s0; R1 = sx; R2 = sm; }
-            }
+            const float wv[8] = {w0, w1, w2, w3, v0, v1, v2, v3};
+            if (g.interior)
+                adj_pairs<EPL, true>(vmask, wv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Nw, Qw, tbr,
+                                     Gr, R0, R1, R2, accT, accG);
+            else
+                adj_pairs<EPL, false>(vmask, wv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Nw, Qw, tbr,
+                                      Gr, R0, R1, R2, accT, accG);
             // ---------------- stage C: chain rule per pair, FP64
             if (vis) {
                 const double4 A = tr[lo], Cn = tr[lo + 1];
