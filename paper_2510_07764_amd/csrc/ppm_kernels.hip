@@ -1058,49 +1058,75 @@ __global__ __launch_bounds__(256) void k_reduce(DevSpec S, const StarRec *stars,
 
 // FP32 partials with E % 4 == 0: a thread owns four consecutive energies and
 // reads them with 16-byte loads; eight ring groups per block.
-constexpr int kReduceGroups = 16;   // waves of k_reduce4, each summing every 16th ring
+constexpr int kReduceGroups = 16;   // ring groups of k_reduce4, group g summing rings g, g + 16, ...
+constexpr int kReduceBatch = 16;    // ring loads in flight per lane
 
-__global__ __launch_bounds__(64 * kReduceGroups) void k_reduce4(DevSpec S, const StarRec *stars, const RingRec *rings,
+// Block = (phase k, 128 energies, instance b), 8 waves: lane l of wave w
+// holds energies 4 (l % 32) .. +3 of the block's 128 for ring group
+// 2 w + l / 32.  Each group sums its rings in increasing order, then the 16
+// group sums are added in group order (groups 0..3 take one energy of the
+// four each): a fixed order independent of the launch.  256 blocks per
+// instance at 128 phases keep every CU busy.
+__global__ __launch_bounds__(32 * kReduceGroups) void k_reduce4(DevSpec S, const StarRec *stars, const RingRec *rings,
                                                  const float *partial, double *flux, float *fold_in)
 {
     extern __shared__ unsigned char act[];
-    __shared__ double4 red[kReduceGroups][64];
+    __shared__ double4 red[kReduceGroups][32];
     const int k = blockIdx.x, b = blockIdx.z;
     const int E = S.E, P = S.P, R = S.R_tot;
-    const int el = threadIdx.x & 63, grp = threadIdx.x >> 6;
-    const int e = (blockIdx.y * 64 + el) * 4;
+    const int el = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int e = (blockIdx.y * 32 + el) * 4;
+    const bool live = e < E;
+    const float *base = partial + ((size_t)b * R * P + k) * E + (live ? e : 0);
+    const size_t rs = (size_t)P * E;
+    // the first batch of partials is in flight while the ring flags are staged
+    // (a partial of an inactive ring is read but not added)
+    float4 v[kReduceBatch];
+#pragma unroll
+    for (int j = 0; j < kReduceBatch; ++j) {
+        const int r = grp + j * kReduceGroups;
+        v[j] = live && r < R ? *(const float4 *)(base + r * rs) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     for (int r = threadIdx.x; r < R; r += blockDim.x) act[r] = (unsigned char)rings[(size_t)b * R + r].active;
     __syncthreads();
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    if (e < E) {
-        const float *base = partial + ((size_t)b * R * P + k) * E + e;
-        const size_t rs = (size_t)P * E;
-#pragma unroll 4
-        for (int r = grp; r < R; r += kReduceGroups) {
-            if (!act[r]) continue;
-            const float4 v = *(const float4 *)(base + r * rs);
-            s0 += (double)v.x;
-            s1 += (double)v.y;
-            s2 += (double)v.z;
-            s3 += (double)v.w;
+    if (live) {
+        for (int r0 = grp; r0 < R; r0 += kReduceGroups * kReduceBatch) {
+            if (r0 != grp) {
+#pragma unroll
+                for (int j = 0; j < kReduceBatch; ++j) {
+                    const int r = r0 + j * kReduceGroups;
+                    v[j] = r < R ? *(const float4 *)(base + r * rs) : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kReduceBatch; ++j) {
+                const int r = r0 + j * kReduceGroups;
+                if (r < R && act[r]) {
+                    s0 += (double)v[j].x;
+                    s1 += (double)v[j].y;
+                    s2 += (double)v[j].z;
+                    s3 += (double)v[j].w;
+                }
+            }
         }
     }
     red[grp][el] = make_double4(s0, s1, s2, s3);
     __syncthreads();
-    if (grp == 0 && e < E) {
-        double t[4] = {0.0, 0.0, 0.0, 0.0};
+    // group q < 4 adds the group sums of energy component q in group order
+    if (grp < 4 && live) {
+        const int q = grp;
+        double t = 0.0;
         for (int g2 = 0; g2 < kReduceGroups; ++g2) {
-            const double4 v = red[g2][el];
-            t[0] += v.x; t[1] += v.y; t[2] += v.z; t[3] += v.w;
+            const double *v = (const double *)&red[g2][el];
+            t += v[q];
         }
         const StarRec st = stars[b];
-        const size_t o = ((size_t)b * P + k) * E + e;
-        for (int q = 0; q < 4; ++q) {
-            double sv = st.status != PPM_INST_OK ? 0.0 : t[q];
-            if (flux) flux[o + q] = sv;
-            double att = S.sigma ? exp(-st.NH * S.sigma[e + q]) : 1.0;
-            fold_in[o + q] = (float)(sv * att * (S.t_exp / P));
-        }
+        const size_t o = ((size_t)b * P + k) * E + e + q;
+        const double sv = st.status != PPM_INST_OK ? 0.0 : t;
+        if (flux) flux[o] = sv;
+        const double att = S.sigma ? exp(-st.NH * S.sigma[e + q]) : 1.0;
+        fold_in[o] = (float)(sv * att * (S.t_exp / P));
     }
 }
 
@@ -1281,7 +1307,7 @@ void launch_reduce_fold32(const DevSpec &S, const Workspace &W, int B, hipStream
                           double *counts_out)
 {
     if ((S.E & 3) == 0)
-        hipLaunchKernelGGL(k_reduce4, dim3(S.P, (S.E + 255) / 256, B), dim3(64 * kReduceGroups), S.R_tot, st, S, W.stars,
+        hipLaunchKernelGGL(k_reduce4, dim3(S.P, (S.E + 127) / 128, B), dim3(32 * kReduceGroups), S.R_tot, st, S, W.stars,
                            W.rings, W.partial32, flux_out, W.fold_in32);
     else
         hipLaunchKernelGGL((k_reduce<float, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S,
