@@ -375,8 +375,9 @@ __global__ __launch_bounds__(256) void k_subtable_tg(DevSpec S, const int32_t *l
 //           zone and the last interval; zero derivative where mu is clamped),
 //           x position of the first energy; wave ballot of visible pairs;
 //  stage B  per visible pair: lane = x node, mu contraction of the sub-table
-//           and of its logT / log g derivatives; lane = x interval, cubic
-//           coefficients of V, dV/dmu, dV/dlogT, dV/dlog g into LDS quads;
+//           and of its logT / log g derivatives; lane = x interval (the
+//           next three nodes' values by DPP wave shifts), cubic coefficients
+//           of V, dV/dmu, dV/dlogT, dV/dlog g into LDS quads;
 //           lane = EPL energies: Horner steps and the sums over e of G~ V,
 //           G~ dV/dt, G~ dV/dmu (wave totals kept by the pair's lane) and
 //           F_p G~ dV/dlogT, F_p G~ dV/dlog g (lane-local FP64 sums), with
@@ -406,6 +407,12 @@ __device__ inline float wave_allsum(float v, int bp32)
     v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
     v += __int_as_float(__builtin_amdgcn_ds_bpermute(bp32, __float_as_int(v)));
     return v;
+}
+
+// value of lane + 1 (0 in lane 63): DPP whole-wave shift
+__device__ inline float wave_next(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
 __device__ inline double wave_sum_d(double v)
@@ -455,7 +462,7 @@ __device__ inline void offset_coeffs(const RingRec &g, int j, double &ca, double
 template <int EPL, bool INTERIOR>
 __device__ __forceinline__ void adj_pairs(uint64_t mask, const float (&wv)[8], float fr, float Fpf, int I0, int m0,
                                           int lane, int bp32, const float *tab, const float2 *tab2, int W, int xw0,
-                                          int xw, int nx, float4 *Nw, float4 *Qw, const float (&tbr)[EPL],
+                                          int xw, int nx, float4 *Qw, const float (&tbr)[EPL],
                                           const float (&Gr)[EPL], float &R0, float &R1, float &R2, double &accT,
                                           double &accG)
 {
@@ -494,10 +501,12 @@ __device__ __forceinline__ void adj_pairs(uint64_t mask, const float (&wv)[8], f
         nv.y = pv0 * a0 + pv1 * a1 + pv2 * a2 + pv3 * a3;
         nv.z = pw0 * b0.x + pw1 * b1.x + pw2 * b2.x + pw3 * b3.x;
         nv.w = pw0 * b0.y + pw1 * b1.y + pw2 * b2.y + pw3 * b3.y;
-        Nw[lane] = nv;
-        wave_sync();
         {
-            const float4 n1 = Nw[lane + 1], n2 = Nw[lane + 2], n3 = Nw[lane + 3];
+            // node values at lanes + 1, + 2, + 3 (zeros past lane 63)
+            float4 n1, n2, n3;
+            n1.x = wave_next(nv.x); n1.y = wave_next(nv.y); n1.z = wave_next(nv.z); n1.w = wave_next(nv.w);
+            n2.x = wave_next(n1.x); n2.y = wave_next(n1.y); n2.z = wave_next(n1.z); n2.w = wave_next(n1.w);
+            n3.x = wave_next(n2.x); n3.y = wave_next(n2.y); n3.z = wave_next(n2.z); n3.w = wave_next(n2.w);
             float4 q0, q1, q2, q3;
             const int gi = pI0 + lane;
             if (INTERIOR || (gi >= 1 && gi <= nx - 3)) {
@@ -571,8 +580,7 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
     double4 *tr = (double4 *)lds_raw;                          // nfp + 1
     double *axmu = (double *)(tr + nfp + 1);                   // nmu (padded to 16 bytes)
     float *tab = (float *)(axmu + ((nmu + 1) & ~1));           // sub_stride
-    float4 *Nb = (float4 *)(tab + S.sub_stride);               // kAdjWaves * 68 node values
-    float4 *Qb = Nb + kAdjWaves * 68;                          // kAdjWaves * 4 * 64 quads
+    float4 *Qb = (float4 *)(tab + S.sub_stride);               // kAdjWaves * 4 * 64 quads
     double *po = (double *)(Qb + kAdjWaves * 4 * 64);          // nfp + 1 phi_o, compact for the search
     double *ipo = po + nfp + 1;                                // nfp: 1 / (phi_o[i+1] - phi_o[i])
     double *mcf = ipo + nfp + 1;                               // nmu * 4 mu-interval coefficients
@@ -611,9 +619,7 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float4 *Nw = Nb + wave * 68;
     float4 *Qw = Qb + wave * 4 * 64;
-    if (lane < 4) Nw[64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
     const int bp32 = (lane ^ 32) << 2;                     // byte address of the xor-32 partner
     const RingTan rt = ringtan[slot];
     const double phio0 = trace[slot * (nfp + 1)].z;        // phi_o of sample 0
@@ -723,10 +729,10 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
             float R0 = 0.f, R1 = 0.f, R2 = 0.f;
             const float wv[8] = {w0, w1, w2, w3, v0, v1, v2, v3};
             if (g.interior)
-                adj_pairs<EPL, true>(vmask, wv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Nw, Qw, tbr,
+                adj_pairs<EPL, true>(vmask, wv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Qw, tbr,
                                      Gr, R0, R1, R2, accT, accG);
             else
-                adj_pairs<EPL, false>(vmask, wv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Nw, Qw, tbr,
+                adj_pairs<EPL, false>(vmask, wv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Qw, tbr,
                                       Gr, R0, R1, R2, accT, accG);
             // ---------------- stage C: chain rule per pair, FP64
             if (vis) {
@@ -827,7 +833,7 @@ __global__ __launch_bounds__(64) void k_grad_final(DevSpec S, const StarRec *sta
 size_t accum_adj_lds(const DevSpec &S)
 {
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
-         + sizeof(float) * S.sub_stride + sizeof(float4) * kAdjWaves * 68
+         + sizeof(float) * S.sub_stride
          + sizeof(float4) * kAdjWaves * 4 * 64 + sizeof(double) * 2 * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
          + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb);
 }
