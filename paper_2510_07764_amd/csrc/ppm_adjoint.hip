@@ -460,7 +460,7 @@ __device__ inline void offset_coeffs(const RingRec &g, int j, double &ca, double
 // column lies in the window; columns past it hold zeros), so the bounds tests
 // drop out.
 template <int EPL, bool INTERIOR>
-__device__ __forceinline__ void adj_pairs(uint64_t mask, const float (&wv)[8], float fr, float Fpf, int I0, int m0,
+__device__ __forceinline__ void adj_pairs(uint64_t mask, const float4 *Pp, const float (&vv)[4], float fr, float Fpf, int I0, int m0,
                                           int lane, int bp32, const float *tab, const float2 *tab2, int W, int xw0,
                                           int xw, int nx, float4 *Qw, const float (&tbr)[EPL],
                                           const float (&Gr)[EPL], float &R0, float &R1, float &R2, double &accT,
@@ -471,10 +471,12 @@ __device__ __forceinline__ void adj_pairs(uint64_t mask, const float (&wv)[8], f
     while (mask) {
         const int p = __ffsll((unsigned long long)mask) - 1;
         mask &= mask - 1;
-        const float pw0 = readlane_f(wv[0], p), pw1 = readlane_f(wv[1], p), pw2 = readlane_f(wv[2], p),
-                    pw3 = readlane_f(wv[3], p);
-        const float pv0 = readlane_f(wv[4], p), pv1 = readlane_f(wv[5], p), pv2 = readlane_f(wv[6], p),
-                    pv3 = readlane_f(wv[7], p);
+        // the pair's mu weights, broadcast from its lane's LDS record; their mu
+        // derivatives by lane reads
+        const float4 pw = Pp[p];
+        const float pw0 = pw.x, pw1 = pw.y, pw2 = pw.z, pw3 = pw.w;
+        const float pv0 = readlane_f(vv[0], p), pv1 = readlane_f(vv[1], p), pv2 = readlane_f(vv[2], p),
+                    pv3 = readlane_f(vv[3], p);
         const float pfr = readlane_f(fr, p), pF = readlane_f(Fpf, p);
         const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
         // the pair's four mu rows of the table and of its logT / log g planes at
@@ -581,7 +583,8 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
     double *axmu = (double *)(tr + nfp + 1);                   // nmu (padded to 16 bytes)
     float *tab = (float *)(axmu + ((nmu + 1) & ~1));           // sub_stride
     float4 *Qb = (float4 *)(tab + S.sub_stride);               // kAdjWaves * 4 * 64 quads
-    double *po = (double *)(Qb + kAdjWaves * 4 * 64);          // nfp + 1 phi_o, compact for the search
+    float4 *Pb = Qb + kAdjWaves * 4 * 64;                      // kAdjWaves * 64 pair mu weights
+    double *po = (double *)(Pb + kAdjWaves * 64);              // nfp + 1 phi_o, compact for the search
     double *ipo = po + nfp + 1;                                // nfp: 1 / (phi_o[i+1] - phi_o[i])
     double *mcf = ipo + nfp + 1;                               // nmu * 4 mu-interval coefficients
     int16_t *pbk = (int16_t *)(mcf + 4 * nmu);                 // 2 nfp phase buckets
@@ -620,6 +623,7 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float4 *Qw = Qb + wave * 4 * 64;
+    float4 *Pw = Pb + wave * 64;
     const int bp32 = (lane ^ 32) << 2;                     // byte address of the xor-32 partner
     const RingTan rt = ringtan[slot];
     const double phio0 = trace[slot * (nfp + 1)].z;        // phi_o of sample 0
@@ -727,12 +731,14 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
             const uint64_t vmask = __ballot(vis);
             // ---------------- stage B: the visible pairs one after another
             float R0 = 0.f, R1 = 0.f, R2 = 0.f;
-            const float wv[8] = {w0, w1, w2, w3, v0, v1, v2, v3};
+            const float vv[4] = {v0, v1, v2, v3};
+            Pw[lane] = make_float4(w0, w1, w2, w3);
+            wave_sync();
             if (g.interior)
-                adj_pairs<EPL, true>(vmask, wv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Qw, tbr,
+                adj_pairs<EPL, true>(vmask, Pw, vv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Qw, tbr,
                                      Gr, R0, R1, R2, accT, accG);
             else
-                adj_pairs<EPL, false>(vmask, wv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Qw, tbr,
+                adj_pairs<EPL, false>(vmask, Pw, vv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Qw, tbr,
                                       Gr, R0, R1, R2, accT, accG);
             // ---------------- stage C: chain rule per pair, FP64
             if (vis) {
@@ -833,7 +839,7 @@ __global__ __launch_bounds__(64) void k_grad_final(DevSpec S, const StarRec *sta
 size_t accum_adj_lds(const DevSpec &S)
 {
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
-         + sizeof(float) * S.sub_stride
+         + sizeof(float) * S.sub_stride + sizeof(float4) * kAdjWaves * 64
          + sizeof(float4) * kAdjWaves * 4 * 64 + sizeof(double) * 2 * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
          + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb);
 }
