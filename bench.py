@@ -47,7 +47,7 @@ KERNEL_SOURCES = ("ppm_kernels.hip", "ppm_device.h", "ppm_dual.h", "ppm_internal
 TRAFFIC = {"sources_sha256": "3f74f095cad614303a9e5966dc3aa1b19845aace6019f34dbe37e8edf8c0dae4",
            "fetch_scale": 1.99980, "write_scale": 1.0,
            # phase tile -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-           "by_tile": {32: (4267.22, 33128.33), 64: (4260.57, 32960.00), 128: (4260.53, 32864.00)},
+           "by_tile": {32: (4267.18, 33128.33), 64: (4260.54, 32960.00), 128: (4260.53, 32864.00)},
            "profile": "profiles/k_accum_fast_config1_traffic.md"}
 
 
