@@ -790,8 +790,13 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     double *mcf = ipo + nfp + 1;                               // nmu * 4 mu-interval coefficients
     int16_t *pbk = (int16_t *)(mcf + 4 * nmu);                 // 2 nfp phase buckets
     int16_t *mbk = pbk + 2 * nfp;                              // mu_nb mu buckets
+    float *sce = (float *)(mbk + S.mu_nb);                     // E: output scale w_cell T^3 / E_e
     const int n_pb = 2 * nfp;
     const double4 *gtr = trace + ((size_t)b * S.R_tot + r) * (nfp + 1);
+    {
+        const double scale = g.w_cell * g.T * g.T * g.T;
+        for (int e = threadIdx.x; e < E; e += blockDim.x) sce[e] = (float)(scale / S.energy[e]);
+    }
     // phases of the tile go to the waves as they finish (waves start on
     // phases 0 .. NW-1); each phase is done by one wave, so the sums do not
     // depend on the assignment
@@ -938,12 +943,11 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
             else
                 pairs_general<EPL>(mask, Pw, fr, I0, m0, lane, tab, NMP, xw0, xw, nx, Sw, Qw, tbr, acc);
         }
-        const double scale = g.w_cell * g.T * g.T * g.T;
         float *out = partial + (((size_t)b * S.R_tot + r) * P + k) * E;
 #pragma unroll
         for (int m = 0; m < EPL; ++m) {
             int e = lane + 64 * m;
-            if (e < E) out[e] = (float)(acc[m] * (scale / S.energy[e]));
+            if (e < E) out[e] = acc[m] * sce[e];
         }
         int nk = 0;
         if (lane == 0) nk = atomicAdd(&k_next, 1);
@@ -1280,7 +1284,7 @@ size_t accum_table_lds(const DevSpec &S)
              + sizeof(float) * fast_tab_floats(S) + sizeof(float4) * kFwdWaves * 64 + sizeof(float) * kFwdWaves * 68
              + sizeof(float4) * kFwdWaves * 64
              + sizeof(double) * 2 * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
-             + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb);
+             + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb) + sizeof(float) * S.E;
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * S.nmu + sizeof(float) * S.nmu * S.nx
          + sizeof(float) * 4 * S.nx;
 }
