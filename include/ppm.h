@@ -98,7 +98,7 @@ enum ppm_interp { PPM_INTERP_MIXED = 0, PPM_INTERP_CUBIC = 1, PPM_INTERP_CUBIC_C
  *              atmosphere table, PPM_F32, the mixed strategy, grad = 0 and an
  *              energy grid spanning at most 59 x intervals.
  *  background  NULL, or [n_phase][n_chan] expected background counts per bin
- *              (Sect. 7): the likelihood and its gradient use model counts
+ *              (Sect. 6): the likelihood and its gradient use model counts
  *              plus background; ppm_forward's counts stay the model's own.
  */
 typedef struct {
@@ -264,7 +264,7 @@ int ppm_autotune_map(ppm_plan *plan, const double *params_dev, int B, const doub
 
 /*
  * GPU-resident parallel-tempered Metropolis sampler (the inference layer
- * named in Sect. 7): C chains at each of T inverse temperatures, every step
+ * named in Sect. 6): C chains at each of T inverse temperatures, every step
  * one batched likelihood call of the T*C proposals, all on the device with
  * no host synchronisation.
  *   move     theta'_j = theta_j + step[j] / sqrt(beta_t) z_j on the free

@@ -1,6 +1,6 @@
 """CPU oracle of the instrument pipeline of Sect. 2.8.4 (absorption table,
 ARF x RMF fine response, down-sampling matrix DS, combined response) and of
-the Poisson likelihood with a background term (Sect. 7).
+the Poisson likelihood with a background term (Sect. 6).
 
 TEST INFRASTRUCTURE.  Only the test-suite may use this module; it shares no
 code with the library.

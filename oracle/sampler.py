@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE.  Only the test-suite may use this module; it shares no
 code with the HIP implementation.
 
 The paper names a fully GPU-resident parallel-tempered MCMC as the inference
-layer its likelihood is built for (Sect. 7).  The sampler here is standard
+layer its likelihood is built for (Sect. 6).  The sampler here is standard
 parallel tempering with random-walk Metropolis moves:
 
 * state: C chains at each of T inverse temperatures beta_0 = 1 > beta_1 > ...;

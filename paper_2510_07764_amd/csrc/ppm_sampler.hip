@@ -1,5 +1,5 @@
 // GPU-resident parallel-tempered Metropolis sampler over the batched
-// likelihood (the inference layer of Sect. 7 of arXiv:2510.07764).  Every
+// likelihood (the inference layer of Sect. 6 of arXiv:2510.07764).  Every
 // step: one proposal kernel (thread per chain and temperature), one batched
 // likelihood evaluation of all proposals, one acceptance kernel (thread per
 // chain: its T Metropolis decisions, then the swap round).  Random numbers

@@ -1,5 +1,5 @@
 """Pins of the oracle's instrument pipeline (Sect. 2.8.4) and of the
-likelihood with a background term (Sect. 7).
+likelihood with a background term (Sect. 6).
 
 * DS: the hat functions of the model grid sum to one, so every fine bin's
   column of DS sums to its width; linear interpolation reproduces linear

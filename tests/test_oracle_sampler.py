@@ -1,4 +1,4 @@
-"""Pins of the oracle's parallel-tempered Metropolis sampler (Sect. 7).
+"""Pins of the oracle's parallel-tempered Metropolis sampler (Sect. 6).
 
 * Philox4x32-10 against its published known-answer values (zero counter and
   key, all-ones counter and key, and the pi-digits counter and key);
