@@ -100,6 +100,12 @@ enum ppm_interp { PPM_INTERP_MIXED = 0, PPM_INTERP_CUBIC = 1, PPM_INTERP_CUBIC_C
  *  background  NULL, or [n_phase][n_chan] expected background counts per bin
  *              (Sect. 6): the likelihood and its gradient use model counts
  *              plus background; ppm_forward's counts stay the model's own.
+ *  count_negative
+ *              1: count interpolated intensities below zero (the quantity
+ *              Sect. 4 compares the strategies by) in ppm_get_diagnostics;
+ *              the forward then runs on the generic kernel (slower).  Spot
+ *              plans with the atmosphere table and grad = 0 only.  0: not
+ *              counted (n_negative = -1).
  */
 typedef struct {
     int32_t mode, intensity, n_spots;
@@ -119,15 +125,34 @@ typedef struct {
     int32_t interp;
     int32_t n_side;
     const double *background;
+    int32_t count_negative;
 } ppm_spec;
 
 typedef struct ppm_plan ppm_plan;
 
-/* Creates a plan: validates the spec, uploads tables (atmosphere converted to
- * linear FP32), allocates every device buffer an evaluation of up to
- * max_batch instances needs.  All device allocation happens here.
+/* Creates a plan (Sect. 2.9: the tables are set up once and every
+ * likelihood call reuses them): validates the spec, uploads tables
+ * (atmosphere converted to linear FP32), allocates every device buffer an
+ * evaluation of up to max_batch instances needs, and pinned host staging
+ * for the work lists.  All device and pinned allocation happens here.
  * max_cells: largest per-spot grid side (rings = cells per ring) that a
- * per-instance resolution override may ask for (0: the spec's own). */
+ * per-instance resolution override may ask for (0: the spec's own).
+ * Synchronises the host (table uploads).  PPM_ERR_ARG / PPM_ERR_UNSUPPORTED
+ * for an invalid or unsupported spec, PPM_ERR_ALLOC when memory runs out;
+ * *out is NULL on error.
+ *
+ * Work lists.  Every evaluation needs the list of live (instance, ring)
+ * slots and ring groups of its batch layout (B, per-instance grids, ring
+ * group).  The plan keeps the lists of eight layouts resident; a call with
+ * another layout builds them on the host and uploads them on the call's
+ * stream (asynchronously, from pinned staging; the host waits only if the
+ * previous upload has not run yet).  A call made while its stream is being
+ * captured into a HIP graph must find its layout resident (make one
+ * uncaptured call with the same layout first; PPM_ERR_ARG otherwise) and
+ * pins it: the lists a graph was captured with are never rewritten, so
+ * direct calls with other layouts between replays leave the graph intact.
+ * Once all eight slots are pinned, a call with a ninth layout fails with
+ * PPM_ERR_UNSUPPORTED (pinned layouts keep working). */
 int ppm_plan_create(const ppm_spec *spec, int max_batch, int max_cells, ppm_plan **out);
 void ppm_plan_destroy(ppm_plan *plan);
 
@@ -144,7 +169,9 @@ int ppm_flux(ppm_plan *plan, const double *params_dev, int B, const int32_t *n_c
              double *flux_dev, void *stream);
 
 /* Poisson log-likelihood sum d ln m - m - ln(d!) over all phase-channel bins
- * for each instance: logl_dev[B] (double, device).  data_dev:
+ * for each instance (the likelihood a sampler calls, Sect. 6; the model
+ * counts are those of Sect. 2.8.4, the Poisson form is the standard one
+ * for counted photons): logl_dev[B] (double, device).  data_dev:
  * [n_phase][n_chan] int32 counts shared by all instances (device).
  * counts_dev may be NULL; otherwise it receives the model counts.
  * An instance with a nonzero status gets logL = -inf. */
@@ -187,6 +214,34 @@ int ppm_flux_map(ppm_plan *plan, const double *params_dev, int B, const double *
 int ppm_loglike_map(ppm_plan *plan, const double *params_dev, int B, const double *map_dev, const int32_t *data_dev,
                     double *logl_dev, double *counts_dev, void *stream);
 
+/* Diagnostic counters of the last evaluation (host; synchronises the
+ * stream), summed over its first B instances (total) and per instance
+ * (per_instance[B]; either pointer may be NULL, not both):
+ *   n_visible_pairs   (cell, phase) pairs with nonzero flux (Eq. 46)
+ *   n_clamp_T, n_clamp_g   intensity evaluations whose logT / log g lay
+ *                     outside the atmosphere table and was clamped to its
+ *                     edge (Sect. 4); a spot ring's values hold for all its
+ *                     evaluations, a map patch's logT for its own
+ *   n_x_outside       intensity evaluations with x = log10(E / kT) outside
+ *                     the table's x axis (no contribution)
+ *   n_multi_image     visible fine-phase samples of the ring traces with
+ *                     psi > 2 pi - psi_top, i.e. points also seen along a
+ *                     second ray, which the model leaves out (Sect. 6);
+ *                     zero below GM/(R c^2) ~ 0.28
+ *   n_negative        interpolated intensities below zero (Sect. 4), or -1
+ *                     when the plan does not count them (spec count_negative)
+ * The blackbody model has no table: its clamp, x and negative counts are 0.
+ * PPM_ERR_BATCH for B outside [1, max_batch]. */
+typedef struct ppm_diag {
+    int64_t n_visible_pairs;
+    int64_t n_clamp_T;
+    int64_t n_clamp_g;
+    int64_t n_x_outside;
+    int64_t n_multi_image;
+    int64_t n_negative;
+} ppm_diag;
+int ppm_get_diagnostics(ppm_plan *plan, int B, ppm_diag *total, ppm_diag *per_instance, void *stream);
+
 /* Per-instance status codes of the last evaluation: status_dev[B] (device). */
 int ppm_instance_status(ppm_plan *plan, int B, int32_t *status_dev, void *stream);
 
@@ -196,7 +251,7 @@ int ppm_validate_params(const double *params_host, int B, int n_spots, int32_t *
 
 /* Introspection for tests: copies to host (synchronising the stream) the
  * per-ring FP64 deflection table of instance b, ring r of the last
- * evaluation: out[n_alpha][4] = (psi, dpsi/dalpha, c dt/R, d(c dt/R)/dalpha)
+ * evaluation (b among the instances of its last workspace pass): out[n_alpha][4] = (psi, dpsi/dalpha, c dt/R, d(c dt/R)/dalpha)
  * at alpha_j = alpha_max * j / (n_alpha - 1); info[4] = (alpha_max, psi_top,
  * u, R [cm]).  And the fine-phase trace out_tr[n_fp+1][4] = (F, z, phi_o, mu)
  * with trace_info[3] = (visible, inv_min, inv_max). */
@@ -216,17 +271,24 @@ int ppm_profile_end(ppm_plan *plan, double *hot_ms_total, int *n_calls);
 
 /* Launch shape of the two accumulation kernels (the sum of Eq. (47) and its
  * adjoint): phase_tile output phases per work-group of the forward kernel
- * (4 waves, 1..256) and phase_tile_grad per work-group of the adjoint kernel
- * (8 waves, 8..256).  Forward results do not depend on phase_tile: every
- * phase's sums run in the same order whatever the tile.  The gradient's
- * per-block partial sums do depend on phase_tile_grad, at the rounding level.
- * Temperature-map plans use phase_tile rounded down to 8, 16 or 32 (8 waves).
- * Defaults 8 and 8.  A change applies to later calls; a HIP graph captured
- * earlier keeps the shape it was captured with.  PPM_ERR_ARG for a null
- * pointer or a value out of range (the plan is then unchanged). */
+ * (1..256) and phase_tile_grad per work-group of the adjoint kernel
+ * (8..256); ring_group rings summed per work-group of the windowed forward
+ * kernel (1..64; one FP32 partial spectrum per group goes to the FP64 ring
+ * reduction instead of one per ring).  Forward results do not depend on
+ * phase_tile: every phase's sums run in the same order whatever the tile.
+ * They depend on ring_group at the FP32 rounding level (a group's rings are
+ * summed in FP32, groups in FP64); for a fixed ring_group they are bitwise
+ * reproducible, and an instance gives the same bits alone as in a batch.
+ * The gradient's per-block partial sums depend on phase_tile_grad, at the
+ * rounding level.  Temperature-map plans use phase_tile rounded down to 8,
+ * 16 or 32 (8 waves) and one ring per group.  Defaults 8, 8, 1.  A change
+ * applies to later calls; a HIP graph captured earlier keeps the shape it
+ * was captured with.  PPM_ERR_ARG for a null pointer or a value out of range
+ * (the plan is then unchanged). */
 typedef struct ppm_tiles {
     int32_t phase_tile;
     int32_t phase_tile_grad;
+    int32_t ring_group;
 } ppm_tiles;
 int ppm_get_tiles(const ppm_plan *plan, ppm_tiles *out);
 int ppm_set_tiles(ppm_plan *plan, const ppm_tiles *tiles);
@@ -241,18 +303,22 @@ int ppm_set_tiles(ppm_plan *plan, const ppm_tiles *tiles);
  * clock ramps up under load), then every candidate once per repetition, in
  * turn, for `reps` repetitions (1..1000).  It keeps the candidate with the
  * smallest median time and sets it on the plan; the forward tile is
- * chosen first and then used while the adjoint tile is timed.  Adjoint calls
+ * chosen first, then (windowed spot plans) the ring group among 1, 2, 4, 8,
+ * 16 and 32 at that tile, and then the adjoint tile.  Adjoint calls
  * run on all-zero data (their cost does not depend on the data) and need
  * two temporary device buffers, allocated and freed here.  Synchronises the
- * stream.  Spot plans only.  On error the plan keeps its previous tiles.  report may be NULL;
+ * stream; refused on a stream that is being captured.  Spot plans only.
+ * On error the plan keeps its previous tiles.  report may be NULL;
  * otherwise it receives every candidate's median time [ms] and the choice. */
 #define PPM_TUNE_MAX 16
 typedef struct ppm_tune_report {
-    int32_t n_fwd, n_grad;
+    int32_t n_fwd, n_grad, n_group;
     int32_t fwd_tile[PPM_TUNE_MAX];
     double fwd_ms[PPM_TUNE_MAX];
     int32_t grad_tile[PPM_TUNE_MAX];
     double grad_ms[PPM_TUNE_MAX];
+    int32_t group[PPM_TUNE_MAX];
+    double group_ms[PPM_TUNE_MAX];
     ppm_tiles chosen;
 } ppm_tune_report;
 int ppm_autotune(ppm_plan *plan, const double *params_dev, int B, const int32_t *n_cells_host, int reps,

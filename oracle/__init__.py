@@ -237,6 +237,33 @@ def fd_gradient(spec, params, data, slots, rel_step=1e-4):
     return g
 
 
+def fd_gradient_counts(spec, params, data, slots, rel_step=1e-6, background=None):
+    """d logL / d theta by the chain rule through the model counts: central
+    finite differences of the oracle's counts m with step
+    h_i = rel_step |theta_i| (absolute rel_step for a zero parameter),
+    contracted with the closed-form derivative of the Poisson log-likelihood
+    at the central point, d logL / d m = d / (m + b) - 1 (-1 where d = 0;
+    b = background counts or 0).  Differencing the counts instead of logL
+    avoids the cancellation of logL's large constant part (sum ln d!,
+    sum d ln m), so that the differences converge to ~1e-9 relative wherever
+    the model is smooth over the step."""
+    os_ = spec if isinstance(spec, OracleSpec) else OracleSpec(spec)
+    p0 = np.asarray(params, dtype=np.float64)
+    d = np.asarray(data, dtype=np.float64)
+    _, m0, _ = forward(os_, p0)
+    mb = m0 + (np.asarray(background, dtype=np.float64) if background is not None else 0.0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        gm = np.where(d > 0, d / mb, 0.0) - 1.0
+    g = np.zeros(len(slots))
+    for n, s in enumerate(slots):
+        h = rel_step * abs(p0[s]) if p0[s] != 0 else rel_step
+        pp, pm = p0.copy(), p0.copy()
+        pp[s] += h
+        pm[s] -= h
+        g[n] = float(np.sum(gm * (forward(os_, pp)[1] - forward(os_, pm)[1]))) / (2 * h)
+    return g
+
+
 # ------------------------------------------------------------- primitives
 def psi(u, alpha):
     return lib().orc_psi(u, alpha)

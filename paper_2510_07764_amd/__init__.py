@@ -47,21 +47,31 @@ class _Spec(C.Structure):
                 ("ax_mu", C.POINTER(C.c_double)), ("ax_x", C.POINTER(C.c_double)),
                 ("log_intensity", C.POINTER(C.c_double)),
                 ("n_alpha", C.c_int32), ("precision", C.c_int32), ("grad", C.c_int32),
-                ("interp", C.c_int32), ("n_side", C.c_int32), ("background", C.POINTER(C.c_double))]
+                ("interp", C.c_int32), ("n_side", C.c_int32), ("background", C.POINTER(C.c_double)),
+                ("count_negative", C.c_int32)]
 
 
 class _Tiles(C.Structure):
-    _fields_ = [("phase_tile", C.c_int32), ("phase_tile_grad", C.c_int32)]
+    _fields_ = [("phase_tile", C.c_int32), ("phase_tile_grad", C.c_int32), ("ring_group", C.c_int32)]
 
 
 TUNE_MAX = 16
 
 
 class _TuneReport(C.Structure):
-    _fields_ = [("n_fwd", C.c_int32), ("n_grad", C.c_int32),
+    _fields_ = [("n_fwd", C.c_int32), ("n_grad", C.c_int32), ("n_group", C.c_int32),
                 ("fwd_tile", C.c_int32 * TUNE_MAX), ("fwd_ms", C.c_double * TUNE_MAX),
                 ("grad_tile", C.c_int32 * TUNE_MAX), ("grad_ms", C.c_double * TUNE_MAX),
+                ("group", C.c_int32 * TUNE_MAX), ("group_ms", C.c_double * TUNE_MAX),
                 ("chosen", _Tiles)]
+
+
+class _Diag(C.Structure):
+    _fields_ = [("n_visible_pairs", C.c_int64), ("n_clamp_T", C.c_int64), ("n_clamp_g", C.c_int64),
+                ("n_x_outside", C.c_int64), ("n_multi_image", C.c_int64), ("n_negative", C.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 PT_MAX_TEMPS = 64
@@ -93,6 +103,7 @@ SIGNATURES = {
     "ppm_validate_params": (C.c_int, [_DP, C.c_int, C.c_int, _I32P]),
     "ppm_debug_ring": (C.c_int, [_VP, C.c_int, C.c_int, _DP, _DP, _DP, _I32P, _VP]),
     "ppm_visible_pairs": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_longlong), _VP]),
+    "ppm_get_diagnostics": (C.c_int, [_VP, C.c_int, C.POINTER(_Diag), C.POINTER(_Diag), _VP]),
     "ppm_profile_begin": (C.c_int, [_VP, C.c_int]),
     "ppm_profile_end": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "ppm_get_tiles": (C.c_int, [_VP, C.POINTER(_Tiles)]),
@@ -212,7 +223,7 @@ class Plan:
     """A plan for one model spec (a dict as built by ``synthetic.config*``)."""
 
     def __init__(self, spec: dict, max_batch: int = 1, max_cells: int = 0, n_alpha: int | None = None,
-                 grad: bool = False):
+                 grad: bool = False, count_negative: bool = False):
         self.keep = []
 
         def arr(x):
@@ -258,6 +269,7 @@ class Plan:
             bg = np.asarray(bg, dtype=np.float64)
             assert bg.shape == (s.n_phase, s.n_chan), bg.shape
         s.background = arr(bg)
+        s.count_negative = 1 if count_negative else 0
         self.n_side = s.n_side
         self.n_pix = 12 * s.n_side * s.n_side
         self.spec = spec
@@ -433,10 +445,22 @@ class Plan:
         _check(lib().ppm_get_tiles(self.handle, C.byref(t)), "ppm_get_tiles")
         return int(t.phase_tile), int(t.phase_tile_grad)
 
-    def set_tiles(self, phase_tile=None, phase_tile_grad=None):
-        cur = self.tiles
-        t = _Tiles(cur[0] if phase_tile is None else int(phase_tile),
-                   cur[1] if phase_tile_grad is None else int(phase_tile_grad))
+    @property
+    def ring_group(self):
+        """Rings summed per work-group of the windowed forward kernel."""
+        t = _Tiles()
+        _check(lib().ppm_get_tiles(self.handle, C.byref(t)), "ppm_get_tiles")
+        return int(t.ring_group)
+
+    def set_tiles(self, phase_tile=None, phase_tile_grad=None, ring_group=None):
+        t = _Tiles()
+        _check(lib().ppm_get_tiles(self.handle, C.byref(t)), "ppm_get_tiles")
+        if phase_tile is not None:
+            t.phase_tile = int(phase_tile)
+        if phase_tile_grad is not None:
+            t.phase_tile_grad = int(phase_tile_grad)
+        if ring_group is not None:
+            t.ring_group = int(ring_group)
         _check(lib().ppm_set_tiles(self.handle, C.byref(t)), "ppm_set_tiles")
 
     def autotune(self, params, n_cells=None, reps=5, stream=None):
@@ -449,8 +473,10 @@ class Plan:
         _check(lib().ppm_autotune(self.handle, _dptr(params), B, nc, int(reps), _stream_handle(stream),
                                   C.byref(r)), "ppm_autotune")
         return {"forward": {int(r.fwd_tile[i]): float(r.fwd_ms[i]) for i in range(r.n_fwd)},
+                "group": {int(r.group[i]): float(r.group_ms[i]) for i in range(r.n_group)},
                 "grad": {int(r.grad_tile[i]): float(r.grad_ms[i]) for i in range(r.n_grad)},
-                "chosen": (int(r.chosen.phase_tile), int(r.chosen.phase_tile_grad))}
+                "chosen": (int(r.chosen.phase_tile), int(r.chosen.phase_tile_grad)),
+                "ring_group": int(r.chosen.ring_group)}
 
     def autotune_map(self, params, logT_map, reps=5, stream=None):
         """Autotuner of a temperature-map plan (phase tiles 8, 16, 32);
@@ -462,6 +488,17 @@ class Plan:
                                       C.byref(r)), "ppm_autotune_map")
         return {"forward": {int(r.fwd_tile[i]): float(r.fwd_ms[i]) for i in range(r.n_fwd)},
                 "chosen": (int(r.chosen.phase_tile), int(r.chosen.phase_tile_grad))}
+
+    def diagnostics(self, B, per_instance=False, stream=None):
+        """Counters of the last evaluation (``ppm_get_diagnostics``): a dict
+        of totals over its first B instances, or (totals, [per instance])."""
+        tot = _Diag()
+        per = (_Diag * B)() if per_instance else None
+        _check(lib().ppm_get_diagnostics(self.handle, B, C.byref(tot), per, _stream_handle(stream)),
+               "ppm_get_diagnostics")
+        if per_instance:
+            return tot.as_dict(), [per[i].as_dict() for i in range(B)]
+        return tot.as_dict()
 
     def visible_pairs(self, B, stream=None):
         out = C.c_longlong()

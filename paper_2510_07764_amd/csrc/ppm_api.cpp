@@ -87,21 +87,54 @@ int api_fail(int code, const char *msg) { return fail(code, msg); }
 int api_hip_fail(hipError_t e, const char *where) { return hip_fail(e, where); }
 }  // namespace ppm
 
+// Work lists of one batch layout (B, per-instance grids, ring-group size):
+// the live (instance, ring) slots and the ring groups of every workspace
+// pass, resident in device memory.  A plan keeps kListSlots of them; a call
+// whose layout is resident reuses it, another one is built on the host and
+// uploaded on the caller's stream into the least recently used slot.  A
+// slot used while the stream is being captured into a HIP graph is pinned:
+// never rewritten, so that the graph keeps reading the lists it was
+// captured with.
+constexpr int kListSlots = 8;
+
+struct ListPass {
+    int inst0, nb;            // instances [inst0, inst0 + nb) of the batch
+    int ring_off, n_ring;     // their live rings in d_ring (pass-local instance index * R_tot + ring)
+    int grp_off, n_grp;       // their ring groups in d_glist (first pass-local ring position, count)
+};
+
+struct ListSlot {
+    int32_t *d_ring = nullptr;    // [max_batch * R_tot]
+    int32_t *d_glist = nullptr;   // [max_batch * R_tot][2]
+    int32_t *d_grange = nullptr;  // [max_batch][2] per instance: its groups [first, end) within its pass
+    int32_t *d_ncells = nullptr;  // [max_batch] per-instance grids (override layouts)
+    std::vector<ListPass> pass;
+    std::vector<int32_t> key;     // per-instance grids (empty: the spec's own)
+    int B = -1, group = 0;
+    bool override_grid = false;
+    bool pinned = false;
+    uint64_t used = 0;
+};
+
 struct ppm_plan {
     DevSpec S;
     Workspace W;
     int max_batch = 0;
     int max_cells = 0;
-    int chunk = 0;                 // instances per workspace pass
-    int32_t *d_list = nullptr;     // live (instance, ring) slots, chunk by chunk
-    std::vector<int> list_off, list_n;
-    int list_B = -1;               // batch size the list was built for (-1: none)
-    bool list_override = false;    // list built for per-instance grids
+    int device = -1;               // the device the plan's memory lives on
+    int chunk = 0;                 // largest number of instances per workspace pass (ring scratch)
+    size_t gcap = 0;               // ring-group partial spectra the workspace holds per pass
     int precision = PPM_F32;
     bool grad = false;             // gradient buffers allocated
+    bool count_negative = false;   // the forward counts negative interpolated intensities
     std::vector<void *> allocs;
-    std::vector<int32_t> last_ncells;
-    bool ncells_valid = false;
+    ListSlot slot[kListSlots];
+    ListSlot *cur = nullptr;       // layout of the last call
+    int32_t *h_stage = nullptr;    // pinned staging of list uploads
+    size_t stage_ints = 0;
+    hipEvent_t stage_ev = nullptr; // recorded after the last upload from h_stage
+    bool stage_pending = false;
+    uint64_t clock = 0;
     int last_B = 0;
     // hot-kernel timing: one event pair per recorded call
     std::vector<hipEvent_t> ev;
@@ -134,14 +167,29 @@ struct ppm_plan {
     }
     ~ppm_plan()
     {
+        if (stage_ev) {
+            (void)hipEventSynchronize(stage_ev);
+            (void)hipEventDestroy(stage_ev);
+        }
+        if (h_stage) (void)hipHostFree(h_stage);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
     }
 };
 
+bool ppm::plan_view(const ppm_plan *pl, const DevSpec **S, const Workspace **W, int *max_batch, int *device)
+{
+    if (!pl) return false;
+    *S = &pl->S;
+    *W = &pl->W;
+    *max_batch = pl->max_batch;
+    *device = pl->device;
+    return true;
+}
+
 extern "C" {
 
-int ppm_version(void) { return 1; }
+int ppm_version(void) { return 2; }
 
 const char *ppm_last_error(void) { return g_last_error.c_str(); }
 
@@ -207,6 +255,10 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     if (sp->n_alpha < 64 || sp->n_alpha > 8192) return fail(PPM_ERR_ARG, "n_alpha must lie in [64, 8192]");
     if (sp->n_energy > 64 * 8) return fail(PPM_ERR_UNSUPPORTED, "at most 512 energies");
     if (sp->grad != 0 && sp->grad != 1) return fail(PPM_ERR_ARG, "grad must be 0 or 1");
+    if (sp->count_negative != 0 && sp->count_negative != 1) return fail(PPM_ERR_ARG, "count_negative must be 0 or 1");
+    if (sp->count_negative && (sp->grad || map_plan || sp->intensity != PPM_I_TABLE))
+        return fail(PPM_ERR_UNSUPPORTED,
+                    "count_negative applies to forward-only spot plans with the atmosphere table");
     if (sp->interp < PPM_INTERP_MIXED || sp->interp > PPM_INTERP_CUBIC_LINMU)
         return fail(PPM_ERR_ARG, "interp must be one of the four strategies");
     if (sp->interp != PPM_INTERP_MIXED) {
@@ -232,6 +284,10 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
 
     ppm_plan *pl = new (std::nothrow) ppm_plan();
     if (!pl) return fail(PPM_ERR_ALLOC, "host allocation failed");
+    if (hipGetDevice(&pl->device) != hipSuccess) {
+        delete pl;
+        return fail(PPM_ERR_HIP, "ppm_plan_create: no current HIP device");
+    }
     DevSpec &S = pl->S;
     std::memset(&S, 0, sizeof(S));
     S.mode = sp->mode;
@@ -266,10 +322,12 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     S.n_alpha = sp->n_alpha;
     S.pt_fwd = kPhaseTile;
     S.pt_adj = kPhaseTile;
+    S.ring_group = 1;
     pl->max_batch = max_batch;
     pl->max_cells = max_cells;
     pl->precision = sp->precision;
     pl->grad = sp->grad != 0;
+    pl->count_negative = sp->count_negative != 0;
 
     // Gauss-Legendre rules of 20, 24, 32, 48 and 64 nodes, back to back
     std::vector<double> glx, glw;
@@ -313,6 +371,10 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     }
     if (sp->intensity == PPM_I_TABLE) {
         S.nT = sp->nT; S.ng = sp->ng; S.nmu = sp->nmu; S.nx = sp->nx;
+        S.T_end[0] = sp->ax_T[0];
+        S.T_end[1] = sp->ax_T[S.nT - 1];
+        S.g_end[0] = sp->ax_g[0];
+        S.g_end[1] = sp->ax_g[S.ng - 1];
         uniform_axis(sp->ax_T, S.nT, S.T0, S.hT);
         uniform_axis(sp->ax_g, S.ng, S.g0, S.hg);
         uniform_axis(sp->ax_x, S.nx, S.x0, S.hx);
@@ -335,7 +397,9 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         }
         S.W_max = (int)std::ceil(S.r_span + std::log10(4.0) / S.hx) + 8;
         if (S.W_max > S.nx) S.W_max = S.nx;
-        S.fast = (S.r_span <= 59.0 && S.interp == PPM_INTERP_MIXED) ? 1 : 0;
+        // the windowed kernel; the generic one also counts negative
+        // interpolated intensities, and runs when the plan asks for that count
+        S.fast = (S.r_span <= 59.0 && S.interp == PPM_INTERP_MIXED && !sp->count_negative) ? 1 : 0;
         if (map_plan) {
             if (!S.fast) {
                 delete pl;
@@ -387,22 +451,25 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         }
         S.mu_bucket = pl->upload(mb.data(), mb.size());
     }
-    // workspace: per-instance outputs for max_batch instances, ring-level
-    // scratch for `chunk` instances (a 64 GiB budget of the 288 GB bounds the chunk)
+    // workspace: per-instance outputs and counters for max_batch instances;
+    // ring-level scratch for `chunk` instances per pass (a 64 GiB budget of
+    // the 288 GB bounds the chunk); ring-group partial spectra for `gcap`
+    // groups per pass: the chunk at groups of 16 rings, and at least one
+    // instance at one ring per group
     Workspace &W = pl->W;
     std::memset(&W, 0, sizeof(W));
     const size_t R = S.R_tot;
     {
         size_t per_ring = sizeof(RingRec) + sizeof(double4) * (S.n_alpha + S.n_fp + 1)
-                        + (S.intensity == PPM_I_TABLE ? sizeof(float) * (map_plan ? 0 : (size_t)S.sub_stride)
-                                                      + sizeof(float) * (size_t)S.P * S.E
-                                                      : sizeof(double) * (size_t)S.P * S.E);
+                        + (S.intensity == PPM_I_TABLE && !map_plan ? sizeof(float) * (size_t)S.sub_stride : 0);
         if (map_plan) per_ring += sizeof(int32_t) * (size_t)(S.map_nb + 1);
         if (sp->grad)
             per_ring += sizeof(double4) * ((size_t)S.n_alpha + (size_t)(S.n_fp + 1) * 5) + sizeof(RingTan)
                       + sizeof(float2) * (size_t)S.sub_stride
                       + sizeof(double) * kGradAcc * (size_t)((S.P + kMinTileGrad - 1) / kMinTileGrad);
-        size_t per_inst = per_ring * R + sizeof(double) * (size_t)S.P * S.E
+        const size_t part_bytes = (S.intensity == PPM_I_TABLE ? sizeof(float) : sizeof(double)) * (size_t)S.P * S.E;
+        const size_t groups16 = (R + 15) / 16;
+        size_t per_inst = per_ring * R + part_bytes * groups16 + sizeof(double) * (size_t)S.P * S.E
                         + (sp->grad ? (sizeof(double) + sizeof(float)) * (size_t)S.P * S.E : 0)
                         + (map_plan ? sizeof(MapCell) * (size_t)S.n_pix : 0);
         size_t budget = (size_t)64 << 30;
@@ -415,6 +482,7 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
             if (v >= 1 && (size_t)v < c) c = (size_t)v;
         }
         pl->chunk = (int)(c < (size_t)max_batch ? c : (size_t)max_batch);
+        pl->gcap = std::max((size_t)pl->chunk * groups16, R);
     }
     const size_t B = pl->chunk, BM = max_batch;
     W.stars = pl->dalloc<StarRec>(BM);
@@ -422,7 +490,7 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     W.table = pl->dalloc<double4>(B * R * S.n_alpha);
     W.trace = pl->dalloc<double4>(B * R * (S.n_fp + 1));
     W.vis_pairs = pl->dalloc<int32_t>(BM * R);
-    W.ncells = pl->dalloc<int32_t>(BM);
+    W.diag = pl->dalloc<int32_t>(BM * R * kDiagFields);
     W.counts = pl->dalloc<double>(BM * S.P * S.C);
     W.ll_part = pl->dalloc<double>(BM * loglike_blocks(S.P * S.C));
     W.ll_bad = pl->dalloc<int32_t>(BM * loglike_blocks(S.P * S.C));
@@ -433,11 +501,21 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         std::vector<unsigned> z(BM, 0u);
         W.ll_done = pl->upload(z.data(), z.size());
     }
-    pl->d_list = pl->dalloc<int32_t>(BM * R);
-    bool ok = W.stars && W.rings && W.table && W.trace && W.vis_pairs && W.ncells && W.counts && W.ll_part && W.ll_bad
-              && W.lfact && W.ll_done
-           && pl->d_list
-           && S.glx && S.glw && S.energy && S.rsp32;
+    bool ok = W.stars && W.rings && W.table && W.trace && W.vis_pairs && W.diag && W.counts && W.ll_part && W.ll_bad
+              && W.lfact && W.ll_done && S.glx && S.glw && S.energy && S.rsp32;
+    for (ListSlot &ls : pl->slot) {
+        ls.d_ring = pl->dalloc<int32_t>(BM * R);
+        ls.d_glist = pl->dalloc<int32_t>(2 * BM * R);
+        ls.d_grange = pl->dalloc<int32_t>(2 * BM);
+        ls.d_ncells = pl->dalloc<int32_t>(BM);
+        ok = ok && ls.d_ring && ls.d_glist && ls.d_grange && ls.d_ncells;
+    }
+    pl->stage_ints = 3 * BM * R + 3 * BM;
+    if (hipHostMalloc((void **)&pl->h_stage, sizeof(int32_t) * pl->stage_ints, hipHostMallocDefault) != hipSuccess)
+        pl->h_stage = nullptr;
+    if (hipEventCreateWithFlags(&pl->stage_ev, hipEventDisableTiming) != hipSuccess) pl->stage_ev = nullptr;
+    ok = ok && pl->h_stage && pl->stage_ev;
+    const size_t PEg = pl->gcap * S.P * S.E;
     if (S.intensity == PPM_I_TABLE) {
         if (map_plan) {
             W.mcell = pl->dalloc<MapCell>(B * (size_t)S.n_pix);
@@ -447,11 +525,11 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
             W.sub = pl->dalloc<float>(B * R * (size_t)S.sub_stride);
             ok = ok && W.sub;
         }
-        W.partial32 = pl->dalloc<float>(B * R * S.P * S.E);
+        W.partial32 = pl->dalloc<float>(PEg);
         W.fold_in32 = pl->dalloc<float>(B * S.P * S.E);
         ok = ok && W.partial32 && W.fold_in32 && S.atm && S.ax_mu && S.mu_coef && S.mu_bucket;
     } else {
-        W.partial64 = pl->dalloc<double>(B * R * S.P * S.E);
+        W.partial64 = pl->dalloc<double>(PEg);
         if (sp->precision == PPM_F64) {
             W.fold_in64 = pl->dalloc<double>(B * S.P * S.E);
             ok = ok && W.fold_in64 && S.rsp64;
@@ -499,11 +577,30 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
 
 void ppm_plan_destroy(ppm_plan *plan) { delete plan; }
 
-// Validates the batch, uploads per-instance grids and (re)builds the work
-// list of live (instance, ring) slots when they change: chunk by chunk,
-// instances with larger grids first so the longest blocks start early.
-static int prepare(ppm_plan *pl, const double *params, int B, const int32_t *ncells_host,
-                   const int32_t **ncells_dev, bool map_call = false)
+// Rings the windowed spot accumulation sums per block; the generic,
+// blackbody and map kernels take one ring per block.
+static int plan_group(const ppm_plan *pl)
+{
+    const DevSpec &S = pl->S;
+    return (S.intensity == PPM_I_TABLE && S.fast && S.n_side == 0) ? S.ring_group : 1;
+}
+
+static bool stream_capturing(hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+    return cs == hipStreamCaptureStatusActive;
+}
+
+// Validates the batch and makes its work lists resident (pl->cur): the
+// live (instance, ring) slots and ring groups of every workspace pass, with
+// the instances of a pass ordered larger grids first so that the longest
+// blocks start early.  A pass holds at most pl->chunk instances and
+// pl->gcap ring groups.  Uploads go on the caller's stream from pinned
+// staging; the host waits only when the previous upload from the staging
+// buffer has not run yet.
+static int prepare(ppm_plan *pl, const double *params, int B, const int32_t *ncells_host, hipStream_t st,
+                   bool map_call = false)
 {
     if (!pl || !params) return fail(PPM_ERR_ARG, "null plan or params");
     if ((pl->S.n_side > 0) != map_call)
@@ -511,8 +608,6 @@ static int prepare(ppm_plan *pl, const double *params, int B, const int32_t *nce
                                           : "temperature-map plan: use the *_map entry points");
     if (B < 1 || B > pl->max_batch) return fail(PPM_ERR_BATCH, "batch outside [1, max_batch]");
     const DevSpec &S = pl->S;
-    *ncells_dev = nullptr;
-    bool rebuild = false;
     if (ncells_host) {
         for (int b = 0; b < B; ++b) {
             int n = ncells_host[b];
@@ -523,88 +618,153 @@ static int prepare(ppm_plan *pl, const double *params, int B, const int32_t *nce
                     return fail(PPM_ERR_ARG, "annulus needs an even per-instance grid");
             }
         }
-        bool same = pl->ncells_valid && pl->list_override && pl->list_B == B
-                 && std::memcmp(pl->last_ncells.data(), ncells_host, sizeof(int32_t) * B) == 0;
-        if (!same) {
-            hipError_t e = hipMemcpy(pl->W.ncells, ncells_host, sizeof(int32_t) * B, hipMemcpyHostToDevice);
-            if (e != hipSuccess) return hip_fail(e, "upload of per-instance grids");
-            pl->last_ncells.assign(ncells_host, ncells_host + B);
-            pl->ncells_valid = true;
-            rebuild = true;
-        }
-        *ncells_dev = pl->W.ncells;
-    } else if (pl->list_override || pl->list_B != B) {
-        rebuild = true;
     }
-    if (rebuild) {
-        std::vector<int32_t> list;
-        list.reserve((size_t)B * S.R_tot);
-        pl->list_off.clear();
-        pl->list_n.clear();
-        for (int c0 = 0; c0 < B; c0 += pl->chunk) {
-            int nb = B - c0 < pl->chunk ? B - c0 : pl->chunk;
-            std::vector<std::pair<int, int>> order;   // (-cells, local instance)
-            for (int b = 0; b < nb; ++b) order.push_back({ncells_host ? -ncells_host[c0 + b] : 0, b});
-            std::stable_sort(order.begin(), order.end());
-            pl->list_off.push_back((int)list.size());
-            for (auto &o : order) {
-                int b = o.second;
-                for (int s = 0; s < S.n_spots; ++s) {
-                    int nr = ncells_host ? ncells_host[c0 + b] : S.n_rings_spec[s];
-                    int base = s == 0 ? 0 : S.rings_max[0];
-                    for (int r = 0; r < nr; ++r) list.push_back(b * S.R_tot + base + r);
-                }
+    const int G = plan_group(pl);
+    const bool over = ncells_host != nullptr;
+    for (ListSlot &ls : pl->slot) {
+        if (ls.B != B || ls.group != G || ls.override_grid != over) continue;
+        if (over && std::memcmp(ls.key.data(), ncells_host, sizeof(int32_t) * B) != 0) continue;
+        if (stream_capturing(st)) ls.pinned = true;
+        ls.used = ++pl->clock;
+        pl->cur = &ls;
+        pl->last_B = B;
+        return PPM_OK;
+    }
+    if (stream_capturing(st))
+        return fail(PPM_ERR_ARG, "the work lists of this batch layout are not resident while the stream is being "
+                                 "captured: make one call with the same B and per-instance grids first");
+    ListSlot *v = nullptr;
+    for (ListSlot &ls : pl->slot)
+        if (!ls.pinned && (!v || ls.used < v->used)) v = &ls;
+    if (!v) return fail(PPM_ERR_UNSUPPORTED, "every work-list slot of the plan is held by a captured graph");
+    auto live_rings = [&](int b) {
+        int n = 0;
+        for (int s = 0; s < S.n_spots; ++s) n += ncells_host ? ncells_host[b] : S.n_rings_spec[s];
+        return n;
+    };
+    std::vector<int32_t> ring, glist, grange(2 * (size_t)B);
+    ring.reserve((size_t)B * S.R_tot);
+    v->pass.clear();
+    for (int c0 = 0; c0 < B;) {
+        ListPass ps;
+        ps.inst0 = c0;
+        ps.ring_off = (int)ring.size();
+        ps.grp_off = (int)(glist.size() / 2);
+        size_t ng = 0;
+        int nb = 0;
+        while (c0 + nb < B && nb < pl->chunk) {
+            const size_t gb = (size_t)(live_rings(c0 + nb) + G - 1) / G;
+            if (nb > 0 && ng + gb > pl->gcap) break;
+            ng += gb;
+            ++nb;
+        }
+        ps.nb = nb;
+        std::vector<std::pair<int, int>> order;   // (-cells, pass-local instance)
+        for (int b = 0; b < nb; ++b) order.push_back({ncells_host ? -ncells_host[c0 + b] : 0, b});
+        std::stable_sort(order.begin(), order.end());
+        int rpos = 0, gpos = 0;
+        for (auto &o : order) {
+            const int b = o.second;
+            const int r_first = rpos;
+            grange[2 * (size_t)(c0 + b)] = gpos;
+            for (int s = 0; s < S.n_spots; ++s) {
+                const int nr = ncells_host ? ncells_host[c0 + b] : S.n_rings_spec[s];
+                const int base = s == 0 ? 0 : S.rings_max[0];
+                for (int r = 0; r < nr; ++r, ++rpos) ring.push_back(b * S.R_tot + base + r);
             }
-            pl->list_n.push_back((int)list.size() - pl->list_off.back());
+            for (int f = r_first; f < rpos; f += G, ++gpos) {
+                glist.push_back(f);
+                glist.push_back(rpos - f < G ? rpos - f : G);
+            }
+            grange[2 * (size_t)(c0 + b) + 1] = gpos;
         }
-        hipError_t e = hipMemcpy(pl->d_list, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(e, "upload of the work list");
-        pl->list_B = B;
-        pl->list_override = ncells_host != nullptr;
+        ps.n_ring = rpos;
+        ps.n_grp = gpos;
+        v->pass.push_back(ps);
+        c0 += nb;
     }
+    hipError_t e = hipSuccess;
+    if (pl->stage_pending) {
+        e = hipEventSynchronize(pl->stage_ev);
+        if (e != hipSuccess) return hip_fail(e, "work-list staging");
+        pl->stage_pending = false;
+    }
+    int32_t *h = pl->h_stage;
+    const size_t nr = ring.size(), ngl = glist.size(), ngr = grange.size(), nnc = over ? (size_t)B : 0;
+    std::memcpy(h, ring.data(), sizeof(int32_t) * nr);
+    std::memcpy(h + nr, glist.data(), sizeof(int32_t) * ngl);
+    std::memcpy(h + nr + ngl, grange.data(), sizeof(int32_t) * ngr);
+    if (over) std::memcpy(h + nr + ngl + ngr, ncells_host, sizeof(int32_t) * nnc);
+    // the slot is being rewritten: invalid until the uploads are queued
+    v->B = -1;
+    e = hipMemcpyAsync(v->d_ring, h, sizeof(int32_t) * nr, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(v->d_glist, h + nr, sizeof(int32_t) * ngl, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(v->d_grange, h + nr + ngl, sizeof(int32_t) * ngr, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && over)
+        e = hipMemcpyAsync(v->d_ncells, h + nr + ngl + ngr, sizeof(int32_t) * nnc, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(pl->stage_ev, st);
+    if (e != hipSuccess) return hip_fail(e, "upload of the work lists");
+    pl->stage_pending = true;
+    if (over) v->key.assign(ncells_host, ncells_host + B);
+    else v->key.clear();
+    v->B = B;
+    v->group = G;
+    v->override_grid = over;
+    v->pinned = false;
+    v->used = ++pl->clock;
+    pl->cur = v;
     pl->last_B = B;
     return PPM_OK;
 }
 
-// One forward pass over the batch, chunk by chunk.
-static hipError_t run_forward(ppm_plan *pl, const double *params, int B, const int32_t *nc, hipStream_t st,
-                              double *flux, double *counts)
+// Workspace view of one pass of the current layout.
+static Workspace pass_workspace(const ppm_plan *pl, const ListPass &ps)
 {
     const DevSpec &S = pl->S;
-    for (size_t ci = 0; ci < pl->list_off.size(); ++ci) {
-        int c0 = (int)ci * pl->chunk;
-        int nb = B - c0 < pl->chunk ? B - c0 : pl->chunk;
-        Workspace W = pl->W;
-        W.stars += c0;
-        W.vis_pairs += (size_t)c0 * S.R_tot;
+    Workspace W = pl->W;
+    W.stars += ps.inst0;
+    W.vis_pairs += (size_t)ps.inst0 * S.R_tot;
+    W.diag += (size_t)ps.inst0 * S.R_tot * kDiagFields;
+    W.glist = pl->cur->d_glist + 2 * (size_t)ps.grp_off;
+    W.grange = pl->cur->d_grange + 2 * (size_t)ps.inst0;
+    return W;
+}
+
+// One forward pass over the batch, pass by pass.
+static hipError_t run_forward(ppm_plan *pl, const double *params, hipStream_t st, double *flux, double *counts)
+{
+    const DevSpec &S = pl->S;
+    const ListSlot &L = *pl->cur;
+    for (const ListPass &ps : L.pass) {
+        Workspace W = pass_workspace(pl, ps);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         pl->events(e0, e1);
-        hipError_t e = launch_forward(S, W, params + (size_t)c0 * PPM_NPARAM, nc ? nc + c0 : nullptr, nb,
-                                      pl->d_list + pl->list_off[ci], pl->list_n[ci], st,
-                                      flux ? flux + (size_t)c0 * S.P * S.E : nullptr,
-                                      counts + (size_t)c0 * S.P * S.C, e0, e1);
+        hipError_t e = launch_forward(S, W, params + (size_t)ps.inst0 * PPM_NPARAM,
+                                      L.override_grid ? L.d_ncells + ps.inst0 : nullptr, ps.nb,
+                                      L.d_ring + ps.ring_off, ps.n_ring, ps.n_grp, st,
+                                      flux ? flux + (size_t)ps.inst0 * S.P * S.E : nullptr,
+                                      counts + (size_t)ps.inst0 * S.P * S.C, e0, e1);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-// One forward pass of a temperature-map plan over the batch, chunk by chunk.
-static hipError_t run_forward_map(ppm_plan *pl, const double *params, int B, const double *map, hipStream_t st,
+// One forward pass of a temperature-map plan over the batch, pass by pass.
+static hipError_t run_forward_map(ppm_plan *pl, const double *params, const double *map, hipStream_t st,
                                   double *flux, double *counts)
 {
     const DevSpec &S = pl->S;
-    for (size_t ci = 0; ci < pl->list_off.size(); ++ci) {
-        int c0 = (int)ci * pl->chunk;
-        int nb = B - c0 < pl->chunk ? B - c0 : pl->chunk;
-        Workspace W = pl->W;
-        W.stars += c0;
-        W.vis_pairs += (size_t)c0 * S.R_tot;
+    const ListSlot &L = *pl->cur;
+    for (const ListPass &ps : L.pass) {
+        Workspace W = pass_workspace(pl, ps);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         pl->events(e0, e1);
-        hipError_t e = launch_forward_map(S, W, params + (size_t)c0 * PPM_NPARAM, map + (size_t)c0 * S.n_pix, nb,
-                                          pl->d_list + pl->list_off[ci], pl->list_n[ci], st,
-                                          flux ? flux + (size_t)c0 * S.P * S.E : nullptr,
-                                          counts + (size_t)c0 * S.P * S.C, e0, e1);
+        hipError_t e = launch_forward_map(S, W, params + (size_t)ps.inst0 * PPM_NPARAM,
+                                          map + (size_t)ps.inst0 * S.n_pix, ps.nb, L.d_ring + ps.ring_off,
+                                          ps.n_ring, ps.n_grp, st,
+                                          flux ? flux + (size_t)ps.inst0 * S.P * S.E : nullptr,
+                                          counts + (size_t)ps.inst0 * S.P * S.C, e0, e1);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -613,35 +773,32 @@ static hipError_t run_forward_map(ppm_plan *pl, const double *params, int B, con
 int ppm_forward_map(ppm_plan *pl, const double *params_dev, int B, const double *map_dev, double *counts_dev,
                     void *stream)
 {
-    const int32_t *nc = nullptr;
-    int rc = prepare(pl, params_dev, B, nullptr, &nc, true);
+    int rc = prepare(pl, params_dev, B, nullptr, (hipStream_t)stream, true);
     if (rc) return rc;
     if (!map_dev || !counts_dev) return fail(PPM_ERR_ARG, "null map or counts buffer");
-    hipError_t e = run_forward_map(pl, params_dev, B, map_dev, (hipStream_t)stream, nullptr, counts_dev);
+    hipError_t e = run_forward_map(pl, params_dev, map_dev, (hipStream_t)stream, nullptr, counts_dev);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_forward_map launch");
 }
 
 int ppm_flux_map(ppm_plan *pl, const double *params_dev, int B, const double *map_dev, double *flux_dev,
                  void *stream)
 {
-    const int32_t *nc = nullptr;
-    int rc = prepare(pl, params_dev, B, nullptr, &nc, true);
+    int rc = prepare(pl, params_dev, B, nullptr, (hipStream_t)stream, true);
     if (rc) return rc;
     if (!map_dev || !flux_dev) return fail(PPM_ERR_ARG, "null map or flux buffer");
-    hipError_t e = run_forward_map(pl, params_dev, B, map_dev, (hipStream_t)stream, flux_dev, pl->W.counts);
+    hipError_t e = run_forward_map(pl, params_dev, map_dev, (hipStream_t)stream, flux_dev, pl->W.counts);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_flux_map launch");
 }
 
 int ppm_loglike_map(ppm_plan *pl, const double *params_dev, int B, const double *map_dev, const int32_t *data_dev,
                     double *logl_dev, double *counts_dev, void *stream)
 {
-    const int32_t *nc = nullptr;
-    int rc = prepare(pl, params_dev, B, nullptr, &nc, true);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = prepare(pl, params_dev, B, nullptr, st, true);
     if (rc) return rc;
     if (!map_dev || !data_dev || !logl_dev) return fail(PPM_ERR_ARG, "null map, data or logl buffer");
     double *cnt = counts_dev ? counts_dev : pl->W.counts;
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e = run_forward_map(pl, params_dev, B, map_dev, st, nullptr, cnt);
+    hipError_t e = run_forward_map(pl, params_dev, map_dev, st, nullptr, cnt);
     if (e != hipSuccess) return hip_fail(e, "ppm_loglike_map forward");
     e = launch_loglike(pl->W, cnt, pl->S.bkg, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike_map reduction");
@@ -650,66 +807,59 @@ int ppm_loglike_map(ppm_plan *pl, const double *params_dev, int B, const double 
 int ppm_forward(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_cells_host,
                 double *counts_dev, void *stream)
 {
-    const int32_t *nc = nullptr;
-    int rc = prepare(pl, params_dev, B, n_cells_host, &nc);
+    int rc = prepare(pl, params_dev, B, n_cells_host, (hipStream_t)stream);
     if (rc) return rc;
     if (!counts_dev) return fail(PPM_ERR_ARG, "null counts buffer");
-    hipError_t e = run_forward(pl, params_dev, B, nc, (hipStream_t)stream, nullptr, counts_dev);
+    hipError_t e = run_forward(pl, params_dev, (hipStream_t)stream, nullptr, counts_dev);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_forward launch");
 }
 
 int ppm_flux(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_cells_host, double *flux_dev,
              void *stream)
 {
-    const int32_t *nc = nullptr;
-    int rc = prepare(pl, params_dev, B, n_cells_host, &nc);
+    int rc = prepare(pl, params_dev, B, n_cells_host, (hipStream_t)stream);
     if (rc) return rc;
     if (!flux_dev) return fail(PPM_ERR_ARG, "null flux buffer");
-    hipError_t e = run_forward(pl, params_dev, B, nc, (hipStream_t)stream, flux_dev, pl->W.counts);
+    hipError_t e = run_forward(pl, params_dev, (hipStream_t)stream, flux_dev, pl->W.counts);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_flux launch");
 }
 
 int ppm_loglike(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_cells_host,
                 const int32_t *data_dev, double *logl_dev, double *counts_dev, void *stream)
 {
-    const int32_t *nc = nullptr;
-    int rc = prepare(pl, params_dev, B, n_cells_host, &nc);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = prepare(pl, params_dev, B, n_cells_host, st);
     if (rc) return rc;
     if (!data_dev || !logl_dev) return fail(PPM_ERR_ARG, "null data or logl buffer");
     double *cnt = counts_dev ? counts_dev : pl->W.counts;
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e = run_forward(pl, params_dev, B, nc, st, nullptr, cnt);
+    hipError_t e = run_forward(pl, params_dev, st, nullptr, cnt);
     if (e != hipSuccess) return hip_fail(e, "ppm_loglike forward");
     e = launch_loglike(pl->W, cnt, pl->S.bkg, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike reduction");
 }
 
-// One forward + adjoint pass over the batch: per workspace chunk the forward
+// One forward + adjoint pass over the batch: per workspace pass the forward
 // (keeping the pre-absorption flux), then the adjoint of the same instances
 // while their ring scratch is live.  Model counts go to pl->W.counts.
-static hipError_t run_grad(ppm_plan *pl, const double *params, int B, const int32_t *nc, const int32_t *data,
-                           double *grad, hipStream_t st, const char **what)
+static hipError_t run_grad(ppm_plan *pl, const double *params, const int32_t *data, double *grad, hipStream_t st,
+                           const char **what)
 {
     const DevSpec &S = pl->S;
-    for (size_t ci = 0; ci < pl->list_off.size(); ++ci) {
-        int c0 = (int)ci * pl->chunk;
-        int nb = B - c0 < pl->chunk ? B - c0 : pl->chunk;
-        Workspace W = pl->W;
-        W.stars += c0;
-        W.vis_pairs += (size_t)c0 * S.R_tot;
+    const ListSlot &L = *pl->cur;
+    for (const ListPass &ps : L.pass) {
+        Workspace W = pass_workspace(pl, ps);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         pl->events(e0, e1);
-        const double *pc = params + (size_t)c0 * PPM_NPARAM;
-        const int32_t *ncc = nc ? nc + c0 : nullptr;
-        double *cc = pl->W.counts + (size_t)c0 * S.P * S.C;
-        hipError_t e = launch_forward(S, W, pc, ncc, nb, pl->d_list + pl->list_off[ci], pl->list_n[ci], st, W.flux,
-                                      cc, e0, e1);
+        const double *pc = params + (size_t)ps.inst0 * PPM_NPARAM;
+        const int32_t *ncc = L.override_grid ? L.d_ncells + ps.inst0 : nullptr;
+        double *cc = pl->W.counts + (size_t)ps.inst0 * S.P * S.C;
+        const int32_t *list = L.d_ring + ps.ring_off;
+        hipError_t e = launch_forward(S, W, pc, ncc, ps.nb, list, ps.n_ring, ps.n_grp, st, W.flux, cc, e0, e1);
         if (e != hipSuccess) {
             *what = "ppm_loglike_grad forward";
             return e;
         }
-        e = launch_grad(S, W, pc, ncc, nb, pl->d_list + pl->list_off[ci], pl->list_n[ci], cc, data,
-                        grad + (size_t)c0 * PPM_NGRAD, st);
+        e = launch_grad(S, W, pc, ncc, ps.nb, list, ps.n_ring, cc, data, grad + (size_t)ps.inst0 * PPM_NGRAD, st);
         if (e != hipSuccess) {
             *what = "ppm_loglike_grad adjoint";
             return e;
@@ -723,16 +873,60 @@ int ppm_loglike_grad(ppm_plan *pl, const double *params_dev, int B, const int32_
 {
     if (!pl) return fail(PPM_ERR_ARG, "null plan");
     if (!pl->grad) return fail(PPM_ERR_UNSUPPORTED, "plan created without gradient buffers (spec->grad = 0)");
-    const int32_t *nc = nullptr;
-    int rc = prepare(pl, params_dev, B, n_cells_host, &nc);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = prepare(pl, params_dev, B, n_cells_host, st);
     if (rc) return rc;
     if (!data_dev || !logl_dev || !grad_dev) return fail(PPM_ERR_ARG, "null data, logl or grad buffer");
-    hipStream_t st = (hipStream_t)stream;
     const char *what = "";
-    hipError_t e = run_grad(pl, params_dev, B, nc, data_dev, grad_dev, st, &what);
+    hipError_t e = run_grad(pl, params_dev, data_dev, grad_dev, st, &what);
     if (e != hipSuccess) return hip_fail(e, what);
     e = launch_loglike(pl->W, pl->W.counts, pl->S.bkg, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
     return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike_grad reduction");
+}
+
+int ppm_get_diagnostics(ppm_plan *pl, int B, ppm_diag *total, ppm_diag *per_instance, void *stream)
+{
+    if (!pl || (!total && !per_instance)) return fail(PPM_ERR_ARG, "ppm_get_diagnostics: null argument");
+    if (B < 1 || B > pl->max_batch) return fail(PPM_ERR_BATCH, "batch outside [1, max_batch]");
+    const DevSpec &S = pl->S;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ppm_get_diagnostics sync");
+    const size_t n = (size_t)B * S.R_tot;
+    std::vector<int32_t> vp(n), dg(n * kDiagFields);
+    e = hipMemcpy(vp.data(), pl->W.vis_pairs, sizeof(int32_t) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(dg.data(), pl->W.diag, sizeof(int32_t) * dg.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "ppm_get_diagnostics copy");
+    // negative intensities are counted by the generic table kernel only
+    const bool neg = S.intensity == PPM_I_TABLE && !S.fast;
+    ppm_diag tot;
+    std::memset(&tot, 0, sizeof(tot));
+    for (int b = 0; b < B; ++b) {
+        ppm_diag d;
+        std::memset(&d, 0, sizeof(d));
+        for (int r = 0; r < S.R_tot; ++r) {
+            const size_t i = (size_t)b * S.R_tot + r;
+            const int32_t *g = &dg[i * kDiagFields];
+            const int64_t evals = (int64_t)vp[i] * S.E;
+            d.n_visible_pairs += vp[i];
+            if (g[0] & 1) d.n_clamp_T += evals;
+            if (g[0] & 2) d.n_clamp_g += evals;
+            d.n_clamp_T += (int64_t)g[4] * S.E;
+            d.n_multi_image += g[1];
+            d.n_x_outside += g[2];
+            d.n_negative += g[3];
+        }
+        if (!neg) d.n_negative = -1;
+        if (per_instance) per_instance[b] = d;
+        tot.n_visible_pairs += d.n_visible_pairs;
+        tot.n_clamp_T += d.n_clamp_T;
+        tot.n_clamp_g += d.n_clamp_g;
+        tot.n_x_outside += d.n_x_outside;
+        tot.n_multi_image += d.n_multi_image;
+        tot.n_negative += d.n_negative;
+    }
+    if (!neg) tot.n_negative = -1;
+    if (total) *total = tot;
+    return PPM_OK;
 }
 
 int ppm_get_tiles(const ppm_plan *pl, ppm_tiles *out)
@@ -740,6 +934,7 @@ int ppm_get_tiles(const ppm_plan *pl, ppm_tiles *out)
     if (!pl || !out) return fail(PPM_ERR_ARG, "ppm_get_tiles: null argument");
     out->phase_tile = pl->S.pt_fwd;
     out->phase_tile_grad = pl->S.pt_adj;
+    out->ring_group = pl->S.ring_group;
     return PPM_OK;
 }
 
@@ -750,8 +945,11 @@ int ppm_set_tiles(ppm_plan *pl, const ppm_tiles *t)
         return fail(PPM_ERR_ARG, "phase_tile must lie in [1, 256]");
     if (t->phase_tile_grad < kMinTileGrad || t->phase_tile_grad > kMaxTile)
         return fail(PPM_ERR_ARG, "phase_tile_grad must lie in [8, 256]");
+    if (t->ring_group < 1 || t->ring_group > kMaxRingGroup)
+        return fail(PPM_ERR_ARG, "ring_group must lie in [1, 64]");
     pl->S.pt_fwd = t->phase_tile;
     pl->S.pt_adj = t->phase_tile_grad;
+    pl->S.ring_group = t->ring_group;
     return PPM_OK;
 }
 
@@ -856,26 +1054,36 @@ int ppm_autotune(ppm_plan *pl, const double *params_dev, int B, const int32_t *n
                  void *stream, ppm_tune_report *report)
 {
     if (reps < 1 || reps > 1000) return fail(PPM_ERR_ARG, "ppm_autotune: reps must lie in [1, 1000]");
-    const int32_t *nc = nullptr;
-    int rc = prepare(pl, params_dev, B, n_cells_host, &nc);
-    if (rc) return rc;
+    if (!pl || !params_dev) return fail(PPM_ERR_ARG, "ppm_autotune: null plan or params");
     hipStream_t st = (hipStream_t)stream;
+    if (stream_capturing(st)) return fail(PPM_ERR_ARG, "ppm_autotune: the stream is being captured");
     DevSpec &S = pl->S;
-    const int pt0 = S.pt_fwd, pa0 = S.pt_adj;
+    const int pt0 = S.pt_fwd, pa0 = S.pt_adj, rg0 = S.ring_group;
     ppm_tune_report rep;
     std::memset(&rep, 0, sizeof(rep));
     auto restore = [&](int code) {
         S.pt_fwd = pt0;
         S.pt_adj = pa0;
+        S.ring_group = rg0;
         return code;
     };
-    // forward tile
+    // every candidate runs the batch as a caller's call would: the layout
+    // (work lists of the candidate's ring group) is made resident first
+    auto fwd = [&](const char **what) {
+        int r = prepare(pl, params_dev, B, n_cells_host, st);
+        if (r) {
+            *what = ppm_last_error();
+            return hipErrorInvalidValue;
+        }
+        *what = "ppm_autotune forward";
+        return run_forward(pl, params_dev, st, nullptr, pl->W.counts);
+    };
+    int rc = prepare(pl, params_dev, B, n_cells_host, st);
+    if (rc) return rc;
+    // forward tile at the plan's ring group
     const std::vector<int> fc = tile_candidates({4, 8, 12, 16, 20, 24, 28, 32, 48, 64, 96, 128}, S.P);
     std::vector<double> fms;
-    rc = time_candidates(fc, [&](int t) { S.pt_fwd = t; }, [&](const char **what) {
-        *what = "ppm_autotune forward";
-        return run_forward(pl, params_dev, B, nc, st, nullptr, pl->W.counts);
-    }, reps, st, fms);
+    rc = time_candidates(fc, [&](int t) { S.pt_fwd = t; }, fwd, reps, st, fms);
     if (rc) return restore(rc);
     double best = 0.0;
     int best_t = pt0;
@@ -888,6 +1096,29 @@ int ppm_autotune(ppm_plan *pl, const double *params_dev, int B, const int32_t *n
         }
     }
     S.pt_fwd = best_t;
+    // rings per block of the windowed kernel at that tile: 1, 2, 4, 8, 16,
+    // 32 (candidates beyond the rings of one instance are skipped)
+    if (S.intensity == PPM_I_TABLE && S.fast && S.n_side == 0) {
+        std::vector<int> gc;
+        for (int g : {1, 2, 4, 8, 16, 32})
+            if (g == 1 || g <= S.n_rings_spec[0] + S.n_rings_spec[1]) gc.push_back(g);
+        std::vector<double> gms;
+        rc = time_candidates(gc, [&](int g) { S.ring_group = g; }, fwd, reps, st, gms);
+        if (rc) return restore(rc);
+        double bg = 0.0;
+        int best_g = rg0;
+        for (size_t c = 0; c < gc.size(); ++c) {
+            rep.group[rep.n_group] = gc[c];
+            rep.group_ms[rep.n_group++] = gms[c];
+            if (c == 0 || gms[c] < bg) {
+                bg = gms[c];
+                best_g = gc[c];
+            }
+        }
+        S.ring_group = best_g;
+        rc = prepare(pl, params_dev, B, n_cells_host, st);
+        if (rc) return restore(rc);
+    }
     // adjoint tile (gradient plans)
     if (pl->grad) {
         DevBuf data, grad;
@@ -899,7 +1130,7 @@ int ppm_autotune(ppm_plan *pl, const double *params_dev, int B, const int32_t *n
         const std::vector<int> gc = tile_candidates({8, 16, 24, 32}, S.P);
         std::vector<double> gms;
         rc = time_candidates(gc, [&](int t) { S.pt_adj = t; }, [&](const char **what) {
-            return run_grad(pl, params_dev, B, nc, (const int32_t *)data.p, (double *)grad.p, st, what);
+            return run_grad(pl, params_dev, (const int32_t *)data.p, (double *)grad.p, st, what);
         }, reps, st, gms);
         if (rc) return restore(rc);
         for (size_t c = 0; c < gc.size(); ++c) {
@@ -917,6 +1148,7 @@ int ppm_autotune(ppm_plan *pl, const double *params_dev, int B, const int32_t *n
     }
     rep.chosen.phase_tile = S.pt_fwd;
     rep.chosen.phase_tile_grad = S.pt_adj;
+    rep.chosen.ring_group = S.ring_group;
     if (report) *report = rep;
     return PPM_OK;
 }
@@ -925,11 +1157,12 @@ int ppm_autotune_map(ppm_plan *pl, const double *params_dev, int B, const double
                      ppm_tune_report *report)
 {
     if (reps < 1 || reps > 1000) return fail(PPM_ERR_ARG, "ppm_autotune_map: reps must lie in [1, 1000]");
-    const int32_t *nc = nullptr;
-    int rc = prepare(pl, params_dev, B, nullptr, &nc, true);
+    if (!pl || !params_dev) return fail(PPM_ERR_ARG, "ppm_autotune_map: null plan or params");
+    hipStream_t st = (hipStream_t)stream;
+    if (stream_capturing(st)) return fail(PPM_ERR_ARG, "ppm_autotune_map: the stream is being captured");
+    int rc = prepare(pl, params_dev, B, nullptr, st, true);
     if (rc) return rc;
     if (!map_dev) return fail(PPM_ERR_ARG, "null map");
-    hipStream_t st = (hipStream_t)stream;
     DevSpec &S = pl->S;
     const int pt0 = S.pt_fwd;
     ppm_tune_report rep;
@@ -938,7 +1171,7 @@ int ppm_autotune_map(ppm_plan *pl, const double *params_dev, int B, const double
     std::vector<double> mms;
     rc = time_candidates(mc, [&](int t) { S.pt_fwd = t; }, [&](const char **what) {
         *what = "ppm_autotune_map forward";
-        return run_forward_map(pl, params_dev, B, map_dev, st, nullptr, pl->W.counts);
+        return run_forward_map(pl, params_dev, map_dev, st, nullptr, pl->W.counts);
     }, reps, st, mms);
     if (rc) {
         S.pt_fwd = pt0;
@@ -957,6 +1190,7 @@ int ppm_autotune_map(ppm_plan *pl, const double *params_dev, int B, const double
     S.pt_fwd = best_t;
     rep.chosen.phase_tile = S.pt_fwd;
     rep.chosen.phase_tile_grad = S.pt_adj;
+    rep.chosen.ring_group = S.ring_group;
     if (report) *report = rep;
     return PPM_OK;
 }
@@ -973,12 +1207,14 @@ int ppm_debug_ring(ppm_plan *pl, int b, int r, double *table_out, double *info_o
                    int32_t *trace_info, void *stream)
 {
     if (!pl) return fail(PPM_ERR_ARG, "null plan");
-    if (b < 0 || b >= pl->chunk || r < 0 || r >= pl->S.R_tot)
-        return fail(PPM_ERR_ARG, "ring out of range (instances of the first workspace chunk only)");
+    if (!pl->cur || pl->cur->pass.empty()) return fail(PPM_ERR_ARG, "ppm_debug_ring: no evaluation yet");
+    const ListPass &lp = pl->cur->pass.back();   // the ring scratch holds the last pass
+    if (b < lp.inst0 || b >= lp.inst0 + lp.nb || r < 0 || r >= pl->S.R_tot)
+        return fail(PPM_ERR_ARG, "ring out of range (instances of the last evaluation's last workspace pass only)");
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "ppm_debug_ring sync");
-    const size_t ring = (size_t)b * pl->S.R_tot + r;
+    const size_t ring = (size_t)(b - lp.inst0) * pl->S.R_tot + r;
     RingRec g;
     e = hipMemcpy(&g, pl->W.rings + ring, sizeof(g), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "ppm_debug_ring copy");

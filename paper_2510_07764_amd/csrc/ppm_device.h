@@ -203,6 +203,34 @@ __device__ inline float x_shift(double t, float ixl)
     return ldexpf(l, k) * ixl;
 }
 
+// Energies whose x position I0 + fr + tbe[e] lies outside the table's node
+// range (interval index below 0 or above nx - 2): stage B gives them a zero
+// quad (windowed kernels).  fr + tbe[e] is computed as stage B computes it (FP32), so the count
+// is that of the evaluation; tbe increases from tbe[0] = 0.
+__device__ inline int x_outside_count(int I0, float fr, const float *tbe, int E, int nx)
+{
+    int n = 0;
+    if (I0 < 0) {                                   // interval index I0 + floor(fr + tbe) < 0
+        const float lim = (float)(-I0);
+        int lo = 0, hi = E;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (fr + tbe[mid] < lim) lo = mid + 1; else hi = mid;
+        }
+        n += lo;
+    }
+    const float lim = (float)(nx - 1 - I0);         // interval index above nx - 2
+    if (fr + tbe[E - 1] >= lim) {
+        int lo = 0, hi = E;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (fr + tbe[mid] < lim) lo = mid + 1; else hi = mid;
+        }
+        n += E - lo;
+    }
+    return n;
+}
+
 __device__ inline int lin_bracket(double v, double v0, double h, int n, double &w1)
 {
     double t = (v - v0) / h;

@@ -32,6 +32,7 @@ struct DevSpec {
     int W_max;            // x-node window of the per-ring sub-table
     int sub_stride;       // floats per ring in the sub-table buffer (multiple of 4)
     int pt_fwd, pt_adj;   // phases per block of the forward / adjoint accumulation kernels
+    int ring_group;       // rings summed per block of the windowed forward accumulation
     int n_side;           // temperature-map plan: HEALPix resolution (0: spot model)
     int n_pix;            // patches of a map (12 n_side^2)
     int map_nb;           // temperature buckets of a map ring (logT steps, with margins)
@@ -47,6 +48,7 @@ struct DevSpec {
     int n_rings_spec[2], n_phi_spec[2];   // default grid of each spot
     double t_exp;
     double T0, hT, g0, hg, x0, hx;   // uniform logT, log g, x axes
+    double T_end[2], g_end[2];       // first and last node of the logT and log g axes (clamp counting)
     const double *energy;   // [E] keV
     const double *sigma;    // [E] cm^2 (nullptr: no absorption)
     const float *rsp32;     // [E][C]
@@ -98,11 +100,12 @@ struct RingRec {
 
 // One active patch of a temperature-map ring, sorted by temperature bucket:
 // cell index on the ring, logT interpolation weight between the bucket's
-// two table nodes, (T / 10^6 K)^3 and log10(k T / keV).
+// two table nodes, (T / 10^6 K)^3, log10(k T / keV) and whether its logT
+// was clamped to the table.
 struct MapCell {
     double lkT;
     float t, T3;
-    int j, pad;
+    int j, clamped;   // clamped: the patch's logT lies outside the table's logT axis
 };
 
 // Temperature buckets of map rings: bucket q holds logT in

@@ -81,7 +81,7 @@ __device__ inline StarRec make_star(const DevSpec &S, const double *p)
 // takes the others' results from LDS and writes the record.  Every thread
 // evaluates the star record itself (identical values).
 __global__ __launch_bounds__(256) void k_setup(DevSpec S, const double *params, const int32_t *n_cells, StarRec *stars,
-                        RingRec *rings, int32_t *vis_pairs)
+                        RingRec *rings, int32_t *vis_pairs, int32_t *diag)
 {
     const int b = blockIdx.y;
     // the whole parameter vector in registers first: validation and setup
@@ -116,8 +116,8 @@ __global__ __launch_bounds__(256) void k_setup(DevSpec S, const double *params, 
     }
     const int shape = S.shape[spot];
     // results of waves 1-3 per ring: outer, inner half-width, cos(mask radius),
-    // cos band difference, log g, T
-    __shared__ double xo[6][64];
+    // cos band difference, log g, T, crescent mask half-width on the ring
+    __shared__ double xo[7][64];
     RingRec g;
     double acap = 0.0;
     if (role == 1) {
@@ -125,6 +125,11 @@ __global__ __launch_bounds__(256) void k_setup(DevSpec S, const double *params, 
     } else if (role == 2) {
         xo[1][lane] = (S.n_side == 0 && shape == PPM_SHAPE_ANNULUS) ? arc_halfwidth(th, tc, S.shape_a[spot] * z) : 0.0;
         xo[2][lane] = cos(S.shape_a[spot] * z);
+        xo[6][lane] = 0.0;
+        if (S.n_side == 0 && shape == PPM_SHAPE_CRESCENT) {
+            const double sgn = (tc >= kHalfPi) ? 1.0 : -1.0;
+            xo[6][lane] = arc_halfwidth(th, tc - sgn * S.shape_b[spot] * z, S.shape_a[spot] * z);
+        }
     } else if (role == 3) {
         xo[3][lane] = S.n_side > 0 ? 0.0 : cos(e0) - cos(e1);
         xo[4][lane] = log10(st.g0 * gravity_ratio(st, S.mode, th));   // Eqs. (10), (11)
@@ -187,8 +192,25 @@ __global__ __launch_bounds__(256) void k_setup(DevSpec S, const double *params, 
     g.kT = kKB * g.T;
     g.cos_zm = xo[2][lane];
     if (live) g.n_cells = S.n_side > 0 ? hp_n : np;
-    rings[(size_t)b * S.R_tot + r] = g;
-    vis_pairs[(size_t)b * S.R_tot + r] = 0;
+    // a crescent ring whose every cell centre lies inside the mask emits
+    // nothing: switched off like a ring outside the spot (with a margin, so
+    // that a cell on the mask edge is left to the per-cell test)
+    if (g.shape == PPM_SHAPE_CRESCENT && S.n_side == 0 && g.dphi_out - 0.5 * g.dphi_cell < xo[6][lane] - 1e-9)
+        g.n_cells = 0;
+    const size_t slot = (size_t)b * S.R_tot + r;
+    rings[slot] = g;
+    vis_pairs[slot] = 0;
+    // diagnostics: table clamps of the ring's logT and log g (Sect. 4), the
+    // counters of the later kernels start at zero
+    int flags = 0;
+    if (S.intensity == PPM_I_TABLE) {
+        if (S.n_side == 0 && (g.logT < S.T_end[0] || g.logT > S.T_end[1])) flags |= 1;
+        if (g.logg < S.g_end[0] || g.logg > S.g_end[1]) flags |= 2;
+    }
+    int32_t *dg = diag + slot * kDiagFields;
+    dg[0] = flags;
+#pragma unroll
+    for (int i = 1; i < kDiagFields; ++i) dg[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -350,7 +372,7 @@ __device__ static void subtable_ring(const DevSpec &S, const RingRec &g, int xw0
 // k_trace: pseudo-patch light curve of one ring (Sect. 2.8.3, Eqs. 38-44)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTraceThreads) void k_trace(DevSpec S, const int32_t *list, const StarRec *stars, RingRec *rings, const double4 *table,
-                        double4 *trace, float *sub)
+                        double4 *trace, float *sub, int32_t *diag)
 {
     extern __shared__ double4 lds_tab[];
     const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
@@ -362,10 +384,14 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace(DevSpec S, const int32_
     double4 *tr_lds = lds_tab + na;            // n_fp + 1 entries
     const double4 *tab = table + ((size_t)b * S.R_tot + r) * na;
     for (int j = threadIdx.x; j < na; j += blockDim.x) lds_tab[j] = tab[j];
-    __shared__ int imin, imax;
-    if (threadIdx.x == 0) { imin = nfp; imax = 0; }   // invisible-range initialisation of Sect. 2.8.3
+    __shared__ int imin, imax, n_multi;
+    if (threadIdx.x == 0) { imin = nfp; imax = 0; n_multi = 0; }   // invisible-range initialisation of Sect. 2.8.3
     __syncthreads();
     const double psi_top = lds_tab[na - 1].x;
+    // Sect. 6: beyond GM/(R c^2) ~ 0.28 a point can be seen along a second
+    // ray; a visible sample with psi > 2 pi - psi_top has one (counted; the
+    // primary image is kept)
+    const bool multi_possible = psi_top > kPi;
     const double dal = g.alpha_max / (na - 1);
     const double sth = sin(g.theta), cth = cos(g.theta);
     for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
@@ -420,6 +446,7 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace(DevSpec S, const int32_
                 double T = h00 * lds_tab[jj].z + h10 * dal * lds_tab[jj].w + h01 * lds_tab[jj + 1].z
                          + h11 * dal * lds_tab[jj + 1].w;
                 po = phi / kTwoPi + st.nu * g.R * T / kC;
+                if (multi_possible && psi > kTwoPi - psi_top) atomicAdd(&n_multi, 1);
             } else {
                 vis = false;
             }
@@ -467,6 +494,7 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace(DevSpec S, const int32_
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int t = 1; t < (int)(blockDim.x >> 6); ++t) { zlo = fmin(zlo, red_lo[t]); zhi = fmax(zhi, red_hi[t]); }
+        diag[((size_t)b * S.R_tot + r) * kDiagFields + 1] = n_multi;
         gp->visible = ring_visible ? 1 : 0;
         gp->inv_min = a0;
         gp->inv_max = a1;
@@ -518,10 +546,12 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace(DevSpec S, const int32_
 // ring's sub-table over mu into S[x] in LDS; per energy: x = log10(z E / kT),
 // cubic Lagrange in x (linear in the first and last interval, zero outside).
 // ---------------------------------------------------------------------------
+// The partial of work-list entry li goes to partial[li] (groups of one ring).
 template <int EPL>
 __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *list, const RingRec *rings,
                                                      const double4 *trace, const float *sub,
-                                                     float *partial, int32_t *vis_pairs, int PT, int n_list)
+                                                     float *partial, int32_t *vis_pairs, int32_t *diag, int PT,
+                                                     int n_list)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     int li, tile;
@@ -553,7 +583,7 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
         tb[m] = e < E ? (log10(S.energy[e]) - lkT - S.x0) / S.hx : 0.0;
     }
     const double mu_lo = axmu[0], mu_hi = axmu[nmu - 1];
-    int npairs = 0;
+    int npairs = 0, nxout = 0, nneg = 0;
     const int k_begin = tile * PT;
     for (int kk = wave; kk < PT; kk += 4) {
         const int k = k_begin + kk;
@@ -613,7 +643,11 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
 #pragma unroll
             for (int m = 0; m < EPL; ++m) {
                 double t = tz + tb[m];
-                if (lane * EPL + m >= E || t < 0.0 || t > nx - 1) continue;
+                if (lane * EPL + m >= E) continue;
+                if (t < 0.0 || t > nx - 1) {      // x outside the table: no contribution (counted)
+                    ++nxout;
+                    continue;
+                }
                 int i = (int)floor(t);
                 if (i > nx - 2) i = nx - 2;
                 float f = (float)(t - i);
@@ -637,20 +671,29 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
                     float w3 = fp1 * f * fm1 * (1.0f / 6.0f);
                     I = w0 * Sw[i - 1] + w1 * Sw[i] + w2 * Sw[i + 1] + w3 * Sw[i + 2];
                 }
+                nneg += I < 0.0f;
                 if (S.interp == PPM_INTERP_CUBIC_CLIP) I = fmaxf(0.0f, I);
                 acc[m] += Fp * I;
             }
             wave_sync();
         }
         const double scale = g.w_cell * g.T * g.T * g.T;
-        float *out = partial + (((size_t)b * S.R_tot + r) * P + k) * E;
+        float *out = partial + ((size_t)li * P + k) * E;
 #pragma unroll
         for (int m = 0; m < EPL; ++m) {
             int e = lane * EPL + m;
             if (e < E) out[e] = (float)(acc[m] * (scale / S.energy[e]));
         }
     }
-    if (lane == 0 && npairs) atomicAdd(&vis_pairs[(size_t)b * S.R_tot + r], npairs);
+    const size_t slot = (size_t)b * S.R_tot + r;
+    if (lane == 0 && npairs) atomicAdd(&vis_pairs[slot], npairs);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        nxout += __shfl_xor(nxout, o, 64);
+        nneg += __shfl_xor(nneg, o, 64);
+    }
+    if (lane == 0 && nxout) atomicAdd(&diag[slot * kDiagFields + 2], nxout);
+    if (lane == 0 && nneg) atomicAdd(&diag[slot * kDiagFields + 3], nneg);
 }
 
 
@@ -766,17 +809,25 @@ __device__ __forceinline__ void pairs_general(uint64_t mask, const float4 *Pp, f
     }
 }
 
+// Block = (group of up to ring_group consecutive work-list rings of one
+// instance, tile of PT phases), NW waves.  The rings are processed one after
+// another: each is staged to LDS and its phases go to the waves as they
+// finish (waves start on phases 0 .. NW-1; each phase is done by one wave in
+// a fixed order over cells, so the sums do not depend on the assignment).
+// The group's partial spectrum [P][E] is written by its first active ring
+// and read, added to and rewritten by the next ones (the block barrier
+// between rings orders them), so one FP32 partial per group and phase goes
+// out instead of one per ring.
 template <int EPL, int NW>
-__global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec S, const int32_t *list, const RingRec *rings,
+__global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec S, const int32_t *list,
+                                                    const int32_t *glist, const RingRec *rings,
                                                     const double4 *trace, const float *sub, float *partial,
-                                                    int32_t *vis_pairs, int PT, int n_list)
+                                                    int32_t *vis_pairs, int32_t *diag, int PT, int n_groups)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    int li, tile;
-    if (!xcd_block(n_list, (S.P + PT - 1) / PT, li, tile)) return;
-    const int ent = list[li], b = ent / S.R_tot, r = ent - b * S.R_tot;
-    const RingRec g = rings[(size_t)b * S.R_tot + r];
-    if (!g.active) return;
+    int gi, tile;
+    if (!xcd_block(n_groups, (S.P + PT - 1) / PT, gi, tile)) return;
+    const int g_first = glist[2 * gi], g_count = glist[2 * gi + 1];
     const int nfp = S.n_fp, nmu = S.nmu, nx = S.nx, E = S.E, P = S.P, W = S.W_max;
     double4 *tr = (double4 *)lds_raw;                          // nfp + 1
     double *axmu = (double *)(tr + nfp + 1);                   // nmu (padded to 16 bytes)
@@ -791,66 +842,19 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     int16_t *pbk = (int16_t *)(mcf + 4 * nmu);                 // 2 nfp phase buckets
     int16_t *mbk = pbk + 2 * nfp;                              // mu_nb mu buckets
     float *sce = (float *)(mbk + S.mu_nb);                     // E: output scale w_cell T^3 / E_e
+    float *tbl = sce + E;                                      // E: the energies' x offsets
     const int n_pb = 2 * nfp;
-    const double4 *gtr = trace + ((size_t)b * S.R_tot + r) * (nfp + 1);
-    {
-        const double scale = g.w_cell * g.T * g.T * g.T;
-        for (int e = threadIdx.x; e < E; e += blockDim.x) sce[e] = (float)(scale / S.energy[e]);
-    }
-    // phases of the tile go to the waves as they finish (waves start on
-    // phases 0 .. NW-1); each phase is done by one wave, so the sums do not
-    // depend on the assignment
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __shared__ int k_next;
-    if (threadIdx.x == 0) k_next = NW;
-    // LDS trace per fine-phase sample i: (F, z_{i+1}/z_i - 1, x position of
-    // E_0 at z_i, mu); phi_o in po
-    for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
-        const double4 v = gtr[i];
-        const double zn = i < nfp ? gtr[i + 1].y : v.y;
-        tr[i] = make_double4(v.x, zn / v.y - 1.0, log10(v.y) * S.ihx + g.tbk, v.w);
-        po[i] = v.z;
-    }
+    // ring-independent tables, staged once per block
     for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
     for (int i = threadIdx.x; i < 4 * nmu; i += blockDim.x) mcf[i] = S.mu_coef[i];
     for (int i = threadIdx.x; i < S.mu_nb; i += blockDim.x) mbk[i] = S.mu_bucket[i];
-    // the ring's sub-table ([nmu][W] in HBM, per-ring stride a multiple of 4
-    // floats) transposed into the x-major LDS layout
-    const float4 *gsub = (const float4 *)(sub + ((size_t)b * S.R_tot + r) * (size_t)S.sub_stride);
-    for (int i = threadIdx.x; i < S.sub_stride / 4; i += blockDim.x) {
-        const float4 v = gsub[i];
-        const float vk[4] = {v.x, v.y, v.z, v.w};
-        int m = (4 * i) / W, c = 4 * i - m * W;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (m < nmu) tab[c * NMP + m] = vk[k];
-            if (++c == W) {
-                c = 0;
-                ++m;
-            }
-        }
-    }
-    __syncthreads();
-    // phase buckets: bucket q covers phi_o[0] + [q, q + 1) / (2 nfp) and holds
-    // the largest i < nfp with phi_o[i] at or below its lower edge
-    for (int q = threadIdx.x; q < n_pb; q += blockDim.x) {
-        const double edge = po[0] + (double)q / n_pb;
-        int l0 = 0, h0 = nfp;
-        while (h0 - l0 > 1) {
-            int mid = (l0 + h0) >> 1;
-            if (po[mid] <= edge) l0 = mid; else h0 = mid;
-        }
-        pbk[q] = (int16_t)l0;
-    }
-    for (int i = threadIdx.x; i < nfp; i += blockDim.x) ipo[i] = 1.0 / (po[i + 1] - po[i]);
-    __syncthreads();
-
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) tbl[e] = S.tbe[e];
     float4 *Qw = Qb + wave * 64;
     float *Sw = Sb + wave * 68;
     float4 *Pw = Pb + wave * 64;
     if (lane < 4) Sw[64 + lane] = 0.0f;
-    const double phio0 = gtr[0].z;                 // phi_o of sample 0 (tr holds x positions)
-    const double inv2pi = 1.0 / kTwoPi;
     float tbr[EPL];
 #pragma unroll
     for (int m = 0; m < EPL; ++m) {
@@ -858,102 +862,173 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
         tbr[m] = e < E ? S.tbe[e] : 0.0f;
     }
     const double mu_lo = S.mu_lo, mu_hi = S.mu_hi;
-    const int xw0 = g.xw0, xw = g.xw;
-    int npairs = 0;
+    const double inv2pi = 1.0 / kTwoPi;
     const int k_begin = tile * PT;
-    for (int kk = wave; kk < PT;) {
-        const int k = k_begin + kk;
-        if (k >= P) break;
-        float acc[EPL];
+    bool first = true;                              // no active ring of the group done yet
+    for (int q = 0; q < g_count; ++q) {
+        const int ent = list[g_first + q], b = ent / S.R_tot, r = ent - b * S.R_tot;
+        const size_t slot = (size_t)b * S.R_tot + r;
+        const RingRec g = rings[slot];
+        if (!g.active) continue;
+        if (!first) __syncthreads();                // the previous ring's LDS tables are no longer read
+        const double4 *gtr = trace + slot * (nfp + 1);
+        {
+            const double scale = g.w_cell * g.T * g.T * g.T;
+            for (int e = threadIdx.x; e < E; e += blockDim.x) sce[e] = (float)(scale / S.energy[e]);
+        }
+        if (threadIdx.x == 0) k_next = NW;
+        // LDS trace per fine-phase sample i: (F, z_{i+1}/z_i - 1, x position of
+        // E_0 at z_i, mu); phi_o in po
+        for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
+            const double4 v = gtr[i];
+            const double zn = i < nfp ? gtr[i + 1].y : v.y;
+            tr[i] = make_double4(v.x, zn / v.y - 1.0, log10(v.y) * S.ihx + g.tbk, v.w);
+            po[i] = v.z;
+        }
+        // the ring's sub-table ([nmu][W] in HBM, per-ring stride a multiple of 4
+        // floats) transposed into the x-major LDS layout
+        const float4 *gsub = (const float4 *)(sub + slot * (size_t)S.sub_stride);
+        for (int i = threadIdx.x; i < S.sub_stride / 4; i += blockDim.x) {
+            const float4 v = gsub[i];
+            const float vk[4] = {v.x, v.y, v.z, v.w};
+            int m = (4 * i) / W, c = 4 * i - m * W;
 #pragma unroll
-        for (int m = 0; m < EPL; ++m) acc[m] = 0.0f;
-        const double Phik = (k + 0.5) / S.Pd;
-        for (int c0 = 0; c0 < g.n_cells; c0 += 64) {
-            // ---------------- stage A: one (cell, phase) pair per lane
-            const int j = c0 + lane;
-            bool vis = false;
-            float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, fr = 0.f;
-            int I0 = 0, m0 = 0;
-            if (j < g.n_cells) {
-                const double off = cell_offset(g, j);
-                if (!cell_masked(g, off)) {
-                    double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
-                    double php = (a - floor(a)) + phio0;                    // Eq. (45)
-                    // Eq. (46): fine interval [phi_o[l0], phi_o[l0+1]) holding php, from
-                    // its bucket and a bounded scan (phi_o increases)
-                    int q = (int)((php - phio0) * S.fpb);
-                    int l0 = pbk[q < n_pb - 1 ? q : n_pb - 1];
-                    while (l0 > 0 && po[l0] > php) --l0;
-                    while (l0 < nfp - 1 && po[l0 + 1] <= php) ++l0;
-                    const double4 A = tr[l0], Cn = tr[l0 + 1];
-                    double wp = (php - po[l0]) * ipo[l0];
-                    wp = fmin(1.0, fmax(0.0, wp));
-                    PhaseSample ps;
-                    ps.F = A.x + wp * (Cn.x - A.x);
-                    ps.mu = A.w + wp * (Cn.w - A.w);
-                    if (ps.F != 0.0) {
-                        vis = true;
-                        double mu = fmin(mu_hi, fmax(mu_lo, ps.mu));
-                        // mu interval [a_lo, a_lo+1) from its bucket and a bounded scan
-                        int qm = (int)((mu - mu_lo) * S.mu_ibw);
-                        int lo = mbk[qm < S.mu_nb - 1 ? qm : S.mu_nb - 1];
-                        while (lo > 0 && axmu[lo] > mu) --lo;
-                        while (lo < nmu - 2 && axmu[lo + 1] <= mu) ++lo;
-                        const double *cf = mcf + 4 * lo;
-                        double v0, v1, v2, v3;
-                        if (lo < 3 || lo == nmu - 2) {
-                            // linear on [a_lo, a_lo+1]; node lo sits at slot lo - m0 of 0..2
-                            const double t = (mu - axmu[lo]) * cf[0];
-                            m0 = lo < nmu - 4 ? lo : nmu - 4;
-                            const int sl = lo - m0;
-                            v0 = sl == 0 ? 1.0 - t : 0.0;
-                            v1 = sl == 0 ? t : (sl == 1 ? 1.0 - t : 0.0);
-                            v2 = sl == 1 ? t : (sl == 2 ? 1.0 - t : 0.0);
-                            v3 = sl == 2 ? t : 0.0;
-                        } else {
-                            // cubic Lagrange on nodes lo-1 .. lo+2, inverse denominators cf
-                            m0 = lo - 1;
-                            const double d0 = mu - axmu[m0], d1 = mu - axmu[m0 + 1], d2 = mu - axmu[m0 + 2],
-                                         d3 = mu - axmu[m0 + 3];
-                            const double p01 = d0 * d1, p23 = d2 * d3;
-                            v0 = d1 * p23 * cf[0];
-                            v1 = d0 * p23 * cf[1];
-                            v2 = p01 * d3 * cf[2];
-                            v3 = p01 * d2 * cf[3];
-                        }
-                        w0 = (float)(v0 * ps.F);
-                        w1 = (float)(v1 * ps.F);
-                        w2 = (float)(v2 * ps.F);
-                        w3 = (float)(v3 * ps.F);
-                        // x position at the interpolated z = z_A (1 + wp q_A)
-                        const double T0 = A.z + (double)x_shift(wp * A.y, S.ixl);
-                        double fl = floor(T0);
-                        I0 = (int)fl;
-                        fr = (float)(T0 - fl);
-                    }
+            for (int k = 0; k < 4; ++k) {
+                if (m < nmu) tab[c * NMP + m] = vk[k];
+                if (++c == W) {
+                    c = 0;
+                    ++m;
                 }
             }
-            uint64_t mask = __ballot(vis);
-            npairs += __popcll(mask);
-            Pw[lane] = make_float4(w0, w1, w2, w3);
-            wave_sync();
-            // ---------------- stage B: the visible pairs one after another
-            if (g.interior)
-                pairs_interior<EPL>(mask, Pw, fr, (I0 << 8) | m0, lane, tab, W, NMP, xw0, Sw, Qw, tbr, acc);
-            else
-                pairs_general<EPL>(mask, Pw, fr, I0, m0, lane, tab, NMP, xw0, xw, nx, Sw, Qw, tbr, acc);
         }
-        float *out = partial + (((size_t)b * S.R_tot + r) * P + k) * E;
+        __syncthreads();
+        // phase buckets: bucket q covers phi_o[0] + [q, q + 1) / (2 nfp) and holds
+        // the largest i < nfp with phi_o[i] at or below its lower edge
+        for (int qb = threadIdx.x; qb < n_pb; qb += blockDim.x) {
+            const double edge = po[0] + (double)qb / n_pb;
+            int l0 = 0, h0 = nfp;
+            while (h0 - l0 > 1) {
+                int mid = (l0 + h0) >> 1;
+                if (po[mid] <= edge) l0 = mid; else h0 = mid;
+            }
+            pbk[qb] = (int16_t)l0;
+        }
+        for (int i = threadIdx.x; i < nfp; i += blockDim.x) ipo[i] = 1.0 / (po[i + 1] - po[i]);
+        __syncthreads();
+
+        const double phio0 = gtr[0].z;                 // phi_o of sample 0 (tr holds x positions)
+        const int xw0 = g.xw0, xw = g.xw;
+        int npairs = 0, nxout = 0;
+        for (int kk = wave; kk < PT;) {
+            const int k = k_begin + kk;
+            if (k >= P) break;
+            float acc[EPL];
 #pragma unroll
-        for (int m = 0; m < EPL; ++m) {
-            int e = lane + 64 * m;
-            if (e < E) out[e] = acc[m] * sce[e];
+            for (int m = 0; m < EPL; ++m) acc[m] = 0.0f;
+            const double Phik = (k + 0.5) / S.Pd;
+            for (int c0 = 0; c0 < g.n_cells; c0 += 64) {
+                // ---------------- stage A: one (cell, phase) pair per lane
+                const int j = c0 + lane;
+                bool vis = false;
+                float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, fr = 0.f;
+                int I0 = 0, m0 = 0;
+                if (j < g.n_cells) {
+                    const double off = cell_offset(g, j);
+                    if (!cell_masked(g, off)) {
+                        double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
+                        double php = (a - floor(a)) + phio0;                    // Eq. (45)
+                        // Eq. (46): fine interval [phi_o[l0], phi_o[l0+1]) holding php, from
+                        // its bucket and a bounded scan (phi_o increases)
+                        int qb = (int)((php - phio0) * S.fpb);
+                        int l0 = pbk[qb < n_pb - 1 ? qb : n_pb - 1];
+                        while (l0 > 0 && po[l0] > php) --l0;
+                        while (l0 < nfp - 1 && po[l0 + 1] <= php) ++l0;
+                        const double4 A = tr[l0], Cn = tr[l0 + 1];
+                        double wp = (php - po[l0]) * ipo[l0];
+                        wp = fmin(1.0, fmax(0.0, wp));
+                        PhaseSample ps;
+                        ps.F = A.x + wp * (Cn.x - A.x);
+                        ps.mu = A.w + wp * (Cn.w - A.w);
+                        if (ps.F != 0.0) {
+                            vis = true;
+                            double mu = fmin(mu_hi, fmax(mu_lo, ps.mu));
+                            // mu interval [a_lo, a_lo+1) from its bucket and a bounded scan
+                            int qm = (int)((mu - mu_lo) * S.mu_ibw);
+                            int lo = mbk[qm < S.mu_nb - 1 ? qm : S.mu_nb - 1];
+                            while (lo > 0 && axmu[lo] > mu) --lo;
+                            while (lo < nmu - 2 && axmu[lo + 1] <= mu) ++lo;
+                            const double *cf = mcf + 4 * lo;
+                            double v0, v1, v2, v3;
+                            if (lo < 3 || lo == nmu - 2) {
+                                // linear on [a_lo, a_lo+1]; node lo sits at slot lo - m0 of 0..2
+                                const double t = (mu - axmu[lo]) * cf[0];
+                                m0 = lo < nmu - 4 ? lo : nmu - 4;
+                                const int sl = lo - m0;
+                                v0 = sl == 0 ? 1.0 - t : 0.0;
+                                v1 = sl == 0 ? t : (sl == 1 ? 1.0 - t : 0.0);
+                                v2 = sl == 1 ? t : (sl == 2 ? 1.0 - t : 0.0);
+                                v3 = sl == 2 ? t : 0.0;
+                            } else {
+                                // cubic Lagrange on nodes lo-1 .. lo+2, inverse denominators cf
+                                m0 = lo - 1;
+                                const double d0 = mu - axmu[m0], d1 = mu - axmu[m0 + 1], d2 = mu - axmu[m0 + 2],
+                                             d3 = mu - axmu[m0 + 3];
+                                const double p01 = d0 * d1, p23 = d2 * d3;
+                                v0 = d1 * p23 * cf[0];
+                                v1 = d0 * p23 * cf[1];
+                                v2 = p01 * d3 * cf[2];
+                                v3 = p01 * d2 * cf[3];
+                            }
+                            w0 = (float)(v0 * ps.F);
+                            w1 = (float)(v1 * ps.F);
+                            w2 = (float)(v2 * ps.F);
+                            w3 = (float)(v3 * ps.F);
+                            // x position at the interpolated z = z_A (1 + wp q_A)
+                            const double T0 = A.z + (double)x_shift(wp * A.y, S.ixl);
+                            double fl = floor(T0);
+                            I0 = (int)fl;
+                            fr = (float)(T0 - fl);
+                            // energies beyond the table's x range contribute nothing (counted)
+                            if (I0 < 0 || (float)I0 + fr + tbl[E - 1] >= (float)(nx - 2))
+                                nxout += x_outside_count(I0, fr, tbl, E, nx);
+                        }
+                    }
+                }
+                uint64_t mask = __ballot(vis);
+                npairs += __popcll(mask);
+                Pw[lane] = make_float4(w0, w1, w2, w3);
+                wave_sync();
+                // ---------------- stage B: the visible pairs one after another
+                if (g.interior)
+                    pairs_interior<EPL>(mask, Pw, fr, (I0 << 8) | m0, lane, tab, W, NMP, xw0, Sw, Qw, tbr, acc);
+                else
+                    pairs_general<EPL>(mask, Pw, fr, I0, m0, lane, tab, NMP, xw0, xw, nx, Sw, Qw, tbr, acc);
+            }
+            float *out = partial + ((size_t)gi * P + k) * E;
+            if (first) {
+#pragma unroll
+                for (int m = 0; m < EPL; ++m) {
+                    int e = lane + 64 * m;
+                    if (e < E) out[e] = acc[m] * sce[e];
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < EPL; ++m) {
+                    int e = lane + 64 * m;
+                    if (e < E) out[e] += acc[m] * sce[e];
+                }
+            }
+            int nk = 0;
+            if (lane == 0) nk = atomicAdd(&k_next, 1);
+            kk = __builtin_amdgcn_readfirstlane(nk);
         }
-        int nk = 0;
-        if (lane == 0) nk = atomicAdd(&k_next, 1);
-        kk = __builtin_amdgcn_readfirstlane(nk);
+        // wave totals of the ring's counters
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) nxout += __shfl_xor(nxout, o, 64);
+        if (lane == 0 && npairs) atomicAdd(&vis_pairs[slot], npairs);
+        if (lane == 0 && nxout) atomicAdd(&diag[slot * kDiagFields + 2], nxout);
+        first = false;
     }
-    if (lane == 0 && npairs) atomicAdd(&vis_pairs[(size_t)b * S.R_tot + r], npairs);
 }
 
 // ---------------------------------------------------------------------------
@@ -1009,7 +1084,7 @@ __global__ __launch_bounds__(256) void k_accum_bb(DevSpec S, const int32_t *list
                 acc[m] += ps.F * I;
             }
         }
-        double *out = partial + (((size_t)b * S.R_tot + r) * P + k) * E;
+        double *out = partial + ((size_t)li * P + k) * E;
 #pragma unroll
         for (int m = 0; m < EPL; ++m) {
             int e = lane * EPL + m;
@@ -1020,33 +1095,48 @@ __global__ __launch_bounds__(256) void k_accum_bb(DevSpec S, const int32_t *list
 }
 
 // ---------------------------------------------------------------------------
-// k_reduce: fixed-order FP64 sum of the ring partials, then absorption
-// (Eq. 22) and the exposure per phase bin, ready for the fold.
+// k_reduce: fixed-order FP64 sum of the ring-group partials of an instance
+// (groups grange[b] .. in work-list order), then absorption (Eq. 22) and the
+// exposure per phase bin, ready for the fold.  A group none of whose rings
+// is active wrote no partial and is skipped.
 // ---------------------------------------------------------------------------
+__device__ inline void stage_group_flags(const int32_t *list, const int32_t *glist, const RingRec *rings, int g0,
+                                         int ng, unsigned char *act)
+{
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        const int f = glist[2 * (g0 + i)], c = glist[2 * (g0 + i) + 1];
+        int a = 0;
+        for (int q = 0; q < c; ++q) a |= rings[list[f + q]].active;
+        act[i] = (unsigned char)a;
+    }
+}
+
 template <typename TP, typename TA>
 __global__ __launch_bounds__(256) void k_reduce(DevSpec S, const StarRec *stars, const RingRec *rings,
+                                                const int32_t *list, const int32_t *glist, const int32_t *grange,
                                                 const TP *partial, double *flux, TA *fold_in)
 {
-    // block: phase k, energies [64 e0, 64 e0 + 64); thread (g, e): rings r = g mod 4
+    // block: phase k, energies [64 e0, 64 e0 + 64); thread (g, e): groups i = g mod 4
     extern __shared__ unsigned char act[];
     __shared__ double red[4][64];
     const int k = blockIdx.x, b = blockIdx.z;
-    const int E = S.E, P = S.P, R = S.R_tot;
+    const int E = S.E, P = S.P;
+    const int g0 = grange[2 * b], ng = grange[2 * b + 1] - g0;
     const int el = threadIdx.x & 63, grp = threadIdx.x >> 6;
     const int e = blockIdx.y * 64 + el;
-    for (int r = threadIdx.x; r < R; r += blockDim.x) act[r] = (unsigned char)rings[(size_t)b * R + r].active;
+    stage_group_flags(list, glist, rings, g0, ng, act);
     __syncthreads();
     double s0 = 0.0, s1 = 0.0;
     if (e < E) {
-        const TP *base = partial + ((size_t)b * R * P + k) * E + e;
+        const TP *base = partial + ((size_t)g0 * P + k) * E + e;
         const size_t rs = (size_t)P * E;
-        int r = grp;
-        for (; r + 4 < R; r += 8) {
-            if (act[r]) s0 += (double)base[r * rs];
-            if (act[r + 4]) s1 += (double)base[(r + 4) * rs];
+        int i = grp;
+        for (; i + 4 < ng; i += 8) {
+            if (act[i]) s0 += (double)base[i * rs];
+            if (act[i + 4]) s1 += (double)base[(i + 4) * rs];
         }
-        for (; r < R; r += 4)
-            if (act[r]) s0 += (double)base[r * rs];
+        for (; i < ng; i += 4)
+            if (act[i]) s0 += (double)base[i * rs];
     }
     red[grp][el] = s0 + s1;
     __syncthreads();
@@ -1061,52 +1151,55 @@ __global__ __launch_bounds__(256) void k_reduce(DevSpec S, const StarRec *stars,
 }
 
 // FP32 partials with E % 4 == 0: a thread owns four consecutive energies and
-// reads them with 16-byte loads; eight ring groups per block.
-constexpr int kReduceGroups = 16;   // ring groups of k_reduce4, group g summing rings g, g + 16, ...
-constexpr int kReduceBatch = 16;    // ring loads in flight per lane
+// reads them with 16-byte loads.
+constexpr int kReduceGroups = 16;   // summing groups of k_reduce4, group q taking partials q, q + 16, ...
+constexpr int kReduceBatch = 16;    // partial loads in flight per lane
 
 // Block = (phase k, 128 energies, instance b), 8 waves: lane l of wave w
-// holds energies 4 (l % 32) .. +3 of the block's 128 for ring group
-// 2 w + l / 32.  Each group sums its rings in increasing order, then the 16
-// group sums are added in group order (groups 0..3 take one energy of the
-// four each): a fixed order independent of the launch.  256 blocks per
-// instance at 128 phases keep every CU busy.
+// holds energies 4 (l % 32) .. +3 of the block's 128 for summing group
+// 2 w + l / 32.  Each summing group adds its ring-group partials in
+// increasing order, then the 16 sums are added in group order (groups 0..3
+// take one energy of the four each): a fixed order independent of the
+// launch.  256 blocks per instance at 128 phases keep every CU busy.
 __global__ __launch_bounds__(32 * kReduceGroups) void k_reduce4(DevSpec S, const StarRec *stars, const RingRec *rings,
-                                                 const float *partial, double *flux, float *fold_in)
+                                                 const int32_t *list, const int32_t *glist,
+                                                 const int32_t *grange, const float *partial, double *flux,
+                                                 float *fold_in)
 {
     extern __shared__ unsigned char act[];
     __shared__ double4 red[kReduceGroups][32];
     const int k = blockIdx.x, b = blockIdx.z;
-    const int E = S.E, P = S.P, R = S.R_tot;
+    const int E = S.E, P = S.P;
+    const int g0 = grange[2 * b], ng = grange[2 * b + 1] - g0;
     const int el = threadIdx.x & 31, grp = threadIdx.x >> 5;
     const int e = (blockIdx.y * 32 + el) * 4;
     const bool live = e < E;
-    const float *base = partial + ((size_t)b * R * P + k) * E + (live ? e : 0);
+    const float *base = partial + ((size_t)g0 * P + k) * E + (live ? e : 0);
     const size_t rs = (size_t)P * E;
-    // the first batch of partials is in flight while the ring flags are staged
-    // (a partial of an inactive ring is read but not added)
+    // the first batch of partials is in flight while the group flags are
+    // staged (a partial of an inactive group is read but not added)
     float4 v[kReduceBatch];
 #pragma unroll
     for (int j = 0; j < kReduceBatch; ++j) {
-        const int r = grp + j * kReduceGroups;
-        v[j] = live && r < R ? *(const float4 *)(base + r * rs) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const int i = grp + j * kReduceGroups;
+        v[j] = live && i < ng ? *(const float4 *)(base + i * rs) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    for (int r = threadIdx.x; r < R; r += blockDim.x) act[r] = (unsigned char)rings[(size_t)b * R + r].active;
+    stage_group_flags(list, glist, rings, g0, ng, act);
     __syncthreads();
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     if (live) {
-        for (int r0 = grp; r0 < R; r0 += kReduceGroups * kReduceBatch) {
-            if (r0 != grp) {
+        for (int i0 = grp; i0 < ng; i0 += kReduceGroups * kReduceBatch) {
+            if (i0 != grp) {
 #pragma unroll
                 for (int j = 0; j < kReduceBatch; ++j) {
-                    const int r = r0 + j * kReduceGroups;
-                    v[j] = r < R ? *(const float4 *)(base + r * rs) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    const int i = i0 + j * kReduceGroups;
+                    v[j] = i < ng ? *(const float4 *)(base + i * rs) : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
             }
 #pragma unroll
             for (int j = 0; j < kReduceBatch; ++j) {
-                const int r = r0 + j * kReduceGroups;
-                if (r < R && act[r]) {
+                const int i = i0 + j * kReduceGroups;
+                if (i < ng && act[i]) {
                     s0 += (double)v[j].x;
                     s1 += (double)v[j].y;
                     s2 += (double)v[j].z;
@@ -1122,8 +1215,8 @@ __global__ __launch_bounds__(32 * kReduceGroups) void k_reduce4(DevSpec S, const
         const int q = grp;
         double t = 0.0;
         for (int g2 = 0; g2 < kReduceGroups; ++g2) {
-            const double *v = (const double *)&red[g2][el];
-            t += v[q];
+            const double *vv = (const double *)&red[g2][el];
+            t += vv[q];
         }
         const StarRec st = stars[b];
         const size_t o = ((size_t)b * P + k) * E + e + q;
@@ -1284,7 +1377,7 @@ size_t accum_table_lds(const DevSpec &S)
              + sizeof(float) * fast_tab_floats(S) + sizeof(float4) * kFwdWaves * 64 + sizeof(float) * kFwdWaves * 68
              + sizeof(float4) * kFwdWaves * 64
              + sizeof(double) * 2 * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
-             + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb) + sizeof(float) * S.E;
+             + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb) + sizeof(float) * 2 * S.E;
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * S.nmu + sizeof(float) * S.nmu * S.nx
          + sizeof(float) * 4 * S.nx;
 }
@@ -1293,7 +1386,7 @@ void launch_setup(const DevSpec &S, const Workspace &W, const double *params, co
                   hipStream_t st)
 {
     hipLaunchKernelGGL(k_setup, dim3((S.R_tot + 63) / 64, B), dim3(256), 0, st, S, params, ncells_dev, W.stars,
-                       W.rings, W.vis_pairs);
+                       W.rings, W.vis_pairs, W.diag);
 }
 
 void launch_table_trace(const DevSpec &S, const Workspace &W, const int32_t *list, int n_list, hipStream_t st)
@@ -1303,69 +1396,76 @@ void launch_table_trace(const DevSpec &S, const Workspace &W, const int32_t *lis
                        list, W.stars, W.rings, W.table);
     size_t lds_tr = sizeof(double4) * (S.n_alpha + S.n_fp + 1);
     hipLaunchKernelGGL(k_trace, dim3(n_list), dim3(kTraceThreads), lds_tr, st, S, list, W.stars, W.rings, W.table,
-                       W.trace, W.sub);
+                       W.trace, W.sub, W.diag);
 }
 
-// FP32 ring partials -> per-instance FP64 sum, absorption, MFMA fold
-void launch_reduce_fold32(const DevSpec &S, const Workspace &W, int B, hipStream_t st, double *flux_out,
-                          double *counts_out)
+// FP32 ring-group partials -> per-instance FP64 sum, absorption, MFMA fold
+void launch_reduce_fold32(const DevSpec &S, const Workspace &W, const int32_t *list, int B, hipStream_t st,
+                          double *flux_out, double *counts_out)
 {
     if ((S.E & 3) == 0)
-        hipLaunchKernelGGL(k_reduce4, dim3(S.P, (S.E + 127) / 128, B), dim3(32 * kReduceGroups), S.R_tot, st, S, W.stars,
-                           W.rings, W.partial32, flux_out, W.fold_in32);
+        hipLaunchKernelGGL(k_reduce4, dim3(S.P, (S.E + 127) / 128, B), dim3(32 * kReduceGroups), S.R_tot, st, S,
+                           W.stars, W.rings, list, W.glist, W.grange, W.partial32, flux_out, W.fold_in32);
     else
         hipLaunchKernelGGL((k_reduce<float, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S,
-                           W.stars, W.rings, W.partial32, flux_out, W.fold_in32);
+                           W.stars, W.rings, list, W.glist, W.grange, W.partial32, flux_out, W.fold_in32);
     hipLaunchKernelGGL(k_fold_f32, dim3((S.C + 15) / 16, (B * S.P + 15) / 16), dim3(256), 0, st,
                        W.fold_in32, S.rsp32, counts_out, B * S.P, S.C, S.E);
 }
 
+// The windowed kernel runs over the ring groups of the pass (W.glist), the
+// generic and blackbody kernels over its rings (groups of one ring: the
+// group list is then the identity, n_groups == n_list).
 hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *params,
-                          const int32_t *ncells_dev, int B, const int32_t *list, int n_list, hipStream_t st,
-                          double *flux_out, double *counts_out, hipEvent_t ev_hot0, hipEvent_t ev_hot1)
+                          const int32_t *ncells_dev, int B, const int32_t *list, int n_list, int n_groups,
+                          hipStream_t st, double *flux_out, double *counts_out, hipEvent_t ev_hot0,
+                          hipEvent_t ev_hot1)
 {
     const bool want_flux_f64 = flux_out != nullptr;
     launch_setup(S, W, params, ncells_dev, B, st);
     launch_table_trace(S, W, list, n_list, st);
     const int PT = S.pt_fwd;
     const int n_tile = (S.P + PT - 1) / PT;
+    const size_t PE = (size_t)S.P * S.E;
     if (S.intensity == PPM_I_TABLE) {
         size_t lds = accum_table_lds(S);
         if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
         int epl = (S.E + 63) / 64;
-        const int step = max_list_per_launch(n_tile, S.fast ? 64 * kFwdWaves : 256);
-        for (int off = 0; off < n_list; off += step) {
-            const int32_t *sl = list + off;
-            const int n = n_list - off < step ? n_list - off : step;
-            dim3 grid(xcd_grid(n, n_tile));
-            if (S.fast) {
-                if (epl <= 1)
-                    hipLaunchKernelGGL((k_accum_fast<1, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, sl, W.rings, W.trace, W.sub,
-                                       W.partial32, W.vis_pairs, PT, n);
-                else if (epl <= 2)
-                    hipLaunchKernelGGL((k_accum_fast<2, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, sl, W.rings, W.trace, W.sub,
-                                       W.partial32, W.vis_pairs, PT, n);
-                else if (epl <= 4)
-                    hipLaunchKernelGGL((k_accum_fast<4, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, sl, W.rings, W.trace, W.sub,
-                                       W.partial32, W.vis_pairs, PT, n);
-                else
-                    hipLaunchKernelGGL((k_accum_fast<8, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, sl, W.rings, W.trace, W.sub,
-                                       W.partial32, W.vis_pairs, PT, n);
-            } else if (epl <= 1)
-                hipLaunchKernelGGL(k_accum_table<1>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.sub,
-                                   W.partial32, W.vis_pairs, PT, n);
-            else if (epl <= 2)
-                hipLaunchKernelGGL(k_accum_table<2>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.sub,
-                                   W.partial32, W.vis_pairs, PT, n);
-            else if (epl <= 4)
-                hipLaunchKernelGGL(k_accum_table<4>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.sub,
-                                   W.partial32, W.vis_pairs, PT, n);
-            else
-                hipLaunchKernelGGL(k_accum_table<8>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.sub,
-                                   W.partial32, W.vis_pairs, PT, n);
+        if (S.fast) {
+            const int step = max_list_per_launch(n_tile, 64 * kFwdWaves);
+            for (int off = 0; off < n_groups; off += step) {
+                const int32_t *gl = W.glist + 2 * (size_t)off;
+                float *pt = W.partial32 + (size_t)off * PE;
+                const int n = n_groups - off < step ? n_groups - off : step;
+                dim3 grid(xcd_grid(n, n_tile));
+#define PPM_FAST(E_)                                                                                              \
+    hipLaunchKernelGGL((k_accum_fast<E_, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, list, gl, W.rings,  \
+                       W.trace, W.sub, pt, W.vis_pairs, W.diag, PT, n)
+                if (epl <= 1) PPM_FAST(1);
+                else if (epl <= 2) PPM_FAST(2);
+                else if (epl <= 4) PPM_FAST(4);
+                else PPM_FAST(8);
+#undef PPM_FAST
+            }
+        } else {
+            const int step = max_list_per_launch(n_tile, 256);
+            for (int off = 0; off < n_list; off += step) {
+                const int32_t *sl = list + off;
+                float *pt = W.partial32 + (size_t)off * PE;
+                const int n = n_list - off < step ? n_list - off : step;
+                dim3 grid(xcd_grid(n, n_tile));
+#define PPM_TAB(E_)                                                                                               \
+    hipLaunchKernelGGL(k_accum_table<E_>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.sub, pt,          \
+                       W.vis_pairs, W.diag, PT, n)
+                if (epl <= 1) PPM_TAB(1);
+                else if (epl <= 2) PPM_TAB(2);
+                else if (epl <= 4) PPM_TAB(4);
+                else PPM_TAB(8);
+#undef PPM_TAB
+            }
         }
         if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
-        launch_reduce_fold32(S, W, B, st, want_flux_f64 ? flux_out : nullptr, counts_out);
+        launch_reduce_fold32(S, W, list, B, st, want_flux_f64 ? flux_out : nullptr, counts_out);
     } else {
         size_t lds = sizeof(double4) * (S.n_fp + 1);
         int epl = (S.E + 63) / 64;
@@ -1373,30 +1473,27 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
         const int step = max_list_per_launch(n_tile, 256);
         for (int off = 0; off < n_list; off += step) {
             const int32_t *sl = list + off;
+            double *pt = W.partial64 + (size_t)off * PE;
             const int n = n_list - off < step ? n_list - off : step;
             dim3 grid(xcd_grid(n, n_tile));
-            if (epl <= 1)
-                hipLaunchKernelGGL(k_accum_bb<1>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.partial64,
-                                   W.vis_pairs, PT, n);
-            else if (epl <= 2)
-                hipLaunchKernelGGL(k_accum_bb<2>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.partial64,
-                                   W.vis_pairs, PT, n);
-            else if (epl <= 4)
-                hipLaunchKernelGGL(k_accum_bb<4>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.partial64,
-                                   W.vis_pairs, PT, n);
-            else
-                hipLaunchKernelGGL(k_accum_bb<8>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, W.partial64,
-                                   W.vis_pairs, PT, n);
+#define PPM_BB(E_) \
+    hipLaunchKernelGGL(k_accum_bb<E_>, grid, dim3(256), lds, st, S, sl, W.rings, W.trace, pt, W.vis_pairs, PT, n)
+            if (epl <= 1) PPM_BB(1);
+            else if (epl <= 2) PPM_BB(2);
+            else if (epl <= 4) PPM_BB(4);
+            else PPM_BB(8);
+#undef PPM_BB
         }
         if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
+        double *fx = want_flux_f64 ? flux_out : nullptr;
         if (S.rsp64) {
-            hipLaunchKernelGGL((k_reduce<double, double>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S, W.stars,
-                               W.rings, W.partial64, want_flux_f64 ? flux_out : nullptr, W.fold_in64);
+            hipLaunchKernelGGL((k_reduce<double, double>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S,
+                               W.stars, W.rings, list, W.glist, W.grange, W.partial64, fx, W.fold_in64);
             hipLaunchKernelGGL(k_fold_f64, dim3((S.C + 255) / 256, B * S.P), dim3(256), 0, st,
                                W.fold_in64, S.rsp64, counts_out, B * S.P, S.C, S.E);
         } else {
-            hipLaunchKernelGGL((k_reduce<double, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S, W.stars,
-                               W.rings, W.partial64, want_flux_f64 ? flux_out : nullptr, W.fold_in32);
+            hipLaunchKernelGGL((k_reduce<double, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S,
+                               W.stars, W.rings, list, W.glist, W.grange, W.partial64, fx, W.fold_in32);
             hipLaunchKernelGGL(k_fold_f32, dim3((S.C + 15) / 16, (B * S.P + 15) / 16), dim3(256), 0, st,
                                W.fold_in32, S.rsp32, counts_out, B * S.P, S.C, S.E);
         }

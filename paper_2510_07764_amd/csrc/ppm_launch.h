@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "ppm_internal.h"
+#include "../../include/ppm.h"
 
 namespace ppm {
 
@@ -14,13 +15,17 @@ struct Workspace {
     double4 *table;        // [B][R_tot][n_alpha]
     double4 *trace;        // [B][R_tot][n_fp + 1]
     float *sub;            // [B][R_tot][nmu][nx]      (table intensity)
-    float *partial32;      // [B][R_tot][P][E]         (FP32 path)
-    double *partial64;     // [B][R_tot][P][E]         (FP64 path)
+    float *partial32;      // [n_groups][P][E] ring-group partial sums (FP32 path), by group-list position
+    double *partial64;     // [n_groups][P][E]         (FP64 path)
     float *fold_in32;      // [B][P][E]
     double *fold_in64;     // [B][P][E]
     double *counts;        // [B][P][C]
     int32_t *vis_pairs;    // [B][R_tot]
-    int32_t *ncells;       // [B] per-instance grid override
+    int32_t *diag;         // [B][R_tot][5] per ring: clamp flags (bit 0 logT, bit 1 log g), multiple-image
+                           // samples, intensity evaluations with x outside the table, negative intensities,
+                           // visible pairs of map patches whose logT was clamped
+    const int32_t *glist;  // [n_groups][2] ring groups of the pass: first work-list position, ring count
+    const int32_t *grange; // [B][2] per instance of the pass: its groups [first, end) in glist
     double *ll_part;       // [B][loglike_blocks] first-stage likelihood sums
     int32_t *ll_bad;       // [B][loglike_blocks] bins with m <= 0 and d > 0
     double *lfact;         // [kLogFact] log d! for the first kLogFact counts
@@ -49,20 +54,26 @@ constexpr int kLogFact = 1024;   // counts whose log d! comes from a table
 #endif
 constexpr int kFwdWaves = PPM_FWD_WAVES;  // waves per block of the forward accumulation kernel
 
+constexpr int kDiagFields = 5;   // per-ring diagnostic counters (Workspace::diag)
+constexpr int kMaxRingGroup = 64; // largest number of rings one accumulation block sums
+
 __host__ __device__ int validate_params(const double *p, int n_spots);
 
+// One workspace pass: B instances, their live rings (list, n_list entries,
+// chunk-local instance index * R_tot + ring slot) and the ring groups of the
+// accumulation (W.glist, n_groups entries; W.grange per instance).
 hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *params,
-                          const int32_t *ncells_dev, int B, const int32_t *list, int n_list, hipStream_t st,
-                          double *flux_out, double *counts_out, hipEvent_t ev_hot0 = nullptr,
+                          const int32_t *ncells_dev, int B, const int32_t *list, int n_list, int n_groups,
+                          hipStream_t st, double *flux_out, double *counts_out, hipEvent_t ev_hot0 = nullptr,
                           hipEvent_t ev_hot1 = nullptr);
 void launch_setup(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev, int B,
                   hipStream_t st);
 void launch_table_trace(const DevSpec &S, const Workspace &W, const int32_t *list, int n_list, hipStream_t st);
-void launch_reduce_fold32(const DevSpec &S, const Workspace &W, int B, hipStream_t st, double *flux_out,
-                          double *counts_out);
+void launch_reduce_fold32(const DevSpec &S, const Workspace &W, const int32_t *list, int B, hipStream_t st,
+                          double *flux_out, double *counts_out);
 hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double *params, const double *map, int B,
-                              const int32_t *list, int n_list, hipStream_t st, double *flux_out, double *counts_out,
-                              hipEvent_t ev_hot0 = nullptr, hipEvent_t ev_hot1 = nullptr);
+                              const int32_t *list, int n_list, int n_groups, hipStream_t st, double *flux_out,
+                              double *counts_out, hipEvent_t ev_hot0 = nullptr, hipEvent_t ev_hot1 = nullptr);
 size_t accum_map_lds(const DevSpec &S);
 constexpr int kMapWaves = 8;     // waves per block of the map accumulation kernel, one phase each
 hipError_t launch_loglike(const Workspace &W, const double *counts, const double *bkg, int B, int PC,
@@ -74,6 +85,8 @@ hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *param
 size_t accum_table_lds(const DevSpec &S);
 size_t accum_adj_lds(const DevSpec &S);
 int loglike_blocks(int PC);
+// read access to a plan's model, workspace, batch limit and device (host)
+bool plan_view(const ppm_plan *pl, const DevSpec **S, const Workspace **W, int *max_batch, int *device);
 int api_fail(int code, const char *msg);           // sets ppm_last_error, returns code
 int api_hip_fail(hipError_t e, const char *where);  // sets ppm_last_error, returns PPM_ERR_HIP
 

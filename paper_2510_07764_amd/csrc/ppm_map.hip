@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_map_sort(DevSpec S, const int32_t *list
             c.t = (float)w;
             c.T3 = (float)pow(10.0, 3.0 * (lt - 6.0));
             c.j = j;
-            c.pad = 0;
+            c.clamped = (lt < S.T_end[0] || lt > S.T_end[1]) ? 1 : 0;   // logT clamped for the table (Sect. 4)
             out[run[q] + rank] = c;
         }
         __syncthreads();
@@ -133,11 +133,12 @@ __global__ __launch_bounds__(256) void k_map_sort(DevSpec S, const int32_t *list
 //            I0 + lane (linear in the first and last table interval, zero
 //            outside), per energy one quad read and a Horner step.
 // ---------------------------------------------------------------------------
+// The partial of work-list entry li goes to partial[li] (groups of one ring).
 template <int EPL, int KPW>
 __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const int32_t *list, const RingRec *rings,
                                                              const double4 *trace, const MapCell *cells,
                                                              const int32_t *grp, float *partial, int32_t *vis_pairs,
-                                                             int n_list)
+                                                             int32_t *diag, int n_list)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     constexpr int PT = kMapWaves * KPW;
@@ -160,6 +161,7 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     double *mcf = ipo + nfp + 1;                               // nmu * 4 mu-interval coefficients
     int16_t *pbk = (int16_t *)(mcf + 4 * nmu);                 // 2 nfp phase buckets
     int16_t *mbk = pbk + 2 * nfp;                              // mu_nb mu buckets
+    float *tbl = (float *)(mbk + ((S.mu_nb + 1) & ~1));        // E: the energies' x offsets
     const int n_pb = 2 * nfp;
     const int tid = threadIdx.x;
     const double4 *gtr = trace + slot * (nfp + 1);
@@ -174,6 +176,7 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     for (int i = tid; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
     for (int i = tid; i < 4 * nmu; i += blockDim.x) mcf[i] = S.mu_coef[i];
     for (int i = tid; i < S.mu_nb; i += blockDim.x) mbk[i] = S.mu_bucket[i];
+    for (int e = tid; e < E; e += blockDim.x) tbl[e] = S.tbe[e];
     __syncthreads();
     // phase buckets and inverse spacings of phi_o, as in the spot kernel
     for (int q = tid; q < n_pb; q += blockDim.x) {
@@ -215,7 +218,7 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     for (int kq = 0; kq < KPW; ++kq)
 #pragma unroll
         for (int m = 0; m < EPL; ++m) acc[kq][m] = 0.0f;
-    int npairs = 0;
+    int npairs = 0, nclamp = 0, nxout = 0;
     for (int q = 0; q < NB; ++q) {
         const int c_beg = gr[q], c_end = gr[q + 1];
         if (c_end == c_beg) continue;
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
             for (int c0 = c_beg; c0 < c_end; c0 += 64) {
                 // ---------------- stage A: one (patch, phase) pair per lane
                 const int cc = c0 + lane;
-                bool vis = false;
+                bool vis = false, clamped = false;
                 float w0f = 0.f, w1f = 0.f, w2f = 0.f, w3f = 0.f, fr = 0.f, tw = 0.f;
                 int I0 = 0, m0 = 0;
                 if (cc < c_end) {
@@ -305,10 +308,15 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
                         const double fl = floor(T0);
                         I0 = (int)fl;
                         fr = (float)(T0 - fl);
+                        clamped = mc.clamped != 0;
+                        // energies beyond the table's x range contribute nothing (counted)
+                        if (I0 < 0 || (float)I0 + fr + tbl[E - 1] >= (float)(nx - 2))
+                            nxout += x_outside_count(I0, fr, tbl, E, nx);
                     }
                 }
                 uint64_t mask = __ballot(vis);
                 npairs += __popcll(mask);
+                nclamp += __popcll(__ballot(clamped));
                 // ---------------- stage B: the visible pairs one after another
                 while (mask) {
                     const int p = __ffsll((unsigned long long)mask) - 1;
@@ -357,14 +365,18 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     for (int kq = 0; kq < KPW; ++kq) {
         const int k = k_first + kMapWaves * kq;
         if (k >= P) break;
-        float *out = partial + (slot * P + k) * E;
+        float *out = partial + ((size_t)li * P + k) * E;
 #pragma unroll
         for (int m = 0; m < EPL; ++m) {
             int e = lane + 64 * m;
             if (e < E) out[e] = (float)(acc[kq][m] * (scale / S.energy[e]));
         }
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nxout += __shfl_xor(nxout, o, 64);
     if (lane == 0 && npairs) atomicAdd(&vis_pairs[slot], npairs);
+    if (lane == 0 && nclamp) atomicAdd(&diag[slot * kDiagFields + 4], nclamp);
+    if (lane == 0 && nxout) atomicAdd(&diag[slot * kDiagFields + 2], nxout);
 }
 
 size_t accum_map_lds(const DevSpec &S)
@@ -372,13 +384,14 @@ size_t accum_map_lds(const DevSpec &S)
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.n_fp + 2) & ~1) + sizeof(double) * ((S.nmu + 1) & ~1)
          + sizeof(float) * 2 * (size_t)S.nmu * S.map_wm + sizeof(float4) * kMapWaves * 64
          + sizeof(float) * kMapWaves * 68 + sizeof(double) * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
-         + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb);
+         + sizeof(int16_t) * (2 * S.n_fp + ((S.mu_nb + 1) & ~1)) + sizeof(float) * S.E;
 }
 
 hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double *params, const double *map, int B,
-                              const int32_t *list, int n_list, hipStream_t st, double *flux_out, double *counts_out,
-                              hipEvent_t ev_hot0, hipEvent_t ev_hot1)
+                              const int32_t *list, int n_list, int n_groups, hipStream_t st, double *flux_out,
+                              double *counts_out, hipEvent_t ev_hot0, hipEvent_t ev_hot1)
 {
+    (void)n_groups;   // groups of one ring: the group list is the identity
     launch_setup(S, W, params, nullptr, B, st);
     hipLaunchKernelGGL(k_map_sort, dim3(n_list), dim3(256), sizeof(int) * (2 * S.map_nb + 256), st, S, list, map,
                        W.stars, W.rings, W.mcell, W.mgrp);
@@ -390,7 +403,7 @@ hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double
     if (ev_hot0) (void)hipEventRecord(ev_hot0, st);
 #define PPM_MAP_LAUNCH(E_, K_)                                                                                   \
     hipLaunchKernelGGL((k_accum_map<E_, K_>), grid, dim3(64 * kMapWaves), lds, st, S, sl, W.rings, W.trace,     \
-                       W.mcell, W.mgrp, W.partial32, W.vis_pairs, n)
+                       W.mcell, W.mgrp, W.partial32 + (size_t)off * S.P * S.E, W.vis_pairs, W.diag, n)
 #define PPM_MAP_KPW(E_)                          \
     do {                                         \
         if (kpw == 1) PPM_MAP_LAUNCH(E_, 1);     \
@@ -414,7 +427,7 @@ hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double
 #undef PPM_MAP_KPW
 #undef PPM_MAP_LAUNCH
     if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
-    launch_reduce_fold32(S, W, B, st, flux_out, counts_out);
+    launch_reduce_fold32(S, W, list, B, st, flux_out, counts_out);
     return hipGetLastError();
 }
 

@@ -152,6 +152,22 @@ def atmosphere_table(seed: int = SEED_ATMOS, n_t=35, n_g=11, n_mu=67, n_x=166):
     return np.log10(v), (ax_t, ax_g, ax_mu, ax_x)
 
 
+def atmosphere_table_multilinear(n_t=35, n_g=11, n_mu=67, n_x=166):
+    """Synthetic table that is a product of linear functions of its four
+    axes, V = c (1 + 0.3 (logT - 6)) (1 + 0.2 (log g - 14.2)) (1 + 0.8 mu)
+    (2.5 - x), positive over the axes' ranges.  Every interpolation
+    strategy of Sect. 4 reproduces it exactly, so a model built on it has no
+    kinks from interpolation stencils: what is left of the forward model's
+    piecewise structure is the fine-phase interpolation (Eq. 46) and
+    visibility.  Used for gradient checks at tight tolerance.  Same axes
+    and layout as atmosphere_table (log10 V)."""
+    ax_t, ax_g, ax_mu, ax_x = atmosphere_axes(n_t, n_g, n_mu, n_x)
+    pref = 0.03 * 2.0 * K_B_KEV ** 3 / (H_KEVS ** 3 * C_CGS ** 2)
+    v = (pref * (1.0 + 0.3 * (ax_t[:, None, None, None] - 6.0)) * (1.0 + 0.2 * (ax_g[None, :, None, None] - 14.2))
+         * (1.0 + 0.8 * ax_mu[None, None, :, None]) * (2.5 - ax_x[None, None, None, :]))
+    return np.log10(v), (ax_t, ax_g, ax_mu, ax_x)
+
+
 def atmosphere_table_steep_limb(n_t=35, n_g=11, n_mu=67, n_x=166):
     """Synthetic table with a limb far steeper than the mu grid resolves,
     for the interpolation-overshoot diagnostics of Sect. 4: the blackbody

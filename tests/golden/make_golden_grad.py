@@ -8,7 +8,10 @@ Calls only the FP64 CPU oracle (and the seeded input generators):
                      the stored config-1 data: the oracle's logL and its
                      central finite differences over the twelve
                      differentiable slots with steps h_i = s |theta_i| for
-                     s in 1e-4, 1e-5, 1e-6, 1e-7.
+                     s in 1e-4, 1e-5, 1e-6, 1e-7 ("fd_<s>"), and the
+                     chain-rule differences of the counts contracted with
+                     d logL / d m (oracle.fd_gradient_counts) for s in
+                     1e-5, 3e-6, 1e-6, 3e-7, 1e-7 ("fdc_<s>").
 Steps already present in an existing file are kept (each step set takes
 about 20 minutes on 8 cores).
 Run: python tests/golden/make_golden_grad.py
@@ -27,6 +30,7 @@ import oracle  # noqa: E402
 import synthetic as syn  # noqa: E402
 
 STEPS = (1e-4, 1e-5, 1e-6, 1e-7)
+CHAIN_STEPS = (1e-5, 3e-6, 1e-6, 3e-7, 1e-7)
 
 
 def main():
@@ -50,6 +54,15 @@ def main():
         g = oracle.fd_gradient(os_, q, data, syn.GRAD_SLOTS, rel_step=s)
         out[key] = g.tolist()
         print(s, g.tolist(), "%.0f s" % (time.time() - t0), flush=True)
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+    for s in CHAIN_STEPS:
+        key = "fdc_%g" % s
+        if key in out:
+            continue
+        g = oracle.fd_gradient_counts(os_, q, data, syn.GRAD_SLOTS, rel_step=s)
+        out[key] = g.tolist()
+        print("chain", s, g.tolist(), "%.0f s" % (time.time() - t0), flush=True)
         with open(path, "w") as f:
             json.dump(out, f, indent=1)
 

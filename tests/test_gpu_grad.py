@@ -6,13 +6,24 @@ theta_2, zeta_2, logT_2, dphi_2), evaluated away from the data's truth
 (the first seeded draw within +-5% of the config-1 parameters) so that no
 component vanishes by construction.
 
-Bar, per component n: |g_gpu - FD_n(1e-6)| <= max(1e-5 * max(|FD_n|, 1e-3 *
-max|FD|), 2 * spread_n), where FD_n(s) is the oracle's central difference
-with step s * |theta_n| and spread_n = max - min of FD_n over s in {1e-5,
-1e-6, 1e-7}: the model is piecewise polynomial (linear phase interpolation,
-piecewise-cubic Lagrange stencils), so central differences converge only
-as far as their steps avoid stencil kinks, and the spread measures how far
-that is.  Where the differences have converged the bar is 1e-5 relative.
+Reference: the oracle's counts differenced centrally with steps
+h_n = s |theta_n| over a ladder of s and contracted with the closed-form
+d logL / d m (``oracle.fd_gradient_counts``).  The model is piecewise
+polynomial (linear phase interpolation, piecewise-cubic Lagrange stencils
+in mu and x, bilinear in logT / log g), so a difference converges only
+while its step crosses no stencil or fine-phase kink.  Per component the
+reference is the mean of the two adjacent ladder steps that agree best, and
+their relative disagreement delta_n says how well the reference is known.
+
+Bar, per component, on the true relative error (no floor).  On the
+multilinear synthetic table (interpolation exact, no stencil kinks) every
+component's differences converge to delta_n <= 1e-6 and the bar is
+|g_n - FD_n| <= (1e-5 + delta_n) |FD_n|: 1e-5 relative for all twelve
+components, Phi and dphi_2 included.  On the synthetic NSX-like table the
+piecewise-cubic stencils put kinks inside every step for the phase-like
+directions (Phi, dphi_2), whose differences wander by up to ~1e-4 between
+steps; there the differences over the steps <= 1e-5 bracket the
+derivative and the bar is 1e-5 beyond that bracket (printed per component).
 """
 import json
 import os
@@ -22,10 +33,10 @@ import pytest
 
 import oracle
 import synthetic as syn
+from fdcheck import LADDER, NAMES, fd_gate, report
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
-NAMES = ("M", "R_e", "i", "Phi", "N_H", "theta1", "zeta1", "logT1", "theta2", "zeta2", "logT2", "dphi2")
 
 
 @pytest.fixture(scope="module")
@@ -35,17 +46,11 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
-def fd_gate(g, fds):
-    """fds: {step: FD vector}; returns per-component (error, bound)."""
-    f6 = fds[1e-6]
-    spread = np.max([fds[s] for s in fds], axis=0) - np.min([fds[s] for s in fds], axis=0)
-    floor = 1e-3 * np.abs(f6).max()
-    bound = np.maximum(1e-5 * np.maximum(np.abs(f6), floor), 2.0 * spread)
-    return np.abs(g - f6), bound
-
-
-def small_problem(cells, phases, energies):
+def small_problem(cells, phases, energies, table="synthetic"):
     spec, p = syn.config1(n_cells=cells, n_phase=phases, n_energy=energies)
+    if table == "multilinear":
+        logi, axes = syn.atmosphere_table_multilinear()
+        spec["atmos_logI"], spec["atmos_axes"] = logi, axes
     os_ = oracle.OracleSpec(spec)
     _, cnt, _ = oracle.forward(os_, p)
     data = syn.poisson_data(cnt)
@@ -53,24 +58,24 @@ def small_problem(cells, phases, energies):
     return spec, os_, data, q
 
 
-@pytest.mark.parametrize("cells,phases,energies", [(16, 32, 64), (24, 40, 256)])
-def test_grad_vs_oracle_fd(torch_dev, cells, phases, energies):
+@pytest.mark.parametrize("cells,phases,energies,table", [(8, 16, 32, "multilinear"), (16, 32, 64, "multilinear"),
+                                                         (16, 32, 64, "synthetic"), (24, 40, 256, "synthetic")])
+def test_grad_vs_oracle_fd(torch_dev, cells, phases, energies, table):
     import paper_2510_07764_amd as ppm
     torch, dev = torch_dev
-    spec, os_, data, q = small_problem(cells, phases, energies)
-    fds = {s: oracle.fd_gradient(os_, q, data, syn.GRAD_SLOTS, rel_step=s) for s in (1e-5, 1e-6, 1e-7)}
-    fd4 = oracle.fd_gradient(os_, q, data, syn.GRAD_SLOTS, rel_step=1e-4)
+    spec, os_, data, q = small_problem(cells, phases, energies, table)
+    ladder = LADDER if cells <= 16 else LADDER[2:7]
+    fds = {s: oracle.fd_gradient_counts(os_, q, data, syn.GRAD_SLOTS, rel_step=s) for s in ladder}
     plan = ppm.Plan(spec, max_batch=1, grad=True)
     ll, g = plan.loglike_grad(torch.tensor(q[None], dtype=torch.float64, device=dev),
                               torch.tensor(data, device=dev))
     g = g.cpu().numpy()[0]
-    err, bound = fd_gate(g, fds)
-    floor = 1e-3 * np.abs(fds[1e-6]).max()
-    for n in range(12):
-        print("%-7s gpu %+.9e  fd(1e-6) %+.9e  err/scale %.1e  bound/scale %.1e  |gpu-fd(1e-4)|/scale %.1e"
-              % (NAMES[n], g[n], fds[1e-6][n], err[n] / max(abs(fds[1e-6][n]), floor),
-                 bound[n] / max(abs(fds[1e-6][n]), floor), abs(g[n] - fd4[n]) / max(abs(fd4[n]), floor)))
-    assert np.all(err <= bound), [(NAMES[n], err[n], bound[n]) for n in range(12) if err[n] > bound[n]]
+    rel, bound, delta = fd_gate(g, fds, kinked=table != "multilinear")
+    report(g, fds, rel, bound, delta)
+    if table == "multilinear":
+        # no stencil kinks: every component's reference is known to 1e-6
+        assert np.all(delta <= 1e-6), [(NAMES[n], delta[n]) for n in range(12) if delta[n] > 1e-6]
+    assert np.all(rel <= bound), [(NAMES[n], rel[n], bound[n]) for n in range(12) if rel[n] > bound[n]]
     # the likelihood value itself is the plain path's
     assert ll.item() == pytest.approx(oracle.loglike(os_, q, data), rel=1e-5)
 
@@ -186,15 +191,11 @@ def test_grad_full_size_golden(torch_dev):
     ll, g = plan.loglike_grad(torch.tensor(q[None], dtype=torch.float64, device=dev),
                               torch.tensor(data, device=dev))
     g = g.cpu().numpy()[0]
-    fds = {float(k[3:]): np.array(v) for k, v in gold.items() if k.startswith("fd_")}
-    steps = sorted(s for s in fds if s <= 1e-5) or [1e-6]
-    sub = {s: fds[s] for s in steps}
-    sub.setdefault(1e-6, fds[1e-6])
-    err, bound = fd_gate(g, sub)
-    floor = 1e-3 * np.abs(fds[1e-6]).max()
-    for n in range(12):
-        print("%-7s gpu %+.9e  fd(1e-6) %+.9e  err/scale %.1e  |gpu-fd(1e-4)|/scale %.1e"
-              % (NAMES[n], g[n], fds[1e-6][n], err[n] / max(abs(fds[1e-6][n]), floor),
-                 abs(g[n] - fds[1e-4][n]) / max(abs(fds[1e-4][n]), floor)))
+    fds = {float(k[4:]): np.array(v) for k, v in gold.items() if k.startswith("fdc_")}
+    assert len(fds) >= 3, "stored chain-rule differences missing (tests/golden/make_golden_grad.py)"
+    rel, bound, delta = fd_gate(g, fds, kinked=True)
+    report(g, fds, rel, bound, delta)
+    fd4 = np.array(gold["fd_0.0001"])
+    print("vs the logL difference at step 1e-4:", np.round(np.abs(g - fd4) / np.abs(fd4), 7).tolist(), flush=True)
     assert ll.item() == pytest.approx(gold["loglike"], rel=1e-6)
-    assert np.all(err <= bound), [(NAMES[n], err[n], bound[n]) for n in range(12) if err[n] > bound[n]]
+    assert np.all(rel <= bound), [(NAMES[n], rel[n], bound[n]) for n in range(12) if rel[n] > bound[n]]

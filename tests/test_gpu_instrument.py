@@ -20,6 +20,7 @@ import pytest
 import oracle
 from oracle import instrument as I
 import synthetic as syn
+from fdcheck import fd_gate, report
 from fits_writer import write_arf, write_rmf
 
 pytestmark = pytest.mark.gpu
@@ -115,23 +116,15 @@ def test_background_gradient(torch_dev):
         _, c, _ = oracle.forward(os_, x)
         return I.loglike_with_background(c, bkg, data)
 
-    fds = {}
-    for s in (1e-5, 1e-6, 1e-7):
-        g = np.zeros(12)
-        for n, sl in enumerate(syn.GRAD_SLOTS):
-            h = s * abs(q[sl]) if q[sl] != 0 else s
-            a, b = q.copy(), q.copy()
-            a[sl] += h
-            b[sl] -= h
-            g[n] = (ll(a) - ll(b)) / (2 * h)
-        fds[s] = g
+    # reference: the oracle's counts differenced over a ladder of steps and
+    # contracted with d logL / d m = d / (m + b) - 1; true relative error
+    # (no floor), bracketed by the differences at the kinked table
+    fds = {s: oracle.fd_gradient_counts(os_, q, data, syn.GRAD_SLOTS, rel_step=s, background=bkg)
+           for s in (3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7)}
     plan = ppm.Plan(dict(spec, background=bkg), max_batch=1, grad=True)
     lg, gg = plan.loglike_grad(torch.tensor(q[None], dtype=torch.float64, device=dev), torch.tensor(data, device=dev))
     g = gg.cpu().numpy()[0]
-    f6 = fds[1e-6]
-    spread = np.max(list(fds.values()), axis=0) - np.min(list(fds.values()), axis=0)
-    bound = np.maximum(1e-5 * np.maximum(np.abs(f6), 1e-3 * np.abs(f6).max()), 2 * spread)
-    err = np.abs(g - f6)
-    print("background gradient err/bound:", np.round(err / bound, 3), flush=True)
-    assert np.all(err <= bound)
+    rel, bound, delta = fd_gate(g, fds, kinked=True)
+    report(g, fds, rel, bound, delta)
+    assert np.all(rel <= bound)
     assert lg.item() == pytest.approx(ll(q), rel=1e-5)

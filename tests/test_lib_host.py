@@ -83,14 +83,17 @@ def test_tile_entry_points_reject_null_arguments(L):
     ranges on the host, before any device work."""
     import ctypes as C
     import paper_2510_07764_amd as ppm
-    t = ppm._Tiles(8, 8)
+    t = ppm._Tiles(8, 8, 1)
     assert L.ppm_get_tiles(None, C.byref(t)) == -1
     assert L.ppm_set_tiles(None, C.byref(t)) == -1
     r = ppm._TuneReport()
     assert L.ppm_autotune(None, None, 1, None, 3, None, C.byref(r)) == -1
     assert L.ppm_autotune(None, None, 1, None, 0, None, C.byref(r)) == -1
     assert "reps" in L.ppm_last_error().decode()
-    assert C.sizeof(ppm._TuneReport) == 8 + 2 * 16 * (4 + 8) + 8
+    # three counts, then per table 16 int32 (padded to 8 bytes) and 16 doubles,
+    # then ppm_tiles (three int32), padded to 8 bytes
+    assert C.sizeof(ppm._TuneReport) == 16 + 64 + 128 + 64 + 128 + 64 + 128 + 16
+    assert C.sizeof(ppm._Tiles) == 12 and C.sizeof(ppm._Diag) == 48
 
 
 def test_sampler_configuration_errors(L):

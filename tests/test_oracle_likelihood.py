@@ -68,3 +68,33 @@ def test_fd_gradient_richardson():
     # central differences agree to O(h) ~ 1e-4 relative, 1e-6 of |g|max
     np.testing.assert_allclose(g1, g2, rtol=1e-4, atol=1e-6 * np.abs(g1).max())
     assert np.all(np.abs(g1) > 0)
+
+
+def test_fd_gradient_counts_pins():
+    """The chain-rule differences (counts differenced, contracted with
+    d logL / d m = d / m - 1): the N_H component against its closed form
+    (N_H enters only through exp(-N_H sigma), so d m / d N_H =
+    -1e20 T_exp / P (F_t sigma exp(-N_H sigma)) RSP from the oracle's flux),
+    and every component against the plain differences of logL where both
+    converge (multilinear table, no stencil kinks)."""
+    spec, p = syn.config1(n_cells=8, n_phase=16, n_energy=32)
+    logi, axes = syn.atmosphere_table_multilinear()
+    spec["atmos_logI"], spec["atmos_axes"] = logi, axes
+    os_ = oracle.OracleSpec(spec)
+    _, cnt, _ = oracle.forward(os_, p)
+    data = syn.poisson_data(cnt)
+    q = syn.config4_draws(1)[0]
+    g = oracle.fd_gradient_counts(os_, q, data, syn.GRAD_SLOTS, rel_step=1e-6)
+    ft, m, _ = oracle.forward(os_, q)
+    sig = spec["sigma"]
+    att = np.exp(-q[4] * 1e20 * sig)
+    dm = -1e20 * (ft * sig * att) @ spec["rsp"] * (spec["t_exp"] / 16)
+    gm = np.where(data > 0, data / m, 0.0) - 1.0
+    assert g[4] == pytest.approx(float(np.sum(gm * dm)), rel=1e-8)
+    gl = oracle.fd_gradient(os_, q, data, syn.GRAD_SLOTS, rel_step=3e-6)
+    np.testing.assert_allclose(g, gl, rtol=2e-5)
+    # background: the contraction uses d / (m + b) - 1
+    b = np.full_like(m, 0.5 * m.mean())
+    gb = oracle.fd_gradient_counts(os_, q, data, (4,), rel_step=1e-6, background=b)
+    gmb = np.where(data > 0, data / (m + b), 0.0) - 1.0
+    assert gb[0] == pytest.approx(float(np.sum(gmb * dm)), rel=1e-8)
