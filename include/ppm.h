@@ -178,6 +178,26 @@ int ppm_flux(ppm_plan *plan, const double *params_dev, int B, const int32_t *n_c
 int ppm_loglike(ppm_plan *plan, const double *params_dev, int B, const int32_t *n_cells_host,
                 const int32_t *data_dev, double *logl_dev, double *counts_dev, void *stream);
 
+/* Allocation-free variant of ppm_loglike, for callers that cannot allocate
+ * device memory during a call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments and results as
+ * ppm_loglike with n_cells_host = NULL (the spec's own grids), computed by
+ * the same kernels with the plan's tiles and ring group: logl_dev[B], and
+ * counts_dev[B][n_phase][n_chan] unless NULL.  Every per-call buffer is
+ * carved from one static device array of 64 MiB per device (held by each
+ * device the library runs on until the process ends) and the work lists are
+ * built on the device; the call makes no allocation, no host-device copy
+ * and no host synchronisation.  The plan supplies its constant tables only.
+ * All calls on one device share that array: calls that overlap on a device
+ * (two streams, or two plans) race and must be serialised by the caller.
+ * PPM_ERR_BATCH when the batch needs more than the 64 MiB (for the
+ * 128x128-cell two-spot workload at 128 phases and 256 energies: one
+ * instance with one ring per group, four with groups of 16 rings),
+ * PPM_ERR_UNSUPPORTED for a temperature-map plan, PPM_ERR_ARG when the
+ * current device is not the plan's. */
+int ppm_loglike_noalloc(ppm_plan *plan, const double *params_dev, int B, const int32_t *data_dev,
+                        double *logl_dev, double *counts_dev, void *stream);
+
 /* Poisson log-likelihood and its gradient with respect to the twelve
  * differentiable parameters, in the order M, R_e, i, Phi, N_H, theta_1,
  * zeta_1, logT_1, theta_2, zeta_2, logT_2, dphi_2 (units of the parameter

@@ -96,6 +96,7 @@ SIGNATURES = {
     "ppm_flux": (C.c_int, [_VP, _VP, C.c_int, _I32P, _VP, _VP]),
     "ppm_loglike": (C.c_int, [_VP, _VP, C.c_int, _I32P, _VP, _VP, _VP, _VP]),
     "ppm_loglike_grad": (C.c_int, [_VP, _VP, C.c_int, _I32P, _VP, _VP, _VP, _VP]),
+    "ppm_loglike_noalloc": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP, _VP]),
     "ppm_forward_map": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP]),
     "ppm_flux_map": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP]),
     "ppm_loglike_map": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP, _VP, _VP]),
@@ -346,6 +347,21 @@ class Plan:
         cptr = _dptr(counts) if counts is not None else None
         _check(lib().ppm_loglike(self.handle, _dptr(params), B, nc, _dptr(data), _dptr(out), cptr,
                                  _stream_handle(stream)), "ppm_loglike")
+        return out
+
+    def loglike_noalloc(self, params, data, counts=None, out=None, stream=None):
+        """logL[B] through ``ppm_loglike_noalloc`` (the spec's own grids; the
+        library allocates nothing in the call; ``out`` given: this binding
+        allocates nothing either)."""
+        import torch
+        B = self._params(params)
+        assert data.is_cuda and data.dtype == torch.int32 and data.is_contiguous()
+        assert data.numel() == self.n_phase * self.n_chan
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=params.device)
+        cptr = _dptr(counts) if counts is not None else None
+        _check(lib().ppm_loglike_noalloc(self.handle, _dptr(params), B, _dptr(data), _dptr(out), cptr,
+                                         _stream_handle(stream)), "ppm_loglike_noalloc")
         return out
 
     def loglike_grad(self, params, data, n_cells=None, out=None, grad=None, stream=None):

@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libppm.so")
-SOURCES = ["ppm_kernels.hip", "ppm_adjoint.hip", "ppm_map.hip", "ppm_sampler.hip", "ppm_ogip.cpp", "ppm_api.cpp"]
+SOURCES = ["ppm_kernels.hip", "ppm_adjoint.hip", "ppm_map.hip", "ppm_sampler.hip", "ppm_ogip.cpp", "ppm_api.cpp",
+           "ppm_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",
          # no packed FP32 instructions: some of their forms have given wrong
