@@ -9,7 +9,8 @@ ring reduction and absorption, MFMA response fold, FP64 log-likelihood) for
 one parameter vector, inputs resident in device memory.
 
 Prints one JSON line.  `value` is the plain (one vector per call) rate; the
-graph-replayed plain rate, the batched rate (B vectors per call) and the
+graph-replayed plain rate, the batched rates (B vectors per call), the
+uneven-resolution sampler batch (1024 draws with their own grids) and the
 +grad rate (logL and its twelve-parameter gradient, B vectors per call) are
 reported beside it.
 """
@@ -129,7 +130,10 @@ def main():
     ap.add_argument("--pt-steps", type=int, default=20, help="timed steps of the sampler leg")
     ap.add_argument("--tiles", default="auto",
                     help="launch shape of the accumulation kernels: 'auto' (autotuner, per leg) or "
-                         "'F,G' (forward and adjoint phase tiles)")
+                         "'F,G[,R]' (forward and adjoint phase tiles, rings per forward work-group)")
+    ap.add_argument("--uneven", type=int, default=1024,
+                    help="seeded sampler draws with their own grids (64..512 cells per side) per call of the "
+                         "uneven-resolution leg (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the batched path shards "
@@ -149,16 +153,17 @@ def main():
     data = np.load(gold)
     data_t = torch.tensor(data, device=dev)
 
-    def tune(plan_, params_, reps):
-        """Autotuned (or fixed) phase tiles of a plan; returns the report."""
+    def tune(plan_, params_, reps, n_cells=None):
+        """Autotuned (or fixed) launch shape of a plan; returns the report."""
         if args.tiles == "auto":
-            rep = plan_.autotune(params_, reps=reps)
-            return {"chosen": list(rep["chosen"]),
+            rep = plan_.autotune(params_, n_cells=n_cells, reps=reps)
+            return {"chosen": list(rep["chosen"]), "ring_group": rep["ring_group"],
                     "forward_ms": {str(k): round(v, 4) for k, v in rep["forward"].items()},
+                    "group_ms": {str(k): round(v, 4) for k, v in rep["group"].items()},
                     "grad_ms": {str(k): round(v, 4) for k, v in rep["grad"].items()}}
-        f, g = (int(v) for v in args.tiles.split(","))
-        plan_.set_tiles(f, g)
-        return {"chosen": [f, g], "fixed": True}
+        f, g, r = (int(v) for v in (args.tiles.split(",") + ["1"])[:3])
+        plan_.set_tiles(f, g, r)
+        return {"chosen": [f, g], "ring_group": r, "fixed": True}
 
     def prewarm(fn, seconds=0.2):
         """Untimed calls for about `seconds` (the GPU clock ramps up under
@@ -216,37 +221,64 @@ def main():
     graph_ok = bool(torch.equal(gl1(pt), ll))
     del gl1
 
-    # ---------------- batched: B config-1-shape vectors per graph replay
-    def batched_leg(B):
-        draws = syn.config4_draws(B)
-        planb = ppm.Plan(spec, max_batch=B)
+    # ---------------- batched: B vectors per graph replay; config-1-shape draws,
+    # or the uneven-resolution sampler draws with their own grids
+    def batched_leg(B, uneven=False, tiles_from=None):
+        if uneven:
+            draws, res = syn.config3_draws(B)
+            nc = np.ascontiguousarray(res, dtype=np.int32)
+            planb = ppm.Plan(spec, max_batch=B, max_cells=int(nc.max()))
+        else:
+            draws, nc = syn.config4_draws(B), None
+            planb = ppm.Plan(spec, max_batch=B)
         ptb = torch.tensor(draws, dtype=torch.float64, device=dev)
-        tuned = tune(planb, ptb, 3)
+        if tiles_from is None:
+            tuned = tune(planb, ptb, 3, n_cells=nc)
+        else:
+            # one evaluation of this leg takes seconds: the launch shape tuned on
+            # the large config-1-shape batch is taken over instead of re-tuned
+            f, g = tiles_from["chosen"]
+            planb.set_tiles(f, g, tiles_from["ring_group"])
+            tuned = {"chosen": [f, g], "ring_group": tiles_from["ring_group"], "from": "batched_large"}
+        prewarm(lambda: planb.loglike(ptb, data_t, n_cells=nc))
         # one direct call with the hot kernel timed (events on the launch stream)
         planb.profile_begin(64)
-        planb.loglike(ptb, data_t)
+        planb.loglike(ptb, data_t, n_cells=nc)
         torch.cuda.synchronize()
         hms, nh = planb.profile_end()
         bunits = planb.visible_pairs(B) * planb.n_energy
-        glb = ppm.GraphedLogLike(planb, data_t, B)
+        passes = planb.passes
+        glb = ppm.GraphedLogLike(planb, data_t, B, n_cells=nc)
         glb(ptb)
         torch.cuda.synchronize()
-        kb = max(2, args.steps // 10)
+        kb = max(5, args.steps // 10)
         t0 = time.perf_counter()
         for _ in range(kb):
             out_b = glb(ptb)
         torch.cuda.synchronize()
         tb = (time.perf_counter() - t0) / kb
         bach = bunits * FLOP_PER_UNIT / (hms * 1e-3) / 1e12
-        res = {"evals_per_s": B / tb, "batch": B, "ms_per_call": tb * 1e3, "calls": kb,
-               "finite": bool(torch.isfinite(out_b).all().item()), "vs_plain": (B / tb) * plain_s,
+        out = {"evals_per_s": B / tb, "batch": B, "ms_per_call": tb * 1e3, "calls": kb, "passes": passes,
+               "finite": bool(torch.isfinite(out_b).all().item()),
+               "n_finite": int(torch.isfinite(out_b).sum().item()), "vs_plain": (B / tb) * plain_s,
                "hot_kernel_ms": hms, "hot_kernel_launches": nh, "units": bunits,
                "roofline_frac": bach / PEAK_FP32_TFLOPS, "tiles": tuned}
+        if uneven:
+            out["grids"] = {str(n): int((nc == n).sum()) for n in (64, 128, 256, 512)}
+            out["workload"] = (f"{B} seeded sampler draws (M 1-2.2, R_e 9-15 km, any geometry, logT 5.8-6.6) with "
+                               f"per-instance grids 64^2..512^2 cells per spot, 128 phases, 256 energies, "
+                               f"300 channels; one captured graph per call; logL is -inf where a "
+                               f"draw's spots leave a phase bin dark (model counts 0 where the data "
+                               f"count is positive)")
         del glb, planb
-        return res
+        return out
 
     batched = batched_leg(args.batch) if args.batch > 0 else None
     batched_large = batched_leg(args.batch_large) if args.batch_large > 0 else None
+    uneven = None
+    if args.uneven > 0:
+        uneven = batched_leg(args.uneven, uneven=True,
+                             tiles_from=batched_large["tiles"] if batched_large is not None else None)
 
     # ---------------- +grad: logL and the twelve-parameter gradient, B vectors per graph replay
     grad = None
@@ -257,9 +289,8 @@ def main():
         ptg = torch.tensor(draws, dtype=torch.float64, device=dev)
         tuned_g = tune(plang, ptg, 2)
         glg = ppm.GraphedLogLike(plang, data_t, B, grad=True)
-        glg(ptg)
-        torch.cuda.synchronize()
-        kg = max(2, args.steps // 10)
+        prewarm(lambda: glg(ptg))
+        kg = max(5, args.steps // 10)
         t0 = time.perf_counter()
         for _ in range(kg):
             out_l, out_g = glg(ptg)
@@ -393,6 +424,7 @@ def main():
         "plain_tiles": tune_plain,
         "batched": batched,
         "batched_large": batched_large,
+        "uneven": uneven,
         "grad": grad,
         "map": tmap,
         "sampler": ptleg,

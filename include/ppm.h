@@ -282,6 +282,11 @@ int ppm_debug_ring(ppm_plan *plan, int b, int r, double *table_out, double *info
  * summed over instances (host; synchronises the stream). */
 int ppm_visible_pairs(ppm_plan *plan, int B, long long *out, void *stream);
 
+/* Workspace passes of the last evaluation (host, no synchronisation): a
+ * batch runs in passes of at most the instances whose ring scratch and
+ * ring-group partial spectra the plan holds (0 before the first call). */
+int ppm_get_passes(const ppm_plan *plan, int *n_passes);
+
 /* Timing of the intensity-accumulation kernel (the hot loop) with HIP events
  * recorded on the caller's stream around each launch, for the next max_calls
  * evaluations.  ppm_profile_end synchronises on the recorded events and

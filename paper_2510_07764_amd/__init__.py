@@ -105,6 +105,7 @@ SIGNATURES = {
     "ppm_debug_ring": (C.c_int, [_VP, C.c_int, C.c_int, _DP, _DP, _DP, _I32P, _VP]),
     "ppm_visible_pairs": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_longlong), _VP]),
     "ppm_get_diagnostics": (C.c_int, [_VP, C.c_int, C.POINTER(_Diag), C.POINTER(_Diag), _VP]),
+    "ppm_get_passes": (C.c_int, [_VP, C.POINTER(C.c_int)]),
     "ppm_profile_begin": (C.c_int, [_VP, C.c_int]),
     "ppm_profile_end": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "ppm_get_tiles": (C.c_int, [_VP, C.POINTER(_Tiles)]),
@@ -515,6 +516,13 @@ class Plan:
         if per_instance:
             return tot.as_dict(), [per[i].as_dict() for i in range(B)]
         return tot.as_dict()
+
+    @property
+    def passes(self):
+        """Workspace passes of the last evaluation."""
+        n = C.c_int()
+        _check(lib().ppm_get_passes(self.handle, C.byref(n)), "ppm_get_passes")
+        return n.value
 
     def visible_pairs(self, B, stream=None):
         out = C.c_longlong()

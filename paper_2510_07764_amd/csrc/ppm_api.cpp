@@ -454,8 +454,9 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     // workspace: per-instance outputs and counters for max_batch instances;
     // ring-level scratch for `chunk` instances per pass (a 64 GiB budget of
     // the 288 GB bounds the chunk); ring-group partial spectra for `gcap`
-    // groups per pass: the chunk at groups of 16 rings, and at least one
-    // instance at one ring per group
+    // groups per pass: the chunk at groups of 4 rings (as fast as one ring
+    // per group for large batches, with a quarter of the partials), and at
+    // least one instance at one ring per group
     Workspace &W = pl->W;
     std::memset(&W, 0, sizeof(W));
     const size_t R = S.R_tot;
@@ -468,8 +469,8 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
                       + sizeof(float2) * (size_t)S.sub_stride
                       + sizeof(double) * kGradAcc * (size_t)((S.P + kMinTileGrad - 1) / kMinTileGrad);
         const size_t part_bytes = (S.intensity == PPM_I_TABLE ? sizeof(float) : sizeof(double)) * (size_t)S.P * S.E;
-        const size_t groups16 = (R + 15) / 16;
-        size_t per_inst = per_ring * R + part_bytes * groups16 + sizeof(double) * (size_t)S.P * S.E
+        const size_t groups4 = (R + 3) / 4;
+        size_t per_inst = per_ring * R + part_bytes * groups4 + sizeof(double) * (size_t)S.P * S.E
                         + (sp->grad ? (sizeof(double) + sizeof(float)) * (size_t)S.P * S.E : 0)
                         + (map_plan ? sizeof(MapCell) * (size_t)S.n_pix : 0);
         size_t budget = (size_t)64 << 30;
@@ -482,7 +483,12 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
             if (v >= 1 && (size_t)v < c) c = (size_t)v;
         }
         pl->chunk = (int)(c < (size_t)max_batch ? c : (size_t)max_batch);
-        pl->gcap = std::max((size_t)pl->chunk * groups16, R);
+        pl->gcap = std::max((size_t)pl->chunk * groups4, R);
+        // PPM_PARTIAL_GROUPS sets the ring-group partials per pass (launch-shape studies)
+        if (const char *env = std::getenv("PPM_PARTIAL_GROUPS")) {
+            long v = std::strtol(env, nullptr, 10);
+            if (v >= (long)R) pl->gcap = (size_t)v;
+        }
     }
     const size_t B = pl->chunk, BM = max_batch;
     W.stars = pl->dalloc<StarRec>(BM);
@@ -492,8 +498,8 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
     W.vis_pairs = pl->dalloc<int32_t>(BM * R);
     W.diag = pl->dalloc<int32_t>(BM * R * kDiagFields);
     W.counts = pl->dalloc<double>(BM * S.P * S.C);
-    W.ll_part = pl->dalloc<double>(BM * loglike_blocks(S.P * S.C));
-    W.ll_bad = pl->dalloc<int32_t>(BM * loglike_blocks(S.P * S.C));
+    W.ll_part = pl->dalloc<double>(BM * loglike_parts(S.P, S.C));
+    W.ll_bad = pl->dalloc<int32_t>(BM * loglike_parts(S.P, S.C));
     {
         std::vector<double> lf(kLogFact);
         for (int d = 0; d < kLogFact; ++d) lf[d] = std::lgamma(d + 1.0);
@@ -728,11 +734,14 @@ static Workspace pass_workspace(const ppm_plan *pl, const ListPass &ps)
     W.diag += (size_t)ps.inst0 * S.R_tot * kDiagFields;
     W.glist = pl->cur->d_glist + 2 * (size_t)ps.grp_off;
     W.grange = pl->cur->d_grange + 2 * (size_t)ps.inst0;
+    W.ll_done += ps.inst0;
     return W;
 }
 
-// One forward pass over the batch, pass by pass.
-static hipError_t run_forward(ppm_plan *pl, const double *params, hipStream_t st, double *flux, double *counts)
+// One forward pass over the batch, pass by pass; with data, the likelihood
+// of every instance goes to logl (counts may then be NULL for FP32 plans).
+static hipError_t run_forward(ppm_plan *pl, const double *params, hipStream_t st, double *flux, double *counts,
+                              const int32_t *data = nullptr, double *logl = nullptr)
 {
     const DevSpec &S = pl->S;
     const ListSlot &L = *pl->cur;
@@ -744,7 +753,8 @@ static hipError_t run_forward(ppm_plan *pl, const double *params, hipStream_t st
                                       L.override_grid ? L.d_ncells + ps.inst0 : nullptr, ps.nb,
                                       L.d_ring + ps.ring_off, ps.n_ring, ps.n_grp, st,
                                       flux ? flux + (size_t)ps.inst0 * S.P * S.E : nullptr,
-                                      counts + (size_t)ps.inst0 * S.P * S.C, e0, e1);
+                                      counts ? counts + (size_t)ps.inst0 * S.P * S.C : nullptr, data,
+                                      logl ? logl + ps.inst0 : nullptr, e0, e1);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -752,7 +762,8 @@ static hipError_t run_forward(ppm_plan *pl, const double *params, hipStream_t st
 
 // One forward pass of a temperature-map plan over the batch, pass by pass.
 static hipError_t run_forward_map(ppm_plan *pl, const double *params, const double *map, hipStream_t st,
-                                  double *flux, double *counts)
+                                  double *flux, double *counts, const int32_t *data = nullptr,
+                                  double *logl = nullptr)
 {
     const DevSpec &S = pl->S;
     const ListSlot &L = *pl->cur;
@@ -764,10 +775,19 @@ static hipError_t run_forward_map(ppm_plan *pl, const double *params, const doub
                                           map + (size_t)ps.inst0 * S.n_pix, ps.nb, L.d_ring + ps.ring_off,
                                           ps.n_ring, ps.n_grp, st,
                                           flux ? flux + (size_t)ps.inst0 * S.P * S.E : nullptr,
-                                          counts + (size_t)ps.inst0 * S.P * S.C, e0, e1);
+                                          counts ? counts + (size_t)ps.inst0 * S.P * S.C : nullptr, data,
+                                          logl ? logl + ps.inst0 : nullptr, e0, e1);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// Model counts the likelihood path writes: the caller's buffer, else none
+// for FP32 plans (the fold's epilogue computes logL from registers) and the
+// plan's buffer for FP64 plans (their likelihood kernel reads counts).
+static double *loglike_counts(ppm_plan *pl, double *counts_dev)
+{
+    return counts_dev ? counts_dev : (pl->S.rsp64 ? pl->W.counts : nullptr);
 }
 
 int ppm_forward_map(ppm_plan *pl, const double *params_dev, int B, const double *map_dev, double *counts_dev,
@@ -797,11 +817,9 @@ int ppm_loglike_map(ppm_plan *pl, const double *params_dev, int B, const double 
     int rc = prepare(pl, params_dev, B, nullptr, st, true);
     if (rc) return rc;
     if (!map_dev || !data_dev || !logl_dev) return fail(PPM_ERR_ARG, "null map, data or logl buffer");
-    double *cnt = counts_dev ? counts_dev : pl->W.counts;
-    hipError_t e = run_forward_map(pl, params_dev, map_dev, st, nullptr, cnt);
-    if (e != hipSuccess) return hip_fail(e, "ppm_loglike_map forward");
-    e = launch_loglike(pl->W, cnt, pl->S.bkg, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
-    return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike_map reduction");
+    hipError_t e = run_forward_map(pl, params_dev, map_dev, st, nullptr, loglike_counts(pl, counts_dev), data_dev,
+                                   logl_dev);
+    return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike_map launch");
 }
 
 int ppm_forward(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_cells_host,
@@ -831,18 +849,15 @@ int ppm_loglike(ppm_plan *pl, const double *params_dev, int B, const int32_t *n_
     int rc = prepare(pl, params_dev, B, n_cells_host, st);
     if (rc) return rc;
     if (!data_dev || !logl_dev) return fail(PPM_ERR_ARG, "null data or logl buffer");
-    double *cnt = counts_dev ? counts_dev : pl->W.counts;
-    hipError_t e = run_forward(pl, params_dev, st, nullptr, cnt);
-    if (e != hipSuccess) return hip_fail(e, "ppm_loglike forward");
-    e = launch_loglike(pl->W, cnt, pl->S.bkg, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
-    return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike reduction");
+    hipError_t e = run_forward(pl, params_dev, st, nullptr, loglike_counts(pl, counts_dev), data_dev, logl_dev);
+    return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike launch");
 }
 
 // One forward + adjoint pass over the batch: per workspace pass the forward
 // (keeping the pre-absorption flux), then the adjoint of the same instances
 // while their ring scratch is live.  Model counts go to pl->W.counts.
-static hipError_t run_grad(ppm_plan *pl, const double *params, const int32_t *data, double *grad, hipStream_t st,
-                           const char **what)
+static hipError_t run_grad(ppm_plan *pl, const double *params, const int32_t *data, double *logl, double *grad,
+                           hipStream_t st, const char **what)
 {
     const DevSpec &S = pl->S;
     const ListSlot &L = *pl->cur;
@@ -854,7 +869,8 @@ static hipError_t run_grad(ppm_plan *pl, const double *params, const int32_t *da
         const int32_t *ncc = L.override_grid ? L.d_ncells + ps.inst0 : nullptr;
         double *cc = pl->W.counts + (size_t)ps.inst0 * S.P * S.C;
         const int32_t *list = L.d_ring + ps.ring_off;
-        hipError_t e = launch_forward(S, W, pc, ncc, ps.nb, list, ps.n_ring, ps.n_grp, st, W.flux, cc, e0, e1);
+        hipError_t e = launch_forward(S, W, pc, ncc, ps.nb, list, ps.n_ring, ps.n_grp, st, W.flux, cc, data,
+                                      logl + ps.inst0, e0, e1);
         if (e != hipSuccess) {
             *what = "ppm_loglike_grad forward";
             return e;
@@ -878,10 +894,8 @@ int ppm_loglike_grad(ppm_plan *pl, const double *params_dev, int B, const int32_
     if (rc) return rc;
     if (!data_dev || !logl_dev || !grad_dev) return fail(PPM_ERR_ARG, "null data, logl or grad buffer");
     const char *what = "";
-    hipError_t e = run_grad(pl, params_dev, data_dev, grad_dev, st, &what);
-    if (e != hipSuccess) return hip_fail(e, what);
-    e = launch_loglike(pl->W, pl->W.counts, pl->S.bkg, B, pl->S.P * pl->S.C, data_dev, logl_dev, st);
-    return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_loglike_grad reduction");
+    hipError_t e = run_grad(pl, params_dev, data_dev, logl_dev, grad_dev, st, &what);
+    return e == hipSuccess ? PPM_OK : hip_fail(e, what);
 }
 
 int ppm_get_diagnostics(ppm_plan *pl, int B, ppm_diag *total, ppm_diag *per_instance, void *stream)
@@ -1121,16 +1135,17 @@ int ppm_autotune(ppm_plan *pl, const double *params_dev, int B, const int32_t *n
     }
     // adjoint tile (gradient plans)
     if (pl->grad) {
-        DevBuf data, grad;
+        DevBuf data, grad, logl;
         hipError_t e = hipMalloc(&data.p, sizeof(int32_t) * (size_t)S.P * S.C);
         if (e == hipSuccess) e = hipMalloc(&grad.p, sizeof(double) * (size_t)B * PPM_NGRAD);
+        if (e == hipSuccess) e = hipMalloc(&logl.p, sizeof(double) * (size_t)B);
         if (e == hipSuccess) e = hipMemsetAsync(data.p, 0, sizeof(int32_t) * (size_t)S.P * S.C, st);
         if (e != hipSuccess) return restore(hip_fail(e, "ppm_autotune temporary buffers"));
         int best_a = pa0;
         const std::vector<int> gc = tile_candidates({8, 16, 24, 32}, S.P);
         std::vector<double> gms;
         rc = time_candidates(gc, [&](int t) { S.pt_adj = t; }, [&](const char **what) {
-            return run_grad(pl, params_dev, (const int32_t *)data.p, (double *)grad.p, st, what);
+            return run_grad(pl, params_dev, (const int32_t *)data.p, (double *)logl.p, (double *)grad.p, st, what);
         }, reps, st, gms);
         if (rc) return restore(rc);
         for (size_t c = 0; c < gc.size(); ++c) {
@@ -1142,7 +1157,7 @@ int ppm_autotune(ppm_plan *pl, const double *params_dev, int B, const int32_t *n
             }
         }
         S.pt_adj = best_a;
-        // the temporaries are freed on return: finish the work that reads them
+        // the temporaries are freed on return: finish the work that uses them
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) return restore(hip_fail(e, "ppm_autotune sync"));
     }
@@ -1279,6 +1294,13 @@ int ppm_profile_end(ppm_plan *pl, double *hot_ms_total, int *n_calls)
     *n_calls = pl->prof_n;
     pl->prof_on = false;
     pl->prof_n = 0;
+    return PPM_OK;
+}
+
+int ppm_get_passes(const ppm_plan *pl, int *n_passes)
+{
+    if (!pl || !n_passes) return fail(PPM_ERR_ARG, "ppm_get_passes: null argument");
+    *n_passes = pl->cur ? (int)pl->cur->pass.size() : 0;
     return PPM_OK;
 }
 

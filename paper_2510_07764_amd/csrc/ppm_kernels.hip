@@ -818,7 +818,9 @@ __device__ __forceinline__ void pairs_general(uint64_t mask, const float4 *Pp, f
 // and read, added to and rewritten by the next ones (the block barrier
 // between rings orders them), so one FP32 partial per group and phase goes
 // out instead of one per ring.
-template <int EPL, int NW>
+// GRP false: groups of one ring (the ring loop compiles away, and with it
+// the registers the loop keeps live).
+template <int EPL, int NW, bool GRP>
 __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec S, const int32_t *list,
                                                     const int32_t *glist, const RingRec *rings,
                                                     const double4 *trace, const float *sub, float *partial,
@@ -827,7 +829,7 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     extern __shared__ __align__(16) unsigned char lds_raw[];
     int gi, tile;
     if (!xcd_block(n_groups, (S.P + PT - 1) / PT, gi, tile)) return;
-    const int g_first = glist[2 * gi], g_count = glist[2 * gi + 1];
+    const int g_first = glist[2 * gi], g_count = GRP ? glist[2 * gi + 1] : 1;
     const int nfp = S.n_fp, nmu = S.nmu, nx = S.nx, E = S.E, P = S.P, W = S.W_max;
     double4 *tr = (double4 *)lds_raw;                          // nfp + 1
     double *axmu = (double *)(tr + nfp + 1);                   // nmu (padded to 16 bytes)
@@ -988,8 +990,9 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
                             double fl = floor(T0);
                             I0 = (int)fl;
                             fr = (float)(T0 - fl);
-                            // energies beyond the table's x range contribute nothing (counted)
-                            if (I0 < 0 || (float)I0 + fr + tbl[E - 1] >= (float)(nx - 2))
+                            // energies beyond the table's x range contribute nothing
+                            // (counted; none on a ring whose window is interior)
+                            if (!g.interior && (I0 < 0 || (float)I0 + fr + tbl[E - 1] >= (float)(nx - 2)))
                                 nxout += x_outside_count(I0, fr, tbl, E, nx);
                         }
                     }
@@ -1005,7 +1008,7 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
                     pairs_general<EPL>(mask, Pw, fr, I0, m0, lane, tab, NMP, xw0, xw, nx, Sw, Qw, tbr, acc);
             }
             float *out = partial + ((size_t)gi * P + k) * E;
-            if (first) {
+            if (!GRP || first) {
 #pragma unroll
                 for (int m = 0; m < EPL; ++m) {
                     int e = lane + 64 * m;
@@ -1279,6 +1282,128 @@ __global__ __launch_bounds__(256) void k_fold_f32(const float *A, const float *B
     }
 }
 
+// k_fold_ll: the fold of k_fold_f32 (same tiles, same K split, the same
+// result bits) followed by the Poisson log-likelihood terms of the tile's
+// bins (FP64; d = 0 contributes -m, m <= 0 with d > 0 is flagged): wave w
+// takes the tile's rows 4 j + w, and per output row (instance b, phase k)
+// the tile's 16 channels are summed in a fixed lane butterfly into
+// part[row][column tile].  k_ll_sum then adds an instance's P x n_ct
+// partials in a fixed order that depends only on P and C, so an instance
+// gives the same logL alone and in a batch.  out (model counts) may be NULL.
+__device__ inline double log_dfact(int d, const double *lfact)
+{
+    return (unsigned)d < (unsigned)kLogFact ? lfact[d] : lgamma(d + 1.0);   // log d!, tabulated below kLogFact
+}
+
+__global__ __launch_bounds__(256) void k_fold_ll(const float *A, const float *Bm, double *out, int M, int N, int K,
+                                                 int P, const double *bkg, const int32_t *data,
+                                                 const double *lfact, double *part, int32_t *bad)
+{
+    __shared__ floatx4 tile[4][64];
+    const int n0 = blockIdx.x * 16, m0 = blockIdx.y * 16;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+    const int kq = ((K + 15) / 16) * 4;
+    const int kb = wave * kq, ke = min(K, kb + kq);
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    const bool mrow = (m0 + li) < M, ncol = (n0 + li) < N;
+    constexpr int kSteps = 16;
+    for (int kc = kb; kc < ke; kc += 4 * kSteps) {
+        float av[kSteps], bv[kSteps];
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) {
+            const int k = kc + 4 * s + lk;
+            const bool oka = mrow && k < ke, okb = ncol && k < ke;
+            const float va = A[oka ? (size_t)(m0 + li) * K + k : 0];
+            const float vb = Bm[okb ? (size_t)k * N + n0 + li : 0];
+            av[s] = oka ? va : 0.0f;
+            bv[s] = okb ? vb : 0.0f;
+        }
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s)
+            if (kc + 4 * s < ke) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc, 0, 0, 0);
+    }
+    tile[wave][l] = acc;
+    __syncthreads();
+    // wave w: accumulator element w of the four partial tiles, summed in
+    // wave order as in k_fold_f32
+    const float *t0 = (const float *)&tile[0][l], *t1 = (const float *)&tile[1][l],
+                *t2 = (const float *)&tile[2][l], *t3 = (const float *)&tile[3][l];
+    float t = t0[wave];
+    t += t1[wave];
+    t += t2[wave];
+    t += t3[wave];
+    const int col = n0 + li, row = m0 + 4 * lk + wave, n_ct = gridDim.x;
+    double term = 0.0;
+    int nbad = 0;
+    if (row < M && col < N) {
+        const double mv = (double)t;
+        if (out) out[(size_t)row * N + col] = mv;
+        const int k = row % P;
+        const int d = data[(size_t)k * N + col];
+        const double mi = bkg ? mv + bkg[(size_t)k * N + col] : mv;   // model plus background counts
+        if (d == 0) term = -mi;
+        else if (!(mi > 0.0)) nbad = 1;
+        else term = d * log(mi) - mi - log_dfact(d, lfact);
+    }
+    // the row's 16 channels: lanes 16 lk .. 16 lk + 15
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+        term += __shfl_xor(term, o, 64);
+        nbad += __shfl_xor(nbad, o, 64);
+    }
+    if (li == 0 && row < M) {
+        part[(size_t)row * n_ct + blockIdx.x] = term;
+        bad[(size_t)row * n_ct + blockIdx.x] = nbad;
+    }
+}
+
+// k_ll_sum: block b adds instance b's n = P x n_ct likelihood partials:
+// thread t the entries t, t + 256, ... in order, then the 256 sums in a
+// fixed tree; -inf where a bin had m <= 0 with d > 0 or the instance is not
+// evaluable.
+__global__ __launch_bounds__(256) void k_ll_sum(int n, const StarRec *stars, const double *part,
+                                                const int32_t *bad, double *logl)
+{
+    __shared__ double red[256];
+    __shared__ int redb[256];
+    const int b = blockIdx.x;
+    const double *pp = part + (size_t)b * n;
+    const int32_t *pb = bad + (size_t)b * n;
+    double sv = 0.0;
+    int sb = 0;
+    constexpr int kU = 8;   // loads in flight per thread
+    for (int i0 = threadIdx.x; i0 < n; i0 += 256 * kU) {
+        double v[kU];
+        int f[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = i0 + 256 * u;
+            v[u] = i < n ? pp[i] : 0.0;
+            f[u] = i < n ? pb[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            sv += v[u];
+            sb += f[u];
+        }
+    }
+    red[threadIdx.x] = sv;
+    redb[threadIdx.x] = sb;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[threadIdx.x] += red[threadIdx.x + w];
+            redb[threadIdx.x] += redb[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double s = red[0];
+        if (redb[0] || stars[b].status != PPM_INST_OK) s = -INFINITY;
+        logl[b] = s;
+    }
+}
+
 // FP64 path (small workloads): one thread per output element, plain FMA loop.
 __global__ __launch_bounds__(256) void k_fold_f64(const double *A, const double *B, double *out, int M,
                                                   int N, int K)
@@ -1370,6 +1495,12 @@ __global__ void k_status(const StarRec *stars, int B, int32_t *out)
 // ---------------------------------------------------------------------------
 int loglike_blocks(int PC) { return (PC + kLLChunk - 1) / kLLChunk; }
 
+int loglike_parts(int P, int C)
+{
+    const int fused = P * ((C + 15) / 16), blocks = loglike_blocks(P * C);
+    return fused > blocks ? fused : blocks;
+}
+
 size_t accum_table_lds(const DevSpec &S)
 {
     if (S.fast)
@@ -1399,9 +1530,10 @@ void launch_table_trace(const DevSpec &S, const Workspace &W, const int32_t *lis
                        W.trace, W.sub, W.diag);
 }
 
-// FP32 ring-group partials -> per-instance FP64 sum, absorption, MFMA fold
+// FP32 ring-group partials -> per-instance FP64 sum, absorption, MFMA fold,
+// and with data the likelihood in the fold's epilogue
 void launch_reduce_fold32(const DevSpec &S, const Workspace &W, const int32_t *list, int B, hipStream_t st,
-                          double *flux_out, double *counts_out)
+                          double *flux_out, double *counts_out, const int32_t *data, double *logl)
 {
     if ((S.E & 3) == 0)
         hipLaunchKernelGGL(k_reduce4, dim3(S.P, (S.E + 127) / 128, B), dim3(32 * kReduceGroups), S.R_tot, st, S,
@@ -1409,8 +1541,21 @@ void launch_reduce_fold32(const DevSpec &S, const Workspace &W, const int32_t *l
     else
         hipLaunchKernelGGL((k_reduce<float, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S,
                            W.stars, W.rings, list, W.glist, W.grange, W.partial32, flux_out, W.fold_in32);
-    hipLaunchKernelGGL(k_fold_f32, dim3((S.C + 15) / 16, (B * S.P + 15) / 16), dim3(256), 0, st,
-                       W.fold_in32, S.rsp32, counts_out, B * S.P, S.C, S.E);
+    launch_fold32(S, W, B, st, counts_out, data, logl);
+}
+
+void launch_fold32(const DevSpec &S, const Workspace &W, int B, hipStream_t st, double *counts_out,
+                   const int32_t *data, double *logl)
+{
+    const dim3 grid((S.C + 15) / 16, (B * S.P + 15) / 16);
+    if (data) {
+        hipLaunchKernelGGL(k_fold_ll, grid, dim3(256), 0, st, W.fold_in32, S.rsp32, counts_out, B * S.P, S.C, S.E,
+                           S.P, S.bkg, data, W.lfact, W.ll_part, W.ll_bad);
+        hipLaunchKernelGGL(k_ll_sum, dim3(B), dim3(256), 0, st, S.P * (int)grid.x, W.stars, W.ll_part, W.ll_bad,
+                           logl);
+    } else {
+        hipLaunchKernelGGL(k_fold_f32, grid, dim3(256), 0, st, W.fold_in32, S.rsp32, counts_out, B * S.P, S.C, S.E);
+    }
 }
 
 // The windowed kernel runs over the ring groups of the pass (W.glist), the
@@ -1418,8 +1563,8 @@ void launch_reduce_fold32(const DevSpec &S, const Workspace &W, const int32_t *l
 // group list is then the identity, n_groups == n_list).
 hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *params,
                           const int32_t *ncells_dev, int B, const int32_t *list, int n_list, int n_groups,
-                          hipStream_t st, double *flux_out, double *counts_out, hipEvent_t ev_hot0,
-                          hipEvent_t ev_hot1)
+                          hipStream_t st, double *flux_out, double *counts_out, const int32_t *data, double *logl,
+                          hipEvent_t ev_hot0, hipEvent_t ev_hot1)
 {
     const bool want_flux_f64 = flux_out != nullptr;
     launch_setup(S, W, params, ncells_dev, B, st);
@@ -1438,13 +1583,19 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
                 float *pt = W.partial32 + (size_t)off * PE;
                 const int n = n_groups - off < step ? n_groups - off : step;
                 dim3 grid(xcd_grid(n, n_tile));
-#define PPM_FAST(E_)                                                                                              \
-    hipLaunchKernelGGL((k_accum_fast<E_, kFwdWaves>), grid, dim3(64 * kFwdWaves), lds, st, S, list, gl, W.rings,  \
-                       W.trace, W.sub, pt, W.vis_pairs, W.diag, PT, n)
-                if (epl <= 1) PPM_FAST(1);
-                else if (epl <= 2) PPM_FAST(2);
-                else if (epl <= 4) PPM_FAST(4);
-                else PPM_FAST(8);
+#define PPM_FAST(E_, G_)                                                                                          \
+    hipLaunchKernelGGL((k_accum_fast<E_, kFwdWaves, G_>), grid, dim3(64 * kFwdWaves), lds, st, S, list, gl,       \
+                       W.rings, W.trace, W.sub, pt, W.vis_pairs, W.diag, PT, n)
+#define PPM_FAST_E(G_)                     \
+    do {                                   \
+        if (epl <= 1) PPM_FAST(1, G_);     \
+        else if (epl <= 2) PPM_FAST(2, G_); \
+        else if (epl <= 4) PPM_FAST(4, G_); \
+        else PPM_FAST(8, G_);              \
+    } while (0)
+                if (S.ring_group > 1) PPM_FAST_E(true);
+                else PPM_FAST_E(false);
+#undef PPM_FAST_E
 #undef PPM_FAST
             }
         } else {
@@ -1465,7 +1616,7 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
             }
         }
         if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
-        launch_reduce_fold32(S, W, list, B, st, want_flux_f64 ? flux_out : nullptr, counts_out);
+        launch_reduce_fold32(S, W, list, B, st, want_flux_f64 ? flux_out : nullptr, counts_out, data, logl);
     } else {
         size_t lds = sizeof(double4) * (S.n_fp + 1);
         int epl = (S.E + 63) / 64;
@@ -1491,22 +1642,17 @@ hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *pa
                                W.stars, W.rings, list, W.glist, W.grange, W.partial64, fx, W.fold_in64);
             hipLaunchKernelGGL(k_fold_f64, dim3((S.C + 255) / 256, B * S.P), dim3(256), 0, st,
                                W.fold_in64, S.rsp64, counts_out, B * S.P, S.C, S.E);
+            if (data) {
+                const int nblk = loglike_blocks(S.P * S.C);
+                hipLaunchKernelGGL(k_loglike, dim3(nblk, B), dim3(256), 0, st, W.stars, counts_out, S.bkg, data,
+                                   W.lfact, S.P * S.C, W.ll_part, W.ll_bad, W.ll_done, logl);
+            }
         } else {
             hipLaunchKernelGGL((k_reduce<double, float>), dim3(S.P, (S.E + 63) / 64, B), dim3(256), S.R_tot, st, S,
                                W.stars, W.rings, list, W.glist, W.grange, W.partial64, fx, W.fold_in32);
-            hipLaunchKernelGGL(k_fold_f32, dim3((S.C + 15) / 16, (B * S.P + 15) / 16), dim3(256), 0, st,
-                               W.fold_in32, S.rsp32, counts_out, B * S.P, S.C, S.E);
+            launch_fold32(S, W, B, st, counts_out, data, logl);
         }
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_loglike(const Workspace &W, const double *counts, const double *bkg, int B, int PC,
-                          const int32_t *data, double *logl, hipStream_t st)
-{
-    const int nblk = (PC + kLLChunk - 1) / kLLChunk;
-    hipLaunchKernelGGL(k_loglike, dim3(nblk, B), dim3(256), 0, st, W.stars, counts, bkg, data, W.lfact, PC, W.ll_part,
-                       W.ll_bad, W.ll_done, logl);
     return hipGetLastError();
 }
 

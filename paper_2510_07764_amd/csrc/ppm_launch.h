@@ -26,8 +26,8 @@ struct Workspace {
                            // visible pairs of map patches whose logT was clamped
     const int32_t *glist;  // [n_groups][2] ring groups of the pass: first work-list position, ring count
     const int32_t *grange; // [B][2] per instance of the pass: its groups [first, end) in glist
-    double *ll_part;       // [B][loglike_blocks] first-stage likelihood sums
-    int32_t *ll_bad;       // [B][loglike_blocks] bins with m <= 0 and d > 0
+    double *ll_part;       // [B][loglike_parts] first-stage likelihood sums
+    int32_t *ll_bad;       // [B][loglike_parts] bins with m <= 0 and d > 0
     double *lfact;         // [kLogFact] log d! for the first kLogFact counts
     unsigned *ll_done;     // [B] blocks of the likelihood kernel done per instance (zero between calls)
     // gradient plans only
@@ -62,22 +62,27 @@ __host__ __device__ int validate_params(const double *p, int n_spots);
 // One workspace pass: B instances, their live rings (list, n_list entries,
 // chunk-local instance index * R_tot + ring slot) and the ring groups of the
 // accumulation (W.glist, n_groups entries; W.grange per instance).
+// counts_out may be NULL when data is given (then only logL is kept); with
+// data (int32 [P][C]) the pass's logL goes to logl[B] (Workspace::stars,
+// ll_part, ll_bad, ll_done of the pass).
 hipError_t launch_forward(const DevSpec &S, const Workspace &W, const double *params,
                           const int32_t *ncells_dev, int B, const int32_t *list, int n_list, int n_groups,
-                          hipStream_t st, double *flux_out, double *counts_out, hipEvent_t ev_hot0 = nullptr,
-                          hipEvent_t ev_hot1 = nullptr);
+                          hipStream_t st, double *flux_out, double *counts_out, const int32_t *data = nullptr,
+                          double *logl = nullptr, hipEvent_t ev_hot0 = nullptr, hipEvent_t ev_hot1 = nullptr);
 void launch_setup(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev, int B,
                   hipStream_t st);
 void launch_table_trace(const DevSpec &S, const Workspace &W, const int32_t *list, int n_list, hipStream_t st);
 void launch_reduce_fold32(const DevSpec &S, const Workspace &W, const int32_t *list, int B, hipStream_t st,
-                          double *flux_out, double *counts_out);
+                          double *flux_out, double *counts_out, const int32_t *data = nullptr,
+                          double *logl = nullptr);
+void launch_fold32(const DevSpec &S, const Workspace &W, int B, hipStream_t st, double *counts_out,
+                   const int32_t *data, double *logl);
 hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double *params, const double *map, int B,
                               const int32_t *list, int n_list, int n_groups, hipStream_t st, double *flux_out,
-                              double *counts_out, hipEvent_t ev_hot0 = nullptr, hipEvent_t ev_hot1 = nullptr);
+                              double *counts_out, const int32_t *data = nullptr, double *logl = nullptr,
+                              hipEvent_t ev_hot0 = nullptr, hipEvent_t ev_hot1 = nullptr);
 size_t accum_map_lds(const DevSpec &S);
 constexpr int kMapWaves = 8;     // waves per block of the map accumulation kernel, one phase each
-hipError_t launch_loglike(const Workspace &W, const double *counts, const double *bkg, int B, int PC,
-                          const int32_t *data, double *logl, hipStream_t st);
 hipError_t launch_status(const Workspace &W, int B, int32_t *out, hipStream_t st);
 hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev,
                        int B, const int32_t *list, int n_list, const double *counts, const int32_t *data,
@@ -85,6 +90,7 @@ hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *param
 size_t accum_table_lds(const DevSpec &S);
 size_t accum_adj_lds(const DevSpec &S);
 int loglike_blocks(int PC);
+int loglike_parts(int P, int C);   // per-instance likelihood partials (fused fold or block sums)
 // read access to a plan's model, workspace, batch limit and device (host)
 bool plan_view(const ppm_plan *pl, const DevSpec **S, const Workspace **W, int *max_batch, int *device);
 int api_fail(int code, const char *msg);           // sets ppm_last_error, returns code

@@ -389,7 +389,8 @@ size_t accum_map_lds(const DevSpec &S)
 
 hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double *params, const double *map, int B,
                               const int32_t *list, int n_list, int n_groups, hipStream_t st, double *flux_out,
-                              double *counts_out, hipEvent_t ev_hot0, hipEvent_t ev_hot1)
+                              double *counts_out, const int32_t *data, double *logl, hipEvent_t ev_hot0,
+                              hipEvent_t ev_hot1)
 {
     (void)n_groups;   // groups of one ring: the group list is the identity
     launch_setup(S, W, params, nullptr, B, st);
@@ -427,7 +428,7 @@ hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double
 #undef PPM_MAP_KPW
 #undef PPM_MAP_LAUNCH
     if (ev_hot1) (void)hipEventRecord(ev_hot1, st);
-    launch_reduce_fold32(S, W, list, B, st, flux_out, counts_out);
+    launch_reduce_fold32(S, W, list, B, st, flux_out, counts_out, data, logl);
     return hipGetLastError();
 }
 

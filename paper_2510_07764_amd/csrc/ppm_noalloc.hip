@@ -111,7 +111,7 @@ size_t carve(const DevSpec &S, int B, int n_live, int n_grp, bool want_counts, u
     W.vis_pairs = c.take<int32_t>(Bz * R);
     W.diag = c.take<int32_t>(Bz * R * kDiagFields);
     W.counts = want_counts ? c.take<double>(Bz * S.P * S.C) : nullptr;
-    const int nblk = loglike_blocks(S.P * S.C);
+    const int nblk = loglike_parts(S.P, S.C);
     W.ll_part = c.take<double>(Bz * nblk);
     W.ll_bad = c.take<int32_t>(Bz * nblk);
     W.ll_done = c.take<unsigned>(Bz);
@@ -175,8 +175,7 @@ extern "C" int ppm_loglike_noalloc(ppm_plan *plan, const double *params_dev, int
     const int nt = B * (n_live > n_grp ? n_live : n_grp);
     hipLaunchKernelGGL(k_default_lists, dim3((nt + 255) / 256), dim3(256), 0, st, S, B, G, n_live, n_grp, list,
                        const_cast<int32_t *>(W.glist), const_cast<int32_t *>(W.grange), W.ll_done);
-    e = launch_forward(S, W, params_dev, nullptr, B, list, B * n_live, B * n_grp, st, nullptr, cnt);
-    if (e != hipSuccess) return api_hip_fail(e, "ppm_loglike_noalloc forward");
-    e = launch_loglike(W, cnt, S.bkg, B, S.P * S.C, data_dev, logl_dev, st);
-    return e == hipSuccess ? PPM_OK : api_hip_fail(e, "ppm_loglike_noalloc reduction");
+    e = launch_forward(S, W, params_dev, nullptr, B, list, B * n_live, B * n_grp, st, nullptr, cnt, data_dev,
+                       logl_dev);
+    return e == hipSuccess ? PPM_OK : api_hip_fail(e, "ppm_loglike_noalloc launch");
 }
