@@ -374,14 +374,15 @@ __global__ __launch_bounds__(256) void k_subtable_tg(DevSpec S, const int32_t *l
 //           their mu derivatives (cubic Lagrange; linear in the protected
 //           zone and the last interval; zero derivative where mu is clamped),
 //           x position of the first energy; wave ballot of visible pairs;
-//  stage B  per visible pair: lane = x node, mu contraction of the sub-table
-//           and of its logT / log g derivatives; lane = x interval (the
-//           next three nodes' values by DPP wave shifts), cubic coefficients
-//           of V, dV/dmu, dV/dlogT, dV/dlog g into LDS quads;
-//           lane = EPL energies: Horner steps and the sums over e of G~ V,
-//           G~ dV/dt, G~ dV/dmu (wave totals kept by the pair's lane) and
-//           F_p G~ dV/dlogT, F_p G~ dV/dlog g (lane-local FP64 sums), with
-//           G~ = G[k][e]/E_e;
+//  stage B  per visible pair: lane = x interval, the moments sum_e G~ f^k
+//           (k = 0..3) of the energies in it from per-bucket prefix sums
+//           (built once per phase), turned into weights of the interval's
+//           interpolation nodes and gathered per node by DPP wave shifts;
+//           lane = x node, mu contraction of the sub-table and of its
+//           logT / log g derivatives, times the node weights: the sums
+//           over e of G~ V, G~ dV/dt, G~ dV/dmu (wave totals kept by the
+//           pair's lane) and F_p G~ dV/dlogT, F_p G~ dV/dlog g (lane-local
+//           FP64 sums), with G~ = G[k][e]/E_e;
 //  stage C  lane = pair, FP64: chain rule through the phase interpolation
 //           into the five geometric directions and the phase direction,
 //           plus the ring-level sums for the cell weight, log g and logT.
@@ -422,15 +423,6 @@ __device__ inline double wave_sum_d(double v)
     return v;
 }
 
-__device__ inline float4 cubic_quad(float s0, float s1, float s2, float s3)
-{
-    const float c2 = 0.5f * (s0 + s2) - s1;
-    const float c3 = (s3 - s0) * (1.0f / 6.0f) + 0.5f * (s1 - s2);
-    return make_float4(s1, s2 - s1 - c2 - c3, c2, c3);
-}
-
-__device__ inline float horner(const float4 q, float f) { return q.x + f * (q.y + f * (q.z + f * q.w)); }
-
 // d(cell azimuth)/d(outer half-width) and d/d(inner half-width) of cell j
 __device__ inline void offset_coeffs(const RingRec &g, int j, double &ca, double &cb)
 {
@@ -451,19 +443,65 @@ __device__ inline void offset_coeffs(const RingRec &g, int j, double &ca, double
     }
 }
 
+// binary-search steps within an energy bucket the kernel unrolls (the plan
+// refuses energy grids whose buckets need more)
+constexpr int kMaxBucketSteps = 4;
+
+// value of lane - 1 (0 in lane 0): DPP whole-wave shift
+__device__ inline float wave_prev(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+
+// Node weights of interval lane's cubic (or linear, or zero) interpolant for
+// its energy moments M: sum_e G_e V(f_e) = sum_j beta_j S_{lane + j} over the
+// interval's four nodes S (V = q.x + q.y f + q.z f^2 + q.w f^3 with q from
+// cubic_quad), and the same for dV/df (moments (0, M0, 2 M1, 3 M2)); each
+// node then gathers the weights of the four intervals that use it (lanes
+// n, n - 1, n - 2, n - 3), so that the sums over e become one product per
+// node lane.
+__device__ inline void node_weights(int kind, float M0, float M1, float M2, float M3, float &B, float &Bx)
+{
+    float b0, b1, b2, b3, d0, d1, d2, d3;
+    if (kind == 0) {                               // cubic on nodes -1, 0, 1, 2
+        b0 = -M1 * (1.0f / 3.0f) + 0.5f * M2 - M3 * (1.0f / 6.0f);
+        b1 = M0 - 0.5f * M1 - M2 + 0.5f * M3;
+        b2 = M1 + 0.5f * M2 - 0.5f * M3;
+        b3 = (M3 - M1) * (1.0f / 6.0f);
+        d0 = -M0 * (1.0f / 3.0f) + M1 - 0.5f * M2;
+        d1 = -0.5f * M0 - 2.0f * M1 + 1.5f * M2;
+        d2 = M0 + M1 - 1.5f * M2;
+        d3 = 0.5f * M2 - M0 * (1.0f / 6.0f);
+    } else if (kind == 1) {                        // linear between nodes 0 and 1
+        b0 = 0.0f; b1 = M0 - M1; b2 = M1; b3 = 0.0f;
+        d0 = 0.0f; d1 = -M0; d2 = M0; d3 = 0.0f;
+    } else {                                       // outside the table: no contribution
+        b0 = b1 = b2 = b3 = d0 = d1 = d2 = d3 = 0.0f;
+    }
+    B = b0 + wave_prev(b1 + wave_prev(b2 + wave_prev(b3)));
+    Bx = d0 + wave_prev(d1 + wave_prev(d2 + wave_prev(d3)));
+}
+
 // Stage B of k_accum_adj for the visible pairs (mask) of one 64-cell group;
-// the pair's lane keeps its three energy sums in R0, R1, R2.  The wave totals
-// of a pair are taken while the next pair's table rows load (their latency is
-// the loop's longest chain), the last pair's after the loop.  INTERIOR: the
-// ring's x window stays one interval clear of the table's first and last
-// intervals (every interval an energy can use is cubic and every stencil
-// column lies in the window; columns past it hold zeros), so the bounds tests
-// drop out.
-template <int EPL, bool INTERIOR>
-__device__ __forceinline__ void adj_pairs(uint64_t mask, const float4 *Pp, const float (&vv)[4], float fr, float Fpf, int I0, int m0,
-                                          int lane, int bp32, const float *tab, const float2 *tab2, int W, int xw0,
-                                          int xw, int nx, float4 *Qw, const float (&tbr)[EPL],
-                                          const float (&Gr)[EPL], float &R0, float &R1, float &R2, double &accT,
+// the pair's lane keeps its three energy sums in R0, R1, R2.
+// Energy sums by moments: lane l stands for x interval I0 + l of the pair,
+// which holds the energies with l <= fr + tbe < l + 1, i.e. the tail of
+// bucket l - 1 (tau >= 1 - fr, f = fr - 1 + tau) and the head of bucket l
+// (tau < 1 - fr, f = fr + tau).  From the per-bucket inclusive prefix sums
+// Lw[e] of G (1, tau, tau^2, tau^3) (the wave's phase) the interval's
+// moments sum_e G f^k, k = 0..3, follow by the binomial expansion in the
+// shift fr or fr - 1; every sum over e of G V, G dV/df, G dV/dmu, G dV/dlogT
+// and G dV/dlog g is then a product of the node values with the interval
+// weights of node_weights, summed over the wave.  The wave totals of a pair
+// are taken while the next pair's table rows load.  INTERIOR: the ring's x
+// window stays one interval clear of the table's first and last intervals
+// (every interval an energy can use is cubic and every stencil column lies
+// in the window; columns past it hold zeros), so the bounds tests drop out.
+template <bool INTERIOR>
+__device__ __forceinline__ void adj_pairs(uint64_t mask, const float4 *Pp, const float (&vv)[4], float fr, float Fpf,
+                                          int I0, int m0, int lane, int bp32, const float *tab, const float2 *tab2,
+                                          int W, int xw0, int xw, int nx, const float4 *Lw, const float *etau,
+                                          int est, int een, int e_it, float &R0, float &R1, float &R2, double &accT,
                                           double &accG)
 {
     float ps0 = 0.f, psx = 0.f, psm = 0.f;   // lane sums of the previous pair
@@ -498,58 +536,49 @@ __device__ __forceinline__ void adj_pairs(uint64_t mask, const float4 *Pp, const
             R1 = mine ? t1 : R1;
             R2 = mine ? t2 : R2;
         }
-        float4 nv;
-        nv.x = pw0 * a0 + pw1 * a1 + pw2 * a2 + pw3 * a3;
-        nv.y = pv0 * a0 + pv1 * a1 + pv2 * a2 + pv3 * a3;
-        nv.z = pw0 * b0.x + pw1 * b1.x + pw2 * b2.x + pw3 * b3.x;
-        nv.w = pw0 * b0.y + pw1 * b1.y + pw2 * b2.y + pw3 * b3.y;
-        {
-            // node values at lanes + 1, + 2, + 3 (zeros past lane 63)
-            float4 n1, n2, n3;
-            n1.x = wave_next(nv.x); n1.y = wave_next(nv.y); n1.z = wave_next(nv.z); n1.w = wave_next(nv.w);
-            n2.x = wave_next(n1.x); n2.y = wave_next(n1.y); n2.z = wave_next(n1.z); n2.w = wave_next(n1.w);
-            n3.x = wave_next(n2.x); n3.y = wave_next(n2.y); n3.z = wave_next(n2.z); n3.w = wave_next(n2.w);
-            float4 q0, q1, q2, q3;
-            const int gi = pI0 + lane;
-            if (INTERIOR || (gi >= 1 && gi <= nx - 3)) {
-                q0 = cubic_quad(nv.x, n1.x, n2.x, n3.x);
-                q1 = cubic_quad(nv.y, n1.y, n2.y, n3.y);
-                q2 = cubic_quad(nv.z, n1.z, n2.z, n3.z);
-                q3 = cubic_quad(nv.w, n1.w, n2.w, n3.w);
-            } else if (gi == 0 || gi == nx - 2) {
-                q0 = make_float4(n1.x, n2.x - n1.x, 0.f, 0.f);
-                q1 = make_float4(n1.y, n2.y - n1.y, 0.f, 0.f);
-                q2 = make_float4(n1.z, n2.z - n1.z, 0.f, 0.f);
-                q3 = make_float4(n1.w, n2.w - n1.w, 0.f, 0.f);
-            } else {
-                q0 = q1 = q2 = q3 = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-            Qw[lane] = q0;
-            Qw[64 + lane] = q1;
-            Qw[128 + lane] = q2;
-            Qw[192 + lane] = q3;
-        }
-        wave_sync();
-        float s0 = 0.f, sx = 0.f, sm = 0.f, sT = 0.f, sg = 0.f;
+        // split of bucket `lane`: its first energy with tau + fr >= 1
+        // (branch-free lower bound; etau[E] closes the array)
+        int sp = est, n = een - est;
 #pragma unroll
-        for (int m = 0; m < EPL; ++m) {
-            const float t = pfr + tbr[m];
-            const float f = __builtin_amdgcn_fractf(t);
-            const int ix = (int)t;
-            const float4 qa = Qw[ix], qm = Qw[64 + ix], qt = Qw[128 + ix], qg = Qw[192 + ix];
-            const float G = Gr[m];
-            s0 += G * horner(qa, f);
-            sx += G * (qa.y + f * (2.0f * qa.z + 3.0f * f * qa.w));
-            sm += G * horner(qm, f);
-            sT += G * horner(qt, f);
-            sg += G * horner(qg, f);
+        for (int it = 0; it < kMaxBucketSteps; ++it) {
+            if (it < e_it) {
+                const int half = n >> 1;
+                const float tv = etau[sp + half];
+                const bool right = (n > 0) & (tv + pfr < 1.0f);
+                sp = right ? sp + half + 1 : sp;
+                n = right ? n - half - 1 : half;
+            }
         }
-        wave_sync();
-        accT += (double)(pF * sT);
-        accG += (double)(pF * sg);
-        ps0 = s0;
-        psx = sx;
-        psm = sm;
+        const bool has_hd = sp > est, has_b = een > est;
+        float4 hd = Lw[has_hd ? sp - 1 : 0];               // head of the bucket: this interval
+        float4 tb = Lw[has_b ? een - 1 : 0];               // whole bucket
+        if (!has_hd) hd = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (!has_b) tb = make_float4(0.f, 0.f, 0.f, 0.f);
+        // tail of bucket lane - 1: this interval's first energies
+        const float t0 = wave_prev(tb.x - hd.x), t1 = wave_prev(tb.y - hd.y), t2 = wave_prev(tb.z - hd.z),
+                    t3 = wave_prev(tb.w - hd.w);
+        const float c = pfr, d = pfr - 1.0f;
+        const float M0 = hd.x + t0;
+        const float M1 = (hd.y + c * hd.x) + (t1 + d * t0);
+        const float M2 = (hd.z + c * (2.0f * hd.y + c * hd.x)) + (t2 + d * (2.0f * t1 + d * t0));
+        const float M3 = (hd.w + c * (3.0f * hd.z + c * (3.0f * hd.y + c * hd.x)))
+                       + (t3 + d * (3.0f * t2 + d * (3.0f * t1 + d * t0)));
+        int kind = 0;
+        if (!INTERIOR) {
+            const int gi = pI0 + lane;
+            kind = (gi >= 1 && gi <= nx - 3) ? 0 : ((gi == 0 || gi == nx - 2) ? 1 : 2);
+        }
+        float Bn, Bx;
+        node_weights(kind, M0, M1, M2, M3, Bn, Bx);
+        const float va = pw0 * a0 + pw1 * a1 + pw2 * a2 + pw3 * a3;
+        const float vm = pv0 * a0 + pv1 * a1 + pv2 * a2 + pv3 * a3;
+        const float vT = pw0 * b0.x + pw1 * b1.x + pw2 * b2.x + pw3 * b3.x;
+        const float vg = pw0 * b0.y + pw1 * b1.y + pw2 * b2.y + pw3 * b3.y;
+        accT += (double)(pF * (vT * Bn));
+        accG += (double)(pF * (vg * Bn));
+        ps0 = va * Bn;
+        psx = va * Bx;
+        psm = vm * Bn;
         pp = p;
     }
     if (pp >= 0) {
@@ -563,7 +592,6 @@ __device__ __forceinline__ void adj_pairs(uint64_t mask, const float4 *Pp, const
 
 constexpr int kAdjWaves = 8;   // waves per block of k_accum_adj
 
-template <int EPL>
 __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, const int32_t *list, const RingRec *rings,
                                                    const RingTan *ringtan, const double4 *trace,
                                                    const double4 *tangent, const float *sub, const float2 *subtg,
@@ -582,13 +610,14 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
     double4 *tr = (double4 *)lds_raw;                          // nfp + 1
     double *axmu = (double *)(tr + nfp + 1);                   // nmu (padded to 16 bytes)
     float *tab = (float *)(axmu + ((nmu + 1) & ~1));           // sub_stride
-    float4 *Qb = (float4 *)(tab + S.sub_stride);               // kAdjWaves * 4 * 64 quads
-    float4 *Pb = Qb + kAdjWaves * 4 * 64;                      // kAdjWaves * 64 pair mu weights
+    float4 *Lb = (float4 *)(tab + S.sub_stride);               // kAdjWaves * E bucket prefix sums
+    float4 *Pb = Lb + kAdjWaves * S.E;                         // kAdjWaves * 64 pair mu weights
     double *po = (double *)(Pb + kAdjWaves * 64);              // nfp + 1 phi_o, compact for the search
     double *ipo = po + nfp + 1;                                // nfp: 1 / (phi_o[i+1] - phi_o[i])
     double *mcf = ipo + nfp + 1;                               // nmu * 4 mu-interval coefficients
     int16_t *pbk = (int16_t *)(mcf + 4 * nmu);                 // 2 nfp phase buckets
     int16_t *mbk = pbk + 2 * nfp;                              // mu_nb mu buckets
+    float *etau = (float *)(mbk + ((S.mu_nb + 1) & ~1));       // E + 1 bucket offsets of the energies
     const int n_pb = 2 * nfp;
     const double4 *tg = tangent + slot * (size_t)(nfp + 1) * 5;   // read through the caches in stage C
     const float2 *tab2 = subtg + slot * (size_t)S.sub_stride;      // logT / log g planes, read through L2
@@ -603,6 +632,7 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
         for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
         for (int i = threadIdx.x; i < 4 * nmu; i += blockDim.x) mcf[i] = S.mu_coef[i];
         for (int i = threadIdx.x; i < S.mu_nb; i += blockDim.x) mbk[i] = S.mu_bucket[i];
+        for (int i = threadIdx.x; i <= E; i += blockDim.x) etau[i] = S.etau[i];
         const float4 *gs = (const float4 *)(sub + slot * (size_t)S.sub_stride);
         float4 *ts = (float4 *)tab;
         for (int i = threadIdx.x; i < S.sub_stride / 4; i += blockDim.x) ts[i] = gs[i];
@@ -622,19 +652,14 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float4 *Qw = Qb + wave * 4 * 64;
+    float4 *Lw = Lb + wave * E;
     float4 *Pw = Pb + wave * 64;
     const int bp32 = (lane ^ 32) << 2;                     // byte address of the xor-32 partner
     const RingTan rt = ringtan[slot];
     const double phio0 = trace[slot * (nfp + 1)].z;        // phi_o of sample 0
     const double inv2pi = 1.0 / kTwoPi;
     const double ihx = S.ihx;
-    float tbr[EPL];
-#pragma unroll
-    for (int m = 0; m < EPL; ++m) {
-        int e = lane + 64 * m;     // energies 64 apart: neighbouring lanes read neighbouring quads
-        tbr[m] = e < E ? S.tbe[e] : 0.0f;
-    }
+    const int est = S.ebkt[lane], een = S.ebkt[lane + 1], e_it = S.e_it;   // lane's energy bucket
     const double mu_lo = S.mu_lo, mu_hi = S.mu_hi;
     const int xw0 = g.xw0, xw = g.xw;
     double U[kGradAcc];
@@ -645,11 +670,24 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
     for (int kk = wave; kk < PT; kk += kAdjWaves) {
         const int k = k_begin + kk;
         if (k >= P) break;
-        float Gr[EPL];
-#pragma unroll
-        for (int m = 0; m < EPL; ++m) {
-            int e = lane + 64 * m;
-            Gr[m] = e < E ? gtil[((size_t)b * P + k) * E + e] : 0.0f;
+        // per-bucket inclusive prefix sums of G (1, tau, tau^2, tau^3) for this
+        // phase: G staged by energy, then lane = bucket
+        {
+            const float *gk = gtil + ((size_t)b * P + k) * E;
+            wave_sync();                                   // the previous phase's sums are no longer read
+            for (int e = lane; e < E; e += 64) ((float *)(Lw + e))[0] = gk[e];
+            wave_sync();
+            float4 run = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int e = est; e < een; ++e) {
+                const float G = ((const float *)(Lw + e))[0], t = etau[e];
+                const float g1 = G * t, g2 = g1 * t;
+                run.x += G;
+                run.y += g1;
+                run.z += g2;
+                run.w += g2 * t;
+                Lw[e] = run;
+            }
+            wave_sync();
         }
         const double Phik = (k + 0.5) / S.Pd;
         for (int c0 = 0; c0 < g.n_cells; c0 += 64) {
@@ -735,11 +773,11 @@ __global__ __launch_bounds__(64 * kAdjWaves, 4) void k_accum_adj(DevSpec S, cons
             Pw[lane] = make_float4(w0, w1, w2, w3);
             wave_sync();
             if (g.interior)
-                adj_pairs<EPL, true>(vmask, Pw, vv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Qw, tbr,
-                                     Gr, R0, R1, R2, accT, accG);
+                adj_pairs<true>(vmask, Pw, vv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Lw, etau, est,
+                                een, e_it, R0, R1, R2, accT, accG);
             else
-                adj_pairs<EPL, false>(vmask, Pw, vv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Qw, tbr,
-                                      Gr, R0, R1, R2, accT, accG);
+                adj_pairs<false>(vmask, Pw, vv, fr, Fpf, I0, m0, lane, bp32, tab, tab2, W, xw0, xw, nx, Lw, etau, est,
+                                 een, e_it, R0, R1, R2, accT, accG);
             // ---------------- stage C: chain rule per pair, FP64
             if (vis) {
                 const double4 A = tr[lo], Cn = tr[lo + 1];
@@ -840,8 +878,8 @@ size_t accum_adj_lds(const DevSpec &S)
 {
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
          + sizeof(float) * S.sub_stride + sizeof(float4) * kAdjWaves * 64
-         + sizeof(float4) * kAdjWaves * 4 * 64 + sizeof(double) * 2 * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
-         + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb);
+         + sizeof(float4) * kAdjWaves * S.E + sizeof(double) * 2 * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
+         + sizeof(int16_t) * (2 * S.n_fp + ((S.mu_nb + 1) & ~1)) + sizeof(float) * (S.E + 1);
 }
 
 hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev,
@@ -858,24 +896,12 @@ hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *param
     hipLaunchKernelGGL(k_subtable_tg, dim3(n_list), dim3(256), 0, st, S, list, W.rings, W.subtg);
     const int n_tile = (S.P + S.pt_adj - 1) / S.pt_adj;
     size_t lds = accum_adj_lds(S);
-    int epl = (S.E + 63) / 64;
     const int step = max_list_per_launch(n_tile, 64 * kAdjWaves);
     for (int off = 0; off < n_list; off += step) {
         const int32_t *sl = list + off;
         const int n = n_list - off < step ? n_list - off : step;
-        dim3 grid(xcd_grid(n, n_tile));
-        if (epl <= 1)
-            hipLaunchKernelGGL(k_accum_adj<1>, grid, dim3(64 * kAdjWaves), lds, st, S, sl, W.rings, W.ringtan, W.trace,
-                               W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n);
-        else if (epl <= 2)
-            hipLaunchKernelGGL(k_accum_adj<2>, grid, dim3(64 * kAdjWaves), lds, st, S, sl, W.rings, W.ringtan, W.trace,
-                               W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n);
-        else if (epl <= 4)
-            hipLaunchKernelGGL(k_accum_adj<4>, grid, dim3(64 * kAdjWaves), lds, st, S, sl, W.rings, W.ringtan, W.trace,
-                               W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n);
-        else
-            hipLaunchKernelGGL(k_accum_adj<8>, grid, dim3(64 * kAdjWaves), lds, st, S, sl, W.rings, W.ringtan, W.trace,
-                               W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n);
+        hipLaunchKernelGGL(k_accum_adj, dim3(xcd_grid(n, n_tile)), dim3(64 * kAdjWaves), lds, st, S, sl, W.rings,
+                           W.ringtan, W.trace, W.tangent, W.sub, W.subtg, W.gtil, W.gpart, n);
     }
     hipLaunchKernelGGL(k_grad_final, dim3(B), dim3(64), 0, st, S, W.stars, W.rings, W.ringtan, W.gpart, n_tile,
                        W.nh_part, grad);

@@ -415,6 +415,33 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
             delete pl;
             return fail(PPM_ERR_UNSUPPORTED, "gradients need an energy grid spanning at most 59 x intervals");
         }
+        if (sp->grad) {
+            // unit x buckets of the energies' offsets (the adjoint sums energy
+            // moments per x interval from per-bucket prefix sums)
+            std::vector<float> tau(S.E + 1);
+            std::vector<int32_t> bk(65, S.E);
+            int nmax = 0;
+            for (int e = 0, h = 0; e < S.E; ++e) {
+                const float t = (float)((std::log10(sp->energy_kev[e]) - std::log10(sp->energy_kev[0])) * S.ihx);
+                const int he = (int)std::floor(t);
+                while (h <= he && h < 65) bk[h++] = e;
+                tau[e] = t - (float)he;
+            }
+            tau[S.E] = 2.0f;
+            for (int h = 0; h < 64; ++h) nmax = std::max(nmax, bk[h + 1] - bk[h]);
+            S.e_it = 0;
+            while ((1 << S.e_it) <= nmax) ++S.e_it;
+            if (S.e_it > 4) {
+                delete pl;
+                return fail(PPM_ERR_UNSUPPORTED, "gradients need at most 15 energies per x interval of the table");
+            }
+            S.ebkt = pl->upload(bk.data(), bk.size());
+            S.etau = pl->upload(tau.data(), tau.size());
+            if (!S.ebkt || !S.etau) {
+                delete pl;
+                return fail(PPM_ERR_ALLOC, "device allocation or upload failed");
+            }
+        }
         S.sub_stride = S.fast ? ((S.nmu * S.W_max + 3) & ~3) : S.nmu * S.nx;
         size_t n = (size_t)S.nT * S.ng * S.nmu * S.nx;
         std::vector<float> lin(n);

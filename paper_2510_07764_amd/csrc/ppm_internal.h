@@ -43,6 +43,12 @@ struct DevSpec {
     double mu_lo, mu_hi;  // first and last mu node
     double Pd, fpb;       // n_phase and 2 n_fp (the phase buckets) as doubles
     const float *tbe;     // [E] (log10 E_e - log10 E_0)/hx, the energies' x offsets
+    // gradient plans: the energies grouped by the unit x interval their offset
+    // falls in, bucket h = [ebkt[h], ebkt[h + 1]) holding floor(tbe) = h, and
+    // each offset's part above its bucket (etau[E] = 2 closes the array)
+    const int32_t *ebkt;  // [65]
+    const float *etau;    // [E + 1] tbe[e] - floor(tbe[e])
+    int e_it;             // binary-search steps that cover the largest bucket
     int R_tot;            // ring slots per instance (spot 0 then spot 1)
     int rings_max[2];     // ring slots of each spot
     int n_rings_spec[2], n_phi_spec[2];   // default grid of each spot
