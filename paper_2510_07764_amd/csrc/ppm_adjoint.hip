@@ -37,44 +37,78 @@ using D5 = Dual<5>;
 constexpr double kLn10 = 2.302585092994045684;
 
 // ---------------------------------------------------------------------------
-// k_fold_bwd: reverse mode through the likelihood, fold and absorption.
-// Block = (phase k, instance b); thread = energy.  FP64 throughout; the flux
-// adjoint divided by E is stored in FP32 for the accumulation kernel.
+// k_fold_bwd: reverse mode through the likelihood, fold and absorption, on
+// the matrix cores in FP64: G[row][e] = (T_exp/P) sum_c g_m[row][c] RSP[e][c]
+// for rows (instance b, phase k), with g_m = d/m - 1 (-1 where d = 0; m the
+// model plus background counts) formed as the A operand is loaded.  Block =
+// one 16 x 16 tile (16 rows, 16 energies), four waves splitting the channels
+// into quarters; per wave K in steps of 4 (v_mfma_f64_16x16x4f64): lane l
+// supplies A[l%16][c0 + l/16] and RSP^T[c0 + l/16][l%16], and the tile comes
+// back as D[l/16 + 4 v][l%16] in accumulator v.  The four partial tiles
+// are added in wave order.  Epilogue: the flux adjoint divided by E (FP32,
+// for the accumulation kernel) and the N_H derivative summed over the
+// tile's 16 energies per row in a fixed lane butterfly.
 // ---------------------------------------------------------------------------
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void k_fold_bwd(DevSpec S, const StarRec *stars, const double *counts,
                                                   const int32_t *data, const double *flux, float *gtil,
-                                                  double *nh_part)
+                                                  double *nh_part, int M)
 {
-    extern __shared__ double gm[];   // [C]
-    __shared__ double red[256];
-    const int k = blockIdx.x, b = blockIdx.y, P = S.P, C = S.C, E = S.E;
-    const double *m = counts + ((size_t)b * P + k) * C;
-    const int32_t *d = data + (size_t)k * C;
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        const int dc = d[c];
-        const double mc = S.bkg ? m[c] + S.bkg[(size_t)k * C + c] : m[c];   // model plus background
-        gm[c] = dc == 0 ? -1.0 : dc / mc - 1.0;       // d/dm of d ln m - m
+    __shared__ doublex4 part[4][64];
+    const int P = S.P, C = S.C, E = S.E;
+    const int n0 = blockIdx.x * 16, m0 = blockIdx.y * 16;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+    const int kq = ((C + 15) / 16) * 4;
+    const int kb = wave * kq, ke = min(C, kb + kq);
+    const int arow = m0 + li, ecol = n0 + li;
+    const bool mrow = arow < M, ncol = ecol < E;
+    const int ak = mrow ? arow % P : 0;
+    const double *mrow_p = counts + (size_t)(mrow ? arow : 0) * C;
+    const int32_t *drow_p = data + (size_t)ak * C;
+    const double *brow_p = S.bkg ? S.bkg + (size_t)ak * C : nullptr;
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    // eight K steps at a time: their operands loaded and formed first, then
+    // the MFMAs in K order
+    constexpr int kSteps = 8;
+    for (int cc = kb; cc < ke; cc += 4 * kSteps) {
+        double av[kSteps], bv[kSteps];
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) {
+            const int c = cc + 4 * s + lk;
+            const bool oka = mrow && c < ke, okb = ncol && c < ke;
+            const int dc = oka ? drow_p[c] : 0;
+            double mc = oka ? mrow_p[c] : 1.0;
+            if (brow_p && oka) mc += brow_p[c];                          // model plus background
+            av[s] = oka ? (dc == 0 ? -1.0 : dc / mc - 1.0) : 0.0;        // d/dm of d ln m - m
+            bv[s] = okb ? S.rspT64[(size_t)c * E + ecol] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s)
+            if (cc + 4 * s < ke) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
     }
+    part[wave][l] = acc;
     __syncthreads();
-    const StarRec st = stars[b];
-    const double scale = S.t_exp / P;
+    // wave w: output rows l/16 + 4 w of the tile
+    const double *p0 = (const double *)&part[0][l], *p1 = (const double *)&part[1][l],
+                 *p2 = (const double *)&part[2][l], *p3 = (const double *)&part[3][l];
+    double t = p0[wave];
+    t += p1[wave];
+    t += p2[wave];
+    t += p3[wave];
+    const int row = m0 + lk + 4 * wave, e = n0 + li;
     double nh = 0.0;
-    for (int e = threadIdx.x; e < E; e += blockDim.x) {
-        double acc = 0.0;
-        for (int c = 0; c < C; ++c) acc = fma(gm[c], S.rspT64[(size_t)c * E + e], acc);
-        const double Gp = acc * scale;                 // adjoint of the absorbed flux
-        const double att = S.sigma ? exp(-st.NH * S.sigma[e]) : 1.0;
-        const size_t o = ((size_t)b * P + k) * E + e;
+    if (row < M && e < E) {
+        const int b = row / P;
+        const double Gp = t * (S.t_exp / P);                   // adjoint of the absorbed flux
+        const double att = S.sigma ? exp(-stars[b].NH * S.sigma[e]) : 1.0;
+        const size_t o = (size_t)row * E + e;
         gtil[o] = (float)(Gp * att / S.energy[e]);
-        if (S.sigma) nh -= Gp * flux[o] * att * S.sigma[e] * 1e20;   // N_H in units of 1e20 cm^-2
+        if (S.sigma) nh = -Gp * flux[o] * att * S.sigma[e] * 1e20;   // N_H in units of 1e20 cm^-2
     }
-    red[threadIdx.x] = nh;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) nh_part[(size_t)b * P + k] = red[0];
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) nh += __shfl_xor(nh, o, 64);
+    if (li == 0 && row < M) nh_part[(size_t)row * gridDim.x + blockIdx.x] = nh;
 }
 
 // ---------------------------------------------------------------------------
@@ -864,8 +898,10 @@ __global__ __launch_bounds__(64) void k_grad_final(DevSpec S, const StarRec *sta
         const int q = threadIdx.x;
         double v = 0.0;
         for (int t = 0; t < 64; ++t) v += red[t][q];
-        if (q == 4)
-            for (int k = 0; k < S.P; ++k) v += nh_part[(size_t)b * S.P + k];
+        if (q == 4) {
+            const int n = S.P * ((S.E + 15) / 16);   // per (phase, energy tile), in order
+            for (int i = 0; i < n; ++i) v += nh_part[(size_t)b * n + i];
+        }
         if (stars[b].status != PPM_INST_OK) v = NAN;
         grad[(size_t)b * PPM_NGRAD + q] = v;
     }
@@ -886,8 +922,8 @@ hipError_t launch_grad(const DevSpec &S, const Workspace &W, const double *param
                        int B, const int32_t *list, int n_list, const double *counts, const int32_t *data,
                        double *grad, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fold_bwd, dim3(S.P, B), dim3(256), sizeof(double) * S.C, st, S, W.stars, counts, data,
-                       W.flux, W.gtil, W.nh_part);
+    hipLaunchKernelGGL(k_fold_bwd, dim3((S.E + 15) / 16, (B * S.P + 15) / 16), dim3(256), 0, st, S, W.stars, counts,
+                       data, W.flux, W.gtil, W.nh_part, B * S.P);
     hipLaunchKernelGGL(k_table_u, dim3(n_list, (S.n_alpha + 63) / 64), dim3(64), 0, st, S, list, W.stars, W.rings,
                        W.table_u);
     size_t lds_tt = sizeof(double4) * (2 * S.n_alpha + (S.n_fp + 1) * 5);

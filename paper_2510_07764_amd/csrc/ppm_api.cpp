@@ -580,7 +580,7 @@ int ppm_plan_create(const ppm_spec *sp, int max_batch, int max_cells, ppm_plan *
         W.subtg = pl->dalloc<float2>(B * R * (size_t)S.sub_stride);
         W.flux = pl->dalloc<double>(B * S.P * S.E);
         W.gtil = pl->dalloc<float>(B * S.P * S.E);
-        W.nh_part = pl->dalloc<double>(B * S.P);
+        W.nh_part = pl->dalloc<double>(B * S.P * ((S.E + 15) / 16));
         W.gpart = pl->dalloc<double>(B * R * n_tile * kGradAcc);
         ok = ok && W.table_u && W.tangent && W.ringtan && W.subtg && W.flux && W.gtil && W.nh_part && W.gpart
            && S.rspT64;

@@ -37,7 +37,7 @@ struct Workspace {
     float2 *subtg;         // [B][R_tot][sub_stride] d sub / d logT, d sub / d log g
     double *flux;          // [B][P][E] flux before absorption
     float *gtil;           // [B][P][E] adjoint of the flux divided by E
-    double *nh_part;       // [B][P] N_H gradient per phase
+    double *nh_part;       // [B][P][E/16] N_H gradient per phase and 16-energy tile
     double *gpart;         // [B][R_tot][n_tile][kGradAcc] per-block adjoint sums
     // temperature-map plans only
     MapCell *mcell;        // [B][n_pix] active patches, per ring sorted by temperature bucket
