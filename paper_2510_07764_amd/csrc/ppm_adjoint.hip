@@ -444,11 +444,6 @@ __device__ inline float wave_allsum(float v, int bp32)
     return v;
 }
 
-// value of lane + 1 (0 in lane 63): DPP whole-wave shift
-__device__ inline float wave_next(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
-}
 
 __device__ inline double wave_sum_d(double v)
 {

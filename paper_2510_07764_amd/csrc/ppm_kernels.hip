@@ -710,7 +710,8 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
 //           T0 = (log10(z_p E_0 / kT) - x0)/hx split into I0 = floor(T0) and
 //           frac0; visible pairs are compacted with a wave ballot;
 //  stage B  per visible pair: lane = x node I0 - 1 + lane, mu contraction of
-//           the ring's LDS sub-table; lane = x interval I0 + lane, cubic
+//           the ring's LDS sub-table; lane = x interval I0 + lane (the next
+//           three nodes' values by DPP whole-wave shifts), cubic
 //           coefficients of the interpolant on that interval (linear in the
 //           first and last interval of the table, zero outside) into an LDS
 //           quad; per energy, t = frac0 + (tb_e - tb_0), one quad read and a
@@ -724,7 +725,7 @@ __global__ __launch_bounds__(256) void k_accum_table(DevSpec S, const int32_t *l
 // and last table interval: every interval is cubic, no selects.
 template <int EPL>
 __device__ __forceinline__ void pairs_interior(uint64_t mask, const float4 *Pp, float fr, int pk, int lane, const float *tab,
-                                               int W, int NMP, int xw0, float *Sw, float4 *Qw,
+                                               int W, int NMP, int xw0, float4 *Qw,
                                                const float (&tbr)[EPL], float (&acc)[EPL])
 {
     while (mask) {
@@ -742,9 +743,7 @@ __device__ __forceinline__ void pairs_interior(uint64_t mask, const float4 *Pp, 
         // 24-bit multiply-add on byte offsets (full-rate, unlike a 32-bit multiply)
         const float *t0 = (const float *)((const char *)(tab + pm0) + __umul24((unsigned)col, 4u * NMP));
         const float Sv = pw0 * t0[0] + pw1 * t0[1] + pw2 * t0[2] + pw3 * t0[3];
-        Sw[lane] = Sv;
-        wave_sync();
-        const float s1 = Sw[lane + 1], s2 = Sw[lane + 2], s3 = Sw[lane + 3];
+        const float s1 = wave_next_f(Sv), s2 = wave_next_f(s1), s3 = wave_next_f(s2);
         const float c2 = 0.5f * (Sv + s2) - s1;
         const float c3 = (s3 - Sv) * (1.0f / 6.0f) + 0.5f * (s1 - s2);
         Qw[lane] = make_float4(s1, s2 - s1 - c2 - c3, c2, c3);
@@ -765,7 +764,7 @@ __device__ __forceinline__ void pairs_interior(uint64_t mask, const float4 *Pp, 
 template <int EPL>
 __device__ __forceinline__ void pairs_general(uint64_t mask, const float4 *Pp, float fr,
                                               int I0, int m0, int lane, const float *tab, int NMP, int xw0, int xw,
-                                              int nx, float *Sw, float4 *Qw, const float (&tbr)[EPL],
+                                              int nx, float4 *Qw, const float (&tbr)[EPL],
                                               float (&acc)[EPL])
 {
     while (mask) {
@@ -781,9 +780,7 @@ __device__ __forceinline__ void pairs_general(uint64_t mask, const float4 *Pp, f
             const float *t0 = (const float *)((const char *)(tab + pm0) + __umul24((unsigned)col, 4u * NMP));
             Sv = pw0 * t0[0] + pw1 * t0[1] + pw2 * t0[2] + pw3 * t0[3];
         }
-        Sw[lane] = Sv;
-        wave_sync();
-        const float s1 = Sw[lane + 1], s2 = Sw[lane + 2], s3 = Sw[lane + 3];
+        const float s1 = wave_next_f(Sv), s2 = wave_next_f(s1), s3 = wave_next_f(s2);
         // interpolant on x interval gi = I0 + lane (nodes gi-1 .. gi+2)
         const int gi = pI0 + lane;
         float4 qd = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -836,8 +833,7 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     float *tab = (float *)(axmu + ((nmu + 1) & ~1));           // x-major sub-table, 16-byte aligned
     const int NMP = fast_tab_stride(nmu);
     float4 *Qb = (float4 *)(tab + fast_tab_floats(S));         // NW waves * 64 quads
-    float *Sb = (float *)(Qb + NW * 64);                       // NW waves * 68
-    float4 *Pb = (float4 *)(Sb + NW * 68);                     // NW waves * 64 pair mu weights
+    float4 *Pb = Qb + NW * 64;                                 // NW waves * 64 pair mu weights
     double *po = (double *)(Pb + NW * 64);                     // nfp + 1 phi_o, compact for the search
     double *ipo = po + nfp + 1;                                // nfp: 1 / (phi_o[i+1] - phi_o[i])
     double *mcf = ipo + nfp + 1;                               // nmu * 4 mu-interval coefficients
@@ -854,9 +850,7 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     for (int i = threadIdx.x; i < S.mu_nb; i += blockDim.x) mbk[i] = S.mu_bucket[i];
     for (int e = threadIdx.x; e < E; e += blockDim.x) tbl[e] = S.tbe[e];
     float4 *Qw = Qb + wave * 64;
-    float *Sw = Sb + wave * 68;
     float4 *Pw = Pb + wave * 64;
-    if (lane < 4) Sw[64 + lane] = 0.0f;
     float tbr[EPL];
 #pragma unroll
     for (int m = 0; m < EPL; ++m) {
@@ -1003,9 +997,9 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
                 wave_sync();
                 // ---------------- stage B: the visible pairs one after another
                 if (g.interior)
-                    pairs_interior<EPL>(mask, Pw, fr, (I0 << 8) | m0, lane, tab, W, NMP, xw0, Sw, Qw, tbr, acc);
+                    pairs_interior<EPL>(mask, Pw, fr, (I0 << 8) | m0, lane, tab, W, NMP, xw0, Qw, tbr, acc);
                 else
-                    pairs_general<EPL>(mask, Pw, fr, I0, m0, lane, tab, NMP, xw0, xw, nx, Sw, Qw, tbr, acc);
+                    pairs_general<EPL>(mask, Pw, fr, I0, m0, lane, tab, NMP, xw0, xw, nx, Qw, tbr, acc);
             }
             float *out = partial + ((size_t)gi * P + k) * E;
             if (!GRP || first) {
@@ -1505,8 +1499,7 @@ size_t accum_table_lds(const DevSpec &S)
 {
     if (S.fast)
         return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
-             + sizeof(float) * fast_tab_floats(S) + sizeof(float4) * kFwdWaves * 64 + sizeof(float) * kFwdWaves * 68
-             + sizeof(float4) * kFwdWaves * 64
+             + sizeof(float) * fast_tab_floats(S) + sizeof(float4) * kFwdWaves * 64 + sizeof(float4) * kFwdWaves * 64
              + sizeof(double) * 2 * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
              + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb) + sizeof(float) * 2 * S.E;
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * S.nmu + sizeof(float) * S.nmu * S.nx

@@ -130,9 +130,60 @@ __global__ __launch_bounds__(256) void k_map_sort(DevSpec S, const int32_t *list
 //            x position of the first energy;
 //   stage B  per visible pair: mu contraction of both slabs and their logT
 //            blend at x node I0 - 1 + lane, cubic coefficients of interval
-//            I0 + lane (linear in the first and last table interval, zero
-//            outside), per energy one quad read and a Horner step.
+//            I0 + lane (next nodes by DPP wave shifts; linear in the first and
+//            last table interval, zero outside), per energy one quad read and
+//            a Horner step.
 // ---------------------------------------------------------------------------
+// Stage B of k_accum_map for the visible pairs (mask) of one 64-patch group
+// of a bucket.  INTERIOR: the bucket's x window stays one interval clear of
+// the table's first and last intervals (every interval an energy can use is
+// cubic and every stencil column lies in the staged window), so the bounds
+// tests drop out; columns past the window are read but never reach a quad
+// an energy uses.
+template <int EPL, bool INTERIOR>
+__device__ __forceinline__ void map_pairs(uint64_t mask, float w0f, float w1f, float w2f, float w3f, float fr,
+                                          float tw, int I0, int m0, int lane, const float *sl0, const float *sl1,
+                                          int WM, int w0, int xw, int nx, float4 *Qw,
+                                          const float (&tbr)[EPL], float (&acc)[EPL])
+{
+    while (mask) {
+        const int p = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const float pw0 = readlane_f(w0f, p), pw1 = readlane_f(w1f, p), pw2 = readlane_f(w2f, p),
+                    pw3 = readlane_f(w3f, p), pfr = readlane_f(fr, p), ptw = readlane_f(tw, p);
+        const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
+        int col = pI0 - 1 + lane - w0;
+        float Sv = 0.0f;
+        if (INTERIOR || (col >= 0 && col < xw)) {
+            if (INTERIOR) col = col < WM - 1 ? col : WM - 1;
+            const float *t0 = sl0 + pm0 * WM + col, *t1 = sl1 + pm0 * WM + col;
+            const float v0 = pw0 * t0[0] + pw1 * t0[WM] + pw2 * t0[2 * WM] + pw3 * t0[3 * WM];
+            const float v1 = pw0 * t1[0] + pw1 * t1[WM] + pw2 * t1[2 * WM] + pw3 * t1[3 * WM];
+            Sv = v0 + ptw * (v1 - v0);
+        }
+        const float s1 = wave_next_f(Sv), s2 = wave_next_f(s1), s3 = wave_next_f(s2);
+        float4 qd = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int gi = pI0 + lane;
+        if (INTERIOR || (gi >= 1 && gi <= nx - 3)) {
+            const float c2 = 0.5f * (Sv + s2) - s1;
+            const float c3 = (s3 - Sv) * (1.0f / 6.0f) + 0.5f * (s1 - s2);
+            qd = make_float4(s1, s2 - s1 - c2 - c3, c2, c3);
+        } else if (gi == 0 || gi == nx - 2) {
+            qd = make_float4(s1, s2 - s1, 0.f, 0.f);
+        }
+        Qw[lane] = qd;
+        wave_sync();
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) {
+            const float t = pfr + tbr[m];
+            const float f = __builtin_amdgcn_fractf(t);
+            const float4 qv = Qw[(int)t];
+            acc[m] += qv.x + f * (qv.y + f * (qv.z + f * qv.w));
+        }
+        wave_sync();
+    }
+}
+
 // The partial of work-list entry li goes to partial[li] (groups of one ring).
 template <int EPL, int KPW>
 __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const int32_t *list, const RingRec *rings,
@@ -156,8 +207,7 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     float *sl0 = (float *)(axmu + ((nmu + 1) & ~1));           // nmu * WM
     float *sl1 = sl0 + nmu * WM;                               // nmu * WM
     float4 *Qb = (float4 *)(sl1 + nmu * WM);                   // kMapWaves * 64 quads (WM % 4 == 0)
-    float *Sb = (float *)(Qb + kMapWaves * 64);                // kMapWaves * 68
-    double *ipo = (double *)(Sb + kMapWaves * 68);             // nfp: 1 / (phi_o[i+1] - phi_o[i])
+    double *ipo = (double *)(Qb + kMapWaves * 64);             // nfp: 1 / (phi_o[i+1] - phi_o[i])
     double *mcf = ipo + nfp + 1;                               // nmu * 4 mu-interval coefficients
     int16_t *pbk = (int16_t *)(mcf + 4 * nmu);                 // 2 nfp phase buckets
     int16_t *mbk = pbk + 2 * nfp;                              // mu_nb mu buckets
@@ -191,8 +241,6 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     for (int i = tid; i < nfp; i += blockDim.x) ipo[i] = 1.0 / (po[i + 1] - po[i]);
     const int wave = tid >> 6, lane = tid & 63;
     float4 *Qw = Qb + wave * 64;
-    float *Sw = Sb + wave * 68;
-    if (lane < 4) Sw[64 + lane] = 0.0f;
     const double ihx = S.ihx;
     float tbr[EPL];
 #pragma unroll
@@ -233,6 +281,9 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
         w1 = w1 > nx - 1 ? nx - 1 : w1;
         int xw = w1 - w0 + 1;
         xw = xw < 0 ? 0 : (xw > WM ? WM : xw);
+        // every interval a pair of the bucket uses lies in [floor(tlo),
+        // floor(thi)] up to one interval of slip (as for the spot rings)
+        const bool interior = floor(tlo) >= 2.0 && floor(thi) <= nx - 4 && w1 - w0 + 1 <= WM;
         __syncthreads();   // the previous bucket's slabs are no longer read (and the trace is staged)
         const float *a00 = S.atm + ((size_t)it * S.ng + ig) * slab, *a01 = a00 + slab;
         const float *a10 = S.atm + ((size_t)(it + 1) * S.ng + ig) * slab, *a11 = a10 + slab;
@@ -309,8 +360,9 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
                         I0 = (int)fl;
                         fr = (float)(T0 - fl);
                         clamped = mc.clamped != 0;
-                        // energies beyond the table's x range contribute nothing (counted)
-                        if (I0 < 0 || (float)I0 + fr + tbl[E - 1] >= (float)(nx - 2))
+                        // energies beyond the table's x range contribute nothing
+                        // (counted; none in an interior bucket)
+                        if (!interior && (I0 < 0 || (float)I0 + fr + tbl[E - 1] >= (float)(nx - 2)))
                             nxout += x_outside_count(I0, fr, tbl, E, nx);
                     }
                 }
@@ -318,45 +370,12 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
                 npairs += __popcll(mask);
                 nclamp += __popcll(__ballot(clamped));
                 // ---------------- stage B: the visible pairs one after another
-                while (mask) {
-                    const int p = __ffsll((unsigned long long)mask) - 1;
-                    mask &= mask - 1;
-                    const float pw0 = readlane_f(w0f, p), pw1 = readlane_f(w1f, p), pw2 = readlane_f(w2f, p),
-                                pw3 = readlane_f(w3f, p), pfr = readlane_f(fr, p), ptw = readlane_f(tw, p);
-                    const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
-                    const int col = pI0 - 1 + lane - w0;
-                    float Sv = 0.0f;
-                    if (col >= 0 && col < xw) {
-                        const float *t0 = sl0 + pm0 * WM + col, *t1 = sl1 + pm0 * WM + col;
-                        const float v0 = pw0 * t0[0] + pw1 * t0[WM] + pw2 * t0[2 * WM] + pw3 * t0[3 * WM];
-                        const float v1 = pw0 * t1[0] + pw1 * t1[WM] + pw2 * t1[2 * WM] + pw3 * t1[3 * WM];
-                        Sv = v0 + ptw * (v1 - v0);
-                    }
-                    Sw[lane] = Sv;
-                    wave_sync();
-                    const float s1 = Sw[lane + 1], s2 = Sw[lane + 2], s3 = Sw[lane + 3];
-                    const int gi = pI0 + lane;
-                    float4 qd = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (gi >= 0 && gi <= nx - 2) {
-                        if (gi == 0 || gi == nx - 2) {
-                            qd = make_float4(s1, s2 - s1, 0.f, 0.f);
-                        } else {
-                            const float c2 = 0.5f * (Sv + s2) - s1;
-                            const float c3 = (s3 - Sv) * (1.0f / 6.0f) + 0.5f * (s1 - s2);
-                            qd = make_float4(s1, s2 - s1 - c2 - c3, c2, c3);
-                        }
-                    }
-                    Qw[lane] = qd;
-                    wave_sync();
-#pragma unroll
-                    for (int m = 0; m < EPL; ++m) {
-                        const float t = pfr + tbr[m];
-                        const float f = __builtin_amdgcn_fractf(t);
-                        const float4 qv = Qw[(int)t];
-                        acc[kq][m] += qv.x + f * (qv.y + f * (qv.z + f * qv.w));
-                    }
-                    wave_sync();
-                }
+                if (interior)
+                    map_pairs<EPL, true>(mask, w0f, w1f, w2f, w3f, fr, tw, I0, m0, lane, sl0, sl1, WM, w0, xw, nx, Qw,
+                                         tbr, acc[kq]);
+                else
+                    map_pairs<EPL, false>(mask, w0f, w1f, w2f, w3f, fr, tw, I0, m0, lane, sl0, sl1, WM, w0, xw, nx,
+                                          Qw, tbr, acc[kq]);
             }
         }
     }
@@ -383,7 +402,7 @@ size_t accum_map_lds(const DevSpec &S)
 {
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.n_fp + 2) & ~1) + sizeof(double) * ((S.nmu + 1) & ~1)
          + sizeof(float) * 2 * (size_t)S.nmu * S.map_wm + sizeof(float4) * kMapWaves * 64
-         + sizeof(float) * kMapWaves * 68 + sizeof(double) * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
+         + sizeof(double) * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
          + sizeof(int16_t) * (2 * S.n_fp + ((S.mu_nb + 1) & ~1)) + sizeof(float) * S.E;
 }
 
