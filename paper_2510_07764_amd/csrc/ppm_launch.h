@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "ppm_internal.h"
+#include "ppm_status.h"
 #include "../../include/ppm.h"
 
 namespace ppm {
@@ -93,7 +94,6 @@ int loglike_blocks(int PC);
 int loglike_parts(int P, int C);   // per-instance likelihood partials (fused fold or block sums)
 // read access to a plan's model, workspace, batch limit and device (host)
 bool plan_view(const ppm_plan *pl, const DevSpec **S, const Workspace **W, int *max_batch, int *device);
-int api_fail(int code, const char *msg);           // sets ppm_last_error, returns code
 int api_hip_fail(hipError_t e, const char *where);  // sets ppm_last_error, returns PPM_ERR_HIP
 
 }  // namespace ppm

@@ -6,20 +6,26 @@
 // standard (2880-byte blocks of 80-character cards, big-endian binary
 // tables, variable-length arrays in the heap); OGIP column conventions per
 // the OGIP calibration memo CAL/GEN/92-002.
+//
+// Every size, offset and count taken from a file is checked before use:
+// header sizes against the file length (with overflow-checked products),
+// variable-length array descriptors against the table's heap, and integer
+// columns read as floating point for finiteness and range before they are
+// converted.  No exception leaves the C entry points.
 
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <new>
 #include <string>
 #include <vector>
 
-#include <hip/hip_runtime.h>
-
 #include "../../include/ppm.h"
-#include "ppm_launch.h"
+#include "ppm_status.h"
 
 using namespace ppm;
 
@@ -37,8 +43,28 @@ struct Hdu {
     std::map<std::string, std::string> keys;
     long data_start = 0;  // file offset of the data unit
     long naxis1 = 0, naxis2 = 0, theap = 0;
+    long heap_end = 0;    // end of the heap, from the data start (NAXIS1 NAXIS2 + PCOUNT)
     std::vector<Column> cols;
 };
+
+// a * b and a + b for non-negative operands, false on overflow
+bool mul_ok(long a, long b, long &out)
+{
+    return a >= 0 && b >= 0 && !__builtin_mul_overflow(a, b, &out);
+}
+
+bool add_ok(long a, long b, long &out)
+{
+    return a >= 0 && b >= 0 && !__builtin_add_overflow(a, b, &out);
+}
+
+// a value read from a file as an integer: finite and within [lo, hi]
+bool to_long(double x, long lo, long hi, long &out)
+{
+    if (!std::isfinite(x) || x < (double)lo || x > (double)hi) return false;
+    out = (long)x;
+    return true;
+}
 
 std::string trim(const std::string &s)
 {
@@ -95,6 +121,7 @@ bool parse_tform(const std::string &tf, Column &c)
     bool digits = false;
     while (i < tf.size() && tf[i] >= '0' && tf[i] <= '9') {
         r = r * 10 + (tf[i] - '0');
+        if (r > (1L << 31)) return false;   // beyond any table row this reader accepts
         ++i;
         digits = true;
     }
@@ -118,6 +145,9 @@ bool read_hdus(FILE *f, std::vector<Hdu> &out)
 {
     char block[2880];
     long pos = 0;
+    if (std::fseek(f, 0, SEEK_END) != 0) return false;
+    const long fsize = std::ftell(f);
+    if (fsize < 0 || std::fseek(f, 0, SEEK_SET) != 0) return false;
     while (true) {
         Hdu h;
         bool end = false, any = false;
@@ -136,35 +166,59 @@ bool read_hdus(FILE *f, std::vector<Hdu> &out)
             }
         }
         h.data_start = pos;
-        long bitpix = std::labs(key_long(h, "BITPIX", 8));
-        long naxis = key_long(h, "NAXIS", 0);
+        const long bitpix = key_long(h, "BITPIX", 8);
+        if (bitpix != 8 && bitpix != 16 && bitpix != 32 && bitpix != 64 && bitpix != -32 && bitpix != -64)
+            return false;
+        const long naxis = key_long(h, "NAXIS", 0);
+        if (naxis < 0 || naxis > 999) return false;
         long n = naxis > 0 ? 1 : 0;
-        for (long a = 1; a <= naxis; ++a) n *= key_long(h, "NAXIS" + std::to_string(a), 0);
-        long bytes = bitpix / 8 * key_long(h, "GCOUNT", 1) * (key_long(h, "PCOUNT", 0) + n);
+        for (long a = 1; a <= naxis; ++a)
+            if (!mul_ok(n, key_long(h, "NAXIS" + std::to_string(a), 0), n)) return false;
+        const long pcount = key_long(h, "PCOUNT", 0), gcount = key_long(h, "GCOUNT", 1);
+        long bytes = 0;
+        if (!add_ok(pcount, n, bytes) || !mul_ok(bytes, gcount, bytes) || !mul_ok(bytes, std::labs(bitpix) / 8, bytes))
+            return false;
+        if (bytes > fsize - pos) return false;                    // the data unit lies inside the file
         h.naxis1 = key_long(h, "NAXIS1", 0);
         h.naxis2 = key_long(h, "NAXIS2", 0);
-        h.theap = key_long(h, "THEAP", h.naxis1 * h.naxis2);
         auto xt = h.keys.find("XTENSION");
         if (xt != h.keys.end() && xt->second == "BINTABLE") {
-            long nf = key_long(h, "TFIELDS", 0), off = 0;
+            long table = 0;
+            if (bitpix != 8 || naxis != 2 || !mul_ok(h.naxis1, h.naxis2, table) || !add_ok(table, pcount, h.heap_end))
+                return false;
+            h.theap = key_long(h, "THEAP", table);
+            if (h.theap < table || h.theap > h.heap_end) return false;
+            const long nf = key_long(h, "TFIELDS", 0);
+            if (nf < 0 || nf > 999) return false;
+            long off = 0;
             for (long j = 1; j <= nf; ++j) {
                 Column c;
                 c.name = h.keys["TTYPE" + std::to_string(j)];
                 if (!parse_tform(h.keys["TFORM" + std::to_string(j)], c)) return false;
                 c.offset = off;
-                off += column_bytes(c);
+                if (!add_ok(off, column_bytes(c), off) || off > h.naxis1) return false;
                 h.cols.push_back(c);
             }
             if (off != h.naxis1) return false;
         }
         out.push_back(h);
         long padded = (bytes + 2879) / 2880 * 2880;
+        if (padded > fsize - pos) padded = fsize - pos;           // a last unit without its final padding
         if (std::fseek(f, padded, SEEK_CUR) != 0) return false;
         pos += padded;
         int ch = std::fgetc(f);
         if (ch == EOF) return true;
         std::ungetc(ch, f);
     }
+}
+
+// big-endian signed integer of a heap descriptor ('J' or 'K')
+int64_t be_int(const unsigned char *p, char t)
+{
+    uint64_t u = 0;
+    const long n = type_bytes(t);
+    for (long i = 0; i < n; ++i) u = (u << 8) | p[i];
+    return t == 'J' ? (int64_t)(int32_t)(uint32_t)u : (int64_t)u;
 }
 
 double be_value(const unsigned char *p, char t)
@@ -203,18 +257,24 @@ const Column *find_col(const Hdu &h, const char *name)
 bool cell(FILE *f, const Hdu &h, const Column &c, long r, std::vector<double> &v)
 {
     v.clear();
+    if (r < 0 || r >= h.naxis2) return false;
     std::vector<unsigned char> buf(column_bytes(c));
     if (std::fseek(f, h.data_start + r * h.naxis1 + c.offset, SEEK_SET) != 0) return false;
     if (std::fread(buf.data(), 1, buf.size(), f) != buf.size()) return false;
     if (c.type == 'P' || c.type == 'Q') {
         const char dt = c.type == 'P' ? 'J' : 'K';
         const long db = type_bytes(dt);
-        long cnt = (long)be_value(buf.data(), dt), off = (long)be_value(buf.data() + db, dt);
+        if ((long)buf.size() < 2 * db) return false;
+        const int64_t cnt = be_int(buf.data(), dt), off = be_int(buf.data() + db, dt);
         const long eb = type_bytes(c.ptype);
-        if (cnt < 0 || eb == 0) return false;
-        std::vector<unsigned char> heap(cnt * eb);
+        // the array lies inside the heap: theap + off + cnt eb <= heap_end
+        long nb = 0, beg = 0, end = 0;
+        if (eb == 0 || cnt < 0 || off < 0 || cnt > LONG_MAX || off > LONG_MAX || !mul_ok((long)cnt, eb, nb)
+            || !add_ok(h.theap, (long)off, beg) || !add_ok(beg, nb, end) || end > h.heap_end)
+            return false;
+        std::vector<unsigned char> heap(nb);
         if (cnt) {
-            if (std::fseek(f, h.data_start + h.theap + off, SEEK_SET) != 0) return false;
+            if (std::fseek(f, h.data_start + beg, SEEK_SET) != 0) return false;
             if (std::fread(heap.data(), 1, heap.size(), f) != heap.size()) return false;
         }
         for (long i = 0; i < cnt; ++i) v.push_back(be_value(heap.data() + i * eb, c.ptype));
@@ -246,9 +306,58 @@ struct File {
 
 }  // namespace
 
+namespace {
+
+// The C entry points run their bodies through guarded(): an exception (a
+// failed allocation) becomes an error status instead of leaving C code.
+template <class F>
+int guarded(const char *who, F &&body)
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return api_fail(PPM_ERR_ALLOC, who);
+    } catch (...) {
+        return api_fail(PPM_ERR_ARG, who);
+    }
+}
+
+int arf_read(const char *path, int32_t *n_energy, double *e_lo, double *e_hi, double *area);
+int rmf_read(const char *path, int32_t *n_energy, int32_t *n_chan, double *e_lo, double *e_hi, double *matrix,
+             double *ch_lo, double *ch_hi);
+int response_build(int32_t n_model, const double *e_model, int32_t n_fine, const double *e_lo, const double *e_hi,
+                   const double *area, int32_t n_chan, const double *matrix, double *rsp);
+
+}  // namespace
+
 extern "C" {
 
 int ppm_arf_read(const char *path, int32_t *n_energy, double *e_lo, double *e_hi, double *area)
+{
+    return guarded("ppm_arf_read: out of memory or internal error",
+                   [&] { return arf_read(path, n_energy, e_lo, e_hi, area); });
+}
+
+int ppm_rmf_read(const char *path, int32_t *n_energy, int32_t *n_chan, double *e_lo, double *e_hi, double *matrix,
+                 double *ch_lo, double *ch_hi)
+{
+    return guarded("ppm_rmf_read: out of memory or internal error",
+                   [&] { return rmf_read(path, n_energy, n_chan, e_lo, e_hi, matrix, ch_lo, ch_hi); });
+}
+
+int ppm_response_build(int32_t n_model, const double *e_model, int32_t n_fine, const double *e_lo, const double *e_hi,
+                       const double *area, int32_t n_chan, const double *matrix, double *rsp)
+{
+    return guarded("ppm_response_build: out of memory or internal error", [&] {
+        return response_build(n_model, e_model, n_fine, e_lo, e_hi, area, n_chan, matrix, rsp);
+    });
+}
+
+}  // extern "C"
+
+namespace {
+
+int arf_read(const char *path, int32_t *n_energy, double *e_lo, double *e_hi, double *area)
 {
     if (!path || !n_energy) return api_fail(PPM_ERR_ARG, "ppm_arf_read: null argument");
     File fh(path);
@@ -259,6 +368,7 @@ int ppm_arf_read(const char *path, int32_t *n_energy, double *e_lo, double *e_hi
     if (!h) return api_fail(PPM_ERR_ARG, "ppm_arf_read: no SPECRESP extension");
     const Column *clo = find_col(*h, "ENERG_LO"), *chi = find_col(*h, "ENERG_HI"), *ca = find_col(*h, "SPECRESP");
     if (!clo || !chi || !ca) return api_fail(PPM_ERR_ARG, "ppm_arf_read: missing ENERG_LO, ENERG_HI or SPECRESP");
+    if (h->naxis2 > INT32_MAX) return api_fail(PPM_ERR_ARG, "ppm_arf_read: too many rows");
     *n_energy = (int32_t)h->naxis2;
     if (!e_lo && !e_hi && !area) return PPM_OK;
     std::vector<double> v;
@@ -279,8 +389,8 @@ int ppm_arf_read(const char *path, int32_t *n_energy, double *e_lo, double *e_hi
     return PPM_OK;
 }
 
-int ppm_rmf_read(const char *path, int32_t *n_energy, int32_t *n_chan, double *e_lo, double *e_hi, double *matrix,
-                 double *ch_lo, double *ch_hi)
+int rmf_read(const char *path, int32_t *n_energy, int32_t *n_chan, double *e_lo, double *e_hi, double *matrix,
+             double *ch_lo, double *ch_hi)
 {
     if (!path || !n_energy || !n_chan) return api_fail(PPM_ERR_ARG, "ppm_rmf_read: null argument");
     File fh(path);
@@ -300,6 +410,8 @@ int ppm_rmf_read(const char *path, int32_t *n_energy, int32_t *n_chan, double *e
     const long tlmin = key_long(*h, "TLMIN" + std::to_string(fcol), 1);
     long nch = key_long(*h, "DETCHANS", eb ? eb->naxis2 : 0);
     if (nch <= 0) return api_fail(PPM_ERR_ARG, "ppm_rmf_read: channel count unknown (DETCHANS / EBOUNDS)");
+    if (nch > INT32_MAX || h->naxis2 > INT32_MAX) return api_fail(PPM_ERR_ARG, "ppm_rmf_read: too many rows");
+    if (tlmin < INT32_MIN || tlmin > INT32_MAX) return api_fail(PPM_ERR_ARG, "ppm_rmf_read: bad TLMIN");
     *n_energy = (int32_t)h->naxis2;
     *n_chan = (int32_t)nch;
     if (!matrix && !e_lo && !e_hi && !ch_lo && !ch_hi) return PPM_OK;
@@ -312,15 +424,19 @@ int ppm_rmf_read(const char *path, int32_t *n_energy, int32_t *n_chan, double *e
         if (!matrix) continue;
         double *row = matrix + (size_t)r * nch;
         for (long c = 0; c < nch; ++c) row[c] = 0.0;
-        if (!cell(fh.f, *h, *cng, r, v) || v.empty()) return api_fail(PPM_ERR_ARG, "ppm_rmf_read: bad N_GRP");
-        const long ng = (long)v[0];
+        long ng = 0;
+        if (!cell(fh.f, *h, *cng, r, v) || v.empty() || !to_long(v[0], 0, INT32_MAX, ng))
+            return api_fail(PPM_ERR_ARG, "ppm_rmf_read: bad N_GRP");
         if (!cell(fh.f, *h, *cfc, r, fc) || !cell(fh.f, *h, *cnc, r, ncv) || !cell(fh.f, *h, *cm, r, mv))
             return api_fail(PPM_ERR_ARG, "ppm_rmf_read: bad group arrays");
         if ((long)fc.size() < ng || (long)ncv.size() < ng) return api_fail(PPM_ERR_ARG, "ppm_rmf_read: short groups");
         long k = 0;
         for (long g = 0; g < ng; ++g) {
-            const long c0 = (long)fc[g] - tlmin, n = (long)ncv[g];
-            if (c0 < 0 || n < 0 || c0 + n > nch || k + n > (long)mv.size())
+            long f0 = 0, n = 0;
+            if (!to_long(fc[g], INT32_MIN, INT32_MAX, f0) || !to_long(ncv[g], 0, INT32_MAX, n))
+                return api_fail(PPM_ERR_ARG, "ppm_rmf_read: bad F_CHAN or N_CHAN");
+            const long c0 = f0 - tlmin;
+            if (c0 < 0 || c0 + n > nch || k + n > (long)mv.size())
                 return api_fail(PPM_ERR_ARG, "ppm_rmf_read: group outside the channel range");
             for (long i = 0; i < n; ++i) row[c0 + i] = mv[k + i];
             k += n;
@@ -330,8 +446,10 @@ int ppm_rmf_read(const char *path, int32_t *n_energy, int32_t *n_chan, double *e
         const Column *cc = find_col(*eb, "CHANNEL"), *cmin = find_col(*eb, "E_MIN"), *cmax = find_col(*eb, "E_MAX");
         if (!cc || !cmin || !cmax) return api_fail(PPM_ERR_ARG, "ppm_rmf_read: EBOUNDS columns missing");
         for (long r = 0; r < eb->naxis2; ++r) {
-            if (!cell(fh.f, *eb, *cc, r, v) || v.empty()) return api_fail(PPM_ERR_ARG, "ppm_rmf_read: bad EBOUNDS");
-            const long ch = (long)v[0] - tlmin;
+            long chv = 0;
+            if (!cell(fh.f, *eb, *cc, r, v) || v.empty() || !to_long(v[0], INT32_MIN, INT32_MAX, chv))
+                return api_fail(PPM_ERR_ARG, "ppm_rmf_read: bad EBOUNDS");
+            const long ch = chv - tlmin;
             if (ch < 0 || ch >= nch) continue;
             if (!cell(fh.f, *eb, *cmin, r, v) || v.empty()) return api_fail(PPM_ERR_ARG, "ppm_rmf_read: bad EBOUNDS");
             if (ch_lo) ch_lo[ch] = v[0];
@@ -342,8 +460,8 @@ int ppm_rmf_read(const char *path, int32_t *n_energy, int32_t *n_chan, double *e
     return PPM_OK;
 }
 
-int ppm_response_build(int32_t n_model, const double *e_model, int32_t n_fine, const double *e_lo, const double *e_hi,
-                       const double *area, int32_t n_chan, const double *matrix, double *rsp)
+int response_build(int32_t n_model, const double *e_model, int32_t n_fine, const double *e_lo, const double *e_hi,
+                   const double *area, int32_t n_chan, const double *matrix, double *rsp)
 {
     if (n_model < 2 || n_fine < 1 || n_chan < 1 || !e_model || !e_lo || !e_hi || !matrix || !rsp)
         return api_fail(PPM_ERR_ARG, "ppm_response_build: bad arguments");
@@ -380,6 +498,10 @@ int ppm_response_build(int32_t n_model, const double *e_model, int32_t n_fine, c
     }
     return PPM_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int ppm_sigma_from_table(int32_t n_tab, const double *e_tab, const double *att_tab, double nh_ref, int32_t n,
                          const double *e, double *sigma)

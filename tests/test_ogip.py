@@ -122,3 +122,31 @@ def test_unreadable_input_is_reported(ppm, tmp_path):
         ppm.read_rmf(pa)
     with pytest.raises(ppm.PPMError, match="increase"):
         ppm.build_response([1.0, 0.5], lo, hi, area, np.ones((10, 3)))
+
+
+def test_malformed_files_are_reported(ppm, tmp_path):
+    """Damaged header sizes, heap descriptors outside the heap, and integer
+    columns holding non-finite or out-of-range floats: an error each, no
+    read outside the file or the arrays (the sanitizer build runs the same
+    files, tests/test_sanitizers.py)."""
+    from fits_mangle import malformed_rmfs, rmf_with_float_columns
+    lo, hi, _, m, cl, ch = synthetic_instrument(n_fine=12, n_chan=10)
+    p = os.path.join(tmp_path, "ok.rmf")
+    write_rmf(p, lo, hi, m, cl, ch)
+    valid = open(p, "rb").read()
+    for name, raw in malformed_rmfs(valid):
+        q = os.path.join(tmp_path, name + ".rmf")
+        with open(q, "wb") as f:
+            f.write(raw)
+        with pytest.raises(ppm.PPMError):
+            ppm.read_rmf(q)
+    q = os.path.join(tmp_path, "float_ok.rmf")
+    rmf_with_float_columns(q, 1.0, 1.0)
+    _, _, rm, _, _ = ppm.read_rmf(q)
+    assert np.array_equal(rm, [[0.5, 0.5, 0.0], [0.5, 0.5, 0.0]])
+    for n_grp, f_chan, channel in [(float("nan"), 1.0, 1.0), (1e30, 1.0, 1.0), (-1.0, 1.0, 1.0),
+                                   (1.0, float("nan"), 1.0), (1.0, 1e30, 1.0), (1.0, 1.0, float("inf"))]:
+        q = os.path.join(tmp_path, "float_bad.rmf")
+        rmf_with_float_columns(q, n_grp, f_chan, channel)
+        with pytest.raises(ppm.PPMError):
+            ppm.read_rmf(q)
