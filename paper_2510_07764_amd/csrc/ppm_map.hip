@@ -121,8 +121,9 @@ __global__ __launch_bounds__(256) void k_map_sort(DevSpec S, const int32_t *list
 // phases 8 KPW tile + w + 8 q (q < KPW) and EPL energies, 64 apart, per
 // lane; the staged slabs of a bucket serve all of the block's phases.  Per
 // temperature bucket (logT nodes it, it + 1 after clamping):
-//   staging  sl0, sl1 = table slabs at logT nodes it and it + 1, linear in
-//            the ring's log g, over the x window the bucket's patches can
+//   staging  the table slabs at logT nodes it and it + 1 (x-major, the two
+//            interleaved), linear in the ring's log g, over the x window the
+//            bucket's patches can
 //            reach (redshift range of the ring, bucket's kT range, energy
 //            span and the cubic stencil);
 //   stage A  lane = patch: observed-phase lookup (Eqs. 45-46), mu weights of
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(256) void k_map_sort(DevSpec S, const int32_t *list
 // an energy uses.
 template <int EPL, bool INTERIOR>
 __device__ __forceinline__ void map_pairs(uint64_t mask, float w0f, float w1f, float w2f, float w3f, float fr,
-                                          float tw, int I0, int m0, int lane, const float *sl0, const float *sl1,
+                                          float tw, int I0, int m0, int lane, const float2 *slb, int NMP,
                                           int WM, int w0, int xw, int nx, float4 *Qw,
                                           const float (&tbr)[EPL], float (&acc)[EPL])
 {
@@ -156,9 +157,12 @@ __device__ __forceinline__ void map_pairs(uint64_t mask, float w0f, float w1f, f
         float Sv = 0.0f;
         if (INTERIOR || (col >= 0 && col < xw)) {
             if (INTERIOR) col = col < WM - 1 ? col : WM - 1;
-            const float *t0 = sl0 + pm0 * WM + col, *t1 = sl1 + pm0 * WM + col;
-            const float v0 = pw0 * t0[0] + pw1 * t0[WM] + pw2 * t0[2 * WM] + pw3 * t0[3 * WM];
-            const float v1 = pw0 * t1[0] + pw1 * t1[WM] + pw2 * t1[2 * WM] + pw3 * t1[3 * WM];
+            // the four mu rows of both slabs at this x node: adjacent pairs
+            // (24-bit multiply-add on the byte offset)
+            const float2 *t = (const float2 *)((const char *)(slb + pm0) + __umul24((unsigned)col, 8u * NMP));
+            const float2 a = t[0], b = t[1], c = t[2], d = t[3];
+            const float v0 = pw0 * a.x + pw1 * b.x + pw2 * c.x + pw3 * d.x;
+            const float v1 = pw0 * a.y + pw1 * b.y + pw2 * c.y + pw3 * d.y;
             Sv = v0 + ptw * (v1 - v0);
         }
         const float s1 = wave_next_f(Sv), s2 = wave_next_f(s1), s3 = wave_next_f(s2);
@@ -204,9 +208,11 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     double4 *tr = (double4 *)lds_raw;                          // nfp + 1
     double *po = (double *)(tr + nfp + 1);                     // nfp + 1, padded to even
     double *axmu = po + ((nfp + 2) & ~1);                      // nmu, padded to even
-    float *sl0 = (float *)(axmu + ((nmu + 1) & ~1));           // nmu * WM
-    float *sl1 = sl0 + nmu * WM;                               // nmu * WM
-    float4 *Qb = (float4 *)(sl1 + nmu * WM);                   // kMapWaves * 64 quads (WM % 4 == 0)
+    // the two logT slabs, x-major and interleaved: (slab 0, slab 1) of mu row m
+    // at x node c in slb[c NMP + m], node stride NMP = nmu | 1
+    const int NMP = fast_tab_stride(nmu);
+    float2 *slb = (float2 *)(axmu + ((nmu + 1) & ~1));         // NMP * WM
+    float4 *Qb = (float4 *)(slb + ((NMP * WM + 1) & ~1));      // kMapWaves * 64 quads
     double *ipo = (double *)(Qb + kMapWaves * 64);             // nfp: 1 / (phi_o[i+1] - phi_o[i])
     double *mcf = ipo + nfp + 1;                               // nmu * 4 mu-interval coefficients
     int16_t *pbk = (int16_t *)(mcf + 4 * nmu);                 // 2 nfp phase buckets
@@ -291,8 +297,7 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
         for (int m = wave; m < nmu; m += kMapWaves) {
             const size_t o = (size_t)m * nx + w0;
             for (int c = lane; c < xw; c += 64) {
-                sl0[m * WM + c] = fg0 * a00[o + c] + fg1 * a01[o + c];
-                sl1[m * WM + c] = fg0 * a10[o + c] + fg1 * a11[o + c];
+                slb[c * NMP + m] = make_float2(fg0 * a00[o + c] + fg1 * a01[o + c], fg0 * a10[o + c] + fg1 * a11[o + c]);
             }
         }
         __syncthreads();
@@ -371,10 +376,10 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
                 nclamp += __popcll(__ballot(clamped));
                 // ---------------- stage B: the visible pairs one after another
                 if (interior)
-                    map_pairs<EPL, true>(mask, w0f, w1f, w2f, w3f, fr, tw, I0, m0, lane, sl0, sl1, WM, w0, xw, nx, Qw,
+                    map_pairs<EPL, true>(mask, w0f, w1f, w2f, w3f, fr, tw, I0, m0, lane, slb, NMP, WM, w0, xw, nx, Qw,
                                          tbr, acc[kq]);
                 else
-                    map_pairs<EPL, false>(mask, w0f, w1f, w2f, w3f, fr, tw, I0, m0, lane, sl0, sl1, WM, w0, xw, nx,
+                    map_pairs<EPL, false>(mask, w0f, w1f, w2f, w3f, fr, tw, I0, m0, lane, slb, NMP, WM, w0, xw, nx,
                                           Qw, tbr, acc[kq]);
             }
         }
@@ -401,7 +406,7 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
 size_t accum_map_lds(const DevSpec &S)
 {
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.n_fp + 2) & ~1) + sizeof(double) * ((S.nmu + 1) & ~1)
-         + sizeof(float) * 2 * (size_t)S.nmu * S.map_wm + sizeof(float4) * kMapWaves * 64
+         + sizeof(float2) * (size_t)((fast_tab_stride(S.nmu) * S.map_wm + 1) & ~1) + sizeof(float4) * kMapWaves * 64
          + sizeof(double) * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
          + sizeof(int16_t) * (2 * S.n_fp + ((S.mu_nb + 1) & ~1)) + sizeof(float) * S.E;
 }
