@@ -109,11 +109,12 @@ __device__ void bend_out(const DevSpec &S, const U &u, double alpha, U &psi, U &
     const U hA = 0.5 * A, hAL = 0.5 * A * L;
     const double s2 = s * s, c2 = c * c;
     U I1 = U(0.0), I3 = U(0.0), IT = U(0.0);
-    for (int q = q0; q < n; q += qs) {
-        U ex = exp(L * gx[q]);
-        U iex = rcp_nr(ex);
+    // the rule is symmetric about 1/2 (n even): node q and its mirror 1 - x_q
+    // share one exponential, exp(L (1 - x_q)) = exp(L) / exp(L x_q)
+    const U EL = exp(L), iEL = rcp_nr(EL);
+    auto point = [&](const U &ex, const U &iex, double wq) {
         U x = hA * (ex - iex);
-        U dx = hAL * (ex + iex) * gw[q];
+        U dx = hAL * (ex + iex) * wq;
         U x2 = x * x, t = 1.0 - x2;
         U D = c2 + x2 * s2 * (2.0 - x2 - w * t * t);
         U ir = rsqrt_nr(D);
@@ -122,6 +123,12 @@ __device__ void bend_out(const DevSpec &S, const U &u, double alpha, U &psi, U &
         I1 += xr;
         I3 += xr * ir * ir;
         IT += xr * rcp_nr(1.0 + r);
+    };
+    for (int q = q0; q < n / 2; q += qs) {
+        const U ex = exp(L * gx[q]);
+        const U iex = rcp_nr(ex);
+        point(ex, iex, gw[q]);
+        point(EL * iex, ex * iEL, gw[n - 1 - q]);
     }
     psi = 2.0 * s / sq * I1;
     dpsi = 2.0 * c / sq * I3;
