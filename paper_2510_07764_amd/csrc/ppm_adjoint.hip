@@ -476,10 +476,11 @@ __device__ inline void offset_coeffs(const RingRec &g, int j, double &ca, double
 // refuses energy grids whose buckets need more)
 constexpr int kMaxBucketSteps = 4;
 
-// value of lane - 1 (0 in lane 0): DPP whole-wave shift
+// value of lane - 1 (0 in lane 0): DPP whole-wave shift (bound control
+// writes the 0)
 __device__ inline float wave_prev(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 
 // Node weights of interval lane's cubic (or linear, or zero) interpolant for

@@ -358,10 +358,12 @@ __device__ inline float readlane_f(float v, int lane)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// value of lane + 1 (0 in lane 63): DPP whole-wave shift
+// value of lane + 1 (0 in lane 63): DPP whole-wave shift; bound control
+// writes 0 where the source lane is past the wave, so no zero operand is
+// materialised
 __device__ inline float wave_next_f(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
 __device__ inline void wave_sync()
