@@ -343,23 +343,34 @@ __device__ static void subtable_ring(const DevSpec &S, const RingRec &g, int xw0
         // window [xw0, xw0 + W_max) of every mu row, row stride W_max
         const int W = S.W_max;
         float *out = sub + slot * (size_t)S.sub_stride;
-        // four elements per thread per round: sixteen independent loads in flight
+        // four elements per thread per round: sixteen loads in flight together.
+        // The loads are unconditional (an element outside the window reads
+        // element 0 of the slabs and is multiplied by 0: the table is finite),
+        // so that none of them waits behind a branch.
         const int n = S.nmu * W, step = blockDim.x;
         for (int i0 = threadIdx.x; i0 < n; i0 += 4 * step) {
-            float v[4];
+            float a[4][4], keep[4];
+            int o[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int i = i0 + k * step;
                 const int m = i / W, c = i - m * W;
-                v[k] = 0.0f;
-                if (i < n && c < xw) {
-                    const size_t o = (size_t)m * S.nx + xw0 + c;
-                    v[k] = w00 * s00[o] + w01 * s01[o] + w10 * s10[o] + w11 * s11[o];
-                }
+                const bool ok = i < n && c < xw;
+                o[k] = ok ? m * S.nx + xw0 + c : 0;
+                keep[k] = ok ? 1.0f : 0.0f;
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (i0 + k * step < n) out[i0 + k * step] = v[k];
+            for (int k = 0; k < 4; ++k) {
+                a[k][0] = s00[o[k]];
+                a[k][1] = s01[o[k]];
+                a[k][2] = s10[o[k]];
+                a[k][3] = s11[o[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float v = (w00 * a[k][0] + w01 * a[k][1] + w10 * a[k][2] + w11 * a[k][3]) * keep[k];
+                if (i0 + k * step < n) out[i0 + k * step] = v;
+            }
         }
         return;
     }
@@ -844,18 +855,31 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     const int n_pb = 2 * nfp;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __shared__ int k_next;
-    // ring-independent tables, staged once per block
-    for (int i = threadIdx.x; i < nmu; i += blockDim.x) axmu[i] = S.ax_mu[i];
-    for (int i = threadIdx.x; i < 4 * nmu; i += blockDim.x) mcf[i] = S.mu_coef[i];
-    for (int i = threadIdx.x; i < S.mu_nb; i += blockDim.x) mbk[i] = S.mu_bucket[i];
-    for (int e = threadIdx.x; e < E; e += blockDim.x) tbl[e] = S.tbe[e];
+    // ring-independent tables, staged once per block.  Every load of a round
+    // is issued (at a clamped, valid index) before the round's LDS writes, so
+    // that the tables cost one memory latency, not one per table.
+    {
+        const int n_st = max(max(4 * nmu, S.mu_nb), E);
+        for (int i = threadIdx.x; i < n_st; i += blockDim.x) {
+            const double ax = S.ax_mu[i < nmu ? i : 0];
+            const double cf = S.mu_coef[i < 4 * nmu ? i : 0];
+            const int16_t bk = S.mu_bucket[i < S.mu_nb ? i : 0];
+            const float tb = S.tbe[i < E ? i : 0];
+            if (i < nmu) axmu[i] = ax;
+            if (i < 4 * nmu) mcf[i] = cf;
+            if (i < S.mu_nb) mbk[i] = bk;
+            if (i < E) tbl[i] = tb;
+        }
+    }
     float4 *Qw = Qb + wave * 64;
     float4 *Pw = Pb + wave * 64;
+    // x offsets of the lane's energies (past E: the last energy's, a valid
+    // window position; those sums are never written)
     float tbr[EPL];
 #pragma unroll
     for (int m = 0; m < EPL; ++m) {
         int e = lane + 64 * m;
-        tbr[m] = e < E ? S.tbe[e] : 0.0f;
+        tbr[m] = S.tbe[e < E ? e : E - 1];
     }
     const double mu_lo = S.mu_lo, mu_hi = S.mu_hi;
     const double inv2pi = 1.0 / kTwoPi;
@@ -868,32 +892,48 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
         if (!g.active) continue;
         if (!first) __syncthreads();                // the previous ring's LDS tables are no longer read
         const double4 *gtr = trace + slot * (nfp + 1);
+        if (threadIdx.x == 0) k_next = NW;
+        // per round of blockDim threads: the output scales of E energies, the
+        // LDS trace per fine-phase sample i (F, z_{i+1}/z_i - 1, x position of
+        // E_0 at z_i, mu; phi_o in po) and four sub-table quads per thread (the
+        // ring's sub-table is [nmu][W] in HBM, per-ring stride a multiple of 4
+        // floats, transposed into the x-major LDS layout).  All of a round's
+        // loads are issued at clamped, valid indices before its LDS writes.
         {
             const double scale = g.w_cell * g.T * g.T * g.T;
-            for (int e = threadIdx.x; e < E; e += blockDim.x) sce[e] = (float)(scale / S.energy[e]);
-        }
-        if (threadIdx.x == 0) k_next = NW;
-        // LDS trace per fine-phase sample i: (F, z_{i+1}/z_i - 1, x position of
-        // E_0 at z_i, mu); phi_o in po
-        for (int i = threadIdx.x; i <= nfp; i += blockDim.x) {
-            const double4 v = gtr[i];
-            const double zn = i < nfp ? gtr[i + 1].y : v.y;
-            tr[i] = make_double4(v.x, zn / v.y - 1.0, log10(v.y) * S.ihx + g.tbk, v.w);
-            po[i] = v.z;
-        }
-        // the ring's sub-table ([nmu][W] in HBM, per-ring stride a multiple of 4
-        // floats) transposed into the x-major LDS layout
-        const float4 *gsub = (const float4 *)(sub + slot * (size_t)S.sub_stride);
-        for (int i = threadIdx.x; i < S.sub_stride / 4; i += blockDim.x) {
-            const float4 v = gsub[i];
-            const float vk[4] = {v.x, v.y, v.z, v.w};
-            int m = (4 * i) / W, c = 4 * i - m * W;
+            const float4 *gsub = (const float4 *)(sub + slot * (size_t)S.sub_stride);
+            const int nsub = S.sub_stride / 4;
+            for (int r0 = 0; r0 < E || r0 <= nfp || 4 * r0 < nsub; r0 += blockDim.x) {
+                const int i = r0 + threadIdx.x;
+                const int it = i <= nfp ? i : 0;
+                const double en = S.energy[i < E ? i : 0];
+                const double4 v = gtr[it];
+                const double zn = gtr[it < nfp ? it + 1 : it].y;
+                float4 sq[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (m < nmu) tab[c * NMP + m] = vk[k];
-                if (++c == W) {
-                    c = 0;
-                    ++m;
+                for (int k = 0; k < 4; ++k) {
+                    const int si = 4 * r0 + threadIdx.x + k * blockDim.x;
+                    sq[k] = gsub[si < nsub ? si : 0];
+                }
+                if (i < E) sce[i] = (float)(scale / en);
+                if (i <= nfp) {
+                    tr[i] = make_double4(v.x, zn / v.y - 1.0, log10(v.y) * S.ihx + g.tbk, v.w);
+                    po[i] = v.z;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int si = 4 * r0 + threadIdx.x + k * blockDim.x;
+                    if (si >= nsub) continue;
+                    const float vk[4] = {sq[k].x, sq[k].y, sq[k].z, sq[k].w};
+                    int m = (4 * si) / W, c = 4 * si - m * W;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (m < nmu) tab[c * NMP + m] = vk[q];
+                        if (++c == W) {
+                            c = 0;
+                            ++m;
+                        }
+                    }
                 }
             }
         }
@@ -1174,35 +1214,37 @@ __global__ __launch_bounds__(32 * kReduceGroups) void k_reduce4(DevSpec S, const
     const float *base = partial + ((size_t)g0 * P + k) * E + (live ? e : 0);
     const size_t rs = (size_t)P * E;
     // the first batch of partials is in flight while the group flags are
-    // staged (a partial of an inactive group is read but not added)
+    // staged (a partial of an inactive group is read but not added).  The
+    // loads are unconditional, all of a batch in flight together: past the
+    // instance's groups they re-read its first group, and the sums take
+    // only groups below ng with their flag set.
     float4 v[kReduceBatch];
+    if (ng > 0) {
 #pragma unroll
-    for (int j = 0; j < kReduceBatch; ++j) {
-        const int i = grp + j * kReduceGroups;
-        v[j] = live && i < ng ? *(const float4 *)(base + i * rs) : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int j = 0; j < kReduceBatch; ++j) {
+            const int i = grp + j * kReduceGroups;
+            v[j] = *(const float4 *)(base + (i < ng ? i : 0) * rs);
+        }
     }
     stage_group_flags(list, glist, rings, g0, ng, act);
     __syncthreads();
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    if (live) {
-        for (int i0 = grp; i0 < ng; i0 += kReduceGroups * kReduceBatch) {
-            if (i0 != grp) {
-#pragma unroll
-                for (int j = 0; j < kReduceBatch; ++j) {
-                    const int i = i0 + j * kReduceGroups;
-                    v[j] = i < ng ? *(const float4 *)(base + i * rs) : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-            }
+    for (int i0 = grp; i0 < ng; i0 += kReduceGroups * kReduceBatch) {
+        if (i0 != grp) {
 #pragma unroll
             for (int j = 0; j < kReduceBatch; ++j) {
                 const int i = i0 + j * kReduceGroups;
-                if (i < ng && act[i]) {
-                    s0 += (double)v[j].x;
-                    s1 += (double)v[j].y;
-                    s2 += (double)v[j].z;
-                    s3 += (double)v[j].w;
-                }
+                v[j] = *(const float4 *)(base + (i < ng ? i : 0) * rs);
             }
+        }
+#pragma unroll
+        for (int j = 0; j < kReduceBatch; ++j) {
+            const int i = i0 + j * kReduceGroups;
+            const bool add = i < ng && act[i < ng ? i : 0];
+            s0 += add ? (double)v[j].x : 0.0;
+            s1 += add ? (double)v[j].y : 0.0;
+            s2 += add ? (double)v[j].z : 0.0;
+            s3 += add ? (double)v[j].w : 0.0;
         }
     }
     red[grp][el] = make_double4(s0, s1, s2, s3);
