@@ -142,13 +142,13 @@ __global__ __launch_bounds__(64) void k_table_u(DevSpec S, const int32_t *list, 
         D1 psi, dpsi, T, dT;
         if (a <= kHalfPi) {
             D1 tp;
-            bend_out(S, u, a, psi, dpsi, tp);
+            bend_out(S.glx, S.glw, u, a, psi, dpsi, tp);
             T = tp + cdt_obl;
             dT = dpsi * sin(a) / sq;
         } else {
             const double be = kPi - a;
             D1 psb, dpsb, tpb;
-            bend_out(S, u, be, psb, dpsb, tpb);
+            bend_out(S.glx, S.glw, u, be, psb, dpsb, tpb);
             const double sa = sin(a), ca = cos(a);
             D1 kk = sqrt(3.0 * (1.0 - u));
             D1 arg = 3.0 * u * kk / (2.0 * sa);
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(64) void k_table_u(DevSpec S, const int32_t *list, 
             D1 rhop = kp * (rho - u) / (3.0 * rho * rho - k);
             D1 v = u / rho, vp = -u * rhop / (rho * rho);
             D1 ph, dph, th, dth;
-            grazing(S, v, ph, dph, th, dth);
+            grazing(S.glx, S.glw, v, ph, dph, th, dth);
             psi = 2.0 * ph - psb;
             dpsi = 2.0 * dph * vp + dpsb;
             D1 cdtp = kap - rho + u * log((kap - u) / (rho - u));

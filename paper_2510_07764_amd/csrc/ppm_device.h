@@ -61,12 +61,14 @@ __device__ inline auto q_s2(const X &x, const V &v) -> decltype(x * v)
     return 2.0 - x * x - v * t * t / (1.0 - v);
 }
 
-// Gauss-Legendre rules on [0, 1] held back to back: 20, 24, 32, 48 and 64 nodes.
-__device__ inline void gl_rule(const DevSpec &S, int n, const double *&x, const double *&w)
+// Gauss-Legendre rules on [0, 1] held back to back: 20, 24, 32, 48 and 64
+// nodes (kGLNodes in all), at bx / bw (the plan's copy, or an LDS copy).
+constexpr int kGLNodes = 188;
+__device__ inline void gl_rule(const double *bx, const double *bw, int n, const double *&x, const double *&w)
 {
     int off = n == 20 ? 0 : (n == 24 ? 20 : (n == 32 ? 44 : (n == 48 ? 76 : 124)));
-    x = S.glx + off;
-    w = S.glw + off;
+    x = bx + off;
+    w = bw + off;
 }
 
 // psi, dpsi/dalpha and c dt_p/R for an outgoing ray, 0 <= alpha <= pi/2.
@@ -79,7 +81,8 @@ __device__ inline void gl_rule(const DevSpec &S, int n, const double *&x, const 
 // terms that are not quadrature sums come from q0 = 0 only, so that summing
 // the results of q0 = 0 .. qs-1 gives the full values (lanes of one ray).
 template <class U>
-__device__ void bend_out(const DevSpec &S, const U &u, double alpha, U &psi, U &dpsi, U &tp, int q0 = 0, int qs = 1)
+__device__ void bend_out(const double *bx, const double *bw, const U &u, double alpha, U &psi, U &dpsi, U &tp,
+                         int q0 = 0, int qs = 1)
 {
     const U sq = sqrt(1.0 - u);
     if (alpha <= 0.0) { psi = U(0.0); dpsi = q0 == 0 ? 1.0 / sq : U(0.0); tp = U(0.0); return; }
@@ -88,7 +91,7 @@ __device__ void bend_out(const DevSpec &S, const U &u, double alpha, U &psi, U &
     const double *gx, *gw;
     if (c < 1e-9) {
         // tangent ray: x/sqrt(x^2 s^2 q) = 1/(s sqrt q), regular on [0, 1]
-        gl_rule(S, 32, gx, gw);
+        gl_rule(bx, bw, 32, gx, gw);
         U I1 = U(0.0), IT = U(0.0);
         for (int q = q0; q < 32; q += qs) {
             double x = gx[q], w = gw[q];
@@ -102,7 +105,7 @@ __device__ void bend_out(const DevSpec &S, const U &u, double alpha, U &psi, U &
         return;
     }
     const int n = c >= 0.5 ? 20 : (c >= 0.2 ? 24 : (c >= 0.05 ? 32 : (c >= 1e-3 ? 48 : 64)));
-    gl_rule(S, n, gx, gw);
+    gl_rule(bx, bw, n, gx, gw);
     U A = c / (s * sqrt(qa));
     U L = asinh(1.0 / A);
     const U w = u / (1.0 - u);        // q(x) = 2 - x^2 - w (1 - x^2)^2
@@ -137,7 +140,8 @@ __device__ void bend_out(const DevSpec &S, const U &u, double alpha, U &psi, U &
 
 // psi(v, pi/2), c dt_p/R (v, pi/2) and their v-derivatives (periastron leg)
 template <class U>
-__device__ void grazing(const DevSpec &S, const U &v, U &ph, U &dph, U &th, U &dth, int q0 = 0, int qs = 1)
+__device__ void grazing(const double *bx, const double *bw, const U &v, U &ph, U &dph, U &th, U &dth, int q0 = 0,
+                        int qs = 1)
 {
     U J = U(0.0), J3 = U(0.0), K = U(0.0), K1 = U(0.0);
     const double *gx, *gw;
@@ -146,7 +150,7 @@ __device__ void grazing(const DevSpec &S, const U &v, U &ph, U &dph, U &th, U &d
     // keep the relative error below 1e-13 (against a 128-node rule)
     const double vv = value(v);
     const int n = vv <= 0.6 ? 20 : (vv <= 0.64 ? 24 : (vv <= 0.66 ? 32 : 48));
-    gl_rule(S, n, gx, gw);
+    gl_rule(bx, bw, n, gx, gw);
     const U vw = v / (1.0 - v);
     for (int q = q0; q < n; q += qs) {
         double x = gx[q], w = gw[q];

@@ -222,11 +222,18 @@ __global__ __launch_bounds__(256) void k_setup(DevSpec S, const double *params, 
 // sqrt(q0)), which resolves the boundary layer of width ~cos(alpha) at
 // x -> 0 for near-grazing rays.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_table(DevSpec S, const int32_t *list, const StarRec *stars, const RingRec *rings, double4 *table)
+__global__ __launch_bounds__(256, 3) void k_table(DevSpec S, const int32_t *list, const StarRec *stars, const RingRec *rings, double4 *table)
 {
     const int ent = list[blockIdx.x], b = ent / S.R_tot, r = ent - b * S.R_tot;
     const RingRec g = rings[(size_t)b * S.R_tot + r];
     if (g.n_cells == 0) return;
+    // the quadrature rules in LDS: the node loops read them at LDS latency
+    __shared__ double sgx[kGLNodes], sgw[kGLNodes];
+    for (int i = threadIdx.x; i < kGLNodes; i += blockDim.x) {
+        sgx[i] = S.glx[i];
+        sgw[i] = S.glw[i];
+    }
+    __syncthreads();
     const StarRec st = stars[b];
     const double u = g.u;
     const double dal = g.alpha_max / (S.n_alpha - 1);
@@ -246,7 +253,7 @@ __global__ __launch_bounds__(256) void k_table(DevSpec S, const int32_t *list, c
             // ray at pi - alpha (its outgoing leg from the periastron)
             const bool inward = a > kHalfPi;
             double psb, dpsb, tpb;
-            bend_out(S, u, inward ? kPi - a : a, psb, dpsb, tpb, kq, kTableSplit);
+            bend_out(sgx, sgw, u, inward ? kPi - a : a, psb, dpsb, tpb, kq, kTableSplit);
             const double sa = sin(a);
             if (!inward) {
                 psi = psb;
@@ -264,7 +271,7 @@ __global__ __launch_bounds__(256) void k_table(DevSpec S, const int32_t *list, c
                 double rhop = kp * (rho - u) / (3.0 * rho * rho - k);
                 double v = u / rho, vp = -u * rhop / (rho * rho);
                 double ph, dph, th, dth;
-                grazing(S, v, ph, dph, th, dth, kq, kTableSplit);
+                grazing(sgx, sgw, v, ph, dph, th, dth, kq, kTableSplit);
                 psi = 2.0 * ph - psb;
                 dpsi = 2.0 * dph * vp + dpsb;
                 double Rp = rho * g.R;
