@@ -73,14 +73,19 @@ __device__ inline StarRec make_star(const DevSpec &S, const double *p)
     return s;
 }
 
-// Block = 64 rings, four waves; lane = ring.  The waves share a ring's
-// transcendental work, each on its own SIMD: wave 0 the shape and velocity
-// chain (Eqs. 2, 3, 7, 18) and the ray limits, wave 1 the outer arc
-// half-width, wave 2 the inner one and the crescent mask radius, wave 3 the
-// colatitude band, surface gravity (Eqs. 10, 11) and temperature; wave 0
-// takes the others' results from LDS and writes the record.  Every thread
-// evaluates the star record itself (identical values).
-__global__ __launch_bounds__(256) void k_setup(DevSpec S, const double *params, const int32_t *n_cells, StarRec *stars,
+// Block = 64 rings, eight waves; lane = ring.  The waves share a ring's
+// transcendental work, two on each SIMD, so that no chain of FP64
+// transcendentals is longer than it must be: wave 0 the shape and velocity
+// chain (Eqs. 2, 3, 7, 18), wave 1 the outer arc half-width, wave 2 the inner
+// one and the cosine of the mask radius, wave 3 the colatitude band and the
+// surface gravity (Eqs. 10, 11), wave 4 the ray limit alpha_max, wave 5 the
+// radial delay of Eq. (16), wave 6 the crescent mask half-width, wave 7 the
+// temperature; waves 4 and 5 redo the few steps of wave 0 they start from
+// (the same operations, so the same values).  Wave 0 takes the others'
+// results from LDS and writes the record.  Every thread evaluates the star
+// record itself (identical values).
+constexpr int kSetupWaves = 8;
+__global__ __launch_bounds__(64 * kSetupWaves) void k_setup(DevSpec S, const double *params, const int32_t *n_cells, StarRec *stars,
                         RingRec *rings, int32_t *vis_pairs, int32_t *diag)
 {
     const int b = blockIdx.y;
@@ -115,25 +120,44 @@ __global__ __launch_bounds__(256) void k_setup(DevSpec S, const double *params, 
         th = 0.5 * (e0 + e1);
     }
     const int shape = S.shape[spot];
-    // results of waves 1-3 per ring: outer, inner half-width, cos(mask radius),
-    // cos band difference, log g, T, crescent mask half-width on the ring
-    __shared__ double xo[7][64];
+    // results of waves 1-7 per ring: outer, inner half-width, cos(mask radius),
+    // cos band difference, log g, T, crescent mask half-width, alpha_max,
+    // c dt(R)/R
+    __shared__ double xo[9][64];
     RingRec g;
-    double acap = 0.0;
     if (role == 1) {
         xo[0][lane] = arc_halfwidth(th, tc, z);
     } else if (role == 2) {
         xo[1][lane] = (S.n_side == 0 && shape == PPM_SHAPE_ANNULUS) ? arc_halfwidth(th, tc, S.shape_a[spot] * z) : 0.0;
         xo[2][lane] = cos(S.shape_a[spot] * z);
+    } else if (role == 3) {
+        xo[3][lane] = S.n_side > 0 ? 0.0 : cos(e0) - cos(e1);
+        xo[4][lane] = log10(st.g0 * gravity_ratio(st, S.mode, th));   // Eqs. (10), (11)
+    } else if (role == 7) {
+        xo[5][lane] = pow(10.0, S.n_side > 0 ? 6.0 : p[10 + 4 * spot]);
+    } else if (role == 6) {
         xo[6][lane] = 0.0;
         if (S.n_side == 0 && shape == PPM_SHAPE_CRESCENT) {
             const double sgn = (tc >= kHalfPi) ? 1.0 : -1.0;
             xo[6][lane] = arc_halfwidth(th, tc - sgn * S.shape_b[spot] * z, S.shape_a[spot] * z);
         }
-    } else if (role == 3) {
-        xo[3][lane] = S.n_side > 0 ? 0.0 : cos(e0) - cos(e1);
-        xo[4][lane] = log10(st.g0 * gravity_ratio(st, S.mode, th));   // Eqs. (10), (11)
-        xo[5][lane] = pow(10.0, S.n_side > 0 ? 6.0 : p[10 + 4 * spot]);
+    } else if (role == 4) {
+        // the largest emission angle: below the cap of rays that reach the
+        // observer and at most pi/2 beyond the local vertical
+        const double ct = cos(th), sn = sin(th);
+        const double R = st.Re * (1.0 + st.o2 * ct * ct);          // Eq. (7)
+        const double dR = -2.0 * st.Re * st.o2 * ct * sn;
+        const double u = st.Rs / R, sq1u = sqrt(1.0 - u);
+        const double f = dR / (R * sq1u);                           // Eq. (2)
+        const double v = 1.5 * u * sqrt(3.0 * (1.0 - u));
+        const double acap = v >= 1.0 ? kHalfPi : kPi - asin(v);
+        double amax = kHalfPi + fabs(atan(f));
+        if (amax > acap - 1e-6) amax = acap - 1e-6;
+        xo[7][lane] = amax;
+    } else if (role == 5) {
+        const double ct = cos(th);
+        const double R = st.Re * (1.0 + st.o2 * ct * ct);          // Eq. (7)
+        xo[8][lane] = cdt_oblate(st.Re, st.Rs, R) / R;
     } else {
         g.spot = spot;
         g.shape = shape;
@@ -154,14 +178,6 @@ __global__ __launch_bounds__(256) void k_setup(DevSpec S, const double *params, 
         g.sineta = g.f / sqrt(1.0 + g.f * g.f);
         g.beta = kTwoPi * st.nu * g.R * sn / (kC * g.sq1u);        // Eq. (18)
         g.gamma = 1.0 / sqrt(1.0 - g.beta * g.beta);
-        {
-            double v = 1.5 * g.u * sqrt(3.0 * (1.0 - g.u));
-            acap = v >= 1.0 ? kHalfPi : kPi - asin(v);
-        }
-        double amax = kHalfPi + fabs(atan(g.f));
-        if (amax > acap - 1e-6) amax = acap - 1e-6;
-        g.alpha_max = amax;
-        g.cdt_obl = cdt_oblate(st.Re, st.Rs, g.R) / g.R;
         g.phi_spot = -kTwoPi * (p[3] + (spot == 1 ? p[15] : 0.0));
         // map rings: per-patch temperatures, 10^6 K is the reference the
         // accumulation scales by
@@ -169,8 +185,10 @@ __global__ __launch_bounds__(256) void k_setup(DevSpec S, const double *params, 
         double sgn = (tc >= kHalfPi) ? 1.0 : -1.0;
         g.tm = tc - sgn * S.shape_b[spot] * z;
     }
-    __syncthreads();                                   // waves 1-3 have written their results
+    __syncthreads();                                   // waves 1-7 have written their results
     if (role != 0 || r >= S.R_tot) return;
+    g.alpha_max = xo[7][lane];
+    g.cdt_obl = xo[8][lane];
     g.dcos = xo[3][lane];
     g.logg = xo[4][lane];
     g.dphi_out = xo[0][lane];
@@ -1558,7 +1576,7 @@ size_t accum_table_lds(const DevSpec &S)
 void launch_setup(const DevSpec &S, const Workspace &W, const double *params, const int32_t *ncells_dev, int B,
                   hipStream_t st)
 {
-    hipLaunchKernelGGL(k_setup, dim3((S.R_tot + 63) / 64, B), dim3(256), 0, st, S, params, ncells_dev, W.stars,
+    hipLaunchKernelGGL(k_setup, dim3((S.R_tot + 63) / 64, B), dim3(64 * kSetupWaves), 0, st, S, params, ncells_dev, W.stars,
                        W.rings, W.vis_pairs, W.diag);
 }
 
