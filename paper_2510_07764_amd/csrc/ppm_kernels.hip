@@ -908,7 +908,10 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     }
     const double mu_lo = S.mu_lo, mu_hi = S.mu_hi;
     const double inv2pi = 1.0 / kTwoPi;
-    const int k_begin = tile * PT;
+    // the tile's phases are interleaved over the ring's rotation (phase tile +
+    // n_tile kk for kk < PT), so that every tile of a ring gets a similar mix
+    // of phases where much or little of the ring is in view
+    const int n_tile = (P + PT - 1) / PT;
     bool first = true;                              // no active ring of the group done yet
     for (int q = 0; q < g_count; ++q) {
         const int ent = list[g_first + q], b = ent / S.R_tot, r = ent - b * S.R_tot;
@@ -981,7 +984,7 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
         const int xw0 = g.xw0, xw = g.xw;
         int npairs = 0, nxout = 0;
         for (int kk = wave; kk < PT;) {
-            const int k = k_begin + kk;
+            const int k = tile + n_tile * kk;
             if (k >= P) break;
             float acc[EPL];
 #pragma unroll
