@@ -870,7 +870,8 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     const int NMP = fast_tab_stride(nmu);
     float4 *Qb = (float4 *)(tab + fast_tab_floats(S));         // NW waves * 64 quads
     float4 *Pb = Qb + NW * 64;                                 // NW waves * 64 pair mu weights
-    double *po = (double *)(Pb + NW * 64);                     // nfp + 1 phi_o, compact for the search
+    float *hs = (float *)(Pb + NW * 64);                       // NW waves * EPL * 64 first-half partials
+    double *po = (double *)(hs + NW * EPL * 64);               // nfp + 1 phi_o, compact for the search
     double *ipo = po + nfp + 1;                                // nfp: 1 / (phi_o[i+1] - phi_o[i])
     double *mcf = ipo + nfp + 1;                               // nmu * 4 mu-interval coefficients
     int16_t *pbk = (int16_t *)(mcf + 4 * nmu);                 // 2 nfp phase buckets
@@ -880,6 +881,7 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
     const int n_pb = 2 * nfp;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __shared__ int k_next;
+    __shared__ int half_done[NW];   // first halves of split phases stored (see the phase loop)
     // ring-independent tables, staged once per block.  Every load of a round
     // is issued (at a clamped, valid index) before the round's LDS writes, so
     // that the tables cost one memory latency, not one per table.
@@ -921,6 +923,7 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
         if (!first) __syncthreads();                // the previous ring's LDS tables are no longer read
         const double4 *gtr = trace + slot * (nfp + 1);
         if (threadIdx.x == 0) k_next = NW;
+        if (threadIdx.x < NW) half_done[threadIdx.x] = 0;
         // per round of blockDim threads: the output scales of E energies, the
         // LDS trace per fine-phase sample i (F, z_{i+1}/z_i - 1, x position of
         // E_0 at z_i, mu; phi_o in po) and four sub-table quads per thread (the
@@ -983,14 +986,46 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
         const double phio0 = gtr[0].z;                 // phi_o of sample 0 (tr holds x positions)
         const int xw0 = g.xw0, xw = g.xw;
         int npairs = 0, nxout = 0;
-        for (int kk = wave; kk < PT;) {
+        // Work units.  With groups of one ring every phase is summed in two
+        // halves, cells [0, H) and [H, n) with H = 64 ceil(n / 128): its
+        // partial is S_A w + S_B w, the second half added to the stored first
+        // (a ring of at most 64 cells has one part).  Whole phases go to the
+        // waves as they finish; the last (phases of the tile mod NW) phases
+        // are handed out as halves, the second half of one adding after the
+        // first half's store, so that the block's last round is half as long.
+        // The sums do not depend on which wave takes which unit.  Groups of
+        // several rings (batches, where the tail is shared by more blocks)
+        // sum a phase in one part.
+        const int pte = min(PT, (P - tile + n_tile - 1) / n_tile);   // phases of this tile
+        const int H = 64 * ((g.n_cells + 127) / 128);
+        const bool two = !GRP && g.n_cells > H;
+        const int n_split = two ? pte % NW : 0;
+        const int n_whole = pte - n_split;
+        const int n_units = n_whole + 2 * n_split;
+        for (int uu = wave; uu < n_units;) {
+            int kk = uu, part = 0;                     // part 0: whole phase, 1: first half, 2: second half
+            if (uu >= n_whole) {
+                kk = n_whole + ((uu - n_whole) >> 1);
+                part = 1 + ((uu - n_whole) & 1);
+            }
             const int k = tile + n_tile * kk;
-            if (k >= P) break;
+            float *out = partial + ((size_t)gi * P + k) * E;
             float acc[EPL];
 #pragma unroll
             for (int m = 0; m < EPL; ++m) acc[m] = 0.0f;
             const double Phik = (k + 0.5) / S.Pd;
-            for (int c0 = 0; c0 < g.n_cells; c0 += 64) {
+            const int c_beg = part == 2 ? H : 0, c_end = part == 1 ? H : g.n_cells;
+            for (int c0 = c_beg; c0 < c_end; c0 += 64) {
+                if (c0 == H && part == 0) {
+                    // whole phase: the first half's scaled partial waits in the
+                    // wave's LDS slot while the second half is summed
+#pragma unroll
+                    for (int m = 0; m < EPL; ++m) {
+                        int e = lane + 64 * m;
+                        hs[(wave * EPL + m) * 64 + lane] = e < E ? acc[m] * sce[e] : 0.0f;
+                        acc[m] = 0.0f;
+                    }
+                }
                 // ---------------- stage A: one (cell, phase) pair per lane
                 const int j = c0 + lane;
                 bool vis = false;
@@ -1069,23 +1104,49 @@ __global__ __launch_bounds__(64 * NW, NW >= 8 ? 6 : 4) void k_accum_fast(DevSpec
                 else
                     pairs_general<EPL>(mask, Pw, fr, I0, m0, lane, tab, NMP, xw0, xw, nx, Qw, tbr, acc);
             }
-            float *out = partial + ((size_t)gi * P + k) * E;
-            if (!GRP || first) {
+            if (part == 1) {
+                // first half of a split phase (groups of one ring: a plain store)
 #pragma unroll
                 for (int m = 0; m < EPL; ++m) {
                     int e = lane + 64 * m;
                     if (e < E) out[e] = acc[m] * sce[e];
                 }
-            } else {
+                __builtin_amdgcn_s_waitcnt(0);         // the stores have completed
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                if (lane == 0) __hip_atomic_store(&half_done[kk - n_whole], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else if (part == 0 && two) {
+                // whole phase in two halves: first half (LDS slot) + second half
+#pragma unroll
+                for (int m = 0; m < EPL; ++m) {
+                    int e = lane + 64 * m;
+                    if (e < E) out[e] = hs[(wave * EPL + m) * 64 + lane] + acc[m] * sce[e];
+                }
+            } else if (part == 2 || (GRP && !first)) {
+                if (part == 2) {
+                    // the first half was handed out earlier, so its wave is running: a
+                    // bounded wait for its store
+                    for (int it = 0; it < (1 << 22); ++it) {
+                        if (__hip_atomic_load(&half_done[kk - n_whole], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                            break;
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                }
 #pragma unroll
                 for (int m = 0; m < EPL; ++m) {
                     int e = lane + 64 * m;
                     if (e < E) out[e] += acc[m] * sce[e];
                 }
+            } else {
+#pragma unroll
+                for (int m = 0; m < EPL; ++m) {
+                    int e = lane + 64 * m;
+                    if (e < E) out[e] = acc[m] * sce[e];
+                }
             }
             int nk = 0;
             if (lane == 0) nk = atomicAdd(&k_next, 1);
-            kk = __builtin_amdgcn_readfirstlane(nk);
+            uu = __builtin_amdgcn_readfirstlane(nk);
         }
         // wave totals of the ring's counters
 #pragma unroll
@@ -1570,6 +1631,7 @@ size_t accum_table_lds(const DevSpec &S)
     if (S.fast)
         return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.nmu + 1) & ~1)
              + sizeof(float) * fast_tab_floats(S) + sizeof(float4) * kFwdWaves * 64 + sizeof(float4) * kFwdWaves * 64
+             + sizeof(float) * kFwdWaves * ((S.E + 63) / 64 <= 1 ? 1 : ((S.E + 63) / 64 <= 2 ? 2 : ((S.E + 63) / 64 <= 4 ? 4 : 8))) * 64
              + sizeof(double) * 2 * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
              + sizeof(int16_t) * (2 * S.n_fp + S.mu_nb) + sizeof(float) * 2 * S.E;
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * S.nmu + sizeof(float) * S.nmu * S.nx
