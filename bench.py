@@ -45,10 +45,10 @@ PEAK_FP32_TFLOPS = 157.3
 # kernel sources the counters were taken on and for the tiles listed; any
 # other case reports null until the counters are taken again.
 KERNEL_SOURCES = ("ppm_kernels.hip", "ppm_device.h", "ppm_dual.h", "ppm_internal.h", "ppm_launch.h")
-TRAFFIC = {"sources_sha256": "9c1bfa54229d53232d312ebb0d9d7d51c9b153324e2089b3fbbabedb9ca49aa2",
+TRAFFIC = {"sources_sha256": "fdd32e6f6973e23cf971741f6ced43d21969141b1c91166e28389d80d68cbd4f",
            "fetch_scale": 1.99980, "write_scale": 1.0,
            # phase tile -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-           "by_tile": {64: (4297.08, 32960.00), 128: (4297.05, 32864.00)},
+           "by_tile": {64: (4316.63, 32960.00), 128: (4316.56, 32864.00)},
            "profile": "profiles/k_accum_fast_config1_traffic.md"}
 
 
