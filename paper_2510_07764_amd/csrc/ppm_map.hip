@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_map_sort(DevSpec S, const int32_t *list
 // an energy uses.
 template <int EPL, bool INTERIOR>
 __device__ __forceinline__ void map_pairs(uint64_t mask, float w0f, float w1f, float w2f, float w3f, float fr,
-                                          float tw, int I0, int m0, int lane, const float2 *slb, int NMP,
+                                          float tw, int pk, int lane, const float2 *slb, int NMP,
                                           int WM, int w0, int xw, int nx, float4 *Qw,
                                           const float (&tbr)[EPL], float (&acc)[EPL])
 {
@@ -152,7 +152,8 @@ __device__ __forceinline__ void map_pairs(uint64_t mask, float w0f, float w1f, f
         mask &= mask - 1;
         const float pw0 = readlane_f(w0f, p), pw1 = readlane_f(w1f, p), pw2 = readlane_f(w2f, p),
                     pw3 = readlane_f(w3f, p), pfr = readlane_f(fr, p), ptw = readlane_f(tw, p);
-        const int pI0 = __builtin_amdgcn_readlane(I0, p), pm0 = __builtin_amdgcn_readlane(m0, p);
+        const int ppk = __builtin_amdgcn_readlane(pk, p);
+        const int pI0 = ppk >> 8, pm0 = ppk & 255;
         int col = pI0 - 1 + lane - w0;
         float Sv = 0.0f;
         if (INTERIOR || (col >= 0 && col < xw)) {
@@ -218,6 +219,8 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     int16_t *pbk = (int16_t *)(mcf + 4 * nmu);                 // 2 nfp phase buckets
     int16_t *mbk = pbk + 2 * nfp;                              // mu_nb mu buckets
     float *tbl = (float *)(mbk + ((S.mu_nb + 1) & ~1));        // E: the energies' x offsets
+    // (bucket, first patch) of the non-empty buckets, 8-byte aligned
+    int2 *nel = (int2 *)(lds_raw + ((((unsigned char *)(tbl + E) - lds_raw) + 7) & ~7));
     const int n_pb = 2 * nfp;
     const int tid = threadIdx.x;
     const double4 *gtr = trace + slot * (nfp + 1);
@@ -246,6 +249,21 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     }
     for (int i = tid; i < nfp; i += blockDim.x) ipo[i] = 1.0 / (po[i + 1] - po[i]);
     const int wave = tid >> 6, lane = tid & 63;
+    const int32_t *gr = grp + slot * (NB + 1);
+    if (wave == 0) {
+        // the non-empty buckets in order, with the sentinel (NB, active patches)
+        int cnt = 0;
+        for (int q0 = 0; q0 < NB; q0 += 64) {
+            const int q = q0 + lane;
+            const int a0 = gr[q < NB ? q : NB], a1 = gr[q < NB ? q + 1 : NB];
+            const bool ne = q < NB && a1 > a0;
+            const uint64_t m = __ballot(ne);
+            if (ne) nel[cnt + __popcll(m & ((1ull << lane) - 1ull))] = make_int2(q, a0);
+            cnt += __popcll(m);
+        }
+        if (lane == 0) nel[cnt] = make_int2(NB, gr[NB]);
+    }
+    __syncthreads();   // phase buckets, spacings and the bucket list are in place
     float4 *Qw = Qb + wave * 64;
     const double ihx = S.ihx;
     float tbr[EPL];
@@ -258,13 +276,11 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
     const double inv2pi = 1.0 / kTwoPi;
     const double phio0 = gtr[0].z;
     const int k_first = tile * PT + wave;
-    const bool kval = k_first < P;
     double wg1;
     const int ig = lin_bracket(g.logg, S.g0, S.hg, S.ng, wg1);
     const float fg1 = (float)wg1, fg0 = (float)(1.0 - wg1);
     const double lz_lo = log10(g.zmin), lz_hi = log10(g.zmax);
     const double lkb = log10(kKB);
-    const int32_t *gr = grp + slot * (NB + 1);
     const MapCell *cl = cells + (size_t)b * S.n_pix + healpix_first_pixel(S.n_side, r + 1);
     const size_t slab = (size_t)nmu * nx;
     float acc[KPW][EPL];
@@ -273,115 +289,145 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
 #pragma unroll
         for (int m = 0; m < EPL; ++m) acc[kq][m] = 0.0f;
     int npairs = 0, nclamp = 0, nxout = 0;
-    for (int q = 0; q < NB; ++q) {
-        const int c_beg = gr[q], c_end = gr[q + 1];
-        if (c_end == c_beg) continue;
-        const int u = q - kMapLow;
-        const int it = u < 0 ? 0 : (u > S.nT - 2 ? S.nT - 2 : u);
-        // x window of the bucket: t = (log10(z E / kT) - x0) / hx over the
-        // ring's z range, the bucket's kT range and the energy grid
-        const double lkt_lo = lkb + S.T0 + u * S.hT, lkt_hi = lkt_lo + S.hT;
-        const double tlo = (lz_lo - lkt_hi) * ihx + S.tb0, thi = (lz_hi - lkt_lo) * ihx + S.tb0 + S.r_span;
-        int w0 = (int)floor(tlo) - 2, w1 = (int)floor(thi) + 3;
-        w0 = w0 < 0 ? 0 : w0;
-        w1 = w1 > nx - 1 ? nx - 1 : w1;
-        int xw = w1 - w0 + 1;
-        xw = xw < 0 ? 0 : (xw > WM ? WM : xw);
-        // every interval a pair of the bucket uses lies in [floor(tlo),
-        // floor(thi)] up to one interval of slip (as for the spot rings)
-        const bool interior = floor(tlo) >= 2.0 && floor(thi) <= nx - 4 && w1 - w0 + 1 <= WM;
-        __syncthreads();   // the previous bucket's slabs are no longer read (and the trace is staged)
-        const float *a00 = S.atm + ((size_t)it * S.ng + ig) * slab, *a01 = a00 + slab;
-        const float *a10 = S.atm + ((size_t)(it + 1) * S.ng + ig) * slab, *a11 = a10 + slab;
-        // wave w stages rows w, w + 8, ...; lanes walk the row's columns
-        for (int m = wave; m < nmu; m += kMapWaves) {
-            const size_t o = (size_t)m * nx + w0;
-            for (int c = lane; c < xw; c += 64) {
-                slb[c * NMP + m] = make_float2(fg0 * a00[o + c] + fg1 * a01[o + c], fg0 * a10[o + c] + fg1 * a11[o + c]);
-            }
-        }
-        __syncthreads();
-        if (!kval) continue;
+    const int n_act = gr[NB];   // active patches of the ring, sorted by bucket
+    int staged = -1, w0 = 0, xw = 0, iq = 0;
+    bool interior = false;
+    for (int c0 = 0; c0 < n_act; c0 += 64) {
+        const int c1 = c0 + 64 < n_act ? c0 + 64 : n_act;
+        // ---------------- stage A: lane = patch c0 + lane, for each of the
+        // wave's phases (whatever the patch's bucket)
+        const int cc = c0 + lane;
+        const MapCell mc = cl[cc < c1 ? cc : c1 - 1];
+        const double off = cell_offset(g, mc.j);
+        float W0[KPW], W1[KPW], W2[KPW], W3[KPW], FR[KPW], TW[KPW];
+        int PK[KPW];
+        uint64_t MK[KPW];
 #pragma unroll
         for (int kq = 0; kq < KPW; ++kq) {
             const int k = k_first + kMapWaves * kq;
-            if (k >= P) break;
             const double Phik = (k + 0.5) / S.Pd;
-            for (int c0 = c_beg; c0 < c_end; c0 += 64) {
-                // ---------------- stage A: one (patch, phase) pair per lane
-                const int cc = c0 + lane;
-                bool vis = false, clamped = false;
-                float w0f = 0.f, w1f = 0.f, w2f = 0.f, w3f = 0.f, fr = 0.f, tw = 0.f;
-                int I0 = 0, m0 = 0;
-                if (cc < c_end) {
-                    const MapCell mc = cl[cc];
-                    const double off = cell_offset(g, mc.j);
-                    double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
-                    double php = (a - floor(a)) + phio0;                    // Eq. (45)
-                    int qb = (int)((php - phio0) * S.fpb);                 // Eq. (46): bucket, bounded scan
-                    int l0 = pbk[qb < n_pb - 1 ? qb : n_pb - 1];
-                    while (l0 > 0 && po[l0] > php) --l0;
-                    while (l0 < nfp - 1 && po[l0 + 1] <= php) ++l0;
-                    const double4 A = tr[l0], Cn = tr[l0 + 1];
-                    double wp = (php - po[l0]) * ipo[l0];
-                    wp = fmin(1.0, fmax(0.0, wp));
-                    const double Fp = A.x + wp * (Cn.x - A.x);
-                    if (Fp != 0.0) {
-                        vis = true;
-                        const double mu = fmin(mu_hi, fmax(mu_lo, A.w + wp * (Cn.w - A.w)));
-                        int qm = (int)((mu - mu_lo) * S.mu_ibw);               // bucket, bounded scan
-                        int lo = mbk[qm < S.mu_nb - 1 ? qm : S.mu_nb - 1];
-                        while (lo > 0 && axmu[lo] > mu) --lo;
-                        while (lo < nmu - 2 && axmu[lo + 1] <= mu) ++lo;
-                        const double *cf = mcf + 4 * lo;
-                        double v0, v1, v2, v3;
-                        if (lo < 3 || lo == nmu - 2) {
-                            const double t = (mu - axmu[lo]) * cf[0];
-                            m0 = lo < nmu - 4 ? lo : nmu - 4;
-                            const int sl = lo - m0;
-                            v0 = sl == 0 ? 1.0 - t : 0.0;
-                            v1 = sl == 0 ? t : (sl == 1 ? 1.0 - t : 0.0);
-                            v2 = sl == 1 ? t : (sl == 2 ? 1.0 - t : 0.0);
-                            v3 = sl == 2 ? t : 0.0;
-                        } else {
-                            m0 = lo - 1;
-                            const double d0 = mu - axmu[m0], d1 = mu - axmu[m0 + 1], d2 = mu - axmu[m0 + 2],
-                                         d3 = mu - axmu[m0 + 3];
-                            const double p01 = d0 * d1, p23 = d2 * d3;
-                            v0 = d1 * p23 * cf[0];
-                            v1 = d0 * p23 * cf[1];
-                            v2 = p01 * d3 * cf[2];
-                            v3 = p01 * d2 * cf[3];
-                        }
-                        const double sc = Fp * (double)mc.T3;
-                        w0f = (float)(v0 * sc);
-                        w1f = (float)(v1 * sc);
-                        w2f = (float)(v2 * sc);
-                        w3f = (float)(v3 * sc);
-                        tw = mc.t;
-                        // x position at zp = z_A (1 + wp q_A) and the patch's kT
-                        const double T0 = A.z + (double)x_shift(wp * A.y, S.ixl) - mc.lkT * ihx;
-                        const double fl = floor(T0);
-                        I0 = (int)fl;
-                        fr = (float)(T0 - fl);
-                        clamped = mc.clamped != 0;
-                        // energies beyond the table's x range contribute nothing
-                        // (counted; none in an interior bucket)
-                        if (!interior && (I0 < 0 || (float)I0 + fr + tbl[E - 1] >= (float)(nx - 2)))
-                            nxout += x_outside_count(I0, fr, tbl, E, nx);
+            bool vis = false, clamped = false;
+            float w0f = 0.f, w1f = 0.f, w2f = 0.f, w3f = 0.f, fr = 0.f;
+            int I0 = 0, m0 = 0;
+            if (cc < c1 && k < P) {
+                double a = Phik + (g.phi_spot + off) * inv2pi + 1.0 - phio0;
+                double php = (a - floor(a)) + phio0;                    // Eq. (45)
+                int qb = (int)((php - phio0) * S.fpb);                 // Eq. (46): bucket, bounded scan
+                int l0 = pbk[qb < n_pb - 1 ? qb : n_pb - 1];
+                while (l0 > 0 && po[l0] > php) --l0;
+                while (l0 < nfp - 1 && po[l0 + 1] <= php) ++l0;
+                const double4 A = tr[l0], Cn = tr[l0 + 1];
+                double wp = (php - po[l0]) * ipo[l0];
+                wp = fmin(1.0, fmax(0.0, wp));
+                const double Fp = A.x + wp * (Cn.x - A.x);
+                if (Fp != 0.0) {
+                    vis = true;
+                    const double mu = fmin(mu_hi, fmax(mu_lo, A.w + wp * (Cn.w - A.w)));
+                    int qm = (int)((mu - mu_lo) * S.mu_ibw);               // bucket, bounded scan
+                    int lo = mbk[qm < S.mu_nb - 1 ? qm : S.mu_nb - 1];
+                    while (lo > 0 && axmu[lo] > mu) --lo;
+                    while (lo < nmu - 2 && axmu[lo + 1] <= mu) ++lo;
+                    const double *cf = mcf + 4 * lo;
+                    double v0, v1, v2, v3;
+                    if (lo < 3 || lo == nmu - 2) {
+                        const double t = (mu - axmu[lo]) * cf[0];
+                        m0 = lo < nmu - 4 ? lo : nmu - 4;
+                        const int sl = lo - m0;
+                        v0 = sl == 0 ? 1.0 - t : 0.0;
+                        v1 = sl == 0 ? t : (sl == 1 ? 1.0 - t : 0.0);
+                        v2 = sl == 1 ? t : (sl == 2 ? 1.0 - t : 0.0);
+                        v3 = sl == 2 ? t : 0.0;
+                    } else {
+                        m0 = lo - 1;
+                        const double d0 = mu - axmu[m0], d1 = mu - axmu[m0 + 1], d2 = mu - axmu[m0 + 2],
+                                     d3 = mu - axmu[m0 + 3];
+                        const double p01 = d0 * d1, p23 = d2 * d3;
+                        v0 = d1 * p23 * cf[0];
+                        v1 = d0 * p23 * cf[1];
+                        v2 = p01 * d3 * cf[2];
+                        v3 = p01 * d2 * cf[3];
+                    }
+                    const double sc = Fp * (double)mc.T3;
+                    w0f = (float)(v0 * sc);
+                    w1f = (float)(v1 * sc);
+                    w2f = (float)(v2 * sc);
+                    w3f = (float)(v3 * sc);
+                    // x position at zp = z_A (1 + wp q_A) and the patch's kT
+                    const double T0 = A.z + (double)x_shift(wp * A.y, S.ixl) - mc.lkT * ihx;
+                    const double fl = floor(T0);
+                    I0 = (int)fl;
+                    fr = (float)(T0 - fl);
+                    clamped = mc.clamped != 0;
+                    // energies beyond the table's x range contribute nothing
+                    // (counted; never the case in a bucket clear of the table's edges)
+                    if (I0 < 0 || (float)I0 + fr + tbl[E - 1] >= (float)(nx - 2))
+                        nxout += x_outside_count(I0, fr, tbl, E, nx);
+                }
+            }
+            W0[kq] = w0f;
+            W1[kq] = w1f;
+            W2[kq] = w2f;
+            W3[kq] = w3f;
+            FR[kq] = fr;
+            TW[kq] = mc.t;
+            PK[kq] = (I0 << 8) | m0;
+            MK[kq] = __ballot(vis);
+            npairs += __popcll(MK[kq]);
+            nclamp += __popcll(__ballot(clamped));
+        }
+        // ---------------- stage B: the buckets holding patches c0 .. c1 - 1,
+        // in order; a bucket that goes on into the next group stays staged
+        for (;;) {
+            const int q = __builtin_amdgcn_readfirstlane(nel[iq].x);
+            const int beg = __builtin_amdgcn_readfirstlane(nel[iq].y);
+            const int end = __builtin_amdgcn_readfirstlane(nel[iq + 1].y);
+            if (q != staged) {
+                const int u = q - kMapLow;
+                const int it = u < 0 ? 0 : (u > S.nT - 2 ? S.nT - 2 : u);
+                // x window of the bucket: t = (log10(z E / kT) - x0) / hx over the
+                // ring's z range, the bucket's kT range and the energy grid
+                const double lkt_lo = lkb + S.T0 + u * S.hT, lkt_hi = lkt_lo + S.hT;
+                const double tlo = (lz_lo - lkt_hi) * ihx + S.tb0, thi = (lz_hi - lkt_lo) * ihx + S.tb0 + S.r_span;
+                w0 = (int)floor(tlo) - 2;
+                int w1 = (int)floor(thi) + 3;
+                w0 = w0 < 0 ? 0 : w0;
+                w1 = w1 > nx - 1 ? nx - 1 : w1;
+                xw = w1 - w0 + 1;
+                xw = xw < 0 ? 0 : (xw > WM ? WM : xw);
+                // every interval a pair of the bucket uses lies in [floor(tlo),
+                // floor(thi)] up to one interval of slip (as for the spot rings)
+                interior = floor(tlo) >= 2.0 && floor(thi) <= nx - 4 && w1 - w0 + 1 <= WM;
+                __syncthreads();   // the previous bucket's slabs are no longer read
+                const float *a00 = S.atm + ((size_t)it * S.ng + ig) * slab, *a01 = a00 + slab;
+                const float *a10 = S.atm + ((size_t)(it + 1) * S.ng + ig) * slab, *a11 = a10 + slab;
+                // wave w stages rows w, w + 8, ...; lanes walk the row's columns
+                for (int m = wave; m < nmu; m += kMapWaves) {
+                    const size_t o = (size_t)m * nx + w0;
+                    for (int c = lane; c < xw; c += 64) {
+                        slb[c * NMP + m] = make_float2(fg0 * a00[o + c] + fg1 * a01[o + c],
+                                                       fg0 * a10[o + c] + fg1 * a11[o + c]);
                     }
                 }
-                uint64_t mask = __ballot(vis);
-                npairs += __popcll(mask);
-                nclamp += __popcll(__ballot(clamped));
-                // ---------------- stage B: the visible pairs one after another
-                if (interior)
-                    map_pairs<EPL, true>(mask, w0f, w1f, w2f, w3f, fr, tw, I0, m0, lane, slb, NMP, WM, w0, xw, nx, Qw,
-                                         tbr, acc[kq]);
-                else
-                    map_pairs<EPL, false>(mask, w0f, w1f, w2f, w3f, fr, tw, I0, m0, lane, slb, NMP, WM, w0, xw, nx,
-                                          Qw, tbr, acc[kq]);
+                __syncthreads();
+                staged = q;
             }
+            // lanes of this group whose patch lies in bucket q
+            const int lo = (beg > c0 ? beg : c0) - c0, hi = (end < c1 ? end : c1) - c0;
+            const uint64_t rng = (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << lo) - 1ull);
+#pragma unroll
+            for (int kq = 0; kq < KPW; ++kq) {
+                const uint64_t mask = MK[kq] & rng;
+                if (!mask) continue;
+                if (interior)
+                    map_pairs<EPL, true>(mask, W0[kq], W1[kq], W2[kq], W3[kq], FR[kq], TW[kq], PK[kq], lane, slb,
+                                         NMP, WM, w0, xw, nx, Qw, tbr, acc[kq]);
+                else
+                    map_pairs<EPL, false>(mask, W0[kq], W1[kq], W2[kq], W3[kq], FR[kq], TW[kq], PK[kq], lane, slb,
+                                          NMP, WM, w0, xw, nx, Qw, tbr, acc[kq]);
+            }
+            if (end > c1) break;
+            ++iq;
+            if (end == c1) break;
         }
     }
     const double scale = g.w_cell * g.T * g.T * g.T;   // g.T = 10^6 K, the patches' reference
@@ -408,7 +454,8 @@ size_t accum_map_lds(const DevSpec &S)
     return sizeof(double4) * (S.n_fp + 1) + sizeof(double) * ((S.n_fp + 2) & ~1) + sizeof(double) * ((S.nmu + 1) & ~1)
          + sizeof(float2) * (size_t)((fast_tab_stride(S.nmu) * S.map_wm + 1) & ~1) + sizeof(float4) * kMapWaves * 64
          + sizeof(double) * (S.n_fp + 1) + sizeof(double) * 4 * S.nmu
-         + sizeof(int16_t) * (2 * S.n_fp + ((S.mu_nb + 1) & ~1)) + sizeof(float) * S.E;
+         + sizeof(int16_t) * (2 * S.n_fp + ((S.mu_nb + 1) & ~1)) + sizeof(float) * S.E + 8
+         + sizeof(int2) * (S.map_nb + 1);
 }
 
 hipError_t launch_forward_map(const DevSpec &S, const Workspace &W, const double *params, const double *map, int B,
