@@ -119,21 +119,26 @@ __global__ __launch_bounds__(256) void k_map_sort(DevSpec S, const int32_t *list
 // ---------------------------------------------------------------------------
 // k_accum_map: block = (ring, 8 KPW output phases), 8 waves, wave w owns
 // phases 8 KPW tile + w + 8 q (q < KPW) and EPL energies, 64 apart, per
-// lane; the staged slabs of a bucket serve all of the block's phases.  Per
-// temperature bucket (logT nodes it, it + 1 after clamping):
-//   staging  the table slabs at logT nodes it and it + 1 (x-major, the two
+// lane; the staged slabs of a bucket serve all of the block's phases.  The
+// ring's active patches, sorted by temperature bucket, go through in groups
+// of 64:
+//   stage A  lane = patch of the group, for each of the wave's phases:
+//            observed-phase lookup (Eqs. 45-46), mu weights of the mixed
+//            scheme pre-scaled by F_p (T / 10^6 K)^3, logT weight, x position
+//            of the first energy (kept in registers);
+// then, for each bucket (logT nodes it, it + 1 after clamping) holding
+// patches of the group, in order:
+//   staging  (unless the bucket is still staged from the previous group) the
+//            table slabs at logT nodes it and it + 1 (x-major, the two
 //            interleaved), linear in the ring's log g, over the x window the
-//            bucket's patches can
-//            reach (redshift range of the ring, bucket's kT range, energy
-//            span and the cubic stencil);
-//   stage A  lane = patch: observed-phase lookup (Eqs. 45-46), mu weights of
-//            the mixed scheme pre-scaled by F_p (T / 10^6 K)^3, logT weight,
-//            x position of the first energy;
-//   stage B  per visible pair: mu contraction of both slabs and their logT
-//            blend at x node I0 - 1 + lane, cubic coefficients of interval
-//            I0 + lane (next nodes by DPP wave shifts; linear in the first and
-//            last table interval, zero outside), per energy one quad read and
-//            a Horner step.
+//            bucket's patches can reach (redshift range of the ring, bucket's
+//            kT range, energy span and the cubic stencil);
+//   stage B  per visible pair of the group in the bucket: mu contraction of
+//            both slabs and their logT blend at x node I0 - 1 + lane, cubic
+//            coefficients of interval I0 + lane (next nodes by DPP wave
+//            shifts; linear in the first and last table interval, zero
+//            outside), per energy one quad read and a Horner step.
+// The pairs are summed in the order of the sorted patches.
 // ---------------------------------------------------------------------------
 // Stage B of k_accum_map for the visible pairs (mask) of one 64-patch group
 // of a bucket.  INTERIOR: the bucket's x window stays one interval clear of
@@ -400,12 +405,28 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_accum_map(DevSpec S, const i
                 __syncthreads();   // the previous bucket's slabs are no longer read
                 const float *a00 = S.atm + ((size_t)it * S.ng + ig) * slab, *a01 = a00 + slab;
                 const float *a10 = S.atm + ((size_t)(it + 1) * S.ng + ig) * slab, *a11 = a10 + slab;
-                // wave w stages rows w, w + 8, ...; lanes walk the row's columns
-                for (int m = wave; m < nmu; m += kMapWaves) {
-                    const size_t o = (size_t)m * nx + w0;
-                    for (int c = lane; c < xw; c += 64) {
-                        slb[c * NMP + m] = make_float2(fg0 * a00[o + c] + fg1 * a01[o + c],
-                                                       fg0 * a10[o + c] + fg1 * a11[o + c]);
+                // wave w stages rows w, w + 8, ..., two rows and 128 columns per
+                // round: the round's sixteen loads (at clamped, valid indices)
+                // are issued before any of them is waited for
+                for (int mA = wave; mA < nmu; mA += 2 * kMapWaves) {
+                    const bool hasB = mA + kMapWaves < nmu;
+                    const int mB = hasB ? mA + kMapWaves : mA;
+                    const size_t oA = (size_t)mA * nx + w0, oB = (size_t)mB * nx + w0;
+                    for (int cb = 0; cb < xw; cb += 128) {
+                        const int c0 = cb + lane, c1 = cb + 64 + lane;
+                        const int d0 = c0 < xw ? c0 : xw - 1, d1 = c1 < xw ? c1 : xw - 1;
+                        const float p0 = a00[oA + d0], p1 = a01[oA + d0], p2 = a10[oA + d0], p3 = a11[oA + d0];
+                        const float q0 = a00[oA + d1], q1 = a01[oA + d1], q2 = a10[oA + d1], q3 = a11[oA + d1];
+                        const float r0 = a00[oB + d0], r1 = a01[oB + d0], r2 = a10[oB + d0], r3 = a11[oB + d0];
+                        const float t0 = a00[oB + d1], t1 = a01[oB + d1], t2 = a10[oB + d1], t3 = a11[oB + d1];
+                        const float2 vp = make_float2(fg0 * p0 + fg1 * p1, fg0 * p2 + fg1 * p3);
+                        const float2 vq = make_float2(fg0 * q0 + fg1 * q1, fg0 * q2 + fg1 * q3);
+                        const float2 vr = make_float2(fg0 * r0 + fg1 * r1, fg0 * r2 + fg1 * r3);
+                        const float2 vt = make_float2(fg0 * t0 + fg1 * t1, fg0 * t2 + fg1 * t3);
+                        if (c0 < xw) slb[c0 * NMP + mA] = vp;
+                        if (c1 < xw) slb[c1 * NMP + mA] = vq;
+                        if (hasB && c0 < xw) slb[c0 * NMP + mB] = vr;
+                        if (hasB && c1 < xw) slb[c1 * NMP + mB] = vt;
                     }
                 }
                 __syncthreads();
