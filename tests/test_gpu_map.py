@@ -47,8 +47,12 @@ def gpu_map(torch_dev, spec, params, maps, what="counts"):
     return out.cpu().numpy(), plan, pt, mt
 
 
+# n_side 32 full and 64 random: rings with more than 64 active patches, so
+# several patch groups per ring, buckets that run on from one group into the
+# next, and (random) many small buckets per group, some outside the table
 @pytest.mark.parametrize("nside,kind,P,E", [(8, "hotspots", 32, 256), (16, "full", 36, 256),
-                                            (8, "random", 24, 64), (4, "full", 16, 37)])
+                                            (8, "random", 24, 64), (4, "full", 16, 37),
+                                            (32, "full", 16, 48), (64, "random", 16, 48)])
 def test_map_parity(torch_dev, nside, kind, P, E):
     spec, p, m = syn.map_config(nside, kind, n_phase=P, n_energy=E)
     print(f"map parity nside {nside} {kind} P {P} E {E}", flush=True)
