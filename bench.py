@@ -137,7 +137,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the batched path shards "
-              "parameter vectors across GPUs by design but no multi-GPU run is part of this build",
+              "parameter vectors across GPUs by design, but this program measures one GPU",
               file=sys.stderr)
         sys.exit(2)
 

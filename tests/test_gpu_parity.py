@@ -3,7 +3,8 @@
 Bar: per phase-channel (or phase-energy) bin, |gpu - oracle| / oracle <= 1e-4
 for bins at or above 1e-6 of the peak (FP32 bulk path); the FP64 path and
 the FP64 intermediate stages (deflection table, fine-phase trace) are held to
-much tighter bounds derived from their arithmetic.
+much tighter bounds derived from their arithmetic (FP64 quadrature and
+Hermite lookups: 1e-8 to 1e-11 relative).
 """
 import json
 import math
