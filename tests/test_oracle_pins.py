@@ -7,7 +7,7 @@ response fold against values fixed outside the oracle (Sects. 2.2, 2.3,
   paper's relations; the recovered coefficients must equal the printed ones
   (``tests/golden/star_shape_coefficients.json``, Sect. 2.2) to rounding,
   and the fit must leave no residual (no missing or extra term);
-* survey spot values of the two benchmark stars (Obar, o2, u range, log g
+* spot values of the two benchmark stars (Obar, o2, u range, log g
   range over a pole-to-pole band, equatorial speed, largest surface tilt),
   computed independently of the oracle and quoted at their printed rounding;
 * oblate radial delay Eq. (delta_t_oblate): the coordinate light-travel
